@@ -1,0 +1,96 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module draws random numbers and evaluates the initial data on a grid.
+It contains none of the solver's arithmetic: no flux, no time scheme, no
+preconditioner, no primal-dual step.  Both the CPU oracle and the GPU path
+receive the arrays produced here as plain inputs.
+
+Workload recipe (the paper uses smooth random-free test data; the benchmark
+family below extends its Burgers examples, Section 4.3, with seeded smooth
+initial data):
+
+    rng   = numpy.random.default_rng(seed)
+    a_k   ~ U(0, 0.25),  k = 1..4
+    th_k  ~ U(0, 2*pi),  k = 1..4
+    u0(x) = 0.5 + sum_k a_k sin(2*pi*k*x + th_k)
+
+evaluated at the finite-difference nodes x_j = j*h_x (Section 3.2), or at
+arbitrary points (for Gauss-point projections).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "fourier_coeffs",
+    "fourier_u0",
+    "fourier_u0_at",
+    "sine_u0",
+    "gaussian_bump_u0",
+    "heat_gamma_at",
+    "batch_shapes",
+    "unit_directions",
+]
+
+
+def fourier_coeffs(seed: int):
+    """Amplitudes a_k and phases th_k (k = 1..4) of the seeded Fourier sum."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 0.25, 4)
+    th = rng.uniform(0.0, 2.0 * np.pi, 4)
+    return a, th
+
+
+def fourier_u0_at(seed: int, x: np.ndarray, length: float = 1.0) -> np.ndarray:
+    """u0(x) = 0.5 + sum_k a_k sin(2 pi k x / length + th_k) at points x (float64)."""
+    a, th = fourier_coeffs(seed)
+    x = np.asarray(x, dtype=np.float64)
+    out = np.full(x.shape, 0.5)
+    for k in range(4):
+        out += a[k] * np.sin(2.0 * np.pi * (k + 1) * x / length + th[k])
+    return out
+
+
+def fourier_u0(seed: int, nx: int, length: float = 1.0) -> np.ndarray:
+    """Seeded Fourier-sum initial data at the nodes x_j = j*length/nx."""
+    x = np.arange(nx, dtype=np.float64) * (length / nx)
+    return fourier_u0_at(seed, x, length)
+
+
+def sine_u0(nx: int, length: float = 1.0) -> np.ndarray:
+    """u0 = sin(2 pi x / length) at the nodes (linear-advection example)."""
+    x = np.arange(nx, dtype=np.float64) * (length / nx)
+    return np.sin(2.0 * np.pi * x / length)
+
+
+def gaussian_bump_u0(nx: int) -> np.ndarray:
+    """u0 = exp(-64 (x - 1/2)^2) on [0,1) (heat example, Section 4.1)."""
+    x = np.arange(nx, dtype=np.float64) / nx
+    return np.exp(-64.0 * (x - 0.5) ** 2)
+
+
+def heat_gamma_at(x: np.ndarray) -> np.ndarray:
+    """Diffusion coefficient gamma(x) = 0.5 + 0.1 sin(2 pi x) (Section 4.1)."""
+    return 0.5 + 0.1 * np.sin(2.0 * np.pi * np.asarray(x, dtype=np.float64))
+
+
+def batch_shapes(seed: int, count: int = 256,
+                 nx_choices=(256, 512, 1024, 2048, 4096),
+                 nt_choices=(64, 128, 256, 512)):
+    """Seeded (nx, nt, u0-seed) triples for a batch of independent problems.
+
+    Sizes are drawn uniformly from the given sets; every problem gets its own
+    initial-data seed derived from the batch seed.
+    """
+    rng = np.random.default_rng(seed)
+    nx = rng.choice(np.asarray(nx_choices), size=count)
+    nt = rng.choice(np.asarray(nt_choices), size=count)
+    seeds = rng.integers(0, 2**31 - 1, size=count)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(nx, nt, seeds)]
+
+
+def unit_directions(seed: int, n: int, count: int) -> np.ndarray:
+    """`count` random unit vectors in R^n (Gaussian, normalised), float64."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((count, n))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
