@@ -1,0 +1,175 @@
+/*
+ * pdhg.h -- C ABI of the space-time primal-dual solver for implicit
+ * discretisations of 1-D periodic conservation laws.
+ *
+ * Method: Liu, Osher, Li, Shu, "A primal-dual approach for solving
+ * conservation laws with implicit in time approximations".  The initial-value
+ * problem u_t + f(u)_x - gamma u_xx = 0, u(x,0) = u0 (Section 2.1) is
+ * discretised implicitly in time (backward Euler or BDF2, Section 3.1) and in
+ * space (finite differences, Section 3.2), and the whole space-time system
+ * A(u) = 0 is solved at once as the saddle point of L(u,phi) = <phi, A(u)>
+ * by the preconditioned primal-dual hybrid gradient iteration of Algorithm 1
+ * (Section 3.3), with the dual proximal step taken in the H-norm induced by
+ * K = -d_tt - c^2 d_xx + ghat^2 d_xxxx (Section 2.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is DEVICE memory on the current HIP device, owned by
+ *   the caller (for example a PyTorch tensor).  The library never frees a
+ *   caller buffer.  Scalars and structs are host memory.
+ * - The element type of every array is the problem's dtype (float or double).
+ * - Layouts, row-major, x fastest:
+ *     u   [nt+1][nx]   levels l = 0..nt; level 0 is the initial data
+ *     phi [nt][nx]     one dual row per implicit equation l = 0..nt-1
+ *     r   [nt][nx]     implicit residual rows A(u)^l
+ *     g   [nt][nx]     J(u)^T phi, row m-1 belongs to unknown level m = 1..nt
+ * - nx must be a power of two, 8 <= nx <= 4096; 1 <= nt <= 2048.
+ * - Calls are asynchronous on the given stream unless stated otherwise.  One
+ *   handle must not be used from two streams at the same time.
+ * - Functions return a pdhg_status; they never throw.  On PDHG_EHIP the HIP
+ *   error text is available from pdhg_last_error(handle).
+ */
+#ifndef PDHG_H_
+#define PDHG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pdhg_stream_t;   /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  PDHG_OK = 0,
+  PDHG_NOT_CONVERGED = 1,   /* max_iter reached; u, phi hold iterate max_iter            */
+  PDHG_DIVERGED = 2,        /* non-finite or exploding residual; u, phi hold the last iterate */
+  PDHG_EINVAL = -1,         /* invalid argument (sizes, enums, null pointers)            */
+  PDHG_EHIP = -2,           /* a HIP runtime call failed                                 */
+  PDHG_EUNSUPPORTED = -3,   /* valid but not implemented combination                     */
+  PDHG_EWORKSPACE = -4      /* workspace too small                                       */
+} pdhg_status;
+
+typedef enum { PDHG_F32 = 0, PDHG_F64 = 1 } pdhg_dtype;
+
+/* Time discretisation (Section 3.1).  BDF2 starts with one backward Euler row,
+ * the start-up step being left open by the paper. */
+typedef enum { PDHG_BE = 0, PDHG_BDF2 = 1 } pdhg_time;
+
+/* Spatial discretisation (Section 3.2, finite differences):
+ *  PDHG_FD_UPWIND: F_j = (f(u_j) - f(u_{j-1}))/h_x, requires f' >= 0 (as the paper's
+ *                  upwind examples assume);
+ *  PDHG_FD_LF:     global Lax-Friedrichs flux with constant lf_speed.
+ * Both add centred diffusion -gamma (u_{j+1} - 2u_j + u_{j-1})/h_x^2 when gamma > 0. */
+typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1 } pdhg_space;
+
+typedef struct {
+  int32_t nx, nt;
+  double length;            /* periodic domain [0, length)                                */
+  double t_final;           /* T; h_t = T / nt                                            */
+  double alpha, beta;       /* flux f(u) = alpha u^2 + beta u (linear transport: alpha = 0) */
+  double gamma;             /* constant viscosity (>= 0)                                  */
+  int32_t time;             /* pdhg_time                                                  */
+  int32_t space;            /* pdhg_space                                                 */
+  int32_t dtype;            /* pdhg_dtype                                                 */
+  int32_t reserved;
+  double lf_speed;          /* Lax-Friedrichs constant; < 0: max |f'(u0)| at solve time    */
+  double precond_c;         /* c of K (Section 2.2); < 0: max |f'(u0)| at solve time       */
+  double precond_gamma_hat; /* ghat of K (>= 0)                                           */
+} pdhg_problem;
+
+typedef struct {
+  double tau_u, tau_phi;    /* step sizes; <= 0: both sqrt(0.95 / nu_max), nu_max the largest
+                               eigenvalue of J(u0)^T K_d^{-1} J(u0) by power iteration
+                               (Proposition 2.1 needs tau_u tau_phi nu < 1)               */
+  double eps;               /* stop when ||A(u)|| <= eps and ||J(u)^T phi|| <= eps (Section 3.3);
+                               eps <= 0 runs exactly max_iter iterations                 */
+  int64_t max_iter;
+  int32_t check_every;      /* iterations per captured graph launch between host polls   */
+  int32_t warm_start;       /* 0: u^l = u0, phi = 0 (Section 3.3);  1: start from u, phi   */
+  double diverge_factor;    /* diverged when max(Rp,Rd) > diverge_factor * best so far;
+                               <= 0: 1e6                                                 */
+  int32_t variant;          /* 0 = auto, 1 = unfused reference kernels, 2 = fused row pass */
+  int32_t reserved;
+  double* history;          /* nullable DEVICE buffer [max_iter+2][2] of doubles: entry n holds
+                               (||A(u^n)||, ||J(u^n)^T phi^n||) for n = 0..n*; entry 0 is
+                               (NaN, ||J(u^0)^T phi^0||); entries past n* may be written */
+} pdhg_params;
+
+typedef struct {
+  int64_t iters;            /* n*, the index of the returned iterate                      */
+  double res_primal;        /* ||A(u^{n*})||   (space-time L2 norm sqrt(h_t h_x sum .^2)) */
+  double res_dual;          /* ||J(u^{n*})^T phi^{n*}||                                    */
+  double tau_u, tau_phi;    /* step sizes used                                            */
+  double nu_max;            /* power-iteration estimate (0 if steps were given)           */
+  double lf_speed, precond_c; /* constants used                                           */
+  double seconds;           /* wall time of the iteration loop                            */
+  int32_t status;
+  int32_t variant;          /* kernel variant that ran                                    */
+} pdhg_stats;
+
+typedef struct pdhg_handle pdhg_handle;
+
+/* Create a plan for one problem: validates it and builds the FFT twiddle
+ * tables on the current device.  The banded Cholesky factors of the
+ * preconditioner are built at the first solve, once c is known. */
+int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out);
+
+/* Bytes of device workspace pdhg_solve/pdhg_adjoint need for this problem. */
+size_t pdhg_workspace_bytes(const pdhg_handle* h);
+
+/* Run Algorithm 1 (u^0 = u0 held fixed, standard PDHG signs; Section 3.3):
+ *   u   <- u - tau_u J(u)^T phibar            (primal step)
+ *   phi <- phi + tau_phi K_d^{-1} A(u)        (dual step; phibar = phi + tau_phi K_d^{-1} A(u))
+ * until both residuals are <= eps or max_iter iterations.  u [nt+1][nx] and
+ * phi [nt][nx] receive the iterate n* (u[0] = u0).  workspace: device buffer
+ * of pdhg_workspace_bytes() bytes, or NULL to let the handle allocate its own
+ * (kept until pdhg_destroy).  stats: host struct, filled on return.
+ * Synchronises the stream (it polls the device-side convergence flag).
+ * Returns PDHG_OK, PDHG_NOT_CONVERGED, PDHG_DIVERGED or an error. */
+int pdhg_solve(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace,
+               const pdhg_params* params, pdhg_stats* stats, pdhg_stream_t stream);
+
+/* Residual of the saddle-point system (Section 2.3): Au = A(u) [nt][nx] and
+ * JTphi = J(u)^T phi [nt][nx] (either may be NULL), and res[2] (host) =
+ * { ||A(u)||, ||J(u)^T phi|| } (res may be NULL; then the call is asynchronous).
+ * u includes level 0.  Uses the constants of the last solve, or the
+ * defaults computed from u[0] when no solve ran yet. */
+int pdhg_residual(pdhg_handle* h, const void* u, const void* phi, void* Au, void* JTphi,
+                  double* res, pdhg_stream_t stream);
+
+/* Preconditioner: s = K_d^{-1} r for r, s of shape [nt][nx] (may alias).
+ * K_d = (B_t B_t^T) (x) I + I (x) (c^2 L_x + ghat^2 L_x^2), solved by FFT in x and
+ * banded Cholesky in t (Sections 2.2, 3.3).  c = precond_c (must be resolved:
+ * either given >= 0 in the problem or set by a previous solve). */
+int pdhg_precond(pdhg_handle* h, const void* r, void* s, pdhg_stream_t stream);
+
+/* Dual-equation operator and the implicit adjoint (Section 3.1).
+ *  mode PDHG_ADJ_APPLY: out[nt][nx] = J(u)^T in, in = phi [nt][nx].
+ *  mode PDHG_ADJ_SOLVE: in = dL/du [nt+1][nx] (all levels, level 0 included);
+ *     solves J(u)^T mu = dL/du[1:] by a backward march in time (one periodic
+ *     tridiagonal solve per level) and writes out[nx] = dL/du0 =
+ *     dL/du^0 - (dA/du0)^T mu.  mu [nt][nx] receives the multiplier if non-NULL.
+ *     u must be the converged implicit solution for this to be the gradient of
+ *     the solution map.  workspace as for pdhg_solve (NULL allowed). */
+typedef enum { PDHG_ADJ_APPLY = 0, PDHG_ADJ_SOLVE = 1 } pdhg_adjoint_mode;
+int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, void* out,
+                 void* mu, void* workspace, pdhg_stream_t stream);
+
+/* Average device time (milliseconds, from HIP events on `stream`) of `reps`
+ * back-to-back launches of one kernel of the solve loop, with the buffers and
+ * step sizes of the last pdhg_solve on this handle (which must have used the
+ * fused variant for kernel 0/1).  kernel: 0 = fused row pass, 1 = column solve.
+ * Used for roofline measurements. */
+int pdhg_time_kernel(pdhg_handle* h, int32_t kernel, int32_t reps, double* ms_per_launch,
+                     pdhg_stream_t stream);
+
+void pdhg_destroy(pdhg_handle* h);
+const char* pdhg_status_string(int status);
+const char* pdhg_last_error(const pdhg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHG_H_ */

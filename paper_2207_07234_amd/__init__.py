@@ -1,0 +1,221 @@
+"""Space-time primal-dual solver for implicit conservation-law schemes on MI355X.
+
+Python face of the HIP library libpdhg.so (include/pdhg.h).  The method is
+Algorithm 1 of Liu, Osher, Li, Shu, "A primal-dual approach for solving
+conservation laws with implicit in time approximations": the whole implicit
+space-time system A(u) = 0 (backward Euler or BDF2 in time, finite
+differences in space, Sections 3.1-3.2) is solved as the saddle point of
+<phi, A(u)> by a preconditioned primal-dual hybrid gradient iteration.
+
+Every numerical step runs in the HIP kernels; this module only passes torch
+device pointers and the current stream across the C ABI.
+
+    import torch, paper_2207_07234_amd as pk
+    prob = pk.Problem(nx=2048, nt=512, t_final=0.5, alpha=0.5, beta=0.0,
+                      time="bdf2", space="fd_lf", dtype=torch.float64)
+    solver = pk.Solver(prob)
+    res = solver.solve(u0, eps=1e-8, max_iter=50000)
+    res.u, res.phi, res.stats
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional
+
+from . import _binding as B
+
+__all__ = ["Problem", "Solver", "SolveResult", "PdhgError", "lib_path"]
+
+lib_path = B.LIB_PATH
+_TIME = {"be": B.PDHG_BE, "bdf2": B.PDHG_BDF2}
+_SPACE = {"fd_upwind": B.PDHG_FD_UPWIND, "fd_lf": B.PDHG_FD_LF}
+
+
+class PdhgError(RuntimeError):
+    pass
+
+
+@dataclass
+class Problem:
+    """u_t + (alpha u^2 + beta u)_x - gamma u_xx = 0 on [0, length) x [0, t_final], periodic."""
+    nx: int
+    nt: int
+    length: float = 1.0
+    t_final: float = 1.0
+    alpha: float = 0.0
+    beta: float = 1.0
+    gamma: float = 0.0
+    time: str = "be"
+    space: str = "fd_upwind"
+    dtype: object = None            # torch.float32 / torch.float64 (default float64)
+    lf_speed: float = -1.0          # < 0: max |f'(u0)|
+    precond_c: float = -1.0         # < 0: max |f'(u0)|
+    precond_gamma_hat: float = 0.0
+
+    def to_c(self) -> B.pdhg_problem:
+        import torch
+        dt = torch.float64 if self.dtype is None else self.dtype
+        p = B.pdhg_problem()
+        p.nx, p.nt = int(self.nx), int(self.nt)
+        p.length, p.t_final = float(self.length), float(self.t_final)
+        p.alpha, p.beta, p.gamma = float(self.alpha), float(self.beta), float(self.gamma)
+        p.time, p.space = _TIME[self.time], _SPACE[self.space]
+        p.dtype = B.PDHG_F64 if dt == torch.float64 else B.PDHG_F32
+        p.lf_speed, p.precond_c = float(self.lf_speed), float(self.precond_c)
+        p.precond_gamma_hat = float(self.precond_gamma_hat)
+        return p
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype is None else self.dtype
+
+
+@dataclass
+class SolveResult:
+    u: object
+    phi: object
+    status: int
+    stats: dict
+    history: Optional[object] = None
+
+
+def _stream_ptr(device) -> C.c_void_p:
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Solver:
+    """One plan (pdhg_setup) for one problem on the current device."""
+
+    def __init__(self, prob: Problem):
+        import torch
+        self.prob = prob
+        self.lib = B.lib()
+        self._h = C.c_void_p()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        rc = self.lib.pdhg_setup(C.byref(prob.to_c()), C.byref(self._h))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_setup failed: {self._status(rc)}")
+
+    # ----------------------------------------------------------------- helpers
+    def _status(self, rc: int) -> str:
+        s = self.lib.pdhg_status_string(rc).decode()
+        if rc == B.PDHG_EHIP and self._h:
+            s += ": " + self.lib.pdhg_last_error(self._h).decode()
+        return f"{s} ({rc})"
+
+    def _check(self, t, shape, name):
+        import torch
+        if t.device.type != "cuda" or t.dtype != self.prob.torch_dtype or not t.is_contiguous():
+            raise PdhgError(f"{name}: need a contiguous {self.prob.torch_dtype} CUDA tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise PdhgError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+        return t
+
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(shape, dtype=self.prob.torch_dtype, device=self.device)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.lib.pdhg_workspace_bytes(self._h))
+
+    # ----------------------------------------------------------------- API
+    def solve(self, u0, tau_u: float = 0.0, tau_phi: float = 0.0, eps: float = 1e-8, max_iter: int = 10000,
+              check_every: int = 64, u=None, phi=None, warm_start: bool = False, workspace=None,
+              history: bool = False, diverge_factor: float = 0.0, variant: int = 0) -> SolveResult:
+        import torch
+        nx, nt = self.prob.nx, self.prob.nt
+        self._check(u0, (nx,), "u0")
+        u = self._empty(nt + 1, nx) if u is None else self._check(u, (nt + 1, nx), "u")
+        phi = self._empty(nt, nx) if phi is None else self._check(phi, (nt, nx), "phi")
+        hist = torch.full((max_iter + 2, 2), float("nan"), dtype=torch.float64, device=self.device) \
+            if history else None
+        p = B.pdhg_params()
+        p.tau_u, p.tau_phi, p.eps = float(tau_u), float(tau_phi), float(eps)
+        p.max_iter, p.check_every, p.warm_start = int(max_iter), int(check_every), int(bool(warm_start))
+        p.diverge_factor, p.variant = float(diverge_factor), int(variant)
+        p.history = hist.data_ptr() if hist is not None else None
+        st = B.pdhg_stats()
+        rc = self.lib.pdhg_solve(self._h, _ptr(u0), _ptr(u), _ptr(phi), _ptr(workspace), C.byref(p),
+                                 C.byref(st), _stream_ptr(self.device))
+        if rc < 0:
+            raise PdhgError(f"pdhg_solve failed: {self._status(rc)}")
+        stats = {k: getattr(st, k) for k, _ in B.pdhg_stats._fields_}
+        if hist is not None:
+            hist = hist[: stats["iters"] + 1]
+        return SolveResult(u, phi, rc, stats, hist)
+
+    def residual(self, u, phi=None, want_fields: bool = True):
+        """(A(u), J(u)^T phi, [||A(u)||, ||J(u)^T phi||])."""
+        nx, nt = self.prob.nx, self.prob.nt
+        self._check(u, (nt + 1, nx), "u")
+        if phi is not None:
+            self._check(phi, (nt, nx), "phi")
+        au = self._empty(nt, nx) if want_fields else None
+        jt = self._empty(nt, nx) if (want_fields and phi is not None) else None
+        res = (C.c_double * 2)()
+        rc = self.lib.pdhg_residual(self._h, _ptr(u), _ptr(phi), _ptr(au), _ptr(jt), res,
+                                    _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_residual failed: {self._status(rc)}")
+        return au, jt, (res[0], res[1])
+
+    def precond(self, r, out=None):
+        """s = K_d^{-1} r."""
+        nx, nt = self.prob.nx, self.prob.nt
+        self._check(r, (nt, nx), "r")
+        s = self._empty(nt, nx) if out is None else self._check(out, (nt, nx), "out")
+        rc = self.lib.pdhg_precond(self._h, _ptr(r), _ptr(s), _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_precond failed: {self._status(rc)}")
+        return s
+
+    def apply_jt(self, u, phi):
+        """J(u)^T phi, rows indexed by unknown level m-1."""
+        nx, nt = self.prob.nx, self.prob.nt
+        self._check(u, (nt + 1, nx), "u")
+        self._check(phi, (nt, nx), "phi")
+        out = self._empty(nt, nx)
+        rc = self.lib.pdhg_adjoint(self._h, B.PDHG_ADJ_APPLY, _ptr(u), _ptr(phi), _ptr(out), None, None,
+                                   _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_adjoint failed: {self._status(rc)}")
+        return out
+
+    def adjoint_solve(self, u, g, want_mu: bool = False):
+        """dL/du0 from dL/du (all levels) through the implicit scheme at its solution u."""
+        nx, nt = self.prob.nx, self.prob.nt
+        self._check(u, (nt + 1, nx), "u")
+        self._check(g, (nt + 1, nx), "g")
+        out = self._empty(nx)
+        mu = self._empty(nt, nx) if want_mu else None
+        rc = self.lib.pdhg_adjoint(self._h, B.PDHG_ADJ_SOLVE, _ptr(u), _ptr(g), _ptr(out), _ptr(mu), None,
+                                   _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_adjoint failed: {self._status(rc)}")
+        return (out, mu) if want_mu else out
+
+    def time_kernel(self, kernel: int, reps: int = 20) -> float:
+        ms = C.c_double()
+        rc = self.lib.pdhg_time_kernel(self._h, int(kernel), int(reps), C.byref(ms), _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_time_kernel failed: {self._status(rc)}")
+        return ms.value
+
+    def close(self):
+        if self._h:
+            self.lib.pdhg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,95 @@
+"""ctypes binding of libpdhg.so (the C ABI declared in include/pdhg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory and the current stream.  Importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdhg.so")
+
+PDHG_OK, PDHG_NOT_CONVERGED, PDHG_DIVERGED = 0, 1, 2
+PDHG_EINVAL, PDHG_EHIP, PDHG_EUNSUPPORTED, PDHG_EWORKSPACE = -1, -2, -3, -4
+PDHG_F32, PDHG_F64 = 0, 1
+PDHG_BE, PDHG_BDF2 = 0, 1
+PDHG_FD_UPWIND, PDHG_FD_LF = 0, 1
+PDHG_ADJ_APPLY, PDHG_ADJ_SOLVE = 0, 1
+
+
+class pdhg_problem(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("nt", C.c_int32),
+        ("length", C.c_double), ("t_final", C.c_double),
+        ("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
+        ("time", C.c_int32), ("space", C.c_int32), ("dtype", C.c_int32), ("reserved", C.c_int32),
+        ("lf_speed", C.c_double), ("precond_c", C.c_double), ("precond_gamma_hat", C.c_double),
+    ]
+
+
+class pdhg_params(C.Structure):
+    _fields_ = [
+        ("tau_u", C.c_double), ("tau_phi", C.c_double), ("eps", C.c_double),
+        ("max_iter", C.c_int64), ("check_every", C.c_int32), ("warm_start", C.c_int32),
+        ("diverge_factor", C.c_double), ("variant", C.c_int32), ("reserved", C.c_int32),
+        ("history", C.c_void_p),
+    ]
+
+
+class pdhg_stats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int64), ("res_primal", C.c_double), ("res_dual", C.c_double),
+        ("tau_u", C.c_double), ("tau_phi", C.c_double), ("nu_max", C.c_double),
+        ("lf_speed", C.c_double), ("precond_c", C.c_double), ("seconds", C.c_double),
+        ("status", C.c_int32), ("variant", C.c_int32),
+    ]
+
+
+EXPORTED = (
+    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_residual", "pdhg_precond",
+    "pdhg_adjoint", "pdhg_time_kernel", "pdhg_destroy", "pdhg_status_string", "pdhg_last_error",
+)
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"HIP library {path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `make -C paper_2207_07234_amd/csrc`")
+    lib = C.CDLL(path)
+    H = C.c_void_p
+    vp = C.c_void_p
+    lib.pdhg_setup.argtypes = [C.POINTER(pdhg_problem), C.POINTER(H)]
+    lib.pdhg_setup.restype = C.c_int
+    lib.pdhg_workspace_bytes.argtypes = [H]
+    lib.pdhg_workspace_bytes.restype = C.c_size_t
+    lib.pdhg_solve.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_params), C.POINTER(pdhg_stats), vp]
+    lib.pdhg_solve.restype = C.c_int
+    lib.pdhg_residual.argtypes = [H, vp, vp, vp, vp, C.POINTER(C.c_double), vp]
+    lib.pdhg_residual.restype = C.c_int
+    lib.pdhg_precond.argtypes = [H, vp, vp, vp]
+    lib.pdhg_precond.restype = C.c_int
+    lib.pdhg_adjoint.argtypes = [H, C.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.pdhg_adjoint.restype = C.c_int
+    lib.pdhg_time_kernel.argtypes = [H, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+    lib.pdhg_time_kernel.restype = C.c_int
+    lib.pdhg_destroy.argtypes = [H]
+    lib.pdhg_destroy.restype = None
+    lib.pdhg_status_string.argtypes = [C.c_int]
+    lib.pdhg_status_string.restype = C.c_char_p
+    lib.pdhg_last_error.argtypes = [H]
+    lib.pdhg_last_error.restype = C.c_char_p
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB

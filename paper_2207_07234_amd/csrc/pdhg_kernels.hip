@@ -1,0 +1,631 @@
+// HIP kernels of the space-time primal-dual solver (gfx950).
+//
+// Unfused reference kernels (one pass per step of Algorithm 1, Section 3.3)
+// and the building blocks of the preconditioner K_d^{-1} (Section 2.2):
+// row FFTs in x and banded Cholesky solves in t per Fourier mode.
+#include "pdhg_internal.hpp"
+
+namespace pdhg {
+
+constexpr int kFftThreads = 256;   // threads per row-FFT block (N <= 16 * 256)
+constexpr int kEwThreads = 256;    // threads per element-wise block
+
+// ------------------------------------------------------------------ row FFTs
+// Forward: real rows [nrows][nx] (row stride nx) -> halfcomplex spectrum rows,
+// two rows per block packed as z = a + i b.
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads)
+k_rows_fwd(const T* __restrict__ rows, int nrows, T* __restrict__ spec, int nt_spec, int lqb, int nx,
+           const C2<T>* __restrict__ tw, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  extern __shared__ char smem[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const int tid = threadIdx.x;
+  const int a = 2 * blockIdx.x, b = a + 1;
+  const bool hasb = b < nrows;
+  const T* ra = rows + (size_t)a * nx;
+  const T* rb = rows + (size_t)b * nx;
+  for (int x = tid; x < nx; x += kFftThreads) buf[x] = {ra[x], hasb ? rb[x] : T(0)};
+  fft_lds<false, kFftThreads>(buf, nx, tw, tid);
+  const int half = nx >> 1;
+  for (int k = tid; k <= half; k += kFftThreads) {
+    const C2<T> zk = buf[k], zm = buf[(nx - k) & (nx - 1)];
+    const T ar = T(0.5) * (zk.x + zm.x), ai = T(0.5) * (zk.y - zm.y);
+    const T br = T(0.5) * (zk.y + zm.y), bi = T(0.5) * (zm.x - zk.x);
+    if (k == 0) {
+      spec[spec_index(a, 0, nt_spec, lqb)] = ar;
+      if (hasb) spec[spec_index(b, 0, nt_spec, lqb)] = br;
+    } else if (k == half) {
+      spec[spec_index(a, 1, nt_spec, lqb)] = ar;
+      if (hasb) spec[spec_index(b, 1, nt_spec, lqb)] = br;
+    } else {
+      spec[spec_index(a, 2 * k, nt_spec, lqb)] = ar;
+      spec[spec_index(a, 2 * k + 1, nt_spec, lqb)] = ai;
+      if (hasb) {
+        spec[spec_index(b, 2 * k, nt_spec, lqb)] = br;
+        spec[spec_index(b, 2 * k + 1, nt_spec, lqb)] = bi;
+      }
+    }
+  }
+}
+
+// Inverse: halfcomplex spectrum rows -> real rows (normalised by 1/nx).
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads)
+k_rows_inv(const T* __restrict__ spec, int nt_spec, int lqb, T* __restrict__ rows, int nrows, int nx,
+           const C2<T>* __restrict__ tw, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  extern __shared__ char smem[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const int tid = threadIdx.x;
+  const int a = 2 * blockIdx.x, b = a + 1;
+  const bool hasb = b < nrows;
+  const int half = nx >> 1;
+  for (int k = tid; k <= half; k += kFftThreads) {
+    T ar, ai = T(0), br = T(0), bi = T(0);
+    if (k == 0 || k == half) {
+      const int q = (k == 0) ? 0 : 1;
+      ar = spec[spec_index(a, q, nt_spec, lqb)];
+      if (hasb) br = spec[spec_index(b, q, nt_spec, lqb)];
+    } else {
+      ar = spec[spec_index(a, 2 * k, nt_spec, lqb)];
+      ai = spec[spec_index(a, 2 * k + 1, nt_spec, lqb)];
+      if (hasb) {
+        br = spec[spec_index(b, 2 * k, nt_spec, lqb)];
+        bi = spec[spec_index(b, 2 * k + 1, nt_spec, lqb)];
+      }
+    }
+    // Z_k = A_k + i B_k ;  Z_{N-k} = conj(A_k) + i conj(B_k)
+    buf[k] = {ar - bi, ai + br};
+    if (k != 0 && k != half) buf[nx - k] = {ar + bi, br - ai};
+  }
+  fft_lds<true, kFftThreads>(buf, nx, tw, tid);
+  const T sc = T(1) / T(nx);
+  T* ra = rows + (size_t)a * nx;
+  T* rb = rows + (size_t)b * nx;
+  for (int x = tid; x < nx; x += kFftThreads) {
+    const C2<T> z = buf[x];
+    ra[x] = z.x * sc;
+    if (hasb) rb[x] = z.y * sc;
+  }
+}
+
+// ------------------------------------------------------------------ column solves
+// Solve (B_t B_t^T + s_k I) y = rhs along t for every halfcomplex column of the
+// spectrum, in place, with the precomputed banded Cholesky factor L (L L^T):
+// forward substitution L z = rhs, then back substitution L^T y = z.  Each
+// column is split into nseg segments handled by different threads: a segment
+// first computes its affine map (particular solution and responses to the two
+// incoming values), the maps are chained sequentially per column, and the
+// segment is re-run from its true incoming state.  Block = QB columns x nseg
+// segments; thread (c, s) = threadIdx.x = s * QB + c.
+template <typename T, int BW, int GMAX>
+__global__ void __launch_bounds__(512)
+k_colsolve(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, int nseg, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  extern __shared__ char smem[];
+  const int QB = 1 << lqb;
+  const int c = threadIdx.x & (QB - 1);
+  const int sg = threadIdx.x >> lqb;
+  T* mapH = reinterpret_cast<T*>(smem);                 // [nseg][QB][4]
+  T* mapP = mapH + (size_t)nseg * QB * 4;               // [nseg][QB][2]
+  T* inst = mapP + (size_t)nseg * QB * 2;               // [nseg][QB][2]
+  const int q = (blockIdx.x << lqb) + c;
+  const int kmode = spec_mode(q, nx);
+  const FacRow<T>* rows = fac.rows + fac.off[kmode];
+  const int last = fac.last[kmode];
+  const int G = (nt + nseg - 1) / nseg;
+  const int l0 = min(nt, sg * G);
+  const int len = min(nt, l0 + G) - l0;
+  T* col = spec + (size_t)blockIdx.x * nt * QB + c;
+  T z[GMAX];
+#pragma unroll
+  for (int i = 0; i < GMAX; ++i) z[i] = (i < len) ? col[(size_t)(l0 + i) * QB] : T(0);
+
+  // ---- forward: z_l = invd_l (rhs_l - e1_l z_{l-1} - e2_l z_{l-2}); state (z_{l-2}, z_{l-1})
+  {
+    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;   // particular, response to z_{-2}, to z_{-1}
+#pragma unroll
+    for (int i = 0; i < GMAX; ++i) {
+      if (i < len) {
+        const FacRow<T> fr = rows[min(l0 + i, last)];
+        const T pz = fr.invd * (z[i] - fr.e1 * p1 - (BW == 2 ? fr.e2 * p2 : T(0)));
+        const T az = fr.invd * (-fr.e1 * a1 - (BW == 2 ? fr.e2 * a2 : T(0)));
+        const T bz = fr.invd * (-fr.e1 * b1 - (BW == 2 ? fr.e2 * b2 : T(0)));
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    T* H = mapH + ((size_t)sg * QB + c) * 4;
+    T* P = mapP + ((size_t)sg * QB + c) * 2;
+    H[0] = a2; H[1] = b2; H[2] = a1; H[3] = b1;
+    P[0] = p2; P[1] = p1;
+    __syncthreads();
+    if (sg == 0) {
+      T s2 = 0, s1 = 0;
+      for (int s = 0; s < nseg; ++s) {
+        T* Hs = mapH + ((size_t)s * QB + c) * 4;
+        T* Ps = mapP + ((size_t)s * QB + c) * 2;
+        inst[((size_t)s * QB + c) * 2 + 0] = s2;
+        inst[((size_t)s * QB + c) * 2 + 1] = s1;
+        const T n2 = Hs[0] * s2 + Hs[1] * s1 + Ps[0];
+        const T n1 = Hs[2] * s2 + Hs[3] * s1 + Ps[1];
+        s2 = n2; s1 = n1;
+      }
+    }
+    __syncthreads();
+    T zm2 = inst[((size_t)sg * QB + c) * 2 + 0], zm1 = inst[((size_t)sg * QB + c) * 2 + 1];
+#pragma unroll
+    for (int i = 0; i < GMAX; ++i) {
+      if (i < len) {
+        const FacRow<T> fr = rows[min(l0 + i, last)];
+        const T zz = fr.invd * (z[i] - fr.e1 * zm1 - (BW == 2 ? fr.e2 * zm2 : T(0)));
+        z[i] = zz;
+        zm2 = zm1; zm1 = zz;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- backward: y_l = invd_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2}); state (y_{l+2}, y_{l+1})
+  {
+    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int ii = 0; ii < GMAX; ++ii) {
+      const int i = GMAX - 1 - ii;
+      if (i < len) {
+        const int l = l0 + i;
+        const FacRow<T> fr = rows[min(l, last)];
+        const T e1 = rows[min(l + 1, last)].e1;
+        const T e2 = (BW == 2) ? rows[min(l + 2, last)].e2 : T(0);
+        const T pz = fr.invd * (z[i] - e1 * p1 - e2 * p2);
+        const T az = fr.invd * (-e1 * a1 - e2 * a2);
+        const T bz = fr.invd * (-e1 * b1 - e2 * b2);
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    T* H = mapH + ((size_t)sg * QB + c) * 4;
+    T* P = mapP + ((size_t)sg * QB + c) * 2;
+    H[0] = a2; H[1] = b2; H[2] = a1; H[3] = b1;
+    P[0] = p2; P[1] = p1;
+    __syncthreads();
+    if (sg == 0) {
+      T s2 = 0, s1 = 0;
+      for (int s = nseg - 1; s >= 0; --s) {
+        T* Hs = mapH + ((size_t)s * QB + c) * 4;
+        T* Ps = mapP + ((size_t)s * QB + c) * 2;
+        inst[((size_t)s * QB + c) * 2 + 0] = s2;
+        inst[((size_t)s * QB + c) * 2 + 1] = s1;
+        const T n2 = Hs[0] * s2 + Hs[1] * s1 + Ps[0];
+        const T n1 = Hs[2] * s2 + Hs[3] * s1 + Ps[1];
+        s2 = n2; s1 = n1;
+      }
+    }
+    __syncthreads();
+    T ym2 = inst[((size_t)sg * QB + c) * 2 + 0], ym1 = inst[((size_t)sg * QB + c) * 2 + 1];
+#pragma unroll
+    for (int ii = 0; ii < GMAX; ++ii) {
+      const int i = GMAX - 1 - ii;
+      if (i < len) {
+        const int l = l0 + i;
+        const FacRow<T> fr = rows[min(l, last)];
+        const T e1 = rows[min(l + 1, last)].e1;
+        const T e2 = (BW == 2) ? rows[min(l + 2, last)].e2 : T(0);
+        const T yy = fr.invd * (z[i] - e1 * ym1 - e2 * ym2);
+        z[i] = yy;
+        ym2 = ym1; ym1 = yy;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < GMAX; ++i)
+    if (i < len) col[(size_t)(l0 + i) * QB] = z[i];
+}
+
+// ------------------------------------------------------------------ stencil kernels
+// A(u): r^l_k for l = 0..nt-1 (u has nt+1 levels).  Optional partial sums of r^2.
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_residual(Scheme s, const T* __restrict__ u, T* __restrict__ r, double* part, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  __shared__ double red[kEwThreads / 64];
+  const Consts<T> C(s);
+  const int nx = s.nx;
+  const size_t idx = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  double acc = 0.0;
+  if (idx < (size_t)s.nt * nx) {
+    const int l = (int)(idx / nx), k = (int)(idx % nx);
+    const int km = (k - 1) & (nx - 1), kp = (k + 1) & (nx - 1);
+    const T* up1 = u + (size_t)(l + 1) * nx;
+    const T* u0 = u + (size_t)l * nx;
+    T t = C.c0(l) * up1[k] + C.c1(l) * u0[k];
+    if (l >= 1 && C.time == kTimeBDF2) t += C.c2(l) * u[(size_t)(l - 1) * nx + k];
+    const T v = t * C.inv_ht + C.F(up1[km], up1[k], up1[kp]);
+    if (r) r[idx] = v;
+    acc = (double)v * (double)v;
+  }
+  if (part) {
+    const double sum = block_sum<kEwThreads>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
+  }
+}
+
+// Value of J(u)^T psi at unknown level m (1..nt), point k.
+template <typename T>
+__device__ __forceinline__ T jt_point(const Consts<T>& C, const T* __restrict__ u, const T* __restrict__ psi,
+                                      int m, int k) {
+  const int nx = C.nx, nt = C.nt;
+  const int km = (k - 1) & (nx - 1), kp = (k + 1) & (nx - 1);
+  const T* pm1 = psi + (size_t)(m - 1) * nx;
+  const T p0 = (m <= nt - 1) ? psi[(size_t)m * nx + k] : T(0);
+  const T pp1 = (m + 1 <= nt - 1) ? psi[(size_t)(m + 1) * nx + k] : T(0);
+  return C.JtTime(m, pm1[k], p0, pp1) + C.JtF(u[(size_t)m * nx + k], pm1[km], pm1[k], pm1[kp]);
+}
+
+// out[m-1][k] = (J(u)^T psi)^m_k.  Optional partial sums of out^2.
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_apply_jt(Scheme s, const T* __restrict__ u, const T* __restrict__ psi, T* __restrict__ out, double* part) {
+  __shared__ double red[kEwThreads / 64];
+  const Consts<T> C(s);
+  const size_t idx = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  double acc = 0.0;
+  if (idx < (size_t)s.nt * s.nx) {
+    const int m = (int)(idx / s.nx) + 1, k = (int)(idx % s.nx);
+    const T v = jt_point(C, u, psi, m, k);
+    if (out) out[idx] = v;
+    acc = (double)v * (double)v;
+  }
+  if (part) {
+    const double sum = block_sum<kEwThreads>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
+  }
+}
+
+// out[l][k] = (J(u) v)^l_k, v indexed by unknown level (row m-1 = level m).
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_apply_j(Scheme s, const T* __restrict__ u, const T* __restrict__ v, T* __restrict__ out) {
+  const Consts<T> C(s);
+  const int nx = s.nx;
+  const size_t idx = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (idx >= (size_t)s.nt * nx) return;
+  const int l = (int)(idx / nx), k = (int)(idx % nx);
+  const int km = (k - 1) & (nx - 1), kp = (k + 1) & (nx - 1);
+  const T* vl = v + (size_t)l * nx;         // level l+1
+  const T* ul = u + (size_t)(l + 1) * nx;
+  T t = C.c0(l) * vl[k];
+  if (l >= 1) t += C.c1(l) * v[(size_t)(l - 1) * nx + k];
+  if (l >= 2 && C.time == kTimeBDF2) t += C.c2(l) * v[(size_t)(l - 2) * nx + k];
+  out[idx] = t * C.inv_ht + C.JF(ul[km], ul[k], ul[kp], vl[km], vl[k], vl[kp]);
+}
+
+// Unfused primal step: u_out^m = u_in^m - tau_u (J(u_in)^T phibar)^m for m = 1..nt,
+// and partial sums of ((J(u_in)^T phi)^m)^2 for the dual residual of u_in.
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_primal(Scheme s, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
+         const T* __restrict__ phi, T tau_u, double* part, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  __shared__ double red[kEwThreads / 64];
+  const Consts<T> C(s);
+  const size_t idx = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  double acc = 0.0;
+  if (idx < (size_t)s.nt * s.nx) {
+    const int m = (int)(idx / s.nx) + 1, k = (int)(idx % s.nx);
+    const T gbar = jt_point(C, u_in, phibar, m, k);
+    const T g = jt_point(C, u_in, phi, m, k);
+    const size_t o = (size_t)m * s.nx + k;
+    u_out[o] = u_in[o] - tau_u * gbar;
+    acc = (double)g * (double)g;
+  }
+  const double sum = block_sum<kEwThreads>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+// Unfused dual step: phi <- phi + tau s ; phibar = phi + tau s.
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_dual(T* __restrict__ phi, T* __restrict__ phibar, const T* __restrict__ srow, size_t n, T tau,
+       const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  const size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (i >= n) return;
+  const T ts = tau * srow[i];
+  const T p = phi[i] + ts;
+  phi[i] = p;
+  phibar[i] = p + ts;
+}
+
+// ------------------------------------------------------------------ small utilities
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, size_t n, T v) {
+  const size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// u^l = u0 for l = 0..nt (copy the initial data into every level).
+template <typename T>
+__global__ void k_broadcast_levels(T* __restrict__ u, const T* __restrict__ u0, int nx, int levels) {
+  const size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (i < (size_t)nx * levels) u[i] = u0[i % nx];
+}
+
+template <typename T>
+__global__ void k_copy(T* __restrict__ dst, const T* __restrict__ src, size_t n) {
+  const size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// Partial sums over a vector: mode 0: sum x^2; 1: sum x*y; 2: max |f'(x)| (as max, not sum).
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_partial_dot(const T* __restrict__ x, const T* __restrict__ y, size_t n, double* part) {
+  __shared__ double red[kEwThreads / 64];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kEwThreads)
+    acc += (double)x[i] * (double)(y ? y[i] : x[i]);
+  const double sum = block_sum<kEwThreads>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_partial_maxabs_dflux(const T* __restrict__ x, size_t n, double a2, double b, double* part) {
+  __shared__ double red[kEwThreads];
+  double m = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kEwThreads)
+    m = fmax(m, fabs(a2 * (double)x[i] + b));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = kEwThreads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Sum `n` partials in a fixed order into out[0] (single block).
+__global__ void __launch_bounds__(kEwThreads) k_reduce_parts(const double* __restrict__ part, int n, double* out) {
+  __shared__ double red[kEwThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kEwThreads) acc += part[i];
+  const double s = block_sum<kEwThreads>(acc, red);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// x <- x * scale (scale read from device: 1/sqrt(*nrm2))
+template <typename T>
+__global__ void k_normalize(T* __restrict__ x, size_t n, const double* nrm2) {
+  const size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (i < n) x[i] = T((double)x[i] / sqrt(nrm2[0]));
+}
+
+// ------------------------------------------------------------------ control
+__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->n_done = 0;
+    c->max_iter = max_iter;
+    c->n_star = 0;
+    c->status = 0;
+    c->pad = 0;
+    c->eps = eps;
+    c->div_factor = div_factor;
+    c->rp_prev = __builtin_nan("");
+    c->best = __builtin_inf();
+    c->rp_star = __builtin_nan("");
+    c->rd_star = __builtin_nan("");
+  }
+}
+
+// End of loop body n = n_done + 1: Rp(n) and Rd(n-1) from the partial sums;
+// decide whether iterate n-1 is converged, diverged or the last one.
+__device__ void finalize_body(Ctrl* c, double srp, double srd, double wscale, double* hist) {
+  const long long n = c->n_done + 1;
+  const double rp = sqrt(wscale * srp), rd = sqrt(wscale * srd);
+  const long long it = n - 1;
+  if (hist) {
+    hist[2 * n] = rp;
+    hist[2 * it + 1] = rd;
+    if (n == 1) hist[0] = __builtin_nan("");
+  }
+  int st = 0;
+  if (it >= 1) {
+    const double m = fmax(c->rp_prev, rd);
+    if (!(m == m) || isinf(m)) st = 2;
+    else if (m <= c->eps) st = 1;
+    else if (m > c->div_factor * c->best) st = 2;
+    if (m < c->best) c->best = m;
+    if (st == 0 && it >= c->max_iter) st = 3;
+  }
+  if (st == 0 && !(rp == rp && rd == rd && !isinf(rp) && !isinf(rd))) st = 2;
+  if (st != 0) {
+    c->status = st;
+    c->n_star = it;
+    c->rp_star = (it >= 1) ? c->rp_prev : __builtin_nan("");
+    c->rd_star = rd;
+  }
+  c->rp_prev = rp;
+  c->n_done = n;
+}
+
+__global__ void __launch_bounds__(kEwThreads)
+k_finalize(Ctrl* c, const double* __restrict__ part_rp, int n_rp, const double* __restrict__ part_rd, int n_rd,
+           double wscale, double* hist) {
+  if (c->status != 0) return;
+  __shared__ double red[kEwThreads / 64];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n_rp; i += kEwThreads) a += part_rp[i];
+  for (int i = threadIdx.x; i < n_rd; i += kEwThreads) b += part_rd[i];
+  const double srp = block_sum<kEwThreads>(a, red);
+  const double srd = block_sum<kEwThreads>(b, red);
+  if (threadIdx.x == 0) finalize_body(c, srp, srd, wscale, hist);
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned grid_for(size_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+template <typename T>
+hipError_t launch_rows_fwd(const T* rows, int nrows, T* spec, int nt_spec, int lqb, int nx, const void* tw,
+                           const Ctrl* ctrl, hipStream_t st) {
+  const size_t lds = sizeof(C2<T>) * nx;
+  hipLaunchKernelGGL(k_rows_fwd<T>, dim3((nrows + 1) / 2), dim3(kFftThreads), lds, st, rows, nrows, spec,
+                     nt_spec, lqb, nx, (const C2<T>*)tw, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rows_inv(const T* spec, int nt_spec, int lqb, T* rows, int nrows, int nx, const void* tw,
+                           const Ctrl* ctrl, hipStream_t st) {
+  const size_t lds = sizeof(C2<T>) * nx;
+  hipLaunchKernelGGL(k_rows_inv<T>, dim3((nrows + 1) / 2), dim3(kFftThreads), lds, st, spec, nt_spec, lqb,
+                     rows, nrows, nx, (const C2<T>*)tw, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T, int BW, int GMAX>
+static hipError_t launch_colsolve_g(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, int nseg,
+                                    const Ctrl* ctrl, hipStream_t st) {
+  const int QB = 1 << lqb;
+  const size_t lds = sizeof(T) * (size_t)nseg * QB * 8;
+  hipLaunchKernelGGL((k_colsolve<T, BW, GMAX>), dim3(nx / QB), dim3(QB * nseg), lds, st, spec, fac, nt, nx,
+                     lqb, nseg, ctrl);
+  return hipGetLastError();
+}
+
+// Segment count: smallest power of two with nt / nseg <= 16, and QB * nseg <= 512.
+template <typename T>
+hipError_t launch_colsolve(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, const Ctrl* ctrl,
+                           hipStream_t st) {
+  const int QB = 1 << lqb;
+  int nseg = 1;
+  while ((nt + nseg - 1) / nseg > 16 && QB * nseg * 2 <= 512) nseg *= 2;
+  const int G = (nt + nseg - 1) / nseg;
+  if (bw == 2) {
+    if (G <= 16) return launch_colsolve_g<T, 2, 16>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
+    if (G <= 32) return launch_colsolve_g<T, 2, 32>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
+    if (G <= 64) return launch_colsolve_g<T, 2, 64>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
+  } else {
+    if (G <= 16) return launch_colsolve_g<T, 1, 16>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
+    if (G <= 32) return launch_colsolve_g<T, 1, 32>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
+    if (G <= 64) return launch_colsolve_g<T, 1, 64>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,
+                           int* nblocks) {
+  const unsigned g = grid_for((size_t)s.nt * s.nx, kEwThreads);
+  if (nblocks) *nblocks = (int)g;
+  hipLaunchKernelGGL(k_residual<T>, dim3(g), dim3(kEwThreads), 0, st, s, u, r, part, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply_jt(const Scheme& s, const T* u, const T* psi, T* out, double* part, hipStream_t st,
+                           int* nblocks) {
+  const unsigned g = grid_for((size_t)s.nt * s.nx, kEwThreads);
+  if (nblocks) *nblocks = (int)g;
+  hipLaunchKernelGGL(k_apply_jt<T>, dim3(g), dim3(kEwThreads), 0, st, s, u, psi, out, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply_j(const Scheme& s, const T* u, const T* v, T* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_apply_j<T>, dim3(grid_for((size_t)s.nt * s.nx, kEwThreads)), dim3(kEwThreads), 0, st, s,
+                     u, v, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_primal(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
+                         double* part, const Ctrl* ctrl, hipStream_t st, int* nblocks) {
+  const unsigned g = grid_for((size_t)s.nt * s.nx, kEwThreads);
+  if (nblocks) *nblocks = (int)g;
+  hipLaunchKernelGGL(k_primal<T>, dim3(g), dim3(kEwThreads), 0, st, s, u_in, u_out, phibar, phi, tau_u, part,
+                     ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dual(T* phi, T* phibar, const T* srow, size_t n, T tau, const Ctrl* ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(k_dual<T>, dim3(grid_for(n, kEwThreads)), dim3(kEwThreads), 0, st, phi, phibar, srow, n,
+                     tau, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t n, T v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, kEwThreads)), dim3(kEwThreads), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_broadcast_levels(T* u, const T* u0, int nx, int levels, hipStream_t st) {
+  hipLaunchKernelGGL(k_broadcast_levels<T>, dim3(grid_for((size_t)nx * levels, kEwThreads)), dim3(kEwThreads), 0,
+                     st, u, u0, nx, levels);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n, kEwThreads)), dim3(kEwThreads), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dot(const T* x, const T* y, size_t n, double* part, double* out, hipStream_t st) {
+  const int g = 256;
+  hipLaunchKernelGGL(k_partial_dot<T>, dim3(g), dim3(kEwThreads), 0, st, x, y, n, part);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(kEwThreads), 0, st, part, g, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_maxabs_dflux(const T* x, size_t n, double a2, double b, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_partial_maxabs_dflux<T>, dim3(64), dim3(kEwThreads), 0, st, x, n, a2, b, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize<T>, dim3(grid_for(n, kEwThreads)), dim3(kEwThreads), 0, st, x, n, nrm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(Ctrl* c, const double* part_rp, int n_rp, const double* part_rd, int n_rd,
+                           double wscale, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kEwThreads), 0, st, c, part_rp, n_rp, part_rd, n_rd, wscale, hist);
+  return hipGetLastError();
+}
+
+#define PDHG_INSTANTIATE(T)                                                                                    \
+  template hipError_t launch_rows_fwd<T>(const T*, int, T*, int, int, int, const void*, const Ctrl*,          \
+                                         hipStream_t);                                                        \
+  template hipError_t launch_rows_inv<T>(const T*, int, int, T*, int, int, const void*, const Ctrl*,          \
+                                         hipStream_t);                                                        \
+  template hipError_t launch_colsolve<T>(T*, const FacTab<T>&, int, int, int, int, const Ctrl*, hipStream_t); \
+  template hipError_t launch_residual<T>(const Scheme&, const T*, T*, double*, const Ctrl*, hipStream_t,      \
+                                         int*);                                                               \
+  template hipError_t launch_apply_jt<T>(const Scheme&, const T*, const T*, T*, double*, hipStream_t, int*);  \
+  template hipError_t launch_apply_j<T>(const Scheme&, const T*, const T*, T*, hipStream_t);                  \
+  template hipError_t launch_primal<T>(const Scheme&, const T*, T*, const T*, const T*, T, double*,           \
+                                       const Ctrl*, hipStream_t, int*);                                       \
+  template hipError_t launch_dual<T>(T*, T*, const T*, size_t, T, const Ctrl*, hipStream_t);                  \
+  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                             \
+  template hipError_t launch_broadcast_levels<T>(T*, const T*, int, int, hipStream_t);                        \
+  template hipError_t launch_copy<T>(T*, const T*, size_t, hipStream_t);                                      \
+  template hipError_t launch_dot<T>(const T*, const T*, size_t, double*, double*, hipStream_t);               \
+  template hipError_t launch_maxabs_dflux<T>(const T*, size_t, double, double, double*, hipStream_t);         \
+  template hipError_t launch_normalize<T>(T*, size_t, const double*, hipStream_t);
+
+PDHG_INSTANTIATE(float)
+PDHG_INSTANTIATE(double)
+
+}  // namespace pdhg

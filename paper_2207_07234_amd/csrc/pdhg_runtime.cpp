@@ -1,0 +1,678 @@
+// Host runtime and C ABI of the space-time primal-dual solver.
+//
+// Responsibilities: validate problems, build the FFT twiddles and the banded
+// Cholesky factors of the preconditioner (Section 2.2 / 3.3), lay out the
+// workspace, estimate step sizes by power iteration (Proposition 2.1 needs
+// tau_u tau_phi nu_max < 1), and drive Algorithm 1: the loop body is captured
+// once into a HIP graph of `check_every` iterations and replayed until the
+// device-side control block reports convergence, divergence or max_iter.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pdhg.h"
+#include "pdhg_internal.hpp"
+
+using namespace pdhg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct WsLayout {
+  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, total;
+  int max_parts;
+};
+
+struct GraphKey {
+  const void* u = nullptr;
+  const void* phi = nullptr;
+  const void* ws = nullptr;
+  const void* hist = nullptr;
+  double tau_u = 0, tau_phi = 0, lf = 0, c = 0;
+  int variant = 0, chunk = 0;
+  bool operator==(const GraphKey& o) const {
+    return u == o.u && phi == o.phi && ws == o.ws && hist == o.hist && tau_u == o.tau_u &&
+           tau_phi == o.tau_phi && lf == o.lf && c == o.c && variant == o.variant && chunk == o.chunk;
+  }
+};
+
+}  // namespace
+
+struct pdhg_handle {
+  pdhg_problem prob{};
+  int device = 0;
+  int lqb = 4;
+  size_t esz = 8;
+  void* d_tw = nullptr;
+  // preconditioner factors
+  void* d_fac_rows = nullptr;
+  int* d_fac_off = nullptr;
+  int* d_fac_last = nullptr;
+  double fac_c = -1.0, fac_g = -1.0;
+  // resolved constants
+  double lf = 0.0, c = 0.0;
+  bool consts_valid = false;
+  // own workspace
+  void* own_ws = nullptr;
+  size_t own_ws_bytes = 0;
+  // host staging
+  Ctrl* h_ctrl = nullptr;       // pinned, 2 slots
+  double* h_scal = nullptr;     // pinned, 64 doubles
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  // graph cache
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  GraphKey gkey;
+  // last solve (for kernel timing)
+  GraphKey last;
+  std::string err;
+};
+
+namespace {
+
+int set_hip_error(pdhg_handle* h, hipError_t e, const char* what) {
+  if (h) {
+    h->err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return PDHG_EHIP;
+}
+
+#define HIP_TRY(expr)                                        \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return set_hip_error(h, e_, #expr); \
+  } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+WsLayout layout_for(const pdhg_problem& p, size_t esz) {
+  WsLayout L{};
+  const size_t nx = (size_t)p.nx, nt = (size_t)p.nt;
+  const size_t field = align_up(nt * nx * esz);
+  const size_t ufield = align_up((nt + 1) * nx * esz);
+  L.max_parts = (int)((nt * nx + 255) / 256) + 256;
+  size_t o = 0;
+  L.u_alt = o; o += ufield;
+  L.phi_alt = o; o += field;
+  L.spec0 = o; o += field;
+  L.spec1 = o; o += field;
+  L.srow = o; o += field;
+  L.phibar = o; o += field;
+  L.part_rp = o; o += align_up(sizeof(double) * L.max_parts);
+  L.part_rd = o; o += align_up(sizeof(double) * L.max_parts);
+  L.scal = o; o += align_up(sizeof(double) * 64);
+  L.ctrl = o; o += align_up(sizeof(Ctrl));
+  L.total = o;
+  return L;
+}
+
+Scheme scheme_of(const pdhg_handle* h) {
+  const pdhg_problem& p = h->prob;
+  Scheme s{};
+  s.nx = p.nx;
+  s.nt = p.nt;
+  s.time = p.time;
+  s.space = p.space;
+  s.ht = p.t_final / p.nt;
+  s.hx = p.length / p.nx;
+  s.alpha = p.alpha;
+  s.beta = p.beta;
+  s.gamma = p.gamma;
+  s.lf = h->lf;
+  return s;
+}
+
+// Banded Cholesky factors of (B_t B_t^T + s_k I), k = 0..nx/2, computed in
+// long double and rounded to T.  B_t is the time difference acting on the
+// unknown levels (row l: c0(l) at column l, c1(l) at l-1, c2(l) at l-2, all
+// over h_t).  Rows of L converge to those of the infinite Toeplitz factor;
+// for each mode only the rows up to the point after which every rounded row
+// equals the last one are stored.
+template <typename T>
+void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
+                       std::vector<int>& off, std::vector<int>& last) {
+  typedef long double LD;
+  const int nt = p.nt, nx = p.nx;
+  const LD ht = (LD)p.t_final / nt, hx = (LD)p.length / nx;
+  const bool bdf2 = p.time == PDHG_BDF2;
+  auto coef = [&](int l, int d) -> LD {   // B_t[l][l-d] * h_t
+    if (d == 0) return (bdf2 && l >= 1) ? 1.5L : 1.0L;
+    if (d == 1) return (l >= 1) ? ((bdf2 && l >= 1) ? -2.0L : -1.0L) : 0.0L;
+    if (d == 2) return (bdf2 && l >= 2) ? 0.5L : 0.0L;
+    return 0.0L;
+  };
+  // K[l][l-d] for d = 0, 1, 2 (times h_t^2)
+  auto kband = [&](int l, int d) -> LD {
+    if (l - d < 0) return 0.0L;
+    LD s = 0.0L;
+    for (int mcol = l - 2; mcol <= l - d; ++mcol) {
+      if (mcol < 0) continue;
+      const int da = l - mcol, db = (l - d) - mcol;
+      if (da > 2 || db < 0 || db > 2) continue;
+      s += coef(l, da) * coef(l - d, db);
+    }
+    return s;
+  };
+  const LD PI = 3.141592653589793238462643383279502884L;
+  const int nmodes = nx / 2 + 1;
+  off.assign(nmodes, 0);
+  last.assign(nmodes, 0);
+  rows.clear();
+  std::vector<LD> d(nt), e1(nt), e2(nt);
+  std::vector<FacRow<T>> tmp(nt);
+  for (int k = 0; k < nmodes; ++k) {
+    const LD sn = sinl(PI * k / nx);
+    const LD mu = 4.0L * sn * sn / (hx * hx);
+    const LD shift = (LD)c * c * mu + (LD)ghat * ghat * mu * mu;
+    for (int l = 0; l < nt; ++l) {
+      const LD k0 = kband(l, 0) / (ht * ht) + shift;
+      const LD k1 = kband(l, 1) / (ht * ht);
+      const LD k2 = kband(l, 2) / (ht * ht);
+      e2[l] = (l >= 2) ? k2 / d[l - 2] : 0.0L;
+      e1[l] = (l >= 1) ? (k1 - ((l >= 2) ? e2[l] * e1[l - 1] : 0.0L)) / d[l - 1] : 0.0L;
+      d[l] = sqrtl(k0 - e1[l] * e1[l] - e2[l] * e2[l]);
+      tmp[l] = FacRow<T>{(T)(1.0L / d[l]), (T)e1[l], (T)e2[l], (T)0};
+    }
+    int lst = nt - 1;
+    while (lst > 0 && memcmp(&tmp[lst - 1], &tmp[nt - 1], sizeof(FacRow<T>)) == 0) --lst;
+    off[k] = (int)rows.size();
+    last[k] = lst;
+    for (int l = 0; l <= lst; ++l) rows.push_back(tmp[l]);
+  }
+}
+
+template <typename T>
+int upload_factors(pdhg_handle* h, double c, double ghat) {
+  std::vector<FacRow<T>> rows;
+  std::vector<int> off, last;
+  build_factor_rows<T>(h->prob, c, ghat, rows, off, last);
+  if (h->d_fac_rows) hipFree(h->d_fac_rows);
+  if (h->d_fac_off) hipFree(h->d_fac_off);
+  if (h->d_fac_last) hipFree(h->d_fac_last);
+  h->d_fac_rows = nullptr;
+  h->d_fac_off = h->d_fac_last = nullptr;
+  HIP_TRY(hipMalloc(&h->d_fac_rows, rows.size() * sizeof(FacRow<T>)));
+  HIP_TRY(hipMalloc((void**)&h->d_fac_off, off.size() * sizeof(int)));
+  HIP_TRY(hipMalloc((void**)&h->d_fac_last, last.size() * sizeof(int)));
+  HIP_TRY(hipMemcpy(h->d_fac_rows, rows.data(), rows.size() * sizeof(FacRow<T>), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_fac_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_fac_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
+  h->fac_c = c;
+  h->fac_g = ghat;
+  return PDHG_OK;
+}
+
+template <typename T>
+int upload_twiddles(pdhg_handle* h) {
+  const int n = h->prob.nx;
+  std::vector<C2<T>> tw(n);
+  const long double PI = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    const long double a = -2.0L * PI * i / n;
+    tw[i] = C2<T>{(T)cosl(a), (T)sinl(a)};
+  }
+  HIP_TRY(hipMalloc(&h->d_tw, n * sizeof(C2<T>)));
+  HIP_TRY(hipMemcpy(h->d_tw, tw.data(), n * sizeof(C2<T>), hipMemcpyHostToDevice));
+  return PDHG_OK;
+}
+
+template <typename T>
+FacTab<T> factab(const pdhg_handle* h) {
+  return FacTab<T>{(const FacRow<T>*)h->d_fac_rows, h->d_fac_off, h->d_fac_last};
+}
+
+int ensure_workspace(pdhg_handle* h, void*& ws) {
+  if (ws) return PDHG_OK;
+  const WsLayout L = layout_for(h->prob, h->esz);
+  if (!h->own_ws || h->own_ws_bytes < L.total) {
+    if (h->own_ws) hipFree(h->own_ws);
+    h->own_ws = nullptr;
+    HIP_TRY(hipMalloc(&h->own_ws, L.total));
+    h->own_ws_bytes = L.total;
+  }
+  ws = h->own_ws;
+  return PDHG_OK;
+}
+
+inline char* wsp(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+// max |f'(u0)| on the device, read back (synchronous).
+template <typename T>
+int max_abs_dflux(pdhg_handle* h, const T* u0, void* ws, hipStream_t st, double* out) {
+  const WsLayout L = layout_for(h->prob, h->esz);
+  double* part = (double*)wsp(ws, L.part_rp);
+  HIP_TRY(launch_maxabs_dflux<T>(u0, (size_t)h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
+  HIP_TRY(hipMemcpyAsync(h->h_scal, part, 64 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double m = 0.0;
+  for (int i = 0; i < 64; ++i) m = std::max(m, h->h_scal[i]);
+  *out = m;
+  return PDHG_OK;
+}
+
+// Resolve lf_speed and c from u0 when they default, and (re)build the factors.
+template <typename T>
+int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  double lf = p.lf_speed, c = p.precond_c;
+  if ((p.space == PDHG_FD_LF && lf < 0.0) || c < 0.0) {
+    double m = 0.0;
+    int rc = max_abs_dflux<T>(h, u0, ws, st, &m);
+    if (rc) return rc;
+    if (lf < 0.0) lf = m;
+    if (c < 0.0) c = m;
+  }
+  if (p.space != PDHG_FD_LF) lf = 0.0;
+  h->lf = lf;
+  h->c = c;
+  h->consts_valid = true;
+  if (!h->d_fac_rows || h->fac_c != c || h->fac_g != p.precond_gamma_hat) {
+    int rc = upload_factors<T>(h, c, p.precond_gamma_hat);
+    if (rc) return rc;
+  }
+  return PDHG_OK;
+}
+
+// s = K_d^{-1} r through the workspace spectrum buffer spec.
+template <typename T>
+int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  HIP_TRY(launch_rows_fwd<T>(r, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st));
+  HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st));
+  HIP_TRY(launch_rows_inv<T>(spec, p.nt, h->lqb, s, p.nt, p.nx, h->d_tw, nullptr, st));
+  return PDHG_OK;
+}
+
+// Largest eigenvalue of J(u)^T K_d^{-1} J(u) at u^l = u0 by power iteration.
+template <typename T>
+int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int iters, double* nu) {
+  const pdhg_problem& p = h->prob;
+  const WsLayout L = layout_for(p, h->esz);
+  const Scheme s = scheme_of(h);
+  const size_t n = (size_t)p.nt * p.nx;
+  T* v = (T*)wsp(ws, L.srow);
+  T* w = (T*)wsp(ws, L.phibar);
+  T* t = (T*)wsp(ws, L.spec1);
+  T* spec = (T*)wsp(ws, L.spec0);
+  double* part = (double*)wsp(ws, L.part_rp);
+  double* scal = (double*)wsp(ws, L.scal);
+  // deterministic start vector (xorshift64)
+  std::vector<T> hv(n);
+  unsigned long long x = 0x9E3779B97F4A7C15ull;
+  for (size_t i = 0; i < n; ++i) {
+    x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+    hv[i] = (T)((double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+  }
+  HIP_TRY(hipMemcpyAsync(v, hv.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_dot<T>(v, nullptr, n, part, scal, st));
+  HIP_TRY(launch_normalize<T>(v, n, scal, st));
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    HIP_TRY(launch_apply_j<T>(s, u, v, w, st));                  // w = J v
+    int rc = precond_apply<T>(h, w, w, spec, st);                 // w = K_d^{-1} w
+    if (rc) return rc;
+    HIP_TRY(launch_apply_jt<T>(s, u, w, t, nullptr, st, nullptr)); // t = J^T w
+    HIP_TRY(launch_dot<T>(t, v, n, part, scal, st));             // scal[0] = <t, v>
+    HIP_TRY(launch_dot<T>(t, nullptr, n, part, scal + 1, st));   // scal[1] = |t|^2
+    HIP_TRY(launch_normalize<T>(t, n, scal + 1, st));
+    std::swap(v, t);
+  }
+  HIP_TRY(hipMemcpyAsync(h->h_scal, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  lam = h->h_scal[0];
+  *nu = lam;
+  return PDHG_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* pdhg_status_string(int status) {
+  switch (status) {
+    case PDHG_OK: return "converged";
+    case PDHG_NOT_CONVERGED: return "max_iter reached";
+    case PDHG_DIVERGED: return "diverged";
+    case PDHG_EINVAL: return "invalid argument";
+    case PDHG_EHIP: return "HIP error";
+    case PDHG_EUNSUPPORTED: return "unsupported";
+    case PDHG_EWORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char* pdhg_last_error(const pdhg_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
+  if (!prob || !out) return PDHG_EINVAL;
+  *out = nullptr;
+  const pdhg_problem& p = *prob;
+  if (!is_pow2(p.nx) || p.nx < 8 || p.nx > 4096 || p.nt < 1) return PDHG_EINVAL;
+  if (!(p.length > 0) || !(p.t_final > 0) || p.gamma < 0 || p.precond_gamma_hat < 0) return PDHG_EINVAL;
+  if (p.time != PDHG_BE && p.time != PDHG_BDF2) return PDHG_EINVAL;
+  if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF) return PDHG_EINVAL;
+  if (p.dtype != PDHG_F32 && p.dtype != PDHG_F64) return PDHG_EINVAL;
+  if (p.nt > 2048) return PDHG_EUNSUPPORTED;   // column solve: <= 32 segments of <= 64 levels
+  pdhg_handle* h = new (std::nothrow) pdhg_handle();
+  if (!h) return PDHG_EINVAL;
+  h->prob = p;
+  h->esz = (p.dtype == PDHG_F64) ? 8 : 4;
+  h->lqb = 0;
+  while ((1 << (h->lqb + 1)) <= std::min(16, p.nx)) ++h->lqb;
+  int rc = PDHG_OK;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) rc = set_hip_error(h, e, "hipGetDevice");
+  if (!rc) rc = (p.dtype == PDHG_F64) ? upload_twiddles<double>(h) : upload_twiddles<float>(h);
+  if (!rc && (e = hipHostMalloc((void**)&h->h_ctrl, 2 * sizeof(Ctrl), hipHostMallocDefault)) != hipSuccess)
+    rc = set_hip_error(h, e, "hipHostMalloc");
+  if (!rc && (e = hipHostMalloc((void**)&h->h_scal, 64 * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+    rc = set_hip_error(h, e, "hipHostMalloc");
+  for (int i = 0; i < 2 && !rc; ++i)
+    if ((e = hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming)) != hipSuccess)
+      rc = set_hip_error(h, e, "hipEventCreate");
+  if (!rc && (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    rc = set_hip_error(h, e, "hipStreamCreate");
+  if (rc) {
+    pdhg_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return PDHG_OK;
+}
+
+size_t pdhg_workspace_bytes(const pdhg_handle* h) { return h ? layout_for(h->prob, h->esz).total : 0; }
+
+void pdhg_destroy(pdhg_handle* h) {
+  if (!h) return;
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  if (h->d_tw) hipFree(h->d_tw);
+  if (h->d_fac_rows) hipFree(h->d_fac_rows);
+  if (h->d_fac_off) hipFree(h->d_fac_off);
+  if (h->d_fac_last) hipFree(h->d_fac_last);
+  if (h->own_ws) hipFree(h->own_ws);
+  if (h->h_ctrl) hipHostFree(h->h_ctrl);
+  if (h->h_scal) hipHostFree(h->h_scal);
+  for (int i = 0; i < 2; ++i)
+    if (h->ev[i]) hipEventDestroy(h->ev[i]);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  delete h;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One unfused loop body (iteration n = ctrl->n_done + 1); `odd` selects the
+// ping-pong direction of u: odd n reads u and writes u_alt.
+template <typename T>
+int enqueue_body_unfused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist,
+                         hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  const WsLayout L = layout_for(p, h->esz);
+  const Scheme s = scheme_of(h);
+  T* u_alt = (T*)wsp(ws, L.u_alt);
+  T* spec = (T*)wsp(ws, L.spec0);
+  T* srow = (T*)wsp(ws, L.srow);
+  T* phibar = (T*)wsp(ws, L.phibar);
+  double* prp = (double*)wsp(ws, L.part_rp);
+  double* prd = (double*)wsp(ws, L.part_rd);
+  Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
+  T* uin = odd ? u : u_alt;
+  T* uout = odd ? u_alt : u;
+  const size_t n = (size_t)p.nt * p.nx;
+  int nb_rd = 0, nb_rp = 0;
+  HIP_TRY(launch_rows_inv<T>(spec, p.nt, h->lqb, srow, p.nt, p.nx, h->d_tw, ctrl, st));
+  HIP_TRY(launch_dual<T>(phi, phibar, srow, n, tau_phi, ctrl, st));
+  HIP_TRY(launch_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
+  HIP_TRY(launch_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
+  HIP_TRY(launch_rows_fwd<T>(srow, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, ctrl, st));
+  HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, ctrl, st));
+  HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
+  return PDHG_OK;
+}
+
+template <typename T>
+int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist) {
+  if (h->gexec && h->gkey == key) return PDHG_OK;
+  if (h->gexec) { hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+  if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = PDHG_OK;
+  for (int b = 0; b < key.chunk && rc == PDHG_OK; ++b)
+    rc = enqueue_body_unfused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc) { if (g) hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return set_hip_error(h, e, "hipStreamEndCapture");
+  h->graph = g;
+  HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  h->gkey = key;
+  return PDHG_OK;
+}
+
+template <typename T>
+int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_params* prm, pdhg_stats* stats,
+               hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  int rc = ensure_workspace(h, ws);
+  if (rc) return rc;
+  const WsLayout L = layout_for(p, h->esz);
+  const size_t nlev = (size_t)(p.nt + 1) * p.nx, n = (size_t)p.nt * p.nx;
+  T* u_alt = (T*)wsp(ws, L.u_alt);
+  T* spec = (T*)wsp(ws, L.spec0);
+  Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
+  // initial guess (Section 3.3): u^l = u0, phi = 0 unless warm start; u^0 = u0 always
+  if (prm->warm_start) {
+    HIP_TRY(launch_copy<T>(u, u0, (size_t)p.nx, st));
+  } else {
+    HIP_TRY(launch_broadcast_levels<T>(u, u0, p.nx, p.nt + 1, st));
+    HIP_TRY(launch_fill<T>(phi, n, T(0), st));
+  }
+  rc = resolve_constants<T>(h, u0, ws, st);
+  if (rc) return rc;
+  double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
+  if (tau_u <= 0.0 || tau_phi <= 0.0) {
+    // power iteration at the constant extension u^l = u0 (u_alt used as scratch)
+    HIP_TRY(launch_broadcast_levels<T>(u_alt, u0, p.nx, p.nt + 1, st));
+    rc = power_iteration<T>(h, u_alt, ws, st, 200, &nu);
+    if (rc) return rc;
+    if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
+    tau_u = tau_phi = std::sqrt(0.95 / nu);
+  }
+  HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
+  HIP_TRY(launch_fill<T>(spec, n, T(0), st));
+  const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
+  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st));
+
+  int chunk = prm->check_every > 0 ? prm->check_every : 64;
+  chunk += chunk & 1;   // even: u ping-pong returns to its start buffer
+  GraphKey key;
+  key.u = u; key.phi = phi; key.ws = ws; key.hist = prm->history;
+  key.tau_u = tau_u; key.tau_phi = tau_phi; key.lf = h->lf; key.c = h->c;
+  key.variant = 1; key.chunk = chunk;
+  h->last = key;
+  const long long bodies = prm->max_iter + 1;
+  auto t0 = std::chrono::steady_clock::now();
+  if (prm->max_iter > 0) {
+    rc = build_graph<T>(h, key, u, phi, ws, (T)tau_u, (T)tau_phi, prm->history);
+    if (rc) return rc;
+    long long launched = 0;
+    int idx = 0;
+    bool stop = false;
+    while (!stop && launched < bodies) {
+      HIP_TRY(hipGraphLaunch(h->gexec, st));
+      launched += chunk;
+      HIP_TRY(hipMemcpyAsync(&h->h_ctrl[idx & 1], ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipEventRecord(h->ev[idx & 1], st));
+      if (idx >= 1) {
+        HIP_TRY(hipEventSynchronize(h->ev[(idx - 1) & 1]));
+        if (h->h_ctrl[(idx - 1) & 1].status != 0) stop = true;
+      }
+      ++idx;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(&h->h_ctrl[0], ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  const Ctrl c = h->h_ctrl[0];
+  long long nstar = c.n_star;
+  int status;
+  if (prm->max_iter <= 0) { nstar = 0; status = PDHG_NOT_CONVERGED; }
+  else if (c.status == 1) status = PDHG_OK;
+  else if (c.status == 2) status = PDHG_DIVERGED;
+  else status = PDHG_NOT_CONVERGED;
+  if (nstar & 1) HIP_TRY(launch_copy<T>(u, u_alt, nlev, st));
+  if (stats) {
+    stats->iters = nstar;
+    stats->res_primal = c.rp_star;
+    stats->res_dual = c.rd_star;
+    stats->tau_u = tau_u;
+    stats->tau_phi = tau_phi;
+    stats->nu_max = nu;
+    stats->lf_speed = h->lf;
+    stats->precond_c = h->c;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->status = status;
+    stats->variant = 1;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_solve(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace, const pdhg_params* params,
+               pdhg_stats* stats, pdhg_stream_t stream) {
+  if (!h || !u0 || !u || !phi || !params) return PDHG_EINVAL;
+  if (params->max_iter < 0) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64)
+    return solve_impl<double>(h, (const double*)u0, (double*)u, (double*)phi, workspace, params, stats, st);
+  return solve_impl<float>(h, (const float*)u0, (float*)u, (float*)phi, workspace, params, stats, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int residual_impl(pdhg_handle* h, const T* u, const T* phi, T* Au, T* JTphi, double* res, hipStream_t st) {
+  void* ws = nullptr;
+  int rc = ensure_workspace(h, ws);
+  if (rc) return rc;
+  if (!h->consts_valid) {
+    rc = resolve_constants<T>(h, u, ws, st);   // u[0] is u0
+    if (rc) return rc;
+  }
+  const WsLayout L = layout_for(h->prob, h->esz);
+  const Scheme s = scheme_of(h);
+  double* prp = (double*)wsp(ws, L.part_rp);
+  double* prd = (double*)wsp(ws, L.part_rd);
+  int nb1 = 0, nb2 = 0;
+  HIP_TRY(launch_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
+  if (phi) HIP_TRY(launch_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  if (res) {
+    // reduce the partials on the host (few thousand doubles)
+    std::vector<double> a(nb1), b(nb2);
+    HIP_TRY(hipMemcpyAsync(a.data(), prp, nb1 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (nb2) HIP_TRY(hipMemcpyAsync(b.data(), prd, nb2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double sa = 0, sb = 0;
+    for (double x : a) sa += x;
+    for (double x : b) sb += x;
+    res[0] = std::sqrt(s.ht * s.hx * sa);
+    res[1] = phi ? std::sqrt(s.ht * s.hx * sb) : 0.0;
+  }
+  return PDHG_OK;
+}
+
+template <typename T>
+int precond_impl(pdhg_handle* h, const T* r, T* s, hipStream_t st) {
+  void* ws = nullptr;
+  int rc = ensure_workspace(h, ws);
+  if (rc) return rc;
+  if (!h->d_fac_rows) {
+    if (h->prob.precond_c < 0.0) return PDHG_EINVAL;
+    rc = upload_factors<T>(h, h->prob.precond_c, h->prob.precond_gamma_hat);
+    if (rc) return rc;
+  }
+  const WsLayout L = layout_for(h->prob, h->esz);
+  return precond_apply<T>(h, r, s, (T*)wsp(ws, L.spec0), st);
+}
+
+template <typename T>
+int adjoint_impl(pdhg_handle* h, int mode, const T* u, const T* in, T* out, T* mu, void* ws, hipStream_t st) {
+  int rc = ensure_workspace(h, ws);
+  if (rc) return rc;
+  if (!h->consts_valid) {
+    rc = resolve_constants<T>(h, u, ws, st);
+    if (rc) return rc;
+  }
+  const Scheme s = scheme_of(h);
+  if (mode == PDHG_ADJ_APPLY) {
+    HIP_TRY(launch_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
+    return PDHG_OK;
+  }
+  if (mode != PDHG_ADJ_SOLVE) return PDHG_EINVAL;
+  HIP_TRY(launch_adjoint_march<T>(s, u, in, mu, out, st));
+  return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_residual(pdhg_handle* h, const void* u, const void* phi, void* Au, void* JTphi, double* res,
+                  pdhg_stream_t stream) {
+  if (!h || !u) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64)
+    return residual_impl<double>(h, (const double*)u, (const double*)phi, (double*)Au, (double*)JTphi, res, st);
+  return residual_impl<float>(h, (const float*)u, (const float*)phi, (float*)Au, (float*)JTphi, res, st);
+}
+
+int pdhg_precond(pdhg_handle* h, const void* r, void* s, pdhg_stream_t stream) {
+  if (!h || !r || !s) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64) return precond_impl<double>(h, (const double*)r, (double*)s, st);
+  return precond_impl<float>(h, (const float*)r, (float*)s, st);
+}
+
+int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, void* out, void* mu, void* workspace,
+                 pdhg_stream_t stream) {
+  if (!h || !u || !in || !out) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64)
+    return adjoint_impl<double>(h, mode, (const double*)u, (const double*)in, (double*)out, (double*)mu, workspace,
+                                st);
+  return adjoint_impl<float>(h, mode, (const float*)u, (const float*)in, (float*)out, (float*)mu, workspace, st);
+}
+
+int pdhg_time_kernel(pdhg_handle* h, int32_t kernel, int32_t reps, double* ms_per_launch, pdhg_stream_t stream) {
+  (void)h; (void)kernel; (void)reps; (void)ms_per_launch; (void)stream;
+  return PDHG_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol declared in include/pdhg.h, and rejects invalid problems before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "pdhg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdhg_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2207_07234_amd import _binding
+    if not os.path.exists(_binding.LIB_PATH):
+        pytest.fail("libpdhg.so not built (run __graft_entry__.build())")
+    return _binding, _binding.load()
+
+
+def test_header_declares_the_core_entry_points():
+    syms = _declared_symbols()
+    for name in ("pdhg_setup", "pdhg_solve", "pdhg_residual", "pdhg_adjoint", "pdhg_destroy"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    _, lib = _lib()
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_binding_struct_sizes_match_header_layout():
+    B, _ = _lib()
+    # field order/size mirrors include/pdhg.h; natural alignment on x86-64
+    assert C.sizeof(B.pdhg_problem) == 4 * 2 + 8 * 5 + 4 * 4 + 8 * 3
+    assert C.sizeof(B.pdhg_params) == 8 * 3 + 8 + 4 * 2 + 8 + 4 * 2 + 8
+    assert C.sizeof(B.pdhg_stats) == 8 * 9 + 4 * 2
+
+
+@pytest.mark.parametrize("bad", [dict(nx=100), dict(nx=4), dict(nx=8192), dict(nt=0), dict(time=7),
+                                 dict(space=9), dict(dtype=5), dict(t_final=0.0), dict(gamma=-1.0)])
+def test_setup_rejects_invalid_problems(bad):
+    B, lib = _lib()
+    p = B.pdhg_problem()
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 64, 16, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype = B.PDHG_BDF2, B.PDHG_FD_LF, B.PDHG_F64
+    for k, v in bad.items():
+        setattr(p, k, v)
+    h = C.c_void_p()
+    assert lib.pdhg_setup(C.byref(p), C.byref(h)) == B.PDHG_EINVAL
+    assert not h.value
+
+
+def test_status_strings():
+    B, lib = _lib()
+    assert lib.pdhg_status_string(B.PDHG_OK) == b"converged"
+    assert lib.pdhg_status_string(B.PDHG_DIVERGED) == b"diverged"
+    assert lib.pdhg_status_string(12345) == b"unknown status"
