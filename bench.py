@@ -1,0 +1,182 @@
+"""Benchmark: space-time PDHG on the inviscid Burgers workload, one MI355X.
+
+Workload (one "step" = one full solve of Algorithm 1 from the initial guess
+u^l = u0, phi = 0 to residual 1e-8): u_t + (u^2/2)_x = 0 on [0,1) periodic,
+N_x = 2048, N_t = 512, T = 0.5 (h_t = 2 h_x), BDF2 in time with a backward
+Euler first row, global Lax-Friedrichs flux, seeded Fourier-sum u0 (seed 0),
+FP64, step sizes sqrt(0.95/nu_max) from the library's power iteration.
+
+Printed (one JSON line on stdout): DOF-iterations/s of the timed solves,
+time to residual 1e-8, the dominant kernel's achieved bandwidth from HIP
+event timing against the 8 TB/s HBM peak, and the FP64 CPU oracle timed on a
+bounded sample of iterations of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDHG space-time DOF-iterations/s; time to residual 1e-8; achieved HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+NX, NT, T_FINAL, EPS, SEED = 2048, 512, 0.5, 1e-8, 0
+
+# Algorithmic words moved per DOF by each kernel of one iteration (library kernel ids
+# of pdhg_time_kernel).  Fused variant: A reads shat and phi, writes phi and phibar;
+# B reads phibar, phi and u, writes u and rhat; C reads rhat and writes shat.
+KERNELS_FUSED = {
+    7: ("A: inverse FFT + dual step", 4),
+    0: ("B: primal step + residual + forward FFT", 5),
+    1: ("C: column solve (banded Cholesky in t)", 2),
+}
+KERNELS_UNFUSED = {
+    1: ("column solve (banded Cholesky in t)", 2),
+    2: ("inverse row FFT", 2),
+    3: ("dual update", 4),
+    4: ("primal update", 4),
+    5: ("implicit residual", 2),
+    6: ("forward row FFT", 2),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sample_iters: int):
+    """FP64 oracle Algorithm 1 on the same workload, timed over `sample_iters` iterations."""
+    import numpy as np
+
+    import synthetic as syn
+    from oracle import pdhg as opdhg
+    from oracle.problem import Problem as OProblem, default_constants
+    u0 = syn.fourier_u0(SEED, NX)
+    oprob = default_constants(OProblem(nx=NX, nt=NT, t_final=T_FINAL, alpha=0.5, beta=0.0, space="fd_lf",
+                                       time="bdf2"), u0)
+    c0, t0 = time.process_time(), time.perf_counter()
+    opdhg.run(oprob, u0, 0.6, 0.6, eps=0.0, max_iter=sample_iters)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {
+        "value": NX * NT * sample_iters / wall,
+        "unit": "DOF-iterations/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1) on the same "
+                  f"{NX}x{NT} BDF2 LF Burgers problem; {wall:.1f} s wall, host has {os.cpu_count()} CPUs",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="run exactly this many iterations per solve instead of solving to 1e-8 (profiling)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto (fused), 1 unfused, 2 fused")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is design-only",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2207_07234_amd as pk
+    import synthetic as syn
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    esz = 8 if dtype == torch.float64 else 4
+    prob = pk.Problem(nx=NX, nt=NT, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf",
+                      dtype=dtype)
+    solver = pk.Solver(prob)
+    u0 = torch.tensor(syn.fourier_u0(SEED, NX), dtype=dtype, device=dev)
+    u = torch.empty((NT + 1, NX), dtype=dtype, device=dev)
+    phi = torch.empty((NT, NX), dtype=dtype, device=dev)
+    ws = torch.empty(solver.workspace_bytes, dtype=torch.uint8, device=dev)
+    eps = EPS if dtype == torch.float64 else 0.0
+    max_iter = 200000 if dtype == torch.float64 else 5000
+    if args.fixed_iters > 0:
+        eps, max_iter = 0.0, args.fixed_iters
+
+    # warm-up: the first solve runs the power iteration; later solves reuse its step sizes
+    kw = dict(u=u, phi=phi, workspace=ws, check_every=128, variant=args.variant)
+    first = solver.solve(u0, eps=eps, max_iter=max_iter, **kw)
+    tau = first.stats["tau_u"]
+    log(f"warm-up solve: status {first.status} iters {first.stats['iters']} nu_max {first.stats['nu_max']:.6f} "
+        f"tau {tau:.6f} Rp {first.stats['res_primal']:.3e} Rd {first.stats['res_dual']:.3e}")
+    for _ in range(max(0, args.warmup - 1)):
+        solver.solve(u0, tau_u=tau, tau_phi=tau, eps=eps, max_iter=max_iter, **kw)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    stats = None
+    for k in range(args.steps):
+        r = solver.solve(u0, tau_u=tau, tau_phi=tau, eps=eps, max_iter=max_iter, **kw)
+        iters.append(r.stats["iters"])
+        stats = r.stats
+        log(f"step {k}: status {r.status} iters {r.stats['iters']} loop {r.stats['seconds']*1e3:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    dof = NX * NT
+    value = dof * sum(iters) / wall
+
+    # per-kernel device time (HIP events on the solve's stream), buffers of the last solve
+    kern = {}
+    table = KERNELS_FUSED if stats["variant"] == 2 else KERNELS_UNFUSED
+    for kid, (name, words) in table.items():
+        ms = solver.time_kernel(kid, reps=50)
+        kern[kid] = (name, words, ms, words * esz * dof / (ms * 1e-3) / 1e9)
+        log(f"kernel {kid} {name}: {ms*1e3:.1f} us/launch, {kern[kid][3]:.0f} GB/s algorithmic")
+    dom = max(kern, key=lambda k: kern[k][2])
+    name, words, ms, gbs = kern[dom]
+    iter_us = sum(v[2] for v in kern.values()) * 1e3
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "kernel": name,
+            "bytes_per_launch": words * esz * dof, "ms_per_launch": ms}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"inviscid Burgers, FD Lax-Friedrichs, BDF2, {NX}x{NT}, T={T_FINAL}, seeded Fourier u0",
+            "nx": NX, "nt": NT, "eps": eps, "seed": SEED, "iterations_per_solve": iters[-1],
+            "time_to_residual_s": ms_per_step / 1e3 if eps > 0 else None,
+            "res_primal": stats["res_primal"], "res_dual": stats["res_dual"], "tau": tau,
+            "kernel_sum_us_per_iteration": iter_us, "variant": stats["variant"],
+            "us_per_iteration_wall": wall / sum(iters) * 1e6,
+            "effective_GBs_all_kernels": sum(w for _, w, _, _ in kern.values()) * esz * dof * sum(iters) / wall / 1e9,
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

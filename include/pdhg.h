@@ -90,7 +90,8 @@ typedef struct {
   int32_t warm_start;       /* 0: u^l = u0, phi = 0 (Section 3.3);  1: start from u, phi   */
   double diverge_factor;    /* diverged when max(Rp,Rd) > diverge_factor * best so far;
                                <= 0: 1e6                                                 */
-  int32_t variant;          /* 0 = auto, 1 = unfused reference kernels, 2 = fused row pass */
+  int32_t variant;          /* 0 = auto (2), 1 = unfused reference kernels (7 per iteration),
+                               2 = fused passes (3 kernels per iteration)                 */
   int32_t reserved;
   double* history;          /* nullable DEVICE buffer [max_iter+2][2] of doubles: entry n holds
                                (||A(u^n)||, ||J(u^n)^T phi^n||) for n = 0..n*; entry 0 is
@@ -159,9 +160,11 @@ int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, vo
 
 /* Average device time (milliseconds, from HIP events on `stream`) of `reps`
  * back-to-back launches of one kernel of the solve loop, with the buffers and
- * step sizes of the last pdhg_solve on this handle (which must have used the
- * fused variant for kernel 0/1).  kernel: 0 = fused row pass, 1 = column solve.
- * Used for roofline measurements. */
+ * step sizes of the last pdhg_solve on this handle (the buffers' contents are
+ * overwritten).  kernel: 0 = fused primal/residual/FFT pass, 1 = column solve,
+ * 2 = inverse row FFT, 3 = dual update, 4 = primal update, 5 = residual,
+ * 6 = forward row FFT, 7 = fused inverse-FFT/dual pass.
+ * Used for roofline measurements.  Returns PDHG_EINVAL without a previous solve. */
 int pdhg_time_kernel(pdhg_handle* h, int32_t kernel, int32_t reps, double* ms_per_launch,
                      pdhg_stream_t stream);
 

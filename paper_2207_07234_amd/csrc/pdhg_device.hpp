@@ -171,15 +171,28 @@ __device__ __forceinline__ void dft8(C2<T>* v) {
   }
 }
 
+// LDS layout of an N-point complex FFT buffer: one padding slot after every 8
+// points, so that the strided Stockham writes (stride 8 points = 128 B for
+// double complex) land in distinct banks.  lds_fft_points(N) slots are needed.
+__device__ __forceinline__ int lpad(int x) { return x + (x >> 3); }
+__host__ __device__ constexpr int lds_fft_points(int n) { return n + n / 8 + 1; }
+
+// Copy the twiddle table w_N^i, i = 0..N-1, from global memory into LDS (padded).
+template <typename T>
+__device__ __forceinline__ void load_twiddles_lds(C2<T>* twl, const C2<T>* __restrict__ tw, int N, int tid,
+                                                  int W) {
+  for (int i = tid; i < N; i += W) twl[lpad(i)] = tw[i];
+}
+
 // One Stockham radix-R stage on an LDS array of N points, in place: every
 // thread loads all inputs of its butterflies, the block synchronises, then
 // the outputs are stored.  Butterfly j (0 <= j < N/R) reads x[j + r N/R],
 // twiddles input r by w_N^{r k N/(Ns R)} with k = j mod Ns, and writes
-// output q to x[(j - k) R + k + q Ns].
-template <bool INV, int R, int W, typename T>
-__device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const C2<T>* __restrict__ tw,
-                                               int tid) {
-  constexpr int MAXB = 16 / R;  // butterflies per thread (N <= 16 W)
+// output q to x[(j - k) R + k + q Ns].  EPT bounds N / W (points per thread).
+template <bool INV, int R, int EPT, typename T>
+__device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const C2<T>* __restrict__ twl,
+                                               int tid, int W) {
+  constexpr int MAXB = (EPT + R - 1) / R;  // butterflies per thread
   const int nbf = N / R;
   C2<T> v[MAXB * R];
 #pragma unroll
@@ -187,7 +200,7 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
     const int j = tid + b * W;
     if (j < nbf) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b * R + r] = buf[j + r * nbf];
+      for (int r = 0; r < R; ++r) v[b * R + r] = buf[lpad(j + r * nbf)];
     }
   }
   __syncthreads();
@@ -200,39 +213,91 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
       C2<T>* vb = v + b * R;
       if (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) vb[r] = cmul_tw<INV>(vb[r], tw[r * k * tstride]);
+        for (int r = 1; r < R; ++r) vb[r] = cmul_tw<INV>(vb[r], twl[lpad(r * k * tstride)]);
       }
       if (R == 8) dft8<INV>(vb);
       else if (R == 4) dft4<INV>(vb);
       else dft2<INV>(vb);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[base + q * Ns] = vb[q];
+      for (int q = 0; q < R; ++q) buf[lpad(base + q * Ns)] = vb[q];
     }
   }
   __syncthreads();
 }
 
-// Unnormalised DFT of the N points in buf (natural order in and out):
-// X_k = sum_x z_x e^{-2 pi i x k / N} (forward) or e^{+...} (inverse).
-// tw[i] = e^{-2 pi i i / N}.  Requires N = 2^m, 2 <= N <= 16 W, and all W
-// threads of the block to call it.
-template <bool INV, int W, typename T>
-__device__ void fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ tw, int tid) {
+// Unnormalised DFT of the N points in buf (natural order in and out, padded
+// layout): X_k = sum_x z_x e^{-2 pi i x k / N} (forward) or e^{+...} (inverse).
+// twl: LDS twiddle table from load_twiddles_lds.  Requires N = 2^m, 2 <= N <=
+// EPT W, and all W threads of the block (tid = 0..W-1) to call it.
+template <bool INV, int EPT, typename T>
+__device__ void fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int tid, int W) {
   __syncthreads();
   int Ns = 1;
   while (Ns < N) {
     const int rem = N / Ns;
     if (rem >= 8) {
-      stockham_stage<INV, 8, W>(buf, N, Ns, tw, tid);
+      stockham_stage<INV, 8, EPT>(buf, N, Ns, twl, tid, W);
       Ns *= 8;
     } else if (rem == 4) {
-      stockham_stage<INV, 4, W>(buf, N, Ns, tw, tid);
+      stockham_stage<INV, 4, EPT>(buf, N, Ns, twl, tid, W);
       Ns *= 4;
     } else {
-      stockham_stage<INV, 2, W>(buf, N, Ns, tw, tid);
+      stockham_stage<INV, 2, EPT>(buf, N, Ns, twl, tid, W);
       Ns *= 2;
     }
+  }
+}
+
+// ------------------------------------------------------------------ cross-lane moves
+// DPP wavefront shifts (all 64 lanes active): from_lane_below(v, fill) gives
+// lane l the value of lane l-1 and lane 0 `fill`; from_lane_above gives lane l
+// the value of lane l+1 and lane 63 `fill`.
+__device__ __forceinline__ int dpp_below_i(int v, int fill) { return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_above_i(int v, int fill) { return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false); }
+
+__device__ __forceinline__ float from_lane_below(float v, float fill) {
+  return __int_as_float(dpp_below_i(__float_as_int(v), __float_as_int(fill)));
+}
+__device__ __forceinline__ float from_lane_above(float v, float fill) {
+  return __int_as_float(dpp_above_i(__float_as_int(v), __float_as_int(fill)));
+}
+__device__ __forceinline__ double from_lane_below(double v, double fill) {
+  const long long a = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = dpp_below_i((int)(a & 0xffffffffll), (int)(f & 0xffffffffll));
+  const int hi = dpp_below_i((int)(a >> 32), (int)(f >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_lane_above(double v, double fill) {
+  const long long a = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = dpp_above_i((int)(a & 0xffffffffll), (int)(f & 0xffffffffll));
+  const int hi = dpp_above_i((int)(a >> 32), (int)(f >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Value of v in lane `src` (uniform result).
+__device__ __forceinline__ float read_lane(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const long long a = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(a & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(a >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Periodic x-neighbours of a row held by a wavefront in "lane-cyclic" order:
+// element e of lane l is x = seg0 + l + 64 e, e = 0..E-1, so x-1 and x+1 are
+// the neighbouring lanes, with wrap-around between consecutive e.  prev_last
+// and next_first are the row values just before and after the wave's segment.
+template <typename T, int E>
+__device__ __forceinline__ void wave_row_neighbours(const T* v, T prev_last, T next_first, T* vm, T* vp) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const T lo = (e == 0) ? prev_last : read_lane(v[e - 1], 63);
+    const T hi = (e == E - 1) ? next_first : read_lane(v[e + 1], 0);
+    vm[e] = from_lane_below(v[e], lo);
+    vp[e] = from_lane_above(v[e], hi);
   }
 }
 
@@ -259,11 +324,78 @@ __device__ __forceinline__ double block_sum(double v, double* red /* >= W/64 dou
   return s;
 }
 
+// Sum over a block of any power-of-two size (blockDim.x <= 1024) by a tree in
+// LDS; result valid in thread 0.  Fixed order.
+__device__ __forceinline__ double block_sum_tree(double v, double* red /* >= blockDim.x doubles */) {
+  const int tid = threadIdx.x, n = blockDim.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int s = n >> 1; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
 // Spectrum layout: halfcomplex column q of row l, stored in column blocks of
 // QB = 2^lqb columns: element (l, q) at ((q >> lqb) * nt + l) * QB + (q & (QB-1)).
 // Column 0 holds Re X_0, column 1 Re X_{N/2}, columns 2k and 2k+1 Re and Im X_k.
 __device__ __forceinline__ size_t spec_index(int l, int q, int nt, int lqb) {
   return ((size_t)(q >> lqb) * nt + l) * ((size_t)1 << lqb) + (q & ((1 << lqb) - 1));
+}
+
+// Halfcomplex spectra of two real rows a, b from Z = DFT(a + i b) in buf:
+// A_k = (Z_k + conj Z_{N-k})/2, B_k = (Z_k - conj Z_{N-k})/(2i), k = 0..N/2.
+// Row b is skipped when !hasb.
+template <typename T>
+__device__ __forceinline__ void store_halfcomplex_pair(const C2<T>* buf, int nx, T* __restrict__ spec, int nt,
+                                                       int lqb, int a, bool hasb, int tid, int W) {
+  const int half = nx >> 1;
+  const int b = a + 1;
+  for (int k = tid; k <= half; k += W) {
+    const C2<T> zk = buf[lpad(k)], zm = buf[lpad((nx - k) & (nx - 1))];
+    const T ar = T(0.5) * (zk.x + zm.x), ai = T(0.5) * (zk.y - zm.y);
+    const T br = T(0.5) * (zk.y + zm.y), bi = T(0.5) * (zm.x - zk.x);
+    if (k == 0 || k == half) {
+      const int q = (k == 0) ? 0 : 1;
+      spec[spec_index(a, q, nt, lqb)] = ar;
+      if (hasb) spec[spec_index(b, q, nt, lqb)] = br;
+    } else {
+      spec[spec_index(a, 2 * k, nt, lqb)] = ar;
+      spec[spec_index(a, 2 * k + 1, nt, lqb)] = ai;
+      if (hasb) {
+        spec[spec_index(b, 2 * k, nt, lqb)] = br;
+        spec[spec_index(b, 2 * k + 1, nt, lqb)] = bi;
+      }
+    }
+  }
+}
+
+// Z_k = A_k + i B_k for k = 0..N-1 in buf from the halfcomplex spectra of rows
+// a and b (B = 0 when !hasb), using A_{N-k} = conj A_k.
+template <typename T>
+__device__ __forceinline__ void load_halfcomplex_pair(C2<T>* buf, int nx, const T* __restrict__ spec, int nt,
+                                                      int lqb, int a, bool hasb, int tid, int W) {
+  const int half = nx >> 1;
+  const int b = a + 1;
+  for (int k = tid; k <= half; k += W) {
+    T ar, ai = T(0), br = T(0), bi = T(0);
+    if (k == 0 || k == half) {
+      const int q = (k == 0) ? 0 : 1;
+      ar = spec[spec_index(a, q, nt, lqb)];
+      if (hasb) br = spec[spec_index(b, q, nt, lqb)];
+    } else {
+      ar = spec[spec_index(a, 2 * k, nt, lqb)];
+      ai = spec[spec_index(a, 2 * k + 1, nt, lqb)];
+      if (hasb) {
+        br = spec[spec_index(b, 2 * k, nt, lqb)];
+        bi = spec[spec_index(b, 2 * k + 1, nt, lqb)];
+      }
+    }
+    buf[lpad(k)] = {ar - bi, ai + br};
+    if (k != 0 && k != half) buf[lpad(nx - k)] = {ar + bi, br - ai};
+  }
 }
 
 // Fourier mode of halfcomplex column q.
@@ -296,5 +428,36 @@ struct Ctrl {
   double best;         // min over checked iterates of max(Rp, Rd)
   double rp_star, rd_star;
 };
+
+// End of loop body n = n_done + 1: Rp(n) and Rd(n-1) from the partial sums;
+// decide whether iterate n-1 is converged, diverged or the last one.
+__device__ inline void finalize_body(Ctrl* c, double srp, double srd, double wscale, double* hist) {
+  const long long n = c->n_done + 1;
+  const double rp = sqrt(wscale * srp), rd = sqrt(wscale * srd);
+  const long long it = n - 1;
+  if (hist) {
+    hist[2 * n] = rp;
+    hist[2 * it + 1] = rd;
+    if (n == 1) hist[0] = __builtin_nan("");
+  }
+  int st = 0;
+  if (it >= 1) {
+    const double m = fmax(c->rp_prev, rd);
+    if (!(m == m) || isinf(m)) st = 2;
+    else if (m <= c->eps) st = 1;
+    else if (m > c->div_factor * c->best) st = 2;
+    if (m < c->best) c->best = m;
+    if (st == 0 && it >= c->max_iter) st = 3;
+  }
+  if (st == 0 && !(rp == rp && rd == rd && !isinf(rp) && !isinf(rd))) st = 2;
+  if (st != 0) {
+    c->status = st;
+    c->n_star = it;
+    c->rp_star = (it >= 1) ? c->rp_prev : __builtin_nan("");
+    c->rd_star = rd;
+  }
+  c->rp_prev = rp;
+  c->n_done = n;
+}
 
 }  // namespace pdhg

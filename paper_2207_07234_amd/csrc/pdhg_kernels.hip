@@ -20,33 +20,16 @@ k_rows_fwd(const T* __restrict__ rows, int nrows, T* __restrict__ spec, int nt_s
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* twl = buf + lds_fft_points(nx);
   const int tid = threadIdx.x;
   const int a = 2 * blockIdx.x, b = a + 1;
   const bool hasb = b < nrows;
   const T* ra = rows + (size_t)a * nx;
   const T* rb = rows + (size_t)b * nx;
-  for (int x = tid; x < nx; x += kFftThreads) buf[x] = {ra[x], hasb ? rb[x] : T(0)};
-  fft_lds<false, kFftThreads>(buf, nx, tw, tid);
-  const int half = nx >> 1;
-  for (int k = tid; k <= half; k += kFftThreads) {
-    const C2<T> zk = buf[k], zm = buf[(nx - k) & (nx - 1)];
-    const T ar = T(0.5) * (zk.x + zm.x), ai = T(0.5) * (zk.y - zm.y);
-    const T br = T(0.5) * (zk.y + zm.y), bi = T(0.5) * (zm.x - zk.x);
-    if (k == 0) {
-      spec[spec_index(a, 0, nt_spec, lqb)] = ar;
-      if (hasb) spec[spec_index(b, 0, nt_spec, lqb)] = br;
-    } else if (k == half) {
-      spec[spec_index(a, 1, nt_spec, lqb)] = ar;
-      if (hasb) spec[spec_index(b, 1, nt_spec, lqb)] = br;
-    } else {
-      spec[spec_index(a, 2 * k, nt_spec, lqb)] = ar;
-      spec[spec_index(a, 2 * k + 1, nt_spec, lqb)] = ai;
-      if (hasb) {
-        spec[spec_index(b, 2 * k, nt_spec, lqb)] = br;
-        spec[spec_index(b, 2 * k + 1, nt_spec, lqb)] = bi;
-      }
-    }
-  }
+  load_twiddles_lds(twl, tw, nx, tid, kFftThreads);
+  for (int x = tid; x < nx; x += kFftThreads) buf[lpad(x)] = {ra[x], hasb ? rb[x] : T(0)};
+  fft_lds<false, 16>(buf, nx, twl, tid, kFftThreads);
+  store_halfcomplex_pair(buf, nx, spec, nt_spec, lqb, a, hasb, tid, kFftThreads);
 }
 
 // Inverse: halfcomplex spectrum rows -> real rows (normalised by 1/nx).
@@ -57,34 +40,18 @@ k_rows_inv(const T* __restrict__ spec, int nt_spec, int lqb, T* __restrict__ row
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* twl = buf + lds_fft_points(nx);
   const int tid = threadIdx.x;
   const int a = 2 * blockIdx.x, b = a + 1;
   const bool hasb = b < nrows;
-  const int half = nx >> 1;
-  for (int k = tid; k <= half; k += kFftThreads) {
-    T ar, ai = T(0), br = T(0), bi = T(0);
-    if (k == 0 || k == half) {
-      const int q = (k == 0) ? 0 : 1;
-      ar = spec[spec_index(a, q, nt_spec, lqb)];
-      if (hasb) br = spec[spec_index(b, q, nt_spec, lqb)];
-    } else {
-      ar = spec[spec_index(a, 2 * k, nt_spec, lqb)];
-      ai = spec[spec_index(a, 2 * k + 1, nt_spec, lqb)];
-      if (hasb) {
-        br = spec[spec_index(b, 2 * k, nt_spec, lqb)];
-        bi = spec[spec_index(b, 2 * k + 1, nt_spec, lqb)];
-      }
-    }
-    // Z_k = A_k + i B_k ;  Z_{N-k} = conj(A_k) + i conj(B_k)
-    buf[k] = {ar - bi, ai + br};
-    if (k != 0 && k != half) buf[nx - k] = {ar + bi, br - ai};
-  }
-  fft_lds<true, kFftThreads>(buf, nx, tw, tid);
+  load_twiddles_lds(twl, tw, nx, tid, kFftThreads);
+  load_halfcomplex_pair(buf, nx, spec, nt_spec, lqb, a, hasb, tid, kFftThreads);
+  fft_lds<true, 16>(buf, nx, twl, tid, kFftThreads);
   const T sc = T(1) / T(nx);
   T* ra = rows + (size_t)a * nx;
   T* rb = rows + (size_t)b * nx;
   for (int x = tid; x < nx; x += kFftThreads) {
-    const C2<T> z = buf[x];
+    const C2<T> z = buf[lpad(x)];
     ra[x] = z.x * sc;
     if (hasb) rb[x] = z.y * sc;
   }
@@ -400,8 +367,9 @@ __global__ void k_normalize(T* __restrict__ x, size_t n, const double* nrm2) {
 }
 
 // ------------------------------------------------------------------ control
-__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor) {
+__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, unsigned* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (counter) *counter = 0u;
     c->n_done = 0;
     c->max_iter = max_iter;
     c->n_star = 0;
@@ -414,37 +382,6 @@ __global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_
     c->rp_star = __builtin_nan("");
     c->rd_star = __builtin_nan("");
   }
-}
-
-// End of loop body n = n_done + 1: Rp(n) and Rd(n-1) from the partial sums;
-// decide whether iterate n-1 is converged, diverged or the last one.
-__device__ void finalize_body(Ctrl* c, double srp, double srd, double wscale, double* hist) {
-  const long long n = c->n_done + 1;
-  const double rp = sqrt(wscale * srp), rd = sqrt(wscale * srd);
-  const long long it = n - 1;
-  if (hist) {
-    hist[2 * n] = rp;
-    hist[2 * it + 1] = rd;
-    if (n == 1) hist[0] = __builtin_nan("");
-  }
-  int st = 0;
-  if (it >= 1) {
-    const double m = fmax(c->rp_prev, rd);
-    if (!(m == m) || isinf(m)) st = 2;
-    else if (m <= c->eps) st = 1;
-    else if (m > c->div_factor * c->best) st = 2;
-    if (m < c->best) c->best = m;
-    if (st == 0 && it >= c->max_iter) st = 3;
-  }
-  if (st == 0 && !(rp == rp && rd == rd && !isinf(rp) && !isinf(rd))) st = 2;
-  if (st != 0) {
-    c->status = st;
-    c->n_star = it;
-    c->rp_star = (it >= 1) ? c->rp_prev : __builtin_nan("");
-    c->rd_star = rd;
-  }
-  c->rp_prev = rp;
-  c->n_done = n;
 }
 
 __global__ void __launch_bounds__(kEwThreads)
@@ -463,10 +400,20 @@ k_finalize(Ctrl* c, const double* __restrict__ part_rp, int n_rp, const double* 
 // ------------------------------------------------------------------ launchers
 static inline unsigned grid_for(size_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// Dynamic LDS above 64 KiB needs an explicit opt-in per kernel.
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
 template <typename T>
 hipError_t launch_rows_fwd(const T* rows, int nrows, T* spec, int nt_spec, int lqb, int nx, const void* tw,
                            const Ctrl* ctrl, hipStream_t st) {
-  const size_t lds = sizeof(C2<T>) * nx;
+  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(nx);
+  hipError_t e = allow_lds(k_rows_fwd<T>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rows_fwd<T>, dim3((nrows + 1) / 2), dim3(kFftThreads), lds, st, rows, nrows, spec,
                      nt_spec, lqb, nx, (const C2<T>*)tw, ctrl);
   return hipGetLastError();
@@ -475,7 +422,9 @@ hipError_t launch_rows_fwd(const T* rows, int nrows, T* spec, int nt_spec, int l
 template <typename T>
 hipError_t launch_rows_inv(const T* spec, int nt_spec, int lqb, T* rows, int nrows, int nx, const void* tw,
                            const Ctrl* ctrl, hipStream_t st) {
-  const size_t lds = sizeof(C2<T>) * nx;
+  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(nx);
+  hipError_t e = allow_lds(k_rows_inv<T>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rows_inv<T>, dim3((nrows + 1) / 2), dim3(kFftThreads), lds, st, spec, nt_spec, lqb,
                      rows, nrows, nx, (const C2<T>*)tw, ctrl);
   return hipGetLastError();
@@ -594,8 +543,9 @@ hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor);
+hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, unsigned* counter,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor, counter);
   return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
-  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, total;
+  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, counter, ctrl_t, counter_t,
+      total;
   int max_parts;
 };
 
@@ -112,6 +113,9 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.part_rd = o; o += align_up(sizeof(double) * L.max_parts);
   L.scal = o; o += align_up(sizeof(double) * 64);
   L.ctrl = o; o += align_up(sizeof(Ctrl));
+  L.counter = o; o += kAlign;
+  L.ctrl_t = o; o += align_up(sizeof(Ctrl));     // control block used only by kernel timing
+  L.counter_t = o; o += kAlign;
   L.total = o;
   return L;
 }
@@ -414,6 +418,14 @@ void pdhg_destroy(pdhg_handle* h) {
 
 namespace {
 
+template <typename T>
+hipError_t colsolve_any(pdhg_handle* h, T* spec, const Ctrl* ctrl, hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  const int bw = p.time == PDHG_BDF2 ? 2 : 1;
+  if (p.nt <= 1024) return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
+  return launch_colsolve<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
+}
+
 // One unfused loop body (iteration n = ctrl->n_done + 1); `odd` selects the
 // ping-pong direction of u: odd n reads u and writes u_alt.
 template <typename T>
@@ -443,6 +455,29 @@ int enqueue_body_unfused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau
   return PDHG_OK;
 }
 
+// One fused loop body: A (inverse FFT + dual step), B (primal step, residual,
+// forward FFT, norms, stopping decision), C (column solve).
+template <typename T>
+int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist,
+                       hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  const WsLayout L = layout_for(p, h->esz);
+  const Scheme s = scheme_of(h);
+  T* u_alt = (T*)wsp(ws, L.u_alt);
+  T* spec = (T*)wsp(ws, L.spec0);
+  T* phibar = (T*)wsp(ws, L.phibar);
+  double* part = (double*)wsp(ws, L.part_rp);
+  Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
+  unsigned* counter = (unsigned*)wsp(ws, L.counter);
+  T* uin = odd ? u : u_alt;
+  T* uout = odd ? u_alt : u;
+  HIP_TRY(launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
+  HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, hist, counter,
+                               st));
+  HIP_TRY(colsolve_any<T>(h, spec, ctrl, st));
+  return PDHG_OK;
+}
+
 template <typename T>
 int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist) {
   if (h->gexec && h->gkey == key) return PDHG_OK;
@@ -450,8 +485,12 @@ int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T t
   if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = PDHG_OK;
-  for (int b = 0; b < key.chunk && rc == PDHG_OK; ++b)
-    rc = enqueue_body_unfused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
+  for (int b = 0; b < key.chunk && rc == PDHG_OK; ++b) {
+    if (key.variant == 1)
+      rc = enqueue_body_unfused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
+    else
+      rc = enqueue_body_fused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
+  }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (rc) { if (g) hipGraphDestroy(g); return rc; }
@@ -494,14 +533,17 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
   HIP_TRY(launch_fill<T>(spec, n, T(0), st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
-  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st));
+  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, (unsigned*)wsp(ws, L.counter), st));
 
   int chunk = prm->check_every > 0 ? prm->check_every : 64;
   chunk += chunk & 1;   // even: u ping-pong returns to its start buffer
   GraphKey key;
   key.u = u; key.phi = phi; key.ws = ws; key.hist = prm->history;
   key.tau_u = tau_u; key.tau_phi = tau_phi; key.lf = h->lf; key.c = h->c;
-  key.variant = 1; key.chunk = chunk;
+  // fused passes need at least one full wavefront per row (nx >= 64)
+  if (prm->variant == 2 && p.nx < 64) return PDHG_EUNSUPPORTED;
+  key.variant = (prm->variant == 1 || p.nx < 64) ? 1 : 2;
+  key.chunk = chunk;
   h->last = key;
   const long long bodies = prm->max_iter + 1;
   auto t0 = std::chrono::steady_clock::now();
@@ -545,7 +587,7 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
     stats->precond_c = h->c;
     stats->seconds = std::chrono::duration<double>(t1 - t0).count();
     stats->status = status;
-    stats->variant = 1;
+    stats->variant = key.variant;
   }
   HIP_TRY(hipStreamSynchronize(st));
   return status;
@@ -634,6 +676,60 @@ int adjoint_impl(pdhg_handle* h, int mode, const T* u, const T* in, T* out, T* m
   return PDHG_OK;
 }
 
+// Launch one kernel of the unfused loop body `reps` times between two timing
+// events on `st`, with the buffers of the last solve (status checks disabled).
+template <typename T>
+int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  void* ws = const_cast<void*>(h->last.ws);
+  const WsLayout L = layout_for(p, h->esz);
+  const Scheme s = scheme_of(h);
+  T* u = (T*)const_cast<void*>(h->last.u);
+  T* phi = (T*)const_cast<void*>(h->last.phi);
+  T* u_alt = (T*)wsp(ws, L.u_alt);
+  T* spec = (T*)wsp(ws, L.spec0);
+  T* srow = (T*)wsp(ws, L.srow);
+  T* phibar = (T*)wsp(ws, L.phibar);
+  double* prp = (double*)wsp(ws, L.part_rp);
+  double* prd = (double*)wsp(ws, L.part_rd);
+  const size_t n = (size_t)p.nt * p.nx;
+  const T tu = (T)h->last.tau_u, tp = (T)h->last.tau_phi;
+  Ctrl* ctrl_t = (Ctrl*)wsp(ws, L.ctrl_t);
+  unsigned* counter_t = (unsigned*)wsp(ws, L.counter_t);
+  if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, counter_t, st));
+  auto launch = [&]() -> hipError_t {
+    switch (kernel) {
+      case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, nullptr,
+                                          counter_t, st);
+      case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
+      case 1:
+        if (h->last.variant == 2) return colsolve_any<T>(h, spec, nullptr, st);
+        return launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st);
+      case 2: return launch_rows_inv<T>(spec, p.nt, h->lqb, srow, p.nt, p.nx, h->d_tw, nullptr, st);
+      case 3: return launch_dual<T>(phi, phibar, srow, n, tp, nullptr, st);
+      case 4: return launch_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
+      case 5: return launch_residual<T>(s, u_alt, srow, prp, nullptr, st, nullptr);
+      case 6: return launch_rows_fwd<T>(srow, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  if (kernel < 0 || kernel > 7) return PDHG_EUNSUPPORTED;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(launch());   // warm-up
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) HIP_TRY(launch());
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  return PDHG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -671,8 +767,13 @@ int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, vo
 }
 
 int pdhg_time_kernel(pdhg_handle* h, int32_t kernel, int32_t reps, double* ms_per_launch, pdhg_stream_t stream) {
-  (void)h; (void)kernel; (void)reps; (void)ms_per_launch; (void)stream;
-  return PDHG_EUNSUPPORTED;
+  if (!h || !ms_per_launch || reps < 1) return PDHG_EINVAL;
+  if (!h->last.ws) return PDHG_EINVAL;   // needs a previous solve
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64) return time_kernel_impl<double>(h, kernel, reps, ms_per_launch, st);
+  return time_kernel_impl<float>(h, kernel, reps, ms_per_launch, st);
 }
 
 }  // extern "C"
