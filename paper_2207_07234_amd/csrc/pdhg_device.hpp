@@ -249,6 +249,18 @@ __device__ void fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int ti
   }
 }
 
+// ------------------------------------------------------------------ XCD-aware block order
+// The dispatcher hands consecutive workgroups to the 8 XCDs of an MI355X in
+// turn, and each XCD has its own L2.  Blocks that share halo data (neighbouring
+// time rows, the two halves of a spectrum column block) should sit on the same
+// XCD: logical block L = (b mod 8) (n / 8) + b / 8 gives XCD x the contiguous
+// range [x n/8, (x+1) n/8).  Identity when n is not a multiple of 8.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  if (n % kNumXcd != 0) return b;
+  return (b % kNumXcd) * (n / kNumXcd) + b / kNumXcd;
+}
+
 // ------------------------------------------------------------------ cross-lane moves
 // DPP wavefront shifts (all 64 lanes active): from_lane_below(v, fill) gives
 // lane l the value of lane l-1 and lane 0 `fill`; from_lane_above gives lane l
@@ -321,6 +333,20 @@ __device__ __forceinline__ double block_sum(double v, double* red /* >= W/64 dou
 #pragma unroll
     for (int i = 0; i < W / 64; ++i) s += red[i];
   }
+  return s;
+}
+
+// Sum over a block whose size is a multiple of 64: wave reductions, then one
+// thread adds the per-wave sums.  Result valid in thread 0.  Fixed order.
+__device__ __forceinline__ double block_sum_waves(double v, double* red /* >= blockDim.x/64 doubles */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) s += red[i];
   return s;
 }
 

@@ -24,7 +24,9 @@ namespace pdhg {
 constexpr int kRowThreadsMax = 512;
 
 // ------------------------------------------------------------------ A
-// W = nx / EPT threads; the twiddle table and the FFT buffer live in LDS.
+// W = nx / EPT threads.  All global loads (twiddles, the two spectrum rows and
+// the two dual rows) are issued before the first LDS write so that their
+// latencies overlap; the twiddle table and the FFT buffer live in LDS.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(kRowThreadsMax)
 k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __restrict__ tw, T* __restrict__ phi,
@@ -34,27 +36,69 @@ k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __r
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(nx);
   const int tid = threadIdx.x, W = blockDim.x;
-  const int a = 2 * blockIdx.x, b = a + 1;
+  const int a = 2 * xcd_block(blockIdx.x, gridDim.x), b = a + 1;
   const bool hasb = b < nt;
-  load_twiddles_lds(twl, tw, nx, tid, W);
-  load_halfcomplex_pair(buf, nx, spec, nt, lqb, a, hasb, tid, W);
-  fft_lds<true, EPT>(buf, nx, twl, tid, W);
-  const T sc = T(1) / T(nx);
+  const int half = nx >> 1;
   T* pa = phi + (size_t)a * nx;
   T* qa = phibar + (size_t)a * nx;
   T* pb = phi + (size_t)b * nx;
   T* qb = phibar + (size_t)b * nx;
+  // ---- loads
+  C2<T> twv[EPT];
+  T fa[EPT], fb[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int x = tid + e * W;
+    twv[e] = tw[x];
+    fa[e] = pa[x];
+    fb[e] = hasb ? pb[x] : T(0);
+  }
+  // halfcomplex pair: thread handles modes k = tid + e W, k <= nx/2 (EPT/2 + 1 of them)
+  constexpr int KPT = EPT / 2 + 1;
+  T sar[KPT], sai[KPT], sbr[KPT], sbi[KPT];
+#pragma unroll
+  for (int e = 0; e < KPT; ++e) {
+    const int k = tid + e * W;
+    sar[e] = sai[e] = sbr[e] = sbi[e] = T(0);
+    if (k <= half) {
+      if (k == 0 || k == half) {
+        const int q = (k == 0) ? 0 : 1;
+        sar[e] = spec[spec_index(a, q, nt, lqb)];
+        if (hasb) sbr[e] = spec[spec_index(b, q, nt, lqb)];
+      } else {
+        sar[e] = spec[spec_index(a, 2 * k, nt, lqb)];
+        sai[e] = spec[spec_index(a, 2 * k + 1, nt, lqb)];
+        if (hasb) {
+          sbr[e] = spec[spec_index(b, 2 * k, nt, lqb)];
+          sbi[e] = spec[spec_index(b, 2 * k + 1, nt, lqb)];
+        }
+      }
+    }
+  }
+  // ---- LDS: twiddles and Z_k = A_k + i B_k (A_{N-k} = conj A_k)
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) twl[lpad(tid + e * W)] = twv[e];
+#pragma unroll
+  for (int e = 0; e < KPT; ++e) {
+    const int k = tid + e * W;
+    if (k <= half) {
+      buf[lpad(k)] = {sar[e] - sbi[e], sai[e] + sbr[e]};
+      if (k != 0 && k != half) buf[lpad(nx - k)] = {sar[e] + sbi[e], sbr[e] - sai[e]};
+    }
+  }
+  fft_lds<true, EPT>(buf, nx, twl, tid, W);
+  const T sc = T(1) / T(nx);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int x = tid + e * W;
     const C2<T> z = buf[lpad(x)];
     const T ta = tau * (z.x * sc);
-    const T p = pa[x] + ta;
+    const T p = fa[e] + ta;
     pa[x] = p;
     qa[x] = p + ta;
     if (hasb) {
       const T tb = tau * (z.y * sc);
-      const T q = pb[x] + tb;
+      const T q = fb[e] + tb;
       pb[x] = q;
       qb[x] = q + tb;
     }
@@ -62,45 +106,43 @@ k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __r
 }
 
 // ------------------------------------------------------------------ B
-// Coherent (L1-bypassing) load for the cross-block reduction.
-__device__ __forceinline__ double load_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Load one row for this lane (x = seg0 + lane + 64 e) and the two values just
+// outside the wave's segment; rows outside [0, nrows) read as zero.
+template <typename T, int E>
+__device__ __forceinline__ void load_row_wave(const T* __restrict__ base, int r, int nrows, int nx, int seg0,
+                                              int lane, T* v, T& prev, T& next) {
+  if (r < 0 || r >= nrows) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = T(0);
+    prev = next = T(0);
+    return;
+  }
+  const T* row = base + (size_t)r * nx;
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = row[seg0 + lane + 64 * e];
+  prev = row[(seg0 - 1) & (nx - 1)];
+  next = row[(seg0 + 64 * E) & (nx - 1)];
 }
 
-// J(u)^T psi at unknown level m for this lane's points x = seg0 + lane + 64 e.
-// psi^{m-1} is loaded once (coalesced) and its x-neighbours come from the
-// neighbouring lanes.
+// J(u)^T psi at unknown level m from registers: c = psi^{m-1} (with segment
+// edges), t1 = psi^m, t2 = psi^{m+1} (zero where absent), uv = u^m.
 template <typename T, int E>
-__device__ __forceinline__ void dual_op_wave(const Consts<T>& C, int m, const T* __restrict__ psi, const T* uv,
-                                             int seg0, int lane, T* out) {
-  const int nx = C.nx, nt = C.nt;
-  const T* p0 = psi + (size_t)(m - 1) * nx;
-  const bool has1 = m <= nt - 1;
-  const bool has2 = (C.time == kTimeBDF2) && (m + 1 <= nt - 1);
-  const T* p1 = psi + (size_t)m * nx;
-  const T* p2 = psi + (size_t)(m + 1) * nx;
-  T c[E], t1[E], t2[E], cm[E], cp[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int x = seg0 + lane + 64 * e;
-    c[e] = p0[x];
-    t1[e] = has1 ? p1[x] : T(0);
-    t2[e] = has2 ? p2[x] : T(0);
-  }
-  const T prev = p0[(seg0 - 1) & (nx - 1)];
-  const T next = p0[(seg0 + 64 * E) & (nx - 1)];
+__device__ __forceinline__ void dual_op_regs(const Consts<T>& C, int m, const T* c, T prev, T next, const T* t1,
+                                             const T* t2, const T* uv, T* out) {
+  T cm[E], cp[E];
   wave_row_neighbours<T, E>(c, prev, next, cm, cp);
 #pragma unroll
   for (int e = 0; e < E; ++e) out[e] = C.JtTime(m, c[e], t1[e], t2[e]) + C.JtF(uv[e], cm[e], c[e], cp[e]);
 }
 
 // W = 64 nw threads; wave v owns x in [v 64E, (v+1) 64E), lane l element e at
-// x = v 64E + l + 64 e.
+// x = v 64E + l + 64 e.  Every global row the block needs is loaded up front:
+// u^{n-1} on levels a-1..a+2, phibar on rows a-2..a+3, phi on rows a..a+3.
 template <typename T, int E>
 __global__ void __launch_bounds__(kRowThreadsMax)
 k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
              const T* __restrict__ phi, T tau_u, T* __restrict__ spec, int lqb, const C2<T>* __restrict__ tw,
-             double* __restrict__ part, Ctrl* ctrl, double* hist, unsigned* counter) {
+             double* __restrict__ part, const Ctrl* ctrl) {
   if (ctrl->status != 0) return;
   extern __shared__ char smem[];
   const Consts<T> C(sch);
@@ -109,37 +151,60 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(nx);
   T* edge = reinterpret_cast<T*>(twl + lds_fft_points(nx));   // [2 rows][first, last][nw]
-  __shared__ double red[kRowThreadsMax];
-  __shared__ unsigned ticket;
+  __shared__ double red[kRowThreadsMax / 64];
   const int seg0 = wv * 64 * E;
-  const int a = 2 * blockIdx.x, b = a + 1;                     // implicit rows of this block
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int a = 2 * blk, b = a + 1;                            // implicit rows of this block
   const bool bdf2 = C.time == kTimeBDF2;
-  load_twiddles_lds(twl, tw, nx, tid, W);
-  // slot i holds level a - 1 + i (i = 0..3); rows a, b need slots {2,1,0} and {3,2,1}
-  T U[4][E];
+  // ---- all global loads first
+  constexpr int TPT = (E < 1) ? 1 : E;                         // twiddles per thread (nx / W)
+  C2<T> twv[TPT];
+#pragma unroll
+  for (int e = 0; e < TPT; ++e) twv[e] = tw[tid + e * W];
+  T U0[4][E], U[4][E];                 // u^{n-1} and u^n on levels a-1+i
+  T PB[6][E], PBp[4], PBn[4];          // phibar rows a-2+j (edges for j = 0..3)
+  T PH[4][E], PHp[2], PHn[2];          // phi rows a+j (edges for j = 0, 1)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = a - 1 + i;
+    const bool ok = m >= 0 && m <= nt && (bdf2 || i > 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) U0[i][e] = ok ? u_in[(size_t)m * nx + seg0 + lane + 64 * e] : T(0);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T pv, nv;
+    load_row_wave<T, E>(phibar, a - 2 + j, nt, nx, seg0, lane, PB[j], pv, nv);
+    if (j < 4) { PBp[j] = pv; PBn[j] = nv; }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    T pv, nv;
+    load_row_wave<T, E>(phi, a + j, nt, nx, seg0, lane, PH[j], pv, nv);
+    if (j < 2) { PHp[j] = pv; PHn[j] = nv; }
+  }
+#pragma unroll
+  for (int e = 0; e < TPT; ++e) twl[lpad(tid + e * W)] = twv[e];
+  // ---- primal step on the four levels, dual residual on the two owned ones
   double rd = 0.0, rp = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int m = a - 1 + i;
     if (m < 0 || m > nt || (!bdf2 && i == 0)) continue;
-    const T* uo = u_in + (size_t)m * nx + seg0 + lane;
-    T uv[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) uv[e] = uo[64 * e];
     if (m == 0) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) U[i][e] = uv[e];
+      for (int e = 0; e < E; ++e) U[i][e] = U0[i][e];
       continue;
     }
     T g[E];
-    dual_op_wave<T, E>(C, m, phibar, uv, seg0, lane, g);
+    dual_op_regs<T, E>(C, m, PB[i], PBp[i], PBn[i], PB[i + 1], PB[i + 2], U0[i], g);
 #pragma unroll
-    for (int e = 0; e < E; ++e) U[i][e] = uv[e] - tau_u * g[e];
+    for (int e = 0; e < E; ++e) U[i][e] = U0[i][e] - tau_u * g[e];
     if (i >= 2) {   // owned level: store u^n and the dual residual of (u^{n-1}, phi^{n-1})
       T* uw = u_out + (size_t)m * nx + seg0 + lane;
 #pragma unroll
       for (int e = 0; e < E; ++e) uw[64 * e] = U[i][e];
-      dual_op_wave<T, E>(C, m, phi, uv, seg0, lane, g);
+      dual_op_regs<T, E>(C, m, PH[i - 2], PHp[i - 2], PHn[i - 2], PH[i - 1], PH[i], U0[i], g);
 #pragma unroll
       for (int e = 0; e < E; ++e) rd += (double)g[e] * (double)g[e];
     }
@@ -181,29 +246,12 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   fft_lds<false, E>(buf, nx, twl, tid, W);
   store_halfcomplex_pair(buf, nx, spec, nt, lqb, a, b < nt, tid, W);
 
-  // per-block partial sums, then the last block reduces them in a fixed order
-  const int nblk = gridDim.x;
-  const double srp = block_sum_tree(rp, red);
-  const double srd = block_sum_tree(rd, red);
+  // per-block partial sums; the column-solve kernel of this iteration reduces them
+  const double srp = block_sum_waves(rp, red);
+  const double srd = block_sum_waves(rd, red);
   if (tid == 0) {
-    part[blockIdx.x] = srp;
-    part[nblk + blockIdx.x] = srd;
-    __threadfence();
-    ticket = atomicAdd(counter, 1u);
-  }
-  __syncthreads();
-  if (ticket != (unsigned)(nblk - 1)) return;
-  __threadfence();
-  double ta = 0.0, tb = 0.0;
-  for (int i = tid; i < nblk; i += W) {
-    ta += load_coherent(part + i);
-    tb += load_coherent(part + nblk + i);
-  }
-  const double sa = block_sum_tree(ta, red);
-  const double sb = block_sum_tree(tb, red);
-  if (tid == 0) {
-    finalize_body(ctrl, sa, sb, sch.ht * sch.hx, hist);
-    *counter = 0u;
+    part[blk] = srp;
+    part[gridDim.x + blk] = srd;
   }
 }
 
@@ -333,39 +381,67 @@ __device__ __forceinline__ void load_factor_rows(const FacTab<T>& fac, int kmode
   e2[LPL + 1] = rows[min(l0 + LPL + 1, last)].e2;
 }
 
+// Norms and stopping decision of iteration n from the nparts per-block partial
+// sums written by k_primal_res (first wave of the block only; fixed order).
+__device__ __forceinline__ void finalize_wave(Ctrl* ctrl, const double* __restrict__ part, int nparts,
+                                              double wscale, double* hist) {
+  const int lane = threadIdx.x & 63;
+  double a = 0.0, b = 0.0;
+  for (int i = lane; i < nparts; i += 64) {
+    a += part[i];
+    b += part[nparts + i];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) finalize_body(ctrl, a, b, wscale, hist);
+}
+
 template <typename T, int BW, int LPL>
 __global__ void __launch_bounds__(64 * kColWaves)
-k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, const Ctrl* ctrl) {
+k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                int nparts, double wscale, double* hist) {
   if (ctrl && ctrl->status != 0) return;
+  if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, wscale, hist);
   extern __shared__ char smem[];
   T* tile = reinterpret_cast<T*>(smem);   // [kColCols][LPL][65], level l of column c at (c LPL + l % LPL) 65 + l / LPL
   const int QB = 1 << lqb;
-  const int q0 = blockIdx.x * kColCols;   // first spectrum column of this block
+  const int q0 = xcd_block(blockIdx.x, gridDim.x) * kColCols;   // first spectrum column of this block
   T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < nt * kColCols; idx += blockDim.x) {
-    const int l = idx / kColCols, c = idx % kColCols;
-    tile[(c * LPL + l % LPL) * 65 + l / LPL] = base[(size_t)l * QB + c];
-  }
-  __syncthreads();
+  constexpr int kPer = 64 * LPL * kColCols / (64 * kColWaves);   // tile elements per thread
   const int wv = tid >> 6, lane = tid & 63;
   const int qa = q0 + 2 * wv, qb = qa + 1;
   const int ka = spec_mode(qa, nx), kb = spec_mode(qb, nx);
   const int l0 = lane * LPL;
+  // factor rows of this wave's mode first, so their latency overlaps the tile loads
+  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<T, LPL>(fac, ka, l0, invd, e1, e2);
+  // all tile loads in flight before the first LDS write
+  T stage[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    tile[(c * LPL + l % LPL) * 65 + l / LPL] = stage[r];
+  }
+  __syncthreads();
   T z[2][LPL];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int i = 0; i < LPL; ++i) z[c][i] = tile[((2 * wv + c) * LPL + i) * 65 + lane];
-  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
   if (ka == kb) {
-    load_factor_rows<T, LPL>(fac, ka, l0, invd, e1, e2);
     cholesky_solve_wave<T, BW, LPL, 2>(z, invd, e1, e2, lane, l0, nt);
   } else {   // real columns of modes 0 and nx/2
     T za[1][LPL], zb[1][LPL];
 #pragma unroll
     for (int i = 0; i < LPL; ++i) { za[0][i] = z[0][i]; zb[0][i] = z[1][i]; }
-    load_factor_rows<T, LPL>(fac, ka, l0, invd, e1, e2);
     cholesky_solve_wave<T, BW, LPL, 1>(za, invd, e1, e2, lane, l0, nt);
     load_factor_rows<T, LPL>(fac, kb, l0, invd, e1, e2);
     cholesky_solve_wave<T, BW, LPL, 1>(zb, invd, e1, e2, lane, l0, nt);
@@ -377,9 +453,17 @@ k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, co
 #pragma unroll
     for (int i = 0; i < LPL; ++i) tile[((2 * wv + c) * LPL + i) * 65 + lane] = z[c][i];
   __syncthreads();
-  for (int idx = tid; idx < nt * kColCols; idx += blockDim.x) {
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
     const int l = idx / kColCols, c = idx % kColCols;
-    base[(size_t)l * QB + c] = tile[(c * LPL + l % LPL) * 65 + l / LPL];
+    stage[r] = tile[(c * LPL + l % LPL) * 65 + l / LPL];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    if (l < nt) base[(size_t)l * QB + c] = stage[r];
   }
 }
 
@@ -406,11 +490,13 @@ static hipError_t launch_dual_fft_e(const T* spec, int nt, int lqb, int nx, cons
   return hipGetLastError();
 }
 
-// A: EPT = clamp(nx / 64, 1, 8) points per thread (nx >= 64).
+// A: nx >= 64.
 template <typename T>
 hipError_t launch_dual_fft(const T* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
                            const Ctrl* ctrl, hipStream_t st) {
-  switch (clampi(nx / 64, 1, 8)) {
+  // EPT = nx / W with W = min(512, nx / 2) threads for nx >= 128 (8 waves at nx = 2048)
+  const int W = nx >= 1024 ? 512 : (nx >= 128 ? nx / 2 : nx);
+  switch (nx / W) {
     case 1: return launch_dual_fft_e<T, 1>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
     case 2: return launch_dual_fft_e<T, 2>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
     case 4: return launch_dual_fft_e<T, 4>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
@@ -421,49 +507,52 @@ hipError_t launch_dual_fft(const T* spec, int nt, int lqb, int nx, const void* t
 
 template <typename T, int E>
 static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi,
-                                      T tau_u, T* spec, int lqb, const void* tw, double* part, Ctrl* ctrl,
-                                      double* hist, unsigned* counter, hipStream_t st) {
+                                      T tau_u, T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl,
+                                      hipStream_t st) {
   const int W = s.nx / E;
   const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(s.nx) + sizeof(T) * 4 * (W / 64);
   hipError_t e = allow_lds(k_primal_res<T, E>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_primal_res<T, E>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out, phibar, phi,
-                     tau_u, spec, lqb, (const C2<T>*)tw, part, ctrl, hist, counter);
+                     tau_u, spec, lqb, (const C2<T>*)tw, part, ctrl);
   return hipGetLastError();
 }
 
 // B: W = 64 * clamp(nx / 256, 1, 8) threads, E = nx / W points per thread (nx >= 64).
 template <typename T>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
-                             T* spec, int lqb, const void* tw, double* part, Ctrl* ctrl, double* hist,
-                             unsigned* counter, hipStream_t st) {
+                             T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st) {
   const int W = 64 * clampi(s.nx / 256, 1, 8);
   switch (s.nx / W) {
-    case 1: return launch_primal_res_e<T, 1>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, hist, counter, st);
-    case 2: return launch_primal_res_e<T, 2>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, hist, counter, st);
-    case 4: return launch_primal_res_e<T, 4>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, hist, counter, st);
-    case 8: return launch_primal_res_e<T, 8>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, hist, counter, st);
+    case 1: return launch_primal_res_e<T, 1>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 2: return launch_primal_res_e<T, 2>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 4: return launch_primal_res_e<T, 4>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 8: return launch_primal_res_e<T, 8>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int BW, int LPL>
-static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, const Ctrl* ctrl,
+static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+                                         const double* part, int nparts, double wscale, double* hist,
                                          hipStream_t st) {
   const size_t lds = sizeof(T) * (size_t)kColCols * LPL * 65;
   hipError_t e = allow_lds(k_colsolve_wave<T, BW, LPL>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_colsolve_wave<T, BW, LPL>), dim3(nx / kColCols), dim3(64 * kColWaves), lds, st, spec, fac,
-                     nt, nx, lqb, ctrl);
+                     nt, nx, lqb, ctrl, part, nparts, wscale, hist);
   return hipGetLastError();
 }
 
-// C: nt <= 1024, nx >= 8 (one wavefront per Fourier mode).
+// C: nt <= 1024, nx >= 8 (one wavefront per Fourier mode).  With part != NULL the
+// first wave of block 0 also reduces the iteration's residual partial sums and
+// takes the stopping decision (ctrl must then be non-NULL).
 template <typename T>
-hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, const Ctrl* ctrl,
-                                hipStream_t st) {
+hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                const double* part, int nparts, double wscale, double* hist, hipStream_t st) {
   const int lpl = (nt + 63) / 64;
-#define PDHG_CW(B, L) return launch_colsolve_wave_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, st)
+#define PDHG_CW(B, L) \
+  return launch_colsolve_wave_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
   if (bw == 2) {
     if (lpl <= 1) PDHG_CW(2, 1);
     if (lpl <= 2) PDHG_CW(2, 2);
@@ -486,14 +575,12 @@ template hipError_t launch_dual_fft<float>(const float*, int, int, int, const vo
 template hipError_t launch_dual_fft<double>(const double*, int, int, int, const void*, double*, double*, double,
                                             const Ctrl*, hipStream_t);
 template hipError_t launch_primal_res<float>(const Scheme&, const float*, float*, const float*, const float*, float,
-                                             float*, int, const void*, double*, Ctrl*, double*, unsigned*,
-                                             hipStream_t);
+                                             float*, int, const void*, double*, const Ctrl*, hipStream_t);
 template hipError_t launch_primal_res<double>(const Scheme&, const double*, double*, const double*, const double*,
-                                              double, double*, int, const void*, double*, Ctrl*, double*,
-                                              unsigned*, hipStream_t);
-template hipError_t launch_colsolve_wave<float>(float*, const FacTab<float>&, int, int, int, int, const Ctrl*,
-                                                hipStream_t);
-template hipError_t launch_colsolve_wave<double>(double*, const FacTab<double>&, int, int, int, int, const Ctrl*,
-                                                 hipStream_t);
+                                              double, double*, int, const void*, double*, const Ctrl*, hipStream_t);
+template hipError_t launch_colsolve_wave<float>(float*, const FacTab<float>&, int, int, int, int, Ctrl*,
+                                                const double*, int, double, double*, hipStream_t);
+template hipError_t launch_colsolve_wave<double>(double*, const FacTab<double>&, int, int, int, int, Ctrl*,
+                                                 const double*, int, double, double*, hipStream_t);
 
 }  // namespace pdhg

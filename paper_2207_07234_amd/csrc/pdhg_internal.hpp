@@ -40,8 +40,7 @@ hipError_t launch_maxabs_dflux(const T* x, size_t n, double a2, double b, double
 template <typename T>
 hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st);
 
-hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, unsigned* counter,
-                            hipStream_t st);
+hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st);
 hipError_t launch_finalize(Ctrl* c, const double* part_rp, int n_rp, const double* part_rd, int n_rd,
                            double wscale, double* hist, hipStream_t st);
 
@@ -58,9 +57,8 @@ hipError_t launch_dual_fft(const T* spec, int nt, int lqb, int nx, const void* t
                            const Ctrl* ctrl, hipStream_t st);
 template <typename T>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
-                             T* spec, int lqb, const void* tw, double* part, Ctrl* ctrl, double* hist,
-                             unsigned* counter, hipStream_t st);
+                             T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st);
 template <typename T>
-hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, const Ctrl* ctrl,
-                                hipStream_t st);
+hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                const double* part, int nparts, double wscale, double* hist, hipStream_t st);
 }  // namespace pdhg

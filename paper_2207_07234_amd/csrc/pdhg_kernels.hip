@@ -367,9 +367,8 @@ __global__ void k_normalize(T* __restrict__ x, size_t n, const double* nrm2) {
 }
 
 // ------------------------------------------------------------------ control
-__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, unsigned* counter) {
+__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (counter) *counter = 0u;
     c->n_done = 0;
     c->max_iter = max_iter;
     c->n_star = 0;
@@ -543,9 +542,8 @@ hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, unsigned* counter,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor, counter);
+hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor);
   return hipGetLastError();
 }
 

@@ -28,8 +28,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
-  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, counter, ctrl_t, counter_t,
-      total;
+  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, total;
   int max_parts;
 };
 
@@ -113,9 +112,7 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.part_rd = o; o += align_up(sizeof(double) * L.max_parts);
   L.scal = o; o += align_up(sizeof(double) * 64);
   L.ctrl = o; o += align_up(sizeof(Ctrl));
-  L.counter = o; o += kAlign;
   L.ctrl_t = o; o += align_up(sizeof(Ctrl));     // control block used only by kernel timing
-  L.counter_t = o; o += kAlign;
   L.total = o;
   return L;
 }
@@ -418,12 +415,20 @@ void pdhg_destroy(pdhg_handle* h) {
 
 namespace {
 
+// Column solve of the fused body.  With part != NULL it also reduces the
+// iteration's residual partial sums (nparts per norm) and takes the stopping
+// decision: inside the wave kernel (nt <= 1024) or in a separate finalize kernel.
 template <typename T>
-hipError_t colsolve_any(pdhg_handle* h, T* spec, const Ctrl* ctrl, hipStream_t st) {
+hipError_t colsolve_any(pdhg_handle* h, T* spec, Ctrl* ctrl, const double* part, int nparts, double* hist,
+                        hipStream_t st) {
   const pdhg_problem& p = h->prob;
   const int bw = p.time == PDHG_BDF2 ? 2 : 1;
-  if (p.nt <= 1024) return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
-  return launch_colsolve<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
+  const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
+  if (p.nt <= 1024)
+    return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale, hist, st);
+  hipError_t e = launch_colsolve<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
+  if (e != hipSuccess || !part) return e;
+  return launch_finalize(ctrl, part, nparts, part + nparts, nparts, wscale, hist, st);
 }
 
 // One unfused loop body (iteration n = ctrl->n_done + 1); `odd` selects the
@@ -468,13 +473,11 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
   T* phibar = (T*)wsp(ws, L.phibar);
   double* part = (double*)wsp(ws, L.part_rp);
   Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
-  unsigned* counter = (unsigned*)wsp(ws, L.counter);
   T* uin = odd ? u : u_alt;
   T* uout = odd ? u_alt : u;
   HIP_TRY(launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
-  HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, hist, counter,
-                               st));
-  HIP_TRY(colsolve_any<T>(h, spec, ctrl, st));
+  HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, st));
+  HIP_TRY(colsolve_any<T>(h, spec, ctrl, part, (p.nt + 1) / 2, hist, st));
   return PDHG_OK;
 }
 
@@ -533,7 +536,7 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
   HIP_TRY(launch_fill<T>(spec, n, T(0), st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
-  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, (unsigned*)wsp(ws, L.counter), st));
+  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st));
 
   int chunk = prm->check_every > 0 ? prm->check_every : 64;
   chunk += chunk & 1;   // even: u ping-pong returns to its start buffer
@@ -695,15 +698,13 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
   const size_t n = (size_t)p.nt * p.nx;
   const T tu = (T)h->last.tau_u, tp = (T)h->last.tau_phi;
   Ctrl* ctrl_t = (Ctrl*)wsp(ws, L.ctrl_t);
-  unsigned* counter_t = (unsigned*)wsp(ws, L.counter_t);
-  if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, counter_t, st));
+  if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, st));
   auto launch = [&]() -> hipError_t {
     switch (kernel) {
-      case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, nullptr,
-                                          counter_t, st);
+      case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
       case 1:
-        if (h->last.variant == 2) return colsolve_any<T>(h, spec, nullptr, st);
+        if (h->last.variant == 2) return colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st);
         return launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st);
       case 2: return launch_rows_inv<T>(spec, p.nt, h->lqb, srow, p.nt, p.nx, h->d_tw, nullptr, st);
       case 3: return launch_dual<T>(phi, phibar, srow, n, tp, nullptr, st);
