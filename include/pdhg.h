@@ -106,6 +106,7 @@ typedef struct {
   double nu_max;            /* power-iteration estimate (0 if steps were given)           */
   double lf_speed, precond_c; /* constants used                                           */
   double seconds;           /* wall time of the iteration loop                            */
+  double mass_drift;        /* max_l |m^l - m^0| with m^l = h_x sum_j u^l_j (conservation check) */
   int32_t status;
   int32_t variant;          /* kernel variant that ran                                    */
 } pdhg_stats;

@@ -25,7 +25,7 @@ from typing import Optional
 
 from . import _binding as B
 
-__all__ = ["Problem", "Solver", "SolveResult", "PdhgError", "lib_path"]
+__all__ = ["Problem", "Solver", "SolveResult", "PdhgError", "lib_path", "differentiable_solve"]
 
 lib_path = B.LIB_PATH
 _TIME = {"be": B.PDHG_BE, "bdf2": B.PDHG_BDF2}
@@ -219,3 +219,9 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def differentiable_solve(u0, solver, **solve_kwargs):
+    """u (all levels) as a differentiable function of u0 (implicit adjoint backward)."""
+    from .autograd import solve
+    return solve(u0, solver, **solve_kwargs)

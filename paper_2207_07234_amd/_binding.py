@@ -44,7 +44,7 @@ class pdhg_stats(C.Structure):
         ("iters", C.c_int64), ("res_primal", C.c_double), ("res_dual", C.c_double),
         ("tau_u", C.c_double), ("tau_phi", C.c_double), ("nu_max", C.c_double),
         ("lf_speed", C.c_double), ("precond_c", C.c_double), ("seconds", C.c_double),
-        ("status", C.c_int32), ("variant", C.c_int32),
+        ("mass_drift", C.c_double), ("status", C.c_int32), ("variant", C.c_int32),
     ]
 
 

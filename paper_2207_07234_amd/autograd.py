@@ -1,0 +1,42 @@
+"""Differentiable space-time solve: d loss / d u0 by the implicit-function adjoint.
+
+Forward: Algorithm 1 (pdhg_solve) to the requested residual; returns u at
+every level, shape (nt+1, nx).  Backward: the converged u solves the implicit
+scheme A(u; u0) = 0 (Section 3.1), so for a loss l(u) the gradient with
+respect to u0 is dl/du^0 - (dA/du0)^T mu with J(u)^T mu = dl/du.  J^T is the
+dual-equation operator obtained by summation by parts (Section 3.1); the
+library solves it by a backward march in time (pdhg_adjoint, mode SOLVE), one
+periodic tridiagonal system per level.  No primal-dual iterate is stored:
+only the converged u is kept for the backward pass.
+
+The gradient is that of the implicit scheme's solution map; it equals the
+derivative of the returned PDHG iterate up to the solve tolerance.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class PDHGSolve(torch.autograd.Function):
+    """u = PDHGSolve.apply(u0, solver, solve_kwargs) with u of shape (nt+1, nx)."""
+
+    @staticmethod
+    def forward(ctx, u0, solver, solve_kwargs):
+        res = solver.solve(u0.detach().contiguous(), **(solve_kwargs or {}))
+        if res.status < 0 or res.status == 2:
+            raise RuntimeError(f"PDHG solve failed (status {res.status}): {res.stats}")
+        ctx.solver = solver
+        ctx.stats = res.stats
+        ctx.save_for_backward(res.u)
+        return res.u
+
+    @staticmethod
+    def backward(ctx, g_u):
+        (u,) = ctx.saved_tensors
+        grad = ctx.solver.adjoint_solve(u, g_u.contiguous())
+        return grad, None, None
+
+
+def solve(u0, solver, **solve_kwargs):
+    """Differentiable solve; see PDHGSolve."""
+    return PDHGSolve.apply(u0, solver, solve_kwargs)

@@ -62,3 +62,8 @@ template <typename T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st);
 }  // namespace pdhg
+
+namespace pdhg {
+template <typename T>
+hipError_t launch_level_sums(const T* u, int nx, int levels, double* out, hipStream_t st);
+}  // namespace pdhg

@@ -100,7 +100,8 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   const size_t nx = (size_t)p.nx, nt = (size_t)p.nt;
   const size_t field = align_up(nt * nx * esz);
   const size_t ufield = align_up((nt + 1) * nx * esz);
-  L.max_parts = (int)((nt * nx + 255) / 256) + 256;
+  // per-block partial sums of the element-wise kernels, or nt+1 level sums
+  L.max_parts = (int)std::max((nt * nx + 255) / 256 + 256, nt + 1 + 256);
   size_t o = 0;
   L.u_alt = o; o += ufield;
   L.phi_alt = o; o += field;
@@ -579,7 +580,18 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   else if (c.status == 2) status = PDHG_DIVERGED;
   else status = PDHG_NOT_CONVERGED;
   if (nstar & 1) HIP_TRY(launch_copy<T>(u, u_alt, nlev, st));
+  double drift = 0.0;
+  {
+    double* lev = (double*)wsp(ws, L.part_rp);   // nt+1 <= max_parts
+    HIP_TRY(launch_level_sums<T>(u, p.nx, p.nt + 1, lev, st));
+    std::vector<double> m(p.nt + 1);
+    HIP_TRY(hipMemcpyAsync(m.data(), lev, m.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double hx = p.length / p.nx;
+    for (int l = 1; l <= p.nt; ++l) drift = std::max(drift, std::fabs(m[l] - m[0]) * hx);
+  }
   if (stats) {
+    stats->mass_drift = drift;
     stats->iters = nstar;
     stats->res_primal = c.rp_star;
     stats->res_dual = c.rd_star;
