@@ -35,6 +35,22 @@ KERNELS_FUSED = {
     0: ("B: primal step + residual + forward FFT", 5),
     1: ("C: column solve (banded Cholesky in t)", 2),
 }
+COPY_KERNEL = 8   # plain copy of N_t*N_x elements: one read and one write per element
+
+# HBM traffic of the dominant kernel from hardware counters (rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, median over dispatches), each scaled by the ratio of known bytes to
+# the same counter's reading for the plain copy kernel in the same run.  The readings are valid
+# only for the kernel sources they were taken on (SHA-256 below); after any change to those
+# sources the traffic field is reported as null until the counters are taken again.
+# Summary and commands: profiles/primal_res_burgers_2048x512_f64_pmc.md.
+COUNTER_SOURCES = ("paper_2207_07234_amd/csrc/pdhg_fused.hip", "paper_2207_07234_amd/csrc/pdhg_device.hpp",
+                   "paper_2207_07234_amd/csrc/pdhg_internal.hpp")
+COUNTERS = {
+    # (dtype, variant, kernel id): per-dispatch KiB of the kernel and of the copy kernel
+    ("f64", 2, 0): {"fetch_kib": 13002.5, "write_kib": 16388.0, "copy_fetch_kib": 4105.5, "copy_write_kib": 8192.0,
+                    "sha": "e3e0c148445f1197e4185b506f808a21476ac17f0fa19e98f311e760308c409e"},
+}
+
 KERNELS_UNFUSED = {
     1: ("column solve (banded Cholesky in t)", 2),
     2: ("inverse row FFT", 2),
@@ -47,6 +63,25 @@ KERNELS_UNFUSED = {
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(dtype: str, variant: int, kid: int, copy_bytes: float):
+    """HBM bytes per launch of kernel `kid` from the recorded counters, or None."""
+    rec = COUNTERS.get((dtype, variant, kid))
+    if rec is None or rec["sha"] != sources_sha():
+        return None
+    fetch = rec["fetch_kib"] * (copy_bytes / 2) / rec["copy_fetch_kib"]
+    write = rec["write_kib"] * (copy_bytes / 2) / rec["copy_write_kib"]
+    return fetch + write
 
 
 def cpu_baseline(sample_iters: int):
@@ -145,9 +180,14 @@ def main():
     dom = max(kern, key=lambda k: kern[k][2])
     name, words, ms, gbs = kern[dom]
     iter_us = sum(v[2] for v in kern.values()) * 1e3
+    copy_ms = solver.time_kernel(COPY_KERNEL, reps=50)
+    copy_bytes = 2 * esz * dof
+    log(f"plain copy of {dof} elements: {copy_ms*1e3:.1f} us, {copy_bytes / (copy_ms * 1e-3) / 1e9:.0f} GB/s")
+    traffic = counter_traffic(args.dtype, stats["variant"], dom, copy_bytes)
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "kernel": name,
-            "bytes_per_launch": words * esz * dof, "ms_per_launch": ms}
+            "traffic": traffic, "kernel": name,
+            "bytes_per_launch": words * esz * dof, "ms_per_launch": ms,
+            "copy_GBs": copy_bytes / (copy_ms * 1e-3) / 1e9}
 
     out = {
         "metric": METRIC,

@@ -164,7 +164,9 @@ int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, vo
  * step sizes of the last pdhg_solve on this handle (the buffers' contents are
  * overwritten).  kernel: 0 = fused primal/residual/FFT pass, 1 = column solve,
  * 2 = inverse row FFT, 3 = dual update, 4 = primal update, 5 = residual,
- * 6 = forward row FFT, 7 = fused inverse-FFT/dual pass.
+ * 6 = forward row FFT, 7 = fused inverse-FFT/dual pass, 8 = plain device copy
+ * of N_t*N_x elements (one read and one write per element; the reference point
+ * for bandwidth and for scaling hardware byte counters).
  * Used for roofline measurements.  Returns PDHG_EINVAL without a previous solve. */
 int pdhg_time_kernel(pdhg_handle* h, int32_t kernel, int32_t reps, double* ms_per_launch,
                      pdhg_stream_t stream);

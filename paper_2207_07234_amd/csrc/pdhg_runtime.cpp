@@ -723,10 +723,11 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
       case 4: return launch_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
       case 5: return launch_residual<T>(s, u_alt, srow, prp, nullptr, st, nullptr);
       case 6: return launch_rows_fwd<T>(srow, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st);
+      case 8: return launch_copy<T>(srow, phibar, n, st);   // plain copy: calibrates bandwidth and counters
       default: return hipErrorInvalidValue;
     }
   };
-  if (kernel < 0 || kernel > 7) return PDHG_EUNSUPPORTED;
+  if (kernel < 0 || kernel > 8) return PDHG_EUNSUPPORTED;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
