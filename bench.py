@@ -12,6 +12,7 @@ event timing against the 8 TB/s HBM peak, and the FP64 CPU oracle timed on a
 bounded sample of iterations of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --workload batch [--batch-iters N] [--ttr-problems M]
 """
 import argparse
 import json
@@ -108,6 +109,137 @@ def cpu_baseline(sample_iters: int):
     }
 
 
+BATCH_COUNT, BATCH_ITERS, BATCH_SEED = 256, 300, 0
+BATCH_WORDS = {0: ("A: inverse FFT + dual step", 4), 1: ("B: primal step + residual + forward FFT", 5),
+               2: ("C: column solve (banded Cholesky in t)", 2)}
+
+
+def batch_problems(pk, torch_dtype, count=BATCH_COUNT):
+    import synthetic as syn
+    shapes = syn.batch_shapes(BATCH_SEED, count)
+    probs = [pk.Problem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf",
+                        dtype=torch_dtype) for nx, nt, _ in shapes]
+    u0s = [syn.fourier_u0(s, nx) for nx, _, s in shapes]
+    return probs, u0s
+
+
+def run_batch(args):
+    """256 independent Burgers problems (BDF2, LF, T = 0.5, nx in {256..4096}, nt in {64..512}):
+    the batched solver against one solve per problem, at a fixed iteration budget (FP32 by default),
+    and FP64 time to residual 1e-8 on the first --ttr-problems problems."""
+    import torch
+
+    import paper_2207_07234_amd as pk
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dtype = torch.float32 if args.dtype == "f32" or args.dtype is None else torch.float64
+    esz = 4 if dtype == torch.float32 else 8
+    probs, u0s = batch_problems(pk, dtype)
+    bs = pk.BatchSolver(probs)
+    u0 = bs.pack_u0(u0s)
+    iters = args.batch_iters
+    first = bs.solve(u0, eps=0.0, max_iter=2, check_every=2)          # step sizes (power iterations)
+    taus = [s["tau_u"] for s in first.stats]
+    grids = bs.tune(u0, tau_u=taus, tau_phi=taus)
+    log(f"batch of {len(probs)}: {bs.u_elems} u points, tuned grids {grids}")
+    for _ in range(args.warmup):
+        bs.solve(u0, tau_u=taus, tau_phi=taus, eps=0.0, max_iter=iters, check_every=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dofit = 0
+    for k in range(args.steps):
+        r = bs.solve(u0, tau_u=taus, tau_phi=taus, eps=0.0, max_iter=iters, check_every=50)
+        dofit += sum(p.nx * p.nt * s["iters"] for p, s in zip(probs, r.stats))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = dofit / wall
+    ndiv = sum(s["status"] == 2 for s in r.stats)
+    log(f"batched: {wall / args.steps * 1e3:.1f} ms per solve of {iters} iterations, {value:.3e} DOF-it/s, "
+        f"{ndiv} problems diverged")
+    # one solve per problem, same step sizes and iteration budget
+    singles = [pk.Solver(p) for p in probs]
+    u0d = [torch.tensor(x, dtype=dtype, device=dev) for x in u0s]
+    for i, s in enumerate(singles):
+        s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], eps=0.0, max_iter=2, check_every=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dofit_s = 0
+    for i, s in enumerate(singles):
+        rr = s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], eps=0.0, max_iter=iters, check_every=50)
+        dofit_s += probs[i].nx * probs[i].nt * rr.stats["iters"]
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    value_s = dofit_s / wall_s
+    log(f"one solve per problem: {wall_s * 1e3:.1f} ms, {value_s:.3e} DOF-it/s")
+    # per-pass device time (every problem running), dominant pass against the HBM roofline
+    dof = sum(p.nx * p.nt for p in probs)
+    kern = {}
+    for kid, (name, words) in BATCH_WORDS.items():
+        ms = bs.time_kernel(kid, reps=10)
+        kern[kid] = (name, words, ms, words * esz * dof / (ms * 1e-3) / 1e9)
+        log(f"batched pass {kid} {name}: {ms*1e3:.1f} us/launch, {kern[kid][3]:.0f} GB/s algorithmic")
+    dom = max(kern, key=lambda k: kern[k][2])
+    name, words, ms, gbs = kern[dom]
+    ttr = None
+    if args.ttr_problems > 0:
+        ttr = batch_time_to_residual(pk, args.ttr_problems, dev)
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if dtype == torch.float32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{len(probs)} independent Burgers IVPs, FD Lax-Friedrichs, BDF2, T={T_FINAL}, "
+                        f"nx in {{256..4096}}, nt in {{64..512}}, seeded Fourier u0, {iters} iterations per solve",
+            "problems": len(probs), "dof": dof, "iterations_per_solve": iters, "diverged": ndiv,
+            "grids": grids, "per_instance_value": value_s, "speedup_vs_per_instance": value / value_s,
+            "time_to_residual_1e-8": ttr,
+        },
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "batched " + name,
+                     "bytes_per_launch": words * esz * dof, "ms_per_launch": ms},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batch_time_to_residual(pk, count, dev):
+    """FP64, eps 1e-8: the first `count` problems of the batch workload solved together against one
+    solve per problem (same step sizes); diverging problems stop at detection in both."""
+    import torch
+    probs, u0s = batch_problems(pk, torch.float64, count)
+    bs = pk.BatchSolver(probs)
+    u0 = bs.pack_u0(u0s)
+    first = bs.solve(u0, eps=0.0, max_iter=2, check_every=2)
+    taus = [s["tau_u"] for s in first.stats]
+    bs.tune(u0, tau_u=taus, tau_phi=taus)
+    kw = dict(eps=EPS, max_iter=40000, check_every=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = bs.solve(u0, tau_u=taus, tau_phi=taus, **kw)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    singles = [pk.Solver(p) for p in probs]
+    u0d = [torch.tensor(x, dtype=torch.float64, device=dev) for x in u0s]
+    for i, s in enumerate(singles):
+        s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], eps=0.0, max_iter=2, check_every=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for i, s in enumerate(singles):
+        rr = s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], **kw)
+        its.append((rr.stats["status"], rr.stats["iters"]))
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    same = all((st["status"], st["iters"]) == it for st, it in zip(r.stats, its))
+    res = {"problems": count, "dtype": "f64", "eps": EPS, "batched_s": wall_b, "one_solve_per_problem_s": wall_s,
+           "speedup": wall_s / wall_b, "converged": sum(s["status"] == 0 for s in r.stats),
+           "diverged": sum(s["status"] == 2 for s in r.stats), "max_iters": max(s["iters"] for s in r.stats),
+           "same_n_star_as_single": same}
+    log(f"time to residual 1e-8 (FP64, {count} problems): batched {wall_b:.2f} s, one solve per problem "
+        f"{wall_s:.2f} s, {res['converged']} converged, {res['diverged']} diverged, n* identical: {same}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,13 +249,23 @@ def main():
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run exactly this many iterations per solve instead of solving to 1e-8 (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default=None,
+                    help="compute type (default f64 for the single workload, f32 for the batch)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto (fused), 1 unfused, 2 fused")
+    ap.add_argument("--workload", choices=["burgers", "batch"], default="burgers")
+    ap.add_argument("--batch-iters", type=int, default=BATCH_ITERS)
+    ap.add_argument("--ttr-problems", type=int, default=32,
+                    help="batch workload: FP64 time-to-residual comparison on this many problems (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is design-only",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.dtype is None:
+        args.dtype = "f64"
 
     import torch
 

@@ -175,6 +175,82 @@ void pdhg_destroy(pdhg_handle* h);
 const char* pdhg_status_string(int status);
 const char* pdhg_last_error(const pdhg_handle* h);
 
+/* ======================================================================
+ * Batched solver: many independent problems of Section 2.1 (each its own
+ * N_x, N_t, flux, scheme and initial data) advanced together by Algorithm 1,
+ * one kernel launch per pass for the whole batch, the iteration loop replayed
+ * as a HIP graph, and a convergence decision per problem (Section 3.3 stopping
+ * rule) taken on the device; converged problems drop out of the work lists.
+ * Each problem's iterates are those of pdhg_solve with the fused passes (the
+ * same pass bodies); the residual norms can differ in the last bits where the
+ * reduction order differs.
+ *
+ * Packed layouts: problem i occupies
+ *     u0  [u0_off_i, u0_off_i + nx_i)                    its initial data
+ *     u   [u_off_i,  u_off_i + (nt_i+1) nx_i)            as [nt_i+1][nx_i]
+ *     phi [phi_off_i, phi_off_i + nt_i nx_i)             as [nt_i][nx_i]
+ * with offsets (in elements) the exclusive prefix sums in problem order, from
+ * pdhg_batch_offsets.  Limits: every problem has the same dtype, nx a power of
+ * two with 256 <= nx <= 4096, 1 <= nt <= 512.
+ * ==================================================================== */
+typedef struct pdhg_batch pdhg_batch;
+
+typedef struct {
+  const double* tau_u;      /* HOST array [nprob] or NULL; entries <= 0 (or NULL): automatic
+                               per problem, as pdhg_params.tau_u                          */
+  const double* tau_phi;    /* HOST array [nprob] or NULL (as tau_u)                      */
+  double eps;               /* per-problem stopping tolerance, as pdhg_params.eps         */
+  int64_t max_iter;         /* per problem                                                */
+  int32_t check_every;      /* iterations per graph launch between host polls (even)      */
+  int32_t warm_start;       /* as pdhg_params.warm_start                                  */
+  double diverge_factor;    /* as pdhg_params.diverge_factor                              */
+} pdhg_batch_params;
+
+/* Plan a batch of nprob >= 1 problems (host array).  Builds twiddle tables
+ * and the problem table on the current device.  Returns PDHG_EINVAL for an
+ * invalid problem, PDHG_EUNSUPPORTED outside the limits above. */
+int pdhg_batch_setup(const pdhg_problem* probs, int32_t nprob, pdhg_batch** out);
+
+/* Element counts of the packed u0, u and phi arrays, and the workspace bytes
+ * pdhg_batch_solve needs (any pointer may be NULL). */
+int pdhg_batch_sizes(const pdhg_batch* b, int64_t* u0_elems, int64_t* u_elems, int64_t* phi_elems,
+                     size_t* workspace_bytes);
+
+/* Offsets (elements) of problem i in the packed u0, u and phi arrays. */
+int pdhg_batch_offsets(const pdhg_batch* b, int32_t i, int64_t* u0_off, int64_t* u_off, int64_t* phi_off);
+
+/* Solve every problem of the batch (Algorithm 1 per problem, all in the same
+ * launches).  u0, u, phi: packed DEVICE arrays; workspace: DEVICE buffer of
+ * pdhg_batch_sizes() bytes (not NULL).  stats: HOST array [nprob], filled on
+ * return (iters, residuals, step sizes, constants, mass drift, status per
+ * problem; seconds = wall time of the whole batch loop).  Synchronises the
+ * stream.  Returns PDHG_OK when every problem converged, PDHG_DIVERGED when one
+ * diverged, else PDHG_NOT_CONVERGED; or an error. */
+int pdhg_batch_solve(pdhg_batch* b, const void* u0, void* u, void* phi, void* workspace,
+                     const pdhg_batch_params* params, pdhg_stats* stats, pdhg_stream_t stream);
+
+/* Autotuner: times each of the three batched passes on this batch (buffers as
+ * for pdhg_batch_solve; their contents are overwritten) for every candidate
+ * persistent grid size (1, 2, 4, 8 blocks per compute unit up to the occupancy
+ * limit, and one block per tile), keeps the fastest per pass for later solves
+ * of this handle, and returns the three grid sizes in grids[3] (host) if not
+ * NULL.  Without a call, grids default to the occupancy limit. */
+int pdhg_batch_tune(pdhg_batch* b, const void* u0, void* u, void* phi, void* workspace,
+                    const pdhg_batch_params* params, int32_t* grids, pdhg_stream_t stream);
+
+/* Average device time (milliseconds, HIP events on `stream`, one event pair
+ * per launch) of `reps` launches of one batched pass with the current grid
+ * sizes and the buffers of the last pdhg_batch_solve (contents overwritten):
+ * kernel 0 = inverse FFT + dual step, 1 = primal step + residual + forward
+ * FFT, 2 = column solve (a primal pass refills the spectrum before each timed
+ * launch).  Every problem is reset to its initial guess and counts as
+ * running.  PDHG_EINVAL before any solve. */
+int pdhg_batch_time_kernel(pdhg_batch* b, int32_t kernel, int32_t reps, double* ms_per_launch,
+                           pdhg_stream_t stream);
+
+void pdhg_batch_destroy(pdhg_batch* b);
+const char* pdhg_batch_last_error(const pdhg_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

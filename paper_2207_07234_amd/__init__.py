@@ -25,7 +25,8 @@ from typing import Optional
 
 from . import _binding as B
 
-__all__ = ["Problem", "Solver", "SolveResult", "PdhgError", "lib_path", "differentiable_solve"]
+__all__ = ["Problem", "Solver", "SolveResult", "BatchSolver", "BatchResult", "PdhgError", "lib_path",
+           "differentiable_solve"]
 
 lib_path = B.LIB_PATH
 _TIME = {"be": B.PDHG_BE, "bdf2": B.PDHG_BDF2}
@@ -212,6 +213,134 @@ class Solver:
     def close(self):
         if self._h:
             self.lib.pdhg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class BatchResult:
+    u: object                       # packed [sum (nt_i+1) nx_i]
+    phi: object                     # packed [sum nt_i nx_i]
+    status: int                     # worst over the batch (0 all converged)
+    stats: list                     # one dict per problem
+    views_u: list = field(default_factory=list)     # [nt_i+1, nx_i] views into u
+    views_phi: list = field(default_factory=list)   # [nt_i, nx_i] views into phi
+
+
+class BatchSolver:
+    """One plan (pdhg_batch_setup) for a batch of independent problems of one dtype."""
+
+    def __init__(self, probs):
+        import torch
+        self.probs = list(probs)
+        if not self.probs:
+            raise PdhgError("empty batch")
+        self.dtype = self.probs[0].torch_dtype
+        if any(p.torch_dtype != self.dtype for p in self.probs):
+            raise PdhgError("all problems of a batch must have the same dtype")
+        self.lib = B.lib()
+        self._h = C.c_void_p()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        arr = (B.pdhg_problem * len(self.probs))(*[p.to_c() for p in self.probs])
+        rc = self.lib.pdhg_batch_setup(arr, len(self.probs), C.byref(self._h))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_batch_setup failed: {self.lib.pdhg_status_string(rc).decode()} ({rc})")
+        n0, nu, nf, ws = C.c_int64(), C.c_int64(), C.c_int64(), C.c_size_t()
+        self.lib.pdhg_batch_sizes(self._h, C.byref(n0), C.byref(nu), C.byref(nf), C.byref(ws))
+        self.u0_elems, self.u_elems, self.phi_elems, self.workspace_bytes = n0.value, nu.value, nf.value, ws.value
+        self.offsets = []
+        for i in range(len(self.probs)):
+            a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+            self.lib.pdhg_batch_offsets(self._h, i, C.byref(a), C.byref(b), C.byref(c))
+            self.offsets.append((a.value, b.value, c.value))
+        self._ws = None
+
+    def _status(self, rc: int) -> str:
+        s = self.lib.pdhg_status_string(rc).decode()
+        if rc == B.PDHG_EHIP and self._h:
+            s += ": " + self.lib.pdhg_batch_last_error(self._h).decode()
+        return f"{s} ({rc})"
+
+    def pack_u0(self, u0_list):
+        """Concatenate per-problem initial data into the packed u0 layout."""
+        import torch
+        return torch.cat([torch.as_tensor(x, dtype=self.dtype, device=self.device).reshape(-1) for x in u0_list])
+
+    def _views(self, u, phi):
+        vu, vp = [], []
+        for p, (_, ou, of) in zip(self.probs, self.offsets):
+            vu.append(u[ou: ou + (p.nt + 1) * p.nx].view(p.nt + 1, p.nx))
+            vp.append(phi[of: of + p.nt * p.nx].view(p.nt, p.nx))
+        return vu, vp
+
+    def _params(self, tau_u, tau_phi, eps, max_iter, check_every, warm_start, diverge_factor):
+        n = len(self.probs)
+        self._tu = (C.c_double * n)(*([0.0] * n if tau_u is None else [float(x) for x in tau_u]))
+        self._tp = (C.c_double * n)(*([0.0] * n if tau_phi is None else [float(x) for x in tau_phi]))
+        p = B.pdhg_batch_params()
+        p.tau_u = C.cast(self._tu, C.c_void_p)
+        p.tau_phi = C.cast(self._tp, C.c_void_p)
+        p.eps, p.max_iter, p.check_every = float(eps), int(max_iter), int(check_every)
+        p.warm_start, p.diverge_factor = int(bool(warm_start)), float(diverge_factor)
+        return p
+
+    def _buffers(self, u, phi, workspace):
+        import torch
+        if u is None:
+            u = torch.empty(self.u_elems, dtype=self.dtype, device=self.device)
+        if phi is None:
+            phi = torch.empty(self.phi_elems, dtype=self.dtype, device=self.device)
+        for t, n, name in ((u, self.u_elems, "u"), (phi, self.phi_elems, "phi")):
+            if t.dtype != self.dtype or t.device.type != "cuda" or not t.is_contiguous() or t.numel() != n:
+                raise PdhgError(f"{name}: need a contiguous CUDA tensor of {n} {self.dtype} elements")
+        if workspace is None:
+            if self._ws is None:
+                self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            workspace = self._ws
+        return u, phi, workspace
+
+    def solve(self, u0, tau_u=None, tau_phi=None, eps: float = 1e-8, max_iter: int = 10000, check_every: int = 64,
+              u=None, phi=None, warm_start: bool = False, workspace=None, diverge_factor: float = 0.0) -> BatchResult:
+        if u0.dtype != self.dtype or u0.numel() != self.u0_elems or not u0.is_contiguous():
+            raise PdhgError(f"u0: need a contiguous tensor of {self.u0_elems} {self.dtype} elements")
+        u, phi, workspace = self._buffers(u, phi, workspace)
+        p = self._params(tau_u, tau_phi, eps, max_iter, check_every, warm_start, diverge_factor)
+        st = (B.pdhg_stats * len(self.probs))()
+        rc = self.lib.pdhg_batch_solve(self._h, _ptr(u0), _ptr(u), _ptr(phi), _ptr(workspace), C.byref(p), st,
+                                       _stream_ptr(self.device))
+        if rc < 0:
+            raise PdhgError(f"pdhg_batch_solve failed: {self._status(rc)}")
+        stats = [{k: getattr(s, k) for k, _ in B.pdhg_stats._fields_} for s in st]
+        vu, vp = self._views(u, phi)
+        return BatchResult(u, phi, rc, stats, vu, vp)
+
+    def tune(self, u0, tau_u=None, tau_phi=None, u=None, phi=None, workspace=None):
+        """Autotune the persistent grid sizes of the three passes; returns them."""
+        u, phi, workspace = self._buffers(u, phi, workspace)
+        p = self._params(tau_u, tau_phi, 0.0, 1, 64, False, 0.0)
+        grids = (C.c_int32 * 3)()
+        rc = self.lib.pdhg_batch_tune(self._h, _ptr(u0), _ptr(u), _ptr(phi), _ptr(workspace), C.byref(p), grids,
+                                      _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_batch_tune failed: {self._status(rc)}")
+        return list(grids)
+
+    def time_kernel(self, kernel: int, reps: int = 20) -> float:
+        """Milliseconds per launch of batched pass `kernel` (0 A, 1 B, 2 C) on the last solve's buffers."""
+        ms = C.c_double()
+        rc = self.lib.pdhg_batch_time_kernel(self._h, int(kernel), int(reps), C.byref(ms), _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_batch_time_kernel failed: {self._status(rc)}")
+        return ms.value
+
+    def close(self):
+        if self._h:
+            self.lib.pdhg_batch_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

@@ -48,9 +48,19 @@ class pdhg_stats(C.Structure):
     ]
 
 
+class pdhg_batch_params(C.Structure):
+    _fields_ = [
+        ("tau_u", C.c_void_p), ("tau_phi", C.c_void_p), ("eps", C.c_double),
+        ("max_iter", C.c_int64), ("check_every", C.c_int32), ("warm_start", C.c_int32),
+        ("diverge_factor", C.c_double),
+    ]
+
+
 EXPORTED = (
     "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_residual", "pdhg_precond",
     "pdhg_adjoint", "pdhg_time_kernel", "pdhg_destroy", "pdhg_status_string", "pdhg_last_error",
+    "pdhg_batch_setup", "pdhg_batch_sizes", "pdhg_batch_offsets", "pdhg_batch_solve", "pdhg_batch_tune",
+    "pdhg_batch_time_kernel", "pdhg_batch_destroy", "pdhg_batch_last_error",
 )
 
 
@@ -82,6 +92,23 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pdhg_status_string.restype = C.c_char_p
     lib.pdhg_last_error.argtypes = [H]
     lib.pdhg_last_error.restype = C.c_char_p
+    i64p = C.POINTER(C.c_int64)
+    lib.pdhg_batch_setup.argtypes = [C.POINTER(pdhg_problem), C.c_int32, C.POINTER(H)]
+    lib.pdhg_batch_setup.restype = C.c_int
+    lib.pdhg_batch_sizes.argtypes = [H, i64p, i64p, i64p, C.POINTER(C.c_size_t)]
+    lib.pdhg_batch_sizes.restype = C.c_int
+    lib.pdhg_batch_offsets.argtypes = [H, C.c_int32, i64p, i64p, i64p]
+    lib.pdhg_batch_offsets.restype = C.c_int
+    lib.pdhg_batch_solve.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_batch_params), C.POINTER(pdhg_stats), vp]
+    lib.pdhg_batch_solve.restype = C.c_int
+    lib.pdhg_batch_tune.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_batch_params), C.POINTER(C.c_int32), vp]
+    lib.pdhg_batch_tune.restype = C.c_int
+    lib.pdhg_batch_time_kernel.argtypes = [H, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+    lib.pdhg_batch_time_kernel.restype = C.c_int
+    lib.pdhg_batch_destroy.argtypes = [H]
+    lib.pdhg_batch_destroy.restype = None
+    lib.pdhg_batch_last_error.argtypes = [H]
+    lib.pdhg_batch_last_error.restype = C.c_char_p
     return lib
 
 

@@ -1,0 +1,684 @@
+// Host runtime of the batched solver (C ABI pdhg_batch_*).
+//
+// Set-up packs the problems (offsets, problem table, twiddles per distinct
+// N_x, tile orders).  A solve resolves each problem's flux constants from its
+// u0 (one launch for the batch), builds the per-problem preconditioner factor
+// tables on the host threads, estimates step sizes where none are given (the
+// single-problem power iteration), then replays a captured HIP graph of
+// `check_every` iterations (three batched passes per iteration, then the
+// work-list rebuild) until no problem is left running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pdhg.h"
+#include "pdhg_internal.hpp"
+
+using namespace pdhg;
+
+namespace {
+constexpr size_t kAlignB = 256;
+inline size_t align_b(size_t x) { return (x + kAlignB - 1) & ~(kAlignB - 1); }
+}  // namespace
+
+struct pdhg_batch {
+  int nprob = 0, dtype = 0, device = 0, ncu = 0;
+  size_t esz = 8;
+  std::vector<pdhg_problem> probs;
+  std::vector<BatchProb> table;
+  std::vector<int64_t> u0_off, u_off, f_off;
+  int64_t u0_elems = 0, u_elems = 0, f_elems = 0;
+  int total_pairs = 0, total_rtiles = 0, total_colg = 0, max_nx = 0;
+  // device
+  BatchProb* d_probs = nullptr;
+  Ctrl* d_ctrls = nullptr;
+  int2* d_row_tiles = nullptr;
+  int2* d_col_tiles = nullptr;
+  int* d_counts = nullptr;
+  int* d_order = nullptr;
+  int* d_corder = nullptr;
+  double* d_part = nullptr;
+  double* d_scal = nullptr;
+  std::map<int, void*> d_tw;
+  void* d_fac_rows = nullptr;
+  int* d_fac_off = nullptr;
+  int* d_fac_last = nullptr;
+  std::vector<double> fac_c, fac_g;   // constants the current factor tables were built with
+  std::vector<double> lf, c;
+  // host staging (pinned)
+  Ctrl* h_ctrls = nullptr;
+  int* h_counts = nullptr;            // 2 slots of 4
+  double* h_scal = nullptr;           // nprob
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  // persistent grid sizes of the passes A, B, C
+  int grid[3] = {0, 0, 0};
+  // graph cache
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  const void* gk_u = nullptr;
+  const void* gk_phi = nullptr;
+  const void* gk_ws = nullptr;
+  int gk_chunk = 0, gk_grid[3] = {0, 0, 0};
+  // buffers of the last solve (kernel timing)
+  const void* last_u0 = nullptr;
+  void* last_u = nullptr;
+  void* last_phi = nullptr;
+  void* last_ws = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int bset_hip_error(pdhg_batch* b, hipError_t e, const char* what) {
+  if (b) b->err = std::string(what) + ": " + hipGetErrorString(e);
+  return PDHG_EHIP;
+}
+
+#define BHIP_TRY(expr)                                         \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return bset_hip_error(b, e_, #expr); \
+  } while (0)
+
+bool is_pow2_b(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+struct BatchWs {
+  size_t u_alt, phibar, spec, total;
+};
+
+BatchWs batch_ws(const pdhg_batch* b) {
+  BatchWs L{};
+  size_t o = 0;
+  L.u_alt = o; o += align_b((size_t)b->u_elems * b->esz);
+  L.phibar = o; o += align_b((size_t)b->f_elems * b->esz);
+  L.spec = o; o += align_b((size_t)b->f_elems * b->esz);
+  L.total = o;
+  return L;
+}
+
+BatchLaunch launch_of(const pdhg_batch* b) {
+  BatchLaunch L{};
+  L.probs = b->d_probs;
+  L.ctrls = b->d_ctrls;
+  L.row_tiles = b->d_row_tiles;
+  L.col_tiles = b->d_col_tiles;
+  L.counts = b->d_counts;
+  L.order = b->d_order;
+  L.corder = b->d_corder;
+  L.nprob = b->nprob;
+  L.max_nx = b->max_nx;
+  return L;
+}
+
+template <typename T>
+int upload_twiddles_b(pdhg_batch* b, int n) {
+  std::vector<C2<T>> tw(n);
+  const long double PI = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    const long double a = -2.0L * PI * i / n;
+    tw[i] = C2<T>{(T)cosl(a), (T)sinl(a)};
+  }
+  void* d = nullptr;
+  BHIP_TRY(hipMalloc(&d, n * sizeof(C2<T>)));
+  b->d_tw[n] = d;
+  BHIP_TRY(hipMemcpy(d, tw.data(), n * sizeof(C2<T>), hipMemcpyHostToDevice));
+  return PDHG_OK;
+}
+
+template <typename T>
+int setup_impl(pdhg_batch* b) {
+  const int P = b->nprob;
+  const int TB = batch_row_block_threads<T>();
+  b->table.assign(P, BatchProb{});
+  b->u0_off.resize(P);
+  b->u_off.resize(P);
+  b->f_off.resize(P);
+  int64_t o0 = 0, ou = 0, of = 0;
+  int pairs = 0, rt = 0, cg = 0;
+  for (int i = 0; i < P; ++i) {
+    const pdhg_problem& p = b->probs[i];
+    BatchProb& q = b->table[i];
+    q.s.nx = p.nx;
+    q.s.nt = p.nt;
+    q.s.time = p.time;
+    q.s.space = p.space;
+    q.s.ht = p.t_final / p.nt;
+    q.s.hx = p.length / p.nx;
+    q.s.alpha = p.alpha;
+    q.s.beta = p.beta;
+    q.s.gamma = p.gamma;
+    q.s.lf = 0.0;
+    b->u0_off[i] = o0;
+    b->u_off[i] = ou;
+    b->f_off[i] = of;
+    q.u0_off = o0;
+    q.u_off = ou;
+    q.f_off = of;
+    o0 += p.nx;
+    ou += (int64_t)(p.nt + 1) * p.nx;
+    of += (int64_t)p.nt * p.nx;
+    int lqb = 0;
+    while ((1 << (lqb + 1)) <= std::min(16, p.nx)) ++lqb;
+    q.lqb = lqb;
+    q.wscale = q.s.ht * q.s.hx;
+    q.npairs = (p.nt + 1) / 2;
+    q.part_off = pairs;
+    pairs += q.npairs;
+    const int W = batch_row_width<T>(p.nx);
+    q.pairs_per_tile = TB / W;
+    q.rtiles = (q.npairs + q.pairs_per_tile - 1) / q.pairs_per_tile;
+    rt += q.rtiles;
+    q.ncolg = p.nx / 8;
+    cg += q.ncolg;
+    b->max_nx = std::max(b->max_nx, p.nx);
+  }
+  b->u0_elems = o0;
+  b->u_elems = ou;
+  b->f_elems = of;
+  b->total_pairs = pairs;
+  b->total_rtiles = rt;
+  b->total_colg = cg;
+  for (int i = 0; i < P; ++i) {
+    const int n = b->probs[i].nx;
+    if (!b->d_tw.count(n)) {
+      int rc = upload_twiddles_b<T>(b, n);
+      if (rc) return rc;
+    }
+    b->table[i].tw = b->d_tw[n];
+  }
+  // tile orders: rows in problem order; columns by decreasing nt (stable)
+  std::vector<int> order(P), corder(P);
+  for (int i = 0; i < P; ++i) order[i] = corder[i] = i;
+  std::stable_sort(corder.begin(), corder.end(),
+                   [&](int x, int y) { return b->probs[x].nt > b->probs[y].nt; });
+  BHIP_TRY(hipMalloc((void**)&b->d_probs, sizeof(BatchProb) * P));
+  BHIP_TRY(hipMalloc((void**)&b->d_ctrls, sizeof(Ctrl) * P));
+  BHIP_TRY(hipMalloc((void**)&b->d_row_tiles, sizeof(int2) * std::max(rt, 1)));
+  BHIP_TRY(hipMalloc((void**)&b->d_col_tiles, sizeof(int2) * std::max(cg, 1)));
+  BHIP_TRY(hipMalloc((void**)&b->d_counts, sizeof(int) * 4));
+  BHIP_TRY(hipMalloc((void**)&b->d_order, sizeof(int) * P));
+  BHIP_TRY(hipMalloc((void**)&b->d_corder, sizeof(int) * P));
+  BHIP_TRY(hipMalloc((void**)&b->d_part, sizeof(double) * 2 * std::max(pairs, 1)));
+  BHIP_TRY(hipMalloc((void**)&b->d_scal, sizeof(double) * P));
+  BHIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int) * P, hipMemcpyHostToDevice));
+  BHIP_TRY(hipMemcpy(b->d_corder, corder.data(), sizeof(int) * P, hipMemcpyHostToDevice));
+  BHIP_TRY(hipMemcpy(b->d_probs, b->table.data(), sizeof(BatchProb) * P, hipMemcpyHostToDevice));
+  BHIP_TRY(hipHostMalloc((void**)&b->h_ctrls, sizeof(Ctrl) * P, hipHostMallocDefault));
+  BHIP_TRY(hipHostMalloc((void**)&b->h_counts, sizeof(int) * 8, hipHostMallocDefault));
+  BHIP_TRY(hipHostMalloc((void**)&b->h_scal, sizeof(double) * P, hipHostMallocDefault));
+  for (int i = 0; i < 2; ++i) BHIP_TRY(hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming));
+  BHIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  BHIP_TRY(hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device));
+  for (int k = 0; k < 3; ++k) {
+    int occ = 1;
+    BHIP_TRY(batch_occupancy<T>(k, b->max_nx, &occ));
+    b->grid[k] = std::max(1, occ) * b->ncu;
+  }
+  b->fac_c.assign(P, -1.0);
+  b->fac_g.assign(P, -1.0);
+  b->lf.assign(P, 0.0);
+  b->c.assign(P, 0.0);
+  return PDHG_OK;
+}
+
+// Factor tables of every problem (host threads), pooled into one allocation.
+template <typename T>
+int build_factors_b(pdhg_batch* b) {
+  const int P = b->nprob;
+  std::vector<std::vector<FacRow<T>>> rows(P);
+  std::vector<std::vector<int>> off(P), last(P);
+  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nth; ++t) {
+    pool.emplace_back([&, t]() {
+      for (int i = (int)t; i < P; i += (int)nth)
+        build_factor_rows<T>(b->probs[i], b->c[i], b->probs[i].precond_gamma_hat, rows[i], off[i], last[i]);
+    });
+  }
+  for (auto& th : pool) th.join();
+  size_t nrows = 0, nmodes = 0;
+  for (int i = 0; i < P; ++i) {
+    nrows += rows[i].size();
+    nmodes += off[i].size();
+  }
+  std::vector<FacRow<T>> all_rows;
+  std::vector<int> all_off, all_last;
+  all_rows.reserve(nrows);
+  all_off.reserve(nmodes);
+  all_last.reserve(nmodes);
+  std::vector<size_t> rbase(P), mbase(P);
+  for (int i = 0; i < P; ++i) {
+    rbase[i] = all_rows.size();
+    mbase[i] = all_off.size();
+    all_rows.insert(all_rows.end(), rows[i].begin(), rows[i].end());
+    all_off.insert(all_off.end(), off[i].begin(), off[i].end());
+    all_last.insert(all_last.end(), last[i].begin(), last[i].end());
+  }
+  if (b->d_fac_rows) hipFree(b->d_fac_rows);
+  if (b->d_fac_off) hipFree(b->d_fac_off);
+  if (b->d_fac_last) hipFree(b->d_fac_last);
+  b->d_fac_rows = nullptr;
+  b->d_fac_off = b->d_fac_last = nullptr;
+  BHIP_TRY(hipMalloc(&b->d_fac_rows, all_rows.size() * sizeof(FacRow<T>)));
+  BHIP_TRY(hipMalloc((void**)&b->d_fac_off, all_off.size() * sizeof(int)));
+  BHIP_TRY(hipMalloc((void**)&b->d_fac_last, all_last.size() * sizeof(int)));
+  BHIP_TRY(hipMemcpy(b->d_fac_rows, all_rows.data(), all_rows.size() * sizeof(FacRow<T>), hipMemcpyHostToDevice));
+  BHIP_TRY(hipMemcpy(b->d_fac_off, all_off.data(), all_off.size() * sizeof(int), hipMemcpyHostToDevice));
+  BHIP_TRY(hipMemcpy(b->d_fac_last, all_last.data(), all_last.size() * sizeof(int), hipMemcpyHostToDevice));
+  for (int i = 0; i < P; ++i) {
+    b->table[i].fac_rows = static_cast<const FacRow<T>*>(b->d_fac_rows) + rbase[i];
+    b->table[i].fac_off = b->d_fac_off + mbase[i];
+    b->table[i].fac_last = b->d_fac_last + mbase[i];
+    b->fac_c[i] = b->c[i];
+    b->fac_g[i] = b->probs[i].precond_gamma_hat;
+  }
+  return PDHG_OK;
+}
+
+// Constants, factor tables and step sizes of every problem; uploads the table.
+// nu[i] receives the power-iteration estimate (0 where steps were given).
+template <typename T>
+int prepare(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batch_params* prm, std::vector<double>& tau_u,
+            std::vector<double>& tau_phi, std::vector<double>& nu, hipStream_t st) {
+  const int P = b->nprob;
+  const BatchLaunch L = launch_of(b);
+  BHIP_TRY(launch_batch_maxabs_dflux<T>(L, u0, b->d_scal, st));
+  BHIP_TRY(hipMemcpyAsync(b->h_scal, b->d_scal, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+  bool refactor = b->d_fac_rows == nullptr;
+  for (int i = 0; i < P; ++i) {
+    const pdhg_problem& p = b->probs[i];
+    const double m = b->h_scal[i];
+    double lf = p.lf_speed < 0.0 ? m : p.lf_speed;
+    if (p.space != PDHG_FD_LF) lf = 0.0;
+    const double c = p.precond_c < 0.0 ? m : p.precond_c;
+    b->lf[i] = lf;
+    b->c[i] = c;
+    b->table[i].s.lf = lf;
+    if (b->fac_c[i] != c || b->fac_g[i] != p.precond_gamma_hat) refactor = true;
+  }
+  if (refactor) {
+    int rc = build_factors_b<T>(b);
+    if (rc) return rc;
+  }
+  tau_u.assign(P, 0.0);
+  tau_phi.assign(P, 0.0);
+  nu.assign(P, 0.0);
+  for (int i = 0; i < P; ++i) {
+    const double tu = prm->tau_u ? prm->tau_u[i] : 0.0;
+    const double tp = prm->tau_phi ? prm->tau_phi[i] : 0.0;
+    if (tu > 0.0 && tp > 0.0) {
+      tau_u[i] = tu;
+      tau_phi[i] = tp;
+      continue;
+    }
+    // the single-problem power iteration on this problem's slices
+    pdhg_problem q = b->probs[i];
+    q.lf_speed = b->lf[i];
+    q.precond_c = b->c[i];
+    pdhg_handle* h = nullptr;
+    int rc = pdhg_setup(&q, &h);
+    if (rc) return rc;
+    pdhg_params sp{};
+    sp.max_iter = 0;        // set-up and power iteration only
+    sp.check_every = 2;
+    sp.warm_start = 1;      // leaves the caller's u (levels >= 1) and phi untouched
+    pdhg_stats ss{};
+    rc = pdhg_solve(h, u0 + b->u0_off[i], u + b->u_off[i], phi + b->f_off[i], nullptr, &sp, &ss, st);
+    if (rc < 0) {
+      b->err = std::string("step-size estimate of problem ") + std::to_string(i) + ": " + pdhg_last_error(h);
+      pdhg_destroy(h);
+      return rc;
+    }
+    pdhg_destroy(h);
+    tau_u[i] = ss.tau_u;
+    tau_phi[i] = ss.tau_phi;
+    nu[i] = ss.nu_max;
+  }
+  for (int i = 0; i < P; ++i) {
+    b->table[i].tau_u = tau_u[i];
+    b->table[i].tau_phi = tau_phi[i];
+  }
+  BHIP_TRY(hipMemcpyAsync(b->d_probs, b->table.data(), sizeof(BatchProb) * P, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+  return PDHG_OK;
+}
+
+inline char* bws(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+// One iteration of every running problem: A, B, C.  `odd` selects the u
+// ping-pong direction (odd iterations read u and write u_alt).
+template <typename T>
+int enqueue_batch_body(pdhg_batch* b, bool odd, T* u, T* phi, void* ws, hipStream_t st) {
+  const BatchWs W = batch_ws(b);
+  const BatchLaunch L = launch_of(b);
+  T* u_alt = (T*)bws(ws, W.u_alt);
+  T* phibar = (T*)bws(ws, W.phibar);
+  T* spec = (T*)bws(ws, W.spec);
+  T* uin = odd ? u : u_alt;
+  T* uout = odd ? u_alt : u;
+  BHIP_TRY(launch_batch_dual_fft<T>(L, b->grid[0], spec, phi, phibar, st));
+  BHIP_TRY(launch_batch_primal_res<T>(L, b->grid[1], uin, uout, phibar, phi, spec, b->d_part, b->total_pairs, st));
+  BHIP_TRY(launch_batch_colsolve<T>(L, b->grid[2], spec, b->d_part, b->total_pairs, st));
+  return PDHG_OK;
+}
+
+template <typename T>
+int build_batch_graph(pdhg_batch* b, int chunk, T* u, T* phi, void* ws) {
+  if (b->gexec && b->gk_u == u && b->gk_phi == phi && b->gk_ws == ws && b->gk_chunk == chunk &&
+      std::equal(b->grid, b->grid + 3, b->gk_grid))
+    return PDHG_OK;
+  if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  BHIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = PDHG_OK;
+  for (int k = 0; k < chunk && rc == PDHG_OK; ++k) rc = enqueue_batch_body<T>(b, (k % 2) == 0, u, phi, ws, b->cap_stream);
+  if (rc == PDHG_OK) {
+    hipError_t e = launch_batch_compact(launch_of(b), b->cap_stream);
+    if (e != hipSuccess) rc = bset_hip_error(b, e, "launch_batch_compact");
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc) { if (g) hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return bset_hip_error(b, e, "hipStreamEndCapture");
+  b->graph = g;
+  BHIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+  b->gk_u = u;
+  b->gk_phi = phi;
+  b->gk_ws = ws;
+  b->gk_chunk = chunk;
+  std::copy(b->grid, b->grid + 3, b->gk_grid);
+  return PDHG_OK;
+}
+
+template <typename T>
+int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const pdhg_batch_params* prm,
+                     pdhg_stats* stats, hipStream_t st) {
+  const int P = b->nprob;
+  std::vector<double> tau_u, tau_phi, nu;
+  int rc = prepare<T>(b, u0, u, phi, prm, tau_u, tau_phi, nu, st);
+  if (rc) return rc;
+  const BatchWs W = batch_ws(b);
+  const BatchLaunch L = launch_of(b);
+  T* u_alt = (T*)bws(ws, W.u_alt);
+  T* spec = (T*)bws(ws, W.spec);
+  const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
+  BHIP_TRY(launch_batch_init<T>(L, u0, u, u_alt, phi, spec, prm->warm_start ? 1 : 0, (long long)prm->max_iter,
+                                prm->eps, div, st));
+  BHIP_TRY(launch_batch_compact(L, st));
+  int chunk = prm->check_every > 0 ? prm->check_every : 64;
+  chunk += chunk & 1;   // even: the u ping-pong returns to its start buffer
+  b->last_u0 = u0;
+  b->last_u = u;
+  b->last_phi = phi;
+  b->last_ws = ws;
+  auto t0 = std::chrono::steady_clock::now();
+  if (prm->max_iter > 0) {
+    rc = build_batch_graph<T>(b, chunk, u, phi, ws);
+    if (rc) return rc;
+    const long long bodies = prm->max_iter + 1;
+    long long launched = 0;
+    int idx = 0;
+    bool stop = false;
+    while (!stop && launched < bodies) {
+      BHIP_TRY(hipGraphLaunch(b->gexec, st));
+      launched += chunk;
+      int* slot = b->h_counts + 4 * (idx & 1);
+      BHIP_TRY(hipMemcpyAsync(slot, b->d_counts, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+      BHIP_TRY(hipEventRecord(b->ev[idx & 1], st));
+      if (idx >= 1) {
+        BHIP_TRY(hipEventSynchronize(b->ev[(idx - 1) & 1]));
+        if (b->h_counts[4 * ((idx - 1) & 1) + 2] == 0) stop = true;
+      }
+      ++idx;
+    }
+  }
+  BHIP_TRY(launch_batch_finish<T>(L, u, u_alt, b->d_scal, st));
+  BHIP_TRY(hipMemcpyAsync(b->h_ctrls, b->d_ctrls, sizeof(Ctrl) * P, hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipMemcpyAsync(b->h_scal, b->d_scal, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  const double secs = std::chrono::duration<double>(t1 - t0).count();
+  int worst = PDHG_OK;
+  for (int i = 0; i < P; ++i) {
+    const Ctrl& c = b->h_ctrls[i];
+    int status;
+    long long nstar = c.n_star;
+    if (prm->max_iter <= 0) { nstar = 0; status = PDHG_NOT_CONVERGED; }
+    else if (c.status == 1) status = PDHG_OK;
+    else if (c.status == 2) status = PDHG_DIVERGED;
+    else status = PDHG_NOT_CONVERGED;
+    if (status == PDHG_DIVERGED) worst = PDHG_DIVERGED;
+    else if (status == PDHG_NOT_CONVERGED && worst == PDHG_OK) worst = PDHG_NOT_CONVERGED;
+    if (stats) {
+      pdhg_stats& s = stats[i];
+      s.iters = nstar;
+      s.res_primal = c.rp_star;
+      s.res_dual = c.rd_star;
+      s.tau_u = tau_u[i];
+      s.tau_phi = tau_phi[i];
+      s.nu_max = nu[i];
+      s.lf_speed = b->lf[i];
+      s.precond_c = b->c[i];
+      s.seconds = secs;
+      s.mass_drift = b->h_scal[i];
+      s.status = status;
+      s.variant = 3;
+    }
+  }
+  return worst;
+}
+
+// Average device time of one launch of pass k with `grid` blocks (events per
+// launch; for the column pass a primal pass refills the spectrum before each
+// timed launch).
+template <typename T>
+int time_pass(pdhg_batch* b, int k, int grid, T* u, T* phi, void* ws, hipStream_t st, double* ms, int reps = 8) {
+  const BatchWs W = batch_ws(b);
+  const BatchLaunch L = launch_of(b);
+  T* u_alt = (T*)bws(ws, W.u_alt);
+  T* phibar = (T*)bws(ws, W.phibar);
+  T* spec = (T*)bws(ws, W.spec);
+  hipEvent_t e0, e1;
+  BHIP_TRY(hipEventCreate(&e0));
+  BHIP_TRY(hipEventCreate(&e1));
+  double total = 0.0;
+  const int warm = 2;
+  for (int r = 0; r < warm + reps; ++r) {
+    if (k == 2)
+      BHIP_TRY(launch_batch_primal_res<T>(L, b->grid[1], u, u_alt, phibar, phi, spec, b->d_part, b->total_pairs, st));
+    BHIP_TRY(hipEventRecord(e0, st));
+    if (k == 0) BHIP_TRY(launch_batch_dual_fft<T>(L, grid, spec, phi, phibar, st));
+    else if (k == 1)
+      BHIP_TRY(launch_batch_primal_res<T>(L, grid, u, u_alt, phibar, phi, spec, b->d_part, b->total_pairs, st));
+    else BHIP_TRY(launch_batch_colsolve<T>(L, grid, spec, b->d_part, b->total_pairs, st));
+    BHIP_TRY(hipEventRecord(e1, st));
+    BHIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    BHIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    if (r >= warm) total += t;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = total / reps;
+  return PDHG_OK;
+}
+
+template <typename T>
+int batch_tune_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const pdhg_batch_params* prm, int32_t* out,
+                    hipStream_t st) {
+  std::vector<double> tau_u, tau_phi, nu;
+  int rc = prepare<T>(b, u0, u, phi, prm, tau_u, tau_phi, nu, st);
+  if (rc) return rc;
+  const BatchWs W = batch_ws(b);
+  const BatchLaunch L = launch_of(b);
+  // the control blocks stay "running" during timing: huge max_iter, no tolerance
+  BHIP_TRY(launch_batch_init<T>(L, u0, u, (T*)bws(ws, W.u_alt), phi, (T*)bws(ws, W.spec), 0, 1ll << 60, 0.0, 1e300,
+                                st));
+  BHIP_TRY(launch_batch_compact(L, st));
+  const int ntiles[3] = {b->total_rtiles, b->total_rtiles, b->total_colg};
+  for (int k = 0; k < 3; ++k) {
+    int occ = 1;
+    BHIP_TRY(batch_occupancy<T>(k, b->max_nx, &occ));
+    occ = std::max(occ, 1);
+    std::vector<int> cand;
+    for (int m : {1, 2, 4, 8})
+      if (m <= occ) cand.push_back(m * b->ncu);
+    cand.push_back(ntiles[k]);
+    double best = 1e300;
+    int best_g = b->grid[k];
+    for (int g : cand) {
+      if (g < 1) continue;
+      double ms = 0.0;
+      rc = time_pass<T>(b, k, g, u, phi, ws, st, &ms);
+      if (rc) return rc;
+      if (ms < best) { best = ms; best_g = g; }
+    }
+    b->grid[k] = best_g;
+  }
+  if (out)
+    for (int k = 0; k < 3; ++k) out[k] = b->grid[k];
+  return PDHG_OK;
+}
+
+// Time pass k on the last solve's buffers, every problem running again.
+template <typename T>
+int time_kernel_b(pdhg_batch* b, int k, int reps, double* ms, hipStream_t st) {
+  const BatchWs W = batch_ws(b);
+  void* ws = b->last_ws;
+  T* u = (T*)b->last_u;
+  BHIP_TRY(launch_batch_init<T>(launch_of(b), (const T*)b->last_u0, u, (T*)bws(ws, W.u_alt), (T*)b->last_phi,
+                                (T*)bws(ws, W.spec), 0, 1ll << 60, 0.0, 1e300, st));
+  BHIP_TRY(launch_batch_compact(launch_of(b), st));
+  return time_pass<T>(b, k, b->grid[k], u, (T*)b->last_phi, ws, st, ms, reps);
+}
+
+int validate_batch_problem(const pdhg_problem& p, int dtype) {
+  if (!is_pow2_b(p.nx) || p.nt < 1) return PDHG_EINVAL;
+  if (!(p.length > 0) || !(p.t_final > 0) || p.gamma < 0 || p.precond_gamma_hat < 0) return PDHG_EINVAL;
+  if (p.time != PDHG_BE && p.time != PDHG_BDF2) return PDHG_EINVAL;
+  if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF) return PDHG_EINVAL;
+  if (p.dtype != PDHG_F32 && p.dtype != PDHG_F64) return PDHG_EINVAL;
+  if (p.dtype != dtype) return PDHG_EINVAL;
+  if (p.nx < 256 || p.nx > 4096 || p.nt > 512) return PDHG_EUNSUPPORTED;
+  return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_batch_setup(const pdhg_problem* probs, int32_t nprob, pdhg_batch** out) {
+  if (!probs || !out || nprob < 1) return PDHG_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < nprob; ++i) {
+    const int rc = validate_batch_problem(probs[i], probs[0].dtype);
+    if (rc) return rc;
+  }
+  pdhg_batch* b = new (std::nothrow) pdhg_batch();
+  if (!b) return PDHG_EINVAL;
+  b->nprob = nprob;
+  b->dtype = probs[0].dtype;
+  b->esz = b->dtype == PDHG_F64 ? 8 : 4;
+  b->probs.assign(probs, probs + nprob);
+  int rc = PDHG_OK;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) rc = bset_hip_error(b, e, "hipGetDevice");
+  if (!rc) rc = b->dtype == PDHG_F64 ? setup_impl<double>(b) : setup_impl<float>(b);
+  if (rc) {
+    pdhg_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return PDHG_OK;
+}
+
+int pdhg_batch_sizes(const pdhg_batch* b, int64_t* u0_elems, int64_t* u_elems, int64_t* phi_elems,
+                     size_t* workspace_bytes) {
+  if (!b) return PDHG_EINVAL;
+  if (u0_elems) *u0_elems = b->u0_elems;
+  if (u_elems) *u_elems = b->u_elems;
+  if (phi_elems) *phi_elems = b->f_elems;
+  if (workspace_bytes) *workspace_bytes = batch_ws(b).total;
+  return PDHG_OK;
+}
+
+int pdhg_batch_offsets(const pdhg_batch* b, int32_t i, int64_t* u0_off, int64_t* u_off, int64_t* phi_off) {
+  if (!b || i < 0 || i >= b->nprob) return PDHG_EINVAL;
+  if (u0_off) *u0_off = b->u0_off[i];
+  if (u_off) *u_off = b->u_off[i];
+  if (phi_off) *phi_off = b->f_off[i];
+  return PDHG_OK;
+}
+
+int pdhg_batch_solve(pdhg_batch* b, const void* u0, void* u, void* phi, void* workspace,
+                     const pdhg_batch_params* params, pdhg_stats* stats, pdhg_stream_t stream) {
+  if (!b || !u0 || !u || !phi || !workspace || !params || params->max_iter < 0) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return bset_hip_error(b, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (b->dtype == PDHG_F64)
+    return batch_solve_impl<double>(b, (const double*)u0, (double*)u, (double*)phi, workspace, params, stats, st);
+  return batch_solve_impl<float>(b, (const float*)u0, (float*)u, (float*)phi, workspace, params, stats, st);
+}
+
+int pdhg_batch_tune(pdhg_batch* b, const void* u0, void* u, void* phi, void* workspace,
+                    const pdhg_batch_params* params, int32_t* grids, pdhg_stream_t stream) {
+  if (!b || !u0 || !u || !phi || !workspace || !params) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return bset_hip_error(b, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (b->dtype == PDHG_F64)
+    return batch_tune_impl<double>(b, (const double*)u0, (double*)u, (double*)phi, workspace, params, grids, st);
+  return batch_tune_impl<float>(b, (const float*)u0, (float*)u, (float*)phi, workspace, params, grids, st);
+}
+
+void pdhg_batch_destroy(pdhg_batch* b) {
+  if (!b) return;
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (auto& kv : b->d_tw) hipFree(kv.second);
+  if (b->d_fac_rows) hipFree(b->d_fac_rows);
+  if (b->d_fac_off) hipFree(b->d_fac_off);
+  if (b->d_fac_last) hipFree(b->d_fac_last);
+  if (b->d_probs) hipFree(b->d_probs);
+  if (b->d_ctrls) hipFree(b->d_ctrls);
+  if (b->d_row_tiles) hipFree(b->d_row_tiles);
+  if (b->d_col_tiles) hipFree(b->d_col_tiles);
+  if (b->d_counts) hipFree(b->d_counts);
+  if (b->d_order) hipFree(b->d_order);
+  if (b->d_corder) hipFree(b->d_corder);
+  if (b->d_part) hipFree(b->d_part);
+  if (b->d_scal) hipFree(b->d_scal);
+  if (b->h_ctrls) hipHostFree(b->h_ctrls);
+  if (b->h_counts) hipHostFree(b->h_counts);
+  if (b->h_scal) hipHostFree(b->h_scal);
+  for (int i = 0; i < 2; ++i)
+    if (b->ev[i]) hipEventDestroy(b->ev[i]);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  delete b;
+}
+
+int pdhg_batch_time_kernel(pdhg_batch* b, int32_t kernel, int32_t reps, double* ms_per_launch,
+                           pdhg_stream_t stream) {
+  if (!b || !ms_per_launch || kernel < 0 || kernel > 2 || reps < 1) return PDHG_EINVAL;
+  if (!b->last_ws) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return bset_hip_error(b, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (b->dtype == PDHG_F64) return time_kernel_b<double>(b, kernel, reps, ms_per_launch, st);
+  return time_kernel_b<float>(b, kernel, reps, ms_per_launch, st);
+}
+
+const char* pdhg_batch_last_error(const pdhg_batch* b) { return b ? b->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,6 +1,9 @@
 // Declarations shared by the kernel translation units and the host runtime.
 #pragma once
 
+#include <vector>
+
+#include "pdhg.h"
 #include "pdhg_device.hpp"
 
 namespace pdhg {
@@ -66,4 +69,74 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
 namespace pdhg {
 template <typename T>
 hipError_t launch_level_sums(const T* u, int nx, int levels, double* out, hipStream_t st);
+}  // namespace pdhg
+
+namespace pdhg {
+
+// One problem of a batch (device table entry; filled on the host).
+struct BatchProb {
+  Scheme s;                  // grid, scheme and resolved flux constants
+  long long u_off;           // element offset of u ([nt+1][nx]) in the packed u and u_alt
+  long long f_off;           // element offset of phi, phibar and the spectrum ([nt][nx])
+  long long u0_off;          // element offset of u0 ([nx])
+  const void* tw;            // twiddles w_nx^i, i < nx (C2<T>)
+  const void* fac_rows;      // preconditioner factor table of this problem (FacRow<T>)
+  const int* fac_off;
+  const int* fac_last;
+  double tau_u, tau_phi, wscale;
+  int lqb;                   // log2 of the spectrum column-block width
+  int part_off;              // first partial-sum slot (one per row pair)
+  int npairs;                // (nt + 1) / 2 row pairs
+  int pairs_per_tile;        // S: row pairs per row tile
+  int rtiles;                // ceil(npairs / S)
+  int ncolg;                 // nx / 8 column groups
+};
+
+// Device pointers shared by the batched launches.
+struct BatchLaunch {
+  const BatchProb* probs;
+  Ctrl* ctrls;
+  int2* row_tiles;
+  int2* col_tiles;
+  int* counts;               // {row tiles, column tiles, active problems}
+  const int* order;          // problem order of the row tiles
+  const int* corder;         // problem order of the column tiles (decreasing nt)
+  int nprob, max_nx;
+};
+
+template <typename T>
+int batch_row_block_threads();
+template <typename T>
+int batch_row_width(int nx);
+template <typename T>
+size_t batch_row_lds(int max_nx);
+template <typename T>
+size_t batch_col_lds();
+template <typename T>
+hipError_t batch_occupancy(int which, int max_nx, int* blocks_per_cu);
+template <typename T>
+hipError_t launch_batch_dual_fft(const BatchLaunch& L, int grid, T* spec, T* phi, T* phibar, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_primal_res(const BatchLaunch& L, int grid, const T* u_in, T* u_out, const T* phibar,
+                                   const T* phi, T* spec, double* part, int rd_base, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_colsolve(const BatchLaunch& L, int grid, T* spec, const double* part, int rd_base,
+                                 hipStream_t st);
+hipError_t launch_batch_compact(const BatchLaunch& L, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_maxabs_dflux(const BatchLaunch& L, const T* u0, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_init(const BatchLaunch& L, const T* u0, T* u, T* u_alt, T* phi, T* spec, int warm,
+                             long long max_iter, double eps, double div_factor, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_finish(const BatchLaunch& L, T* u, const T* u_alt, double* drift, hipStream_t st);
+
+}  // namespace pdhg
+
+namespace pdhg {
+// Host: banded Cholesky factor table of the time Gram plus the mode shifts
+// (compressed per mode; rows[off[k] + min(l, last[k])]).
+template <typename T>
+void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
+                       std::vector<int>& off, std::vector<int>& last);
 }  // namespace pdhg

@@ -1,0 +1,489 @@
+// Device bodies of the three fused passes of one iteration of Algorithm 1
+// (Section 3.3), shared by the single-problem kernels (pdhg_fused.hip) and the
+// batched persistent kernels (pdhg_batch.hip).
+//
+//   A  dual_fft_pair     one pair of dual rows: inverse FFT of the
+//                        preconditioned residual, dual step and extrapolation
+//   B  primal_res_pair   one pair of implicit rows: primal step on the levels
+//                        the rows touch, dual residual of the owned levels,
+//                        implicit residual of the two rows and its forward FFT
+//   C  colsolve_group    eight halfcomplex spectrum columns: banded Cholesky
+//                        solve along t (the preconditioner K_d^{-1}, Section 2.2)
+//
+// A and B run on a sub-group of W threads (tid = 0..W-1, a multiple of 64) of a
+// block of TB threads (gtid = 0..TB-1); all sub-groups of a block work on rows
+// of the same length nx, share the LDS twiddle table, and call the bodies
+// together (the FFT synchronises the whole block).  A pair whose first row is
+// >= nt is idle: it takes part in the barriers and stores nothing.
+#pragma once
+
+#include "pdhg_device.hpp"
+
+namespace pdhg {
+
+// ------------------------------------------------------------------ A
+// EPT = nx / W points per thread.  All global loads (twiddles, the two spectrum
+// rows and the two dual rows) are issued before the first LDS write so that
+// their latencies overlap.
+template <typename T, int EPT>
+__device__ __forceinline__ void dual_fft_pair(const T* __restrict__ spec, int nt, int lqb, int nx,
+                                              const C2<T>* __restrict__ tw, T* __restrict__ phi,
+                                              T* __restrict__ phibar, T tau, int a, int tid, int W, int gtid, int TB,
+                                              C2<T>* buf, C2<T>* twl) {
+  const int b = a + 1;
+  const bool act = a < nt, hasb = b < nt;
+  const int half = nx >> 1;
+  const int ar = act ? a : 0, br = hasb ? b : 0;
+  T* pa = phi + (size_t)ar * nx;
+  T* qa = phibar + (size_t)ar * nx;
+  T* pb = phi + (size_t)br * nx;
+  T* qb = phibar + (size_t)br * nx;
+  // ---- loads
+  C2<T> twv[EPT];
+  T fa[EPT], fb[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int xt = gtid + e * TB;
+    twv[e] = (xt < nx) ? tw[xt] : C2<T>{T(0), T(0)};
+    const int x = tid + e * W;
+    fa[e] = act ? pa[x] : T(0);
+    fb[e] = hasb ? pb[x] : T(0);
+  }
+  // halfcomplex pair: thread handles modes k = tid + e W, k <= nx/2 (EPT/2 + 1 of them)
+  constexpr int KPT = EPT / 2 + 1;
+  T sar[KPT], sai[KPT], sbr[KPT], sbi[KPT];
+#pragma unroll
+  for (int e = 0; e < KPT; ++e) {
+    const int k = tid + e * W;
+    sar[e] = sai[e] = sbr[e] = sbi[e] = T(0);
+    if (act && k <= half) {
+      if (k == 0 || k == half) {
+        const int q = (k == 0) ? 0 : 1;
+        sar[e] = spec[spec_index(a, q, nt, lqb)];
+        if (hasb) sbr[e] = spec[spec_index(b, q, nt, lqb)];
+      } else {
+        sar[e] = spec[spec_index(a, 2 * k, nt, lqb)];
+        sai[e] = spec[spec_index(a, 2 * k + 1, nt, lqb)];
+        if (hasb) {
+          sbr[e] = spec[spec_index(b, 2 * k, nt, lqb)];
+          sbi[e] = spec[spec_index(b, 2 * k + 1, nt, lqb)];
+        }
+      }
+    }
+  }
+  // ---- LDS: twiddles and Z_k = A_k + i B_k (A_{N-k} = conj A_k)
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int xt = gtid + e * TB;
+    if (xt < nx) twl[lpad(xt)] = twv[e];
+  }
+#pragma unroll
+  for (int e = 0; e < KPT; ++e) {
+    const int k = tid + e * W;
+    if (k <= half) {
+      buf[lpad(k)] = {sar[e] - sbi[e], sai[e] + sbr[e]};
+      if (k != 0 && k != half) buf[lpad(nx - k)] = {sar[e] + sbi[e], sbr[e] - sai[e]};
+    }
+  }
+  fft_lds<true, EPT>(buf, nx, twl, tid, W);
+  const T sc = T(1) / T(nx);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int x = tid + e * W;
+    const C2<T> z = buf[lpad(x)];
+    if (act) {
+      const T ta = tau * (z.x * sc);
+      const T p = fa[e] + ta;
+      pa[x] = p;
+      qa[x] = p + ta;
+    }
+    if (hasb) {
+      const T tb = tau * (z.y * sc);
+      const T q = fb[e] + tb;
+      pb[x] = q;
+      qb[x] = q + tb;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ B
+// Load one row for this lane (x = seg0 + lane + 64 e) and the two values just
+// outside the wave's segment; rows outside [0, nrows) read as zero.
+template <typename T, int E>
+__device__ __forceinline__ void load_row_wave(const T* __restrict__ base, int r, int nrows, int nx, int seg0,
+                                              int lane, T* v, T& prev, T& next) {
+  if (r < 0 || r >= nrows) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = T(0);
+    prev = next = T(0);
+    return;
+  }
+  const T* row = base + (size_t)r * nx;
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = row[seg0 + lane + 64 * e];
+  prev = row[(seg0 - 1) & (nx - 1)];
+  next = row[(seg0 + 64 * E) & (nx - 1)];
+}
+
+// J(u)^T psi at unknown level m from registers: c = psi^{m-1} (with segment
+// edges), t1 = psi^m, t2 = psi^{m+1} (zero where absent), uv = u^m.
+template <typename T, int E>
+__device__ __forceinline__ void dual_op_regs(const Consts<T>& C, int m, const T* c, T prev, T next, const T* t1,
+                                             const T* t2, const T* uv, T* out) {
+  T cm[E], cp[E];
+  wave_row_neighbours<T, E>(c, prev, next, cm, cp);
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[e] = C.JtTime(m, c[e], t1[e], t2[e]) + C.JtF(uv[e], cm[e], c[e], cp[e]);
+}
+
+// E = nx / W points per thread; wave v of the sub-group owns x in
+// [v 64E, (v+1) 64E), lane l element e at x = v 64E + l + 64 e.  Every global
+// row the pair needs is loaded up front: u^{n-1} on levels a-1..a+2, phibar on
+// rows a-2..a+3, phi on rows a..a+3.  Returns this thread's contributions to
+// ||A(u^n)||^2 (rows a, a+1) and ||J(u^{n-1})^T phi^{n-1}||^2 (levels a+1, a+2).
+// edge: 4 (W / 64) values of LDS for this sub-group.
+template <typename T, int E>
+__device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __restrict__ u_in,
+                                                T* __restrict__ u_out, const T* __restrict__ phibar,
+                                                const T* __restrict__ phi, T tau_u, T* __restrict__ spec, int lqb,
+                                                const C2<T>* __restrict__ tw, int a, int tid, int W, int gtid,
+                                                int TB, C2<T>* buf, C2<T>* twl, T* edge, double& rp_out,
+                                                double& rd_out) {
+  const int nx = C.nx, nt = C.nt;
+  const int lane = tid & 63, wv = tid >> 6, nw = W >> 6;
+  const int seg0 = wv * 64 * E;
+  const int b = a + 1;
+  const bool act = a < nt;
+  const bool bdf2 = C.time == kTimeBDF2;
+  // ---- all global loads first
+  C2<T> twv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int xt = gtid + e * TB;
+    twv[e] = (xt < nx) ? tw[xt] : C2<T>{T(0), T(0)};
+  }
+  T U0[4][E], U[4][E];                 // u^{n-1} and u^n on levels a-1+i
+  T PB[6][E], PBp[4], PBn[4];          // phibar rows a-2+j (edges for j = 0..3)
+  T PH[4][E], PHp[2], PHn[2];          // phi rows a+j (edges for j = 0, 1)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = a - 1 + i;
+    const bool ok = m >= 0 && m <= nt && (bdf2 || i > 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) U0[i][e] = ok ? u_in[(size_t)m * nx + seg0 + lane + 64 * e] : T(0);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T pv, nv;
+    load_row_wave<T, E>(phibar, a - 2 + j, nt, nx, seg0, lane, PB[j], pv, nv);
+    if (j < 4) { PBp[j] = pv; PBn[j] = nv; }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    T pv, nv;
+    load_row_wave<T, E>(phi, a + j, nt, nx, seg0, lane, PH[j], pv, nv);
+    if (j < 2) { PHp[j] = pv; PHn[j] = nv; }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int xt = gtid + e * TB;
+    if (xt < nx) twl[lpad(xt)] = twv[e];
+  }
+  // ---- primal step on the four levels, dual residual on the two owned ones
+  double rd = 0.0, rp = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = a - 1 + i;
+    if (m < 0 || m > nt || (!bdf2 && i == 0)) continue;
+    if (m == 0) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) U[i][e] = U0[i][e];
+      continue;
+    }
+    T g[E];
+    dual_op_regs<T, E>(C, m, PB[i], PBp[i], PBn[i], PB[i + 1], PB[i + 2], U0[i], g);
+#pragma unroll
+    for (int e = 0; e < E; ++e) U[i][e] = U0[i][e] - tau_u * g[e];
+    if (i >= 2) {   // owned level: store u^n and the dual residual of (u^{n-1}, phi^{n-1})
+      T* uw = u_out + (size_t)m * nx + seg0 + lane;
+#pragma unroll
+      for (int e = 0; e < E; ++e) uw[64 * e] = U[i][e];
+      dual_op_regs<T, E>(C, m, PH[i - 2], PHp[i - 2], PHn[i - 2], PH[i - 1], PH[i], U0[i], g);
+#pragma unroll
+      for (int e = 0; e < E; ++e) rd += (double)g[e] * (double)g[e];
+    }
+  }
+  // segment-edge values of the two levels whose flux differences are taken
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (lane == 0) edge[(2 * s + 0) * nw + wv] = U[2 + s][0];
+    if (lane == 63) edge[(2 * s + 1) * nw + wv] = U[2 + s][E - 1];
+  }
+  __syncthreads();
+  T R[2][E];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int l = a + s;
+    if (l < nt) {
+      const int ms = 2 + s;
+      T vm[E], vp[E];
+      const T prev = edge[(2 * s + 1) * nw + ((wv - 1 + nw) % nw)];
+      const T next = edge[(2 * s + 0) * nw + ((wv + 1) % nw)];
+      wave_row_neighbours<T, E>(U[ms], prev, next, vm, vp);
+      const T c0 = C.c0(l), c1 = C.c1(l), c2 = C.c2(l);
+      const bool use2 = bdf2 && l >= 1;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        T t = c0 * U[ms][e] + c1 * U[ms - 1][e];
+        if (use2) t += c2 * U[ms - 2][e];
+        const T r = t * C.inv_ht + C.F(vm[e], U[ms][e], vp[e]);
+        R[s][e] = r;
+        rp += (double)r * (double)r;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) R[s][e] = T(0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) buf[lpad(seg0 + lane + 64 * e)] = {R[0][e], R[1][e]};
+  fft_lds<false, E>(buf, nx, twl, tid, W);
+  if (act) store_halfcomplex_pair(buf, nx, spec, nt, lqb, a, b < nt, tid, W);
+  rp_out = rp;
+  rd_out = rd;
+}
+
+// Sum of v over the W threads of a sub-group whose first wave is wave w0 of the
+// block: wave reductions, then the sub-group's first thread adds the per-wave
+// sums in order (the order of block_sum_waves).  Result valid in that thread.
+// red: LDS, one double per wave of the block.  All threads of the block call it.
+__device__ __forceinline__ double subgroup_sum(double v, double* red, int w0, int nw) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (wid == w0 && lane == 0)
+    for (int i = 0; i < nw; ++i) s += red[w0 + i];
+  return s;
+}
+
+// ------------------------------------------------------------------ C
+// Banded Cholesky solve along t.  One wavefront per Fourier mode k handles the
+// two halfcomplex columns of that mode (Re and Im share the factor; the first
+// wave of the spectrum handles the real columns of modes 0 and nx/2).  Lane j
+// owns levels [j LPL, (j+1) LPL).  Each lane computes the affine map of its
+// segment (particular solution and the responses to the two incoming values),
+// an inclusive scan of the maps across the 64 lanes (shuffles, no barriers)
+// gives every lane its incoming state, and the segment is re-run from it.
+// The block stages a [nt][8-column] tile of the spectrum through LDS (lane-major,
+// padded) so that global accesses are coalesced and LDS accesses conflict-free.
+constexpr int kColWaves = 4;
+constexpr int kColCols = 2 * kColWaves;
+
+template <typename T>
+__device__ __forceinline__ T shfl_up_T(T v, int d) { return __shfl_up(v, d, 64); }
+template <typename T>
+__device__ __forceinline__ T shfl_down_T(T v, int d) { return __shfl_down(v, d, 64); }
+
+// (H, P) <- (H, P) o (H', P') : apply (H', P') first, then (H, P).
+template <typename T>
+__device__ __forceinline__ void compose(T* H, T* P, const T* H2, const T* P2) {
+  const T h0 = H[0] * H2[0] + H[1] * H2[2];
+  const T h1 = H[0] * H2[1] + H[1] * H2[3];
+  const T h2 = H[2] * H2[0] + H[3] * H2[2];
+  const T h3 = H[2] * H2[1] + H[3] * H2[3];
+  const T p0 = H[0] * P2[0] + H[1] * P2[1] + P[0];
+  const T p1 = H[2] * P2[0] + H[3] * P2[1] + P[1];
+  H[0] = h0; H[1] = h1; H[2] = h2; H[3] = h3;
+  P[0] = p0; P[1] = p1;
+}
+
+// Inclusive scan of segment maps over the lanes, forward (from lane 0) or
+// backward (from lane 63); returns the state entering this lane's segment.
+template <typename T, bool FWD>
+__device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& in1) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T H2[4], P2[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) H2[k] = FWD ? shfl_up_T(H[k], d) : shfl_down_T(H[k], d);
+    P2[0] = FWD ? shfl_up_T(P[0], d) : shfl_down_T(P[0], d);
+    P2[1] = FWD ? shfl_up_T(P[1], d) : shfl_down_T(P[1], d);
+    if (FWD ? (lane >= d) : (lane + d < 64)) compose(H, P, H2, P2);
+  }
+  in2 = FWD ? shfl_up_T(P[0], 1) : shfl_down_T(P[0], 1);
+  in1 = FWD ? shfl_up_T(P[1], 1) : shfl_down_T(P[1], 1);
+  if (FWD ? (lane == 0) : (lane == 63)) { in2 = T(0); in1 = T(0); }
+}
+
+// Solve L L^T y = z in place for NC columns sharing the factor rows; z[c][i]
+// is level l0 + i of column c.
+template <typename T, int BW, int LPL, int NC>
+__device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* invd, const T* e1, const T* e2,
+                                                    int lane, int l0, int nt) {
+  // forward: z_l = invd_l (rhs_l - e1_l z_{l-1} - e2_l z_{l-2})
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      if (l0 + i < nt) {
+        const T pz = invd[i] * (z[c][i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : T(0)));
+        const T az = invd[i] * (-e1[i] * a1 - (BW == 2 ? e2[i] * a2 : T(0)));
+        const T bz = invd[i] * (-e1[i] * b1 - (BW == 2 ? e2[i] * b2 : T(0)));
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
+    T zm2, zm1;
+    scan_incoming<T, true>(H, P, lane, zm2, zm1);
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      if (l0 + i < nt) {
+        const T zz = invd[i] * (z[c][i] - e1[i] * zm1 - (BW == 2 ? e2[i] * zm2 : T(0)));
+        z[c][i] = zz;
+        zm2 = zm1; zm1 = zz;
+      }
+    }
+  }
+  // backward: y_l = invd_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2})
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int ii = 0; ii < LPL; ++ii) {
+      const int i = LPL - 1 - ii;
+      if (l0 + i < nt) {
+        const T f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : T(0);
+        const T pz = invd[i] * (z[c][i] - f1 * p1 - f2 * p2);
+        const T az = invd[i] * (-f1 * a1 - f2 * a2);
+        const T bz = invd[i] * (-f1 * b1 - f2 * b2);
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
+    T ym2, ym1;
+    scan_incoming<T, false>(H, P, lane, ym2, ym1);
+#pragma unroll
+    for (int ii = 0; ii < LPL; ++ii) {
+      const int i = LPL - 1 - ii;
+      if (l0 + i < nt) {
+        const T f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : T(0);
+        const T yy = invd[i] * (z[c][i] - f1 * ym1 - f2 * ym2);
+        z[c][i] = yy;
+        ym2 = ym1; ym1 = yy;
+      }
+    }
+  }
+}
+
+template <typename T, int LPL>
+__device__ __forceinline__ void load_factor_rows(const FacTab<T>& fac, int kmode, int l0, T* invd, T* e1, T* e2) {
+  const FacRow<T>* rows = fac.rows + fac.off[kmode];
+  const int last = fac.last[kmode];
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) {
+    const FacRow<T> fr = rows[min(l0 + i, last)];
+    invd[i] = fr.invd;
+    e1[i] = fr.e1;
+    e2[i] = fr.e2;
+  }
+  e1[LPL] = rows[min(l0 + LPL, last)].e1;
+  e2[LPL] = rows[min(l0 + LPL, last)].e2;
+  e2[LPL + 1] = rows[min(l0 + LPL + 1, last)].e2;
+}
+
+// Norms and stopping decision of iteration n from the nparts partial sums of
+// each norm (part[0..nparts) for the residual, part[stride..stride+nparts) for
+// the dual residual), reduced in a fixed order by one wavefront.
+__device__ __forceinline__ void finalize_wave(Ctrl* ctrl, const double* __restrict__ part, int nparts, int stride,
+                                              double wscale, double* hist) {
+  const int lane = threadIdx.x & 63;
+  double a = 0.0, b = 0.0;
+  for (int i = lane; i < nparts; i += 64) {
+    a += part[i];
+    b += part[stride + i];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) finalize_body(ctrl, a, b, wscale, hist);
+}
+
+// Column solve of spectrum columns q0..q0+7 (q0 a multiple of 8) by the 4
+// waves of the calling block.  tile: kColCols * LPL * 65 elements of LDS.
+template <typename T, int BW, int LPL>
+__device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx, int lqb,
+                                               int q0, T* tile) {
+  const int QB = 1 << lqb;
+  T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
+  const int tid = threadIdx.x;
+  constexpr int kPer = 64 * LPL * kColCols / (64 * kColWaves);   // tile elements per thread
+  const int wv = tid >> 6, lane = tid & 63;
+  const int qa = q0 + 2 * wv, qb = qa + 1;
+  const int ka = spec_mode(qa, nx), kb = spec_mode(qb, nx);
+  const int l0 = lane * LPL;
+  // factor rows of this wave's mode first, so their latency overlaps the tile loads
+  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<T, LPL>(fac, ka, l0, invd, e1, e2);
+  // all tile loads in flight before the first LDS write
+  T stage[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    tile[(c * LPL + l % LPL) * 65 + l / LPL] = stage[r];
+  }
+  __syncthreads();
+  T z[2][LPL];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) z[c][i] = tile[((2 * wv + c) * LPL + i) * 65 + lane];
+  if (ka == kb) {
+    cholesky_solve_wave<T, BW, LPL, 2>(z, invd, e1, e2, lane, l0, nt);
+  } else {   // real columns of modes 0 and nx/2
+    T za[1][LPL], zb[1][LPL];
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) { za[0][i] = z[0][i]; zb[0][i] = z[1][i]; }
+    cholesky_solve_wave<T, BW, LPL, 1>(za, invd, e1, e2, lane, l0, nt);
+    load_factor_rows<T, LPL>(fac, kb, l0, invd, e1, e2);
+    cholesky_solve_wave<T, BW, LPL, 1>(zb, invd, e1, e2, lane, l0, nt);
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) { z[0][i] = za[0][i]; z[1][i] = zb[0][i]; }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) tile[((2 * wv + c) * LPL + i) * 65 + lane] = z[c][i];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = tile[(c * LPL + l % LPL) * 65 + l / LPL];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * 64 * kColWaves;
+    const int l = idx / kColCols, c = idx % kColCols;
+    if (l < nt) base[(size_t)l * QB + c] = stage[r];
+  }
+}
+
+// Dynamic LDS above 64 KiB needs an explicit opt-in per kernel.
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace pdhg

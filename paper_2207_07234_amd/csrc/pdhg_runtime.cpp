@@ -22,6 +22,74 @@
 
 using namespace pdhg;
 
+namespace pdhg {
+
+// Banded Cholesky factors of (B_t B_t^T + s_k I), k = 0..nx/2, computed in
+// long double and rounded to T.  B_t is the time difference acting on the
+// unknown levels (row l: c0(l) at column l, c1(l) at l-1, c2(l) at l-2, all
+// over h_t).  Rows of L converge to those of the infinite Toeplitz factor;
+// for each mode only the rows up to the point after which every rounded row
+// equals the last one are stored.
+template <typename T>
+void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
+                       std::vector<int>& off, std::vector<int>& last) {
+  typedef long double LD;
+  const int nt = p.nt, nx = p.nx;
+  const LD ht = (LD)p.t_final / nt, hx = (LD)p.length / nx;
+  const bool bdf2 = p.time == PDHG_BDF2;
+  auto coef = [&](int l, int d) -> LD {   // B_t[l][l-d] * h_t
+    if (d == 0) return (bdf2 && l >= 1) ? 1.5L : 1.0L;
+    if (d == 1) return (l >= 1) ? ((bdf2 && l >= 1) ? -2.0L : -1.0L) : 0.0L;
+    if (d == 2) return (bdf2 && l >= 2) ? 0.5L : 0.0L;
+    return 0.0L;
+  };
+  // K[l][l-d] for d = 0, 1, 2 (times h_t^2)
+  auto kband = [&](int l, int d) -> LD {
+    if (l - d < 0) return 0.0L;
+    LD s = 0.0L;
+    for (int mcol = l - 2; mcol <= l - d; ++mcol) {
+      if (mcol < 0) continue;
+      const int da = l - mcol, db = (l - d) - mcol;
+      if (da > 2 || db < 0 || db > 2) continue;
+      s += coef(l, da) * coef(l - d, db);
+    }
+    return s;
+  };
+  const LD PI = 3.141592653589793238462643383279502884L;
+  const int nmodes = nx / 2 + 1;
+  off.assign(nmodes, 0);
+  last.assign(nmodes, 0);
+  rows.clear();
+  std::vector<LD> d(nt), e1(nt), e2(nt);
+  std::vector<FacRow<T>> tmp(nt);
+  for (int k = 0; k < nmodes; ++k) {
+    const LD sn = sinl(PI * k / nx);
+    const LD mu = 4.0L * sn * sn / (hx * hx);
+    const LD shift = (LD)c * c * mu + (LD)ghat * ghat * mu * mu;
+    for (int l = 0; l < nt; ++l) {
+      const LD k0 = kband(l, 0) / (ht * ht) + shift;
+      const LD k1 = kband(l, 1) / (ht * ht);
+      const LD k2 = kband(l, 2) / (ht * ht);
+      e2[l] = (l >= 2) ? k2 / d[l - 2] : 0.0L;
+      e1[l] = (l >= 1) ? (k1 - ((l >= 2) ? e2[l] * e1[l - 1] : 0.0L)) / d[l - 1] : 0.0L;
+      d[l] = sqrtl(k0 - e1[l] * e1[l] - e2[l] * e2[l]);
+      tmp[l] = FacRow<T>{(T)(1.0L / d[l]), (T)e1[l], (T)e2[l], (T)0};
+    }
+    int lst = nt - 1;
+    while (lst > 0 && memcmp(&tmp[lst - 1], &tmp[nt - 1], sizeof(FacRow<T>)) == 0) --lst;
+    off[k] = (int)rows.size();
+    last[k] = lst;
+    for (int l = 0; l <= lst; ++l) rows.push_back(tmp[l]);
+  }
+}
+
+template void build_factor_rows<float>(const pdhg_problem&, double, double, std::vector<FacRow<float>>&,
+                                        std::vector<int>&, std::vector<int>&);
+template void build_factor_rows<double>(const pdhg_problem&, double, double, std::vector<FacRow<double>>&,
+                                         std::vector<int>&, std::vector<int>&);
+
+}  // namespace pdhg
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -132,65 +200,6 @@ Scheme scheme_of(const pdhg_handle* h) {
   s.gamma = p.gamma;
   s.lf = h->lf;
   return s;
-}
-
-// Banded Cholesky factors of (B_t B_t^T + s_k I), k = 0..nx/2, computed in
-// long double and rounded to T.  B_t is the time difference acting on the
-// unknown levels (row l: c0(l) at column l, c1(l) at l-1, c2(l) at l-2, all
-// over h_t).  Rows of L converge to those of the infinite Toeplitz factor;
-// for each mode only the rows up to the point after which every rounded row
-// equals the last one are stored.
-template <typename T>
-void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
-                       std::vector<int>& off, std::vector<int>& last) {
-  typedef long double LD;
-  const int nt = p.nt, nx = p.nx;
-  const LD ht = (LD)p.t_final / nt, hx = (LD)p.length / nx;
-  const bool bdf2 = p.time == PDHG_BDF2;
-  auto coef = [&](int l, int d) -> LD {   // B_t[l][l-d] * h_t
-    if (d == 0) return (bdf2 && l >= 1) ? 1.5L : 1.0L;
-    if (d == 1) return (l >= 1) ? ((bdf2 && l >= 1) ? -2.0L : -1.0L) : 0.0L;
-    if (d == 2) return (bdf2 && l >= 2) ? 0.5L : 0.0L;
-    return 0.0L;
-  };
-  // K[l][l-d] for d = 0, 1, 2 (times h_t^2)
-  auto kband = [&](int l, int d) -> LD {
-    if (l - d < 0) return 0.0L;
-    LD s = 0.0L;
-    for (int mcol = l - 2; mcol <= l - d; ++mcol) {
-      if (mcol < 0) continue;
-      const int da = l - mcol, db = (l - d) - mcol;
-      if (da > 2 || db < 0 || db > 2) continue;
-      s += coef(l, da) * coef(l - d, db);
-    }
-    return s;
-  };
-  const LD PI = 3.141592653589793238462643383279502884L;
-  const int nmodes = nx / 2 + 1;
-  off.assign(nmodes, 0);
-  last.assign(nmodes, 0);
-  rows.clear();
-  std::vector<LD> d(nt), e1(nt), e2(nt);
-  std::vector<FacRow<T>> tmp(nt);
-  for (int k = 0; k < nmodes; ++k) {
-    const LD sn = sinl(PI * k / nx);
-    const LD mu = 4.0L * sn * sn / (hx * hx);
-    const LD shift = (LD)c * c * mu + (LD)ghat * ghat * mu * mu;
-    for (int l = 0; l < nt; ++l) {
-      const LD k0 = kband(l, 0) / (ht * ht) + shift;
-      const LD k1 = kband(l, 1) / (ht * ht);
-      const LD k2 = kband(l, 2) / (ht * ht);
-      e2[l] = (l >= 2) ? k2 / d[l - 2] : 0.0L;
-      e1[l] = (l >= 1) ? (k1 - ((l >= 2) ? e2[l] * e1[l - 1] : 0.0L)) / d[l - 1] : 0.0L;
-      d[l] = sqrtl(k0 - e1[l] * e1[l] - e2[l] * e2[l]);
-      tmp[l] = FacRow<T>{(T)(1.0L / d[l]), (T)e1[l], (T)e2[l], (T)0};
-    }
-    int lst = nt - 1;
-    while (lst > 0 && memcmp(&tmp[lst - 1], &tmp[nt - 1], sizeof(FacRow<T>)) == 0) --lst;
-    off[k] = (int)rows.size();
-    last[k] = lst;
-    for (int l = 0; l <= lst; ++l) rows.push_back(tmp[l]);
-  }
 }
 
 template <typename T>

@@ -62,3 +62,32 @@ def test_status_strings():
     assert lib.pdhg_status_string(B.PDHG_OK) == b"converged"
     assert lib.pdhg_status_string(B.PDHG_DIVERGED) == b"diverged"
     assert lib.pdhg_status_string(12345) == b"unknown status"
+
+
+def test_batch_params_struct_size():
+    B, _ = _lib()
+    assert C.sizeof(B.pdhg_batch_params) == 8 * 3 + 8 + 4 * 2 + 8
+
+
+def _batch_problem(B, **kw):
+    p = B.pdhg_problem()
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 512, 64, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype = B.PDHG_BDF2, B.PDHG_FD_LF, B.PDHG_F32
+    p.lf_speed = p.precond_c = -1.0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=128), "PDHG_EUNSUPPORTED"), (dict(nx=8192), "PDHG_EUNSUPPORTED"), (dict(nt=1024), "PDHG_EUNSUPPORTED"),
+    (dict(nx=1000), "PDHG_EINVAL"), (dict(nt=0), "PDHG_EINVAL"), (dict(dtype=1), "PDHG_EINVAL"),
+    (dict(time=5), "PDHG_EINVAL")])
+def test_batch_setup_rejects_before_touching_the_device(bad, code):
+    """The second problem of the batch is invalid (or of another dtype); setup fails on the host."""
+    B, lib = _lib()
+    arr = (B.pdhg_problem * 2)(_batch_problem(B), _batch_problem(B, **bad))
+    h = C.c_void_p()
+    assert lib.pdhg_batch_setup(arr, 2, C.byref(h)) == getattr(B, code)
+    assert not h.value
+    assert lib.pdhg_batch_setup(arr, 0, C.byref(h)) == B.PDHG_EINVAL
