@@ -79,6 +79,13 @@ def default_constants(prob: Problem, u0: np.ndarray) -> Problem:
       the initial data (Section 3.3); default max |f'(u0)|.
     """
     kw = {}
+    if prob.space == "dg_p2_llf":
+        # DG: u0 is the (3, N_x) coefficient array; the speed is taken over the
+        # cell-edge traces of u0_h (the states the local Lax-Friedrichs flux sees)
+        from .dg import default_speed
+        if prob.precond_c <= 0.0:
+            kw["precond_c"] = default_speed(prob, u0)
+        return prob.with_(**kw) if kw else prob
     if prob.space == "fd_lf" and prob.lf_speed <= 0.0:
         kw["lf_speed"] = float(np.max(np.abs(prob.fp(np.asarray(u0)))))
     if prob.precond_c <= 0.0 and prob.space != "heat_var":
