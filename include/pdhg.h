@@ -20,6 +20,7 @@
  * - The element type of every array is the problem's dtype (float or double).
  * - Layouts, row-major, x fastest:
  *     u   [nt+1][nx]   levels l = 0..nt; level 0 is the initial data
+ *                      (DG: [nt+1][3][nx], and every [nt][nx] below is [nt][3][nx])
  *     phi [nt][nx]     one dual row per implicit equation l = 0..nt-1
  *     r   [nt][nx]     implicit residual rows A(u)^l
  *     g   [nt][nx]     J(u)^T phi, row m-1 belongs to unknown level m = 1..nt
@@ -57,12 +58,22 @@ typedef enum { PDHG_F32 = 0, PDHG_F64 = 1 } pdhg_dtype;
  * the start-up step being left open by the paper. */
 typedef enum { PDHG_BE = 0, PDHG_BDF2 = 1 } pdhg_time;
 
-/* Spatial discretisation (Section 3.2, finite differences):
+/* Spatial discretisation (Section 3.2):
  *  PDHG_FD_UPWIND: F_j = (f(u_j) - f(u_{j-1}))/h_x, requires f' >= 0 (as the paper's
  *                  upwind examples assume);
  *  PDHG_FD_LF:     global Lax-Friedrichs flux with constant lf_speed.
- * Both add centred diffusion -gamma (u_{j+1} - 2u_j + u_{j-1})/h_x^2 when gamma > 0. */
-typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1 } pdhg_space;
+ *  Both add centred diffusion -gamma (u_{j+1} - 2u_j + u_{j-1})/h_x^2 when gamma > 0.
+ *  PDHG_DG_P2_LLF: discontinuous Galerkin on nx cells, Legendre basis of degree 2
+ *                  (3 coefficients per cell), local Lax-Friedrichs flux
+ *                  (s = max(|f'(a)|, |f'(b)|) per interface), volume integrals by
+ *                  3-point Gauss.  Arrays carry coefficient planes: u [nt+1][3][nx],
+ *                  phi [nt][3][nx], u0 [3][nx] (the projected initial data).
+ *                  Requires 16 <= nx, nt <= 512, gamma = 0; lf_speed and
+ *                  precond_gamma_hat are not used; the default precond_c is
+ *                  max |f'| over the cell-edge traces of u0.  The preconditioner
+ *                  couples the three planes through the unit-speed upwind DG
+ *                  operator G: K_d = (B_t B_t^T) (x) I + I_t (x) c^2 G G^T. */
+typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1, PDHG_DG_P2_LLF = 2 } pdhg_space;
 
 typedef struct {
   int32_t nx, nt;
@@ -90,8 +101,9 @@ typedef struct {
   int32_t warm_start;       /* 0: u^l = u0, phi = 0 (Section 3.3);  1: start from u, phi   */
   double diverge_factor;    /* diverged when max(Rp,Rd) > diverge_factor * best so far;
                                <= 0: 1e6                                                 */
-  int32_t variant;          /* 0 = auto (2), 1 = unfused reference kernels (7 per iteration),
-                               2 = fused passes (3 kernels per iteration)                 */
+  int32_t variant;          /* 0 = auto (2; DG: 4), 1 = unfused reference kernels (7 per
+                               iteration), 2 = fused passes (3 kernels per iteration),
+                               4 = the DG loop body (6 kernels per iteration)            */
   int32_t reserved;
   double* history;          /* nullable DEVICE buffer [max_iter+2][2] of doubles: entry n holds
                                (||A(u^n)||, ||J(u^n)^T phi^n||) for n = 0..n*; entry 0 is
@@ -149,7 +161,8 @@ int pdhg_precond(pdhg_handle* h, const void* r, void* s, pdhg_stream_t stream);
 
 /* Dual-equation operator and the implicit adjoint (Section 3.1).
  *  mode PDHG_ADJ_APPLY: out[nt][nx] = J(u)^T in, in = phi [nt][nx].
- *  mode PDHG_ADJ_SOLVE: in = dL/du [nt+1][nx] (all levels, level 0 included);
+ *  mode PDHG_ADJ_SOLVE (finite differences; PDHG_EUNSUPPORTED for DG):
+ *     in = dL/du [nt+1][nx] (all levels, level 0 included);
  *     solves J(u)^T mu = dL/du[1:] by a backward march in time (one periodic
  *     tridiagonal solve per level) and writes out[nx] = dL/du0 =
  *     dL/du^0 - (dA/du0)^T mu.  mu [nt][nx] receives the multiplier if non-NULL.
@@ -165,6 +178,9 @@ int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, vo
  * overwritten).  kernel: 0 = fused primal/residual/FFT pass, 1 = column solve,
  * 2 = inverse row FFT, 3 = dual update, 4 = primal update, 5 = residual,
  * 6 = forward row FFT, 7 = fused inverse-FFT/dual pass, 8 = plain device copy
+ * (DG: 1 = column solve in the per-mode eigenbasis, 4 = primal step with the
+ * dual residual, 5 = residual, 6 = forward row FFT of the 3 nt coefficient
+ * rows, 7 = inverse FFT + dual step, 8 = copy; others PDHG_EUNSUPPORTED)
  * of N_t*N_x elements (one read and one write per element; the reference point
  * for bandwidth and for scaling hardware byte counters).
  * Used for roofline measurements.  Returns PDHG_EINVAL without a previous solve. */

@@ -30,7 +30,7 @@ __all__ = ["Problem", "Solver", "SolveResult", "BatchSolver", "BatchResult", "Pd
 
 lib_path = B.LIB_PATH
 _TIME = {"be": B.PDHG_BE, "bdf2": B.PDHG_BDF2}
-_SPACE = {"fd_upwind": B.PDHG_FD_UPWIND, "fd_lf": B.PDHG_FD_LF}
+_SPACE = {"fd_upwind": B.PDHG_FD_UPWIND, "fd_lf": B.PDHG_FD_LF, "dg_p2_llf": B.PDHG_DG_P2_LLF}
 
 
 class PdhgError(RuntimeError):
@@ -71,6 +71,11 @@ class Problem:
     def torch_dtype(self):
         import torch
         return torch.float64 if self.dtype is None else self.dtype
+
+    @property
+    def level_shape(self):
+        """Shape of one time level: (nx,) for finite differences, (3, nx) coefficient planes for DG."""
+        return (3, self.nx) if self.space == "dg_p2_llf" else (self.nx,)
 
 
 @dataclass
@@ -132,10 +137,10 @@ class Solver:
               check_every: int = 64, u=None, phi=None, warm_start: bool = False, workspace=None,
               history: bool = False, diverge_factor: float = 0.0, variant: int = 0) -> SolveResult:
         import torch
-        nx, nt = self.prob.nx, self.prob.nt
-        self._check(u0, (nx,), "u0")
-        u = self._empty(nt + 1, nx) if u is None else self._check(u, (nt + 1, nx), "u")
-        phi = self._empty(nt, nx) if phi is None else self._check(phi, (nt, nx), "phi")
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u0, lv, "u0")
+        u = self._empty(nt + 1, *lv) if u is None else self._check(u, (nt + 1,) + lv, "u")
+        phi = self._empty(nt, *lv) if phi is None else self._check(phi, (nt,) + lv, "phi")
         hist = torch.full((max_iter + 2, 2), float("nan"), dtype=torch.float64, device=self.device) \
             if history else None
         p = B.pdhg_params()
@@ -155,12 +160,12 @@ class Solver:
 
     def residual(self, u, phi=None, want_fields: bool = True):
         """(A(u), J(u)^T phi, [||A(u)||, ||J(u)^T phi||])."""
-        nx, nt = self.prob.nx, self.prob.nt
-        self._check(u, (nt + 1, nx), "u")
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u, (nt + 1,) + lv, "u")
         if phi is not None:
-            self._check(phi, (nt, nx), "phi")
-        au = self._empty(nt, nx) if want_fields else None
-        jt = self._empty(nt, nx) if (want_fields and phi is not None) else None
+            self._check(phi, (nt,) + lv, "phi")
+        au = self._empty(nt, *lv) if want_fields else None
+        jt = self._empty(nt, *lv) if (want_fields and phi is not None) else None
         res = (C.c_double * 2)()
         rc = self.lib.pdhg_residual(self._h, _ptr(u), _ptr(phi), _ptr(au), _ptr(jt), res,
                                     _stream_ptr(self.device))
@@ -170,9 +175,9 @@ class Solver:
 
     def precond(self, r, out=None):
         """s = K_d^{-1} r."""
-        nx, nt = self.prob.nx, self.prob.nt
-        self._check(r, (nt, nx), "r")
-        s = self._empty(nt, nx) if out is None else self._check(out, (nt, nx), "out")
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(r, (nt,) + lv, "r")
+        s = self._empty(nt, *lv) if out is None else self._check(out, (nt,) + lv, "out")
         rc = self.lib.pdhg_precond(self._h, _ptr(r), _ptr(s), _stream_ptr(self.device))
         if rc != B.PDHG_OK:
             raise PdhgError(f"pdhg_precond failed: {self._status(rc)}")
@@ -180,10 +185,10 @@ class Solver:
 
     def apply_jt(self, u, phi):
         """J(u)^T phi, rows indexed by unknown level m-1."""
-        nx, nt = self.prob.nx, self.prob.nt
-        self._check(u, (nt + 1, nx), "u")
-        self._check(phi, (nt, nx), "phi")
-        out = self._empty(nt, nx)
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u, (nt + 1,) + lv, "u")
+        self._check(phi, (nt,) + lv, "phi")
+        out = self._empty(nt, *lv)
         rc = self.lib.pdhg_adjoint(self._h, B.PDHG_ADJ_APPLY, _ptr(u), _ptr(phi), _ptr(out), None, None,
                                    _stream_ptr(self.device))
         if rc != B.PDHG_OK:

@@ -68,7 +68,7 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
 
 namespace pdhg {
 template <typename T>
-hipError_t launch_level_sums(const T* u, int nx, int levels, double* out, hipStream_t st);
+hipError_t launch_level_sums(const T* u, int nx, size_t stride, int levels, double* out, hipStream_t st);
 }  // namespace pdhg
 
 namespace pdhg {
@@ -139,4 +139,28 @@ namespace pdhg {
 template <typename T>
 void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
                        std::vector<int>& off, std::vector<int>& last);
+// The same for an explicit list of shifts (one table per entry).
+template <typename T>
+void build_factor_rows_shifts(const pdhg_problem& p, const std::vector<long double>& shifts,
+                              std::vector<FacRow<T>>& rows, std::vector<int>& off, std::vector<int>& last);
+}  // namespace pdhg
+
+namespace pdhg {
+// DG P2 space discretisation (pdhg_dg.hip).
+template <typename T>
+hipError_t launch_dg_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,
+                              int* nblocks);
+template <typename T>
+hipError_t launch_dg_apply_jt(const Scheme& s, const T* u, const T* psi, T* out, double* part, hipStream_t st,
+                              int* nblocks);
+template <typename T>
+hipError_t launch_dg_apply_j(const Scheme& s, const T* u, const T* v, T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_dg_primal(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
+                            double* part, const Ctrl* ctrl, hipStream_t st, int* nblocks);
+template <typename T>
+hipError_t launch_dg_maxabs_trace(const T* u0, int nx, double a2, double b, double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
+                              const Ctrl* ctrl, hipStream_t st);
 }  // namespace pdhg

@@ -352,22 +352,24 @@ k_partial_maxabs_dflux(const T* __restrict__ x, size_t n, double a2, double b, d
 
 // Discrete mass of every level: out[l] = sum_j u^l_j (one block per level).
 template <typename T>
-__global__ void __launch_bounds__(kEwThreads) k_level_sums(const T* __restrict__ u, int nx, double* out) {
+__global__ void __launch_bounds__(kEwThreads) k_level_sums(const T* __restrict__ u, int nx, size_t stride,
+                                                           double* out) {
   __shared__ double red[kEwThreads / 64];
-  const T* row = u + (size_t)blockIdx.x * nx;
+  const T* row = u + (size_t)blockIdx.x * stride;
   double acc = 0.0;
   for (int j = threadIdx.x; j < nx; j += kEwThreads) acc += (double)row[j];
   const double s = block_sum<kEwThreads>(acc, red);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// Sums of the first nx entries of `levels` rows spaced `stride` elements apart.
 template <typename T>
-hipError_t launch_level_sums(const T* u, int nx, int levels, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_level_sums<T>, dim3(levels), dim3(kEwThreads), 0, st, u, nx, out);
+hipError_t launch_level_sums(const T* u, int nx, size_t stride, int levels, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_sums<T>, dim3(levels), dim3(kEwThreads), 0, st, u, nx, stride, out);
   return hipGetLastError();
 }
-template hipError_t launch_level_sums<float>(const float*, int, int, double*, hipStream_t);
-template hipError_t launch_level_sums<double>(const double*, int, int, double*, hipStream_t);
+template hipError_t launch_level_sums<float>(const float*, int, size_t, int, double*, hipStream_t);
+template hipError_t launch_level_sums<double>(const double*, int, size_t, int, double*, hipStream_t);
 
 // Sum `n` partials in a fixed order into out[0] (single block).
 __global__ void __launch_bounds__(kEwThreads) k_reduce_parts(const double* __restrict__ part, int n, double* out) {

@@ -31,11 +31,11 @@ namespace pdhg {
 // for each mode only the rows up to the point after which every rounded row
 // equals the last one are stored.
 template <typename T>
-void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
-                       std::vector<int>& off, std::vector<int>& last) {
+void build_factor_rows_shifts(const pdhg_problem& p, const std::vector<long double>& shifts,
+                              std::vector<FacRow<T>>& rows, std::vector<int>& off, std::vector<int>& last) {
   typedef long double LD;
-  const int nt = p.nt, nx = p.nx;
-  const LD ht = (LD)p.t_final / nt, hx = (LD)p.length / nx;
+  const int nt = p.nt;
+  const LD ht = (LD)p.t_final / nt;
   const bool bdf2 = p.time == PDHG_BDF2;
   auto coef = [&](int l, int d) -> LD {   // B_t[l][l-d] * h_t
     if (d == 0) return (bdf2 && l >= 1) ? 1.5L : 1.0L;
@@ -55,17 +55,14 @@ void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector
     }
     return s;
   };
-  const LD PI = 3.141592653589793238462643383279502884L;
-  const int nmodes = nx / 2 + 1;
+  const int nmodes = (int)shifts.size();
   off.assign(nmodes, 0);
   last.assign(nmodes, 0);
   rows.clear();
   std::vector<LD> d(nt), e1(nt), e2(nt);
   std::vector<FacRow<T>> tmp(nt);
   for (int k = 0; k < nmodes; ++k) {
-    const LD sn = sinl(PI * k / nx);
-    const LD mu = 4.0L * sn * sn / (hx * hx);
-    const LD shift = (LD)c * c * mu + (LD)ghat * ghat * mu * mu;
+    const LD shift = shifts[k];
     for (int l = 0; l < nt; ++l) {
       const LD k0 = kband(l, 0) / (ht * ht) + shift;
       const LD k1 = kband(l, 1) / (ht * ht);
@@ -83,10 +80,35 @@ void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector
   }
 }
 
+// Banded Cholesky factors of (B_t B_t^T + s_k I), k = 0..nx/2, s_k = c^2 mu_k +
+// ghat^2 mu_k^2 with mu_k = 4 sin^2(pi k / nx) / h_x^2, computed in long double and
+// rounded to T.  B_t is the time difference acting on the unknown levels (row l:
+// c0(l) at column l, c1(l) at l-1, c2(l) at l-2, all over h_t).  Rows of L
+// converge to those of the infinite Toeplitz factor; for each mode only the rows
+// up to the point after which every rounded row equals the last one are stored.
+template <typename T>
+void build_factor_rows(const pdhg_problem& p, double c, double ghat, std::vector<FacRow<T>>& rows,
+                       std::vector<int>& off, std::vector<int>& last) {
+  typedef long double LD;
+  const LD hx = (LD)p.length / p.nx;
+  const LD PI = 3.141592653589793238462643383279502884L;
+  std::vector<LD> shifts(p.nx / 2 + 1);
+  for (int k = 0; k <= p.nx / 2; ++k) {
+    const LD sn = sinl(PI * k / p.nx);
+    const LD mu = 4.0L * sn * sn / (hx * hx);
+    shifts[k] = (LD)c * c * mu + (LD)ghat * ghat * mu * mu;
+  }
+  build_factor_rows_shifts<T>(p, shifts, rows, off, last);
+}
+
 template void build_factor_rows<float>(const pdhg_problem&, double, double, std::vector<FacRow<float>>&,
                                         std::vector<int>&, std::vector<int>&);
 template void build_factor_rows<double>(const pdhg_problem&, double, double, std::vector<FacRow<double>>&,
                                          std::vector<int>&, std::vector<int>&);
+template void build_factor_rows_shifts<float>(const pdhg_problem&, const std::vector<long double>&,
+                                              std::vector<FacRow<float>>&, std::vector<int>&, std::vector<int>&);
+template void build_factor_rows_shifts<double>(const pdhg_problem&, const std::vector<long double>&,
+                                               std::vector<FacRow<double>>&, std::vector<int>&, std::vector<int>&);
 
 }  // namespace pdhg
 
@@ -126,6 +148,7 @@ struct pdhg_handle {
   int* d_fac_off = nullptr;
   int* d_fac_last = nullptr;
   double fac_c = -1.0, fac_g = -1.0;
+  void* d_vtab = nullptr;       // DG: per-mode 6x6 eigenbases of the coefficient coupling
   // resolved constants
   double lf = 0.0, c = 0.0;
   bool consts_valid = false;
@@ -163,9 +186,12 @@ int set_hip_error(pdhg_handle* h, hipError_t e, const char* what) {
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// Coefficients per cell: 3 for DG P2, 1 for finite differences.
+inline int planes(const pdhg_problem& p) { return p.space == PDHG_DG_P2_LLF ? 3 : 1; }
+
 WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   WsLayout L{};
-  const size_t nx = (size_t)p.nx, nt = (size_t)p.nt;
+  const size_t nx = (size_t)p.nx * planes(p), nt = (size_t)p.nt;
   const size_t field = align_up(nt * nx * esz);
   const size_t ufield = align_up((nt + 1) * nx * esz);
   // per-block partial sums of the element-wise kernels, or nt+1 level sums
@@ -223,6 +249,115 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
   return PDHG_OK;
 }
 
+// Eigen-decomposition of a real symmetric 6x6 matrix by cyclic Jacobi rotations
+// (long double): A = V diag(w) V^T, columns of V the eigenvectors.
+void jacobi6(long double A[6][6], long double V[6][6], long double w[6]) {
+  typedef long double LD;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) V[i][j] = (i == j) ? 1.0L : 0.0L;
+  LD scale = 0.0L;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) scale += A[i][j] * A[i][j];
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    LD off = 0.0L;
+    for (int p = 0; p < 6; ++p)
+      for (int q = p + 1; q < 6; ++q) off += A[p][q] * A[p][q];
+    if (off <= 1e-36L * scale) break;
+    for (int p = 0; p < 6; ++p)
+      for (int q = p + 1; q < 6; ++q) {
+        if (A[p][q] == 0.0L) continue;
+        const LD th = (A[q][q] - A[p][p]) / (2.0L * A[p][q]);
+        const LD t = (th >= 0.0L ? 1.0L : -1.0L) / (fabsl(th) + sqrtl(th * th + 1.0L));
+        const LD c = 1.0L / sqrtl(t * t + 1.0L), sn = t * c;
+        for (int k = 0; k < 6; ++k) {   // columns p, q
+          const LD akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 6; ++k) {   // rows p, q
+          const LD apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 6; ++k) {
+          const LD vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 6; ++i) w[i] = A[i][i];
+}
+
+// DG preconditioner data: for each Fourier mode m = 0..nx/2 over the cells, the
+// unit-speed upwind DG symbol G(theta) = G_0 + G_-1 e^{-i theta} (theta = 2 pi m / nx),
+// G_0 = [1 1 1; -3 3 3; 5 -5 5] / h_x, G_-1 = [-1 -1 -1; 3 3 3; -5 -5 -5] / h_x, the
+// Hermitian coupling H = c^2 G G^*, and the eigen-decomposition of its real 6x6
+// form [Re H, -Im H; Im H, Re H] (acting on (Re, Im) of the three coefficient
+// planes).  Uploads the factor tables of B_t B_t^T + lambda (6 per mode) and the
+// eigenvector matrices (36 values per mode).
+template <typename T>
+int upload_factors_dg(pdhg_handle* h, double c) {
+  typedef long double LD;
+  const int nx = h->prob.nx, nmodes = nx / 2 + 1;
+  const LD hx = (LD)h->prob.length / nx, PI = 3.141592653589793238462643383279502884L;
+  const LD g0[3][3] = {{1, 1, 1}, {-3, 3, 3}, {5, -5, 5}};
+  const LD gm[3][3] = {{-1, -1, -1}, {3, 3, 3}, {-5, -5, -5}};
+  std::vector<long double> shifts((size_t)nmodes * 6);
+  std::vector<T> vtab((size_t)nmodes * 36);
+  for (int m = 0; m < nmodes; ++m) {
+    // e^{-i theta}; exactly real for the real modes 0 and nx/2
+    const LD th = 2.0L * PI * m / nx;
+    const LD cr = (m == 0) ? 1.0L : (2 * m == nx ? -1.0L : cosl(th));
+    const LD ci = (m == 0 || 2 * m == nx) ? 0.0L : -sinl(th);
+    LD Gr[3][3], Gi[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        Gr[a][b] = (g0[a][b] + gm[a][b] * cr) / hx;
+        Gi[a][b] = (gm[a][b] * ci) / hx;
+      }
+    LD A[6][6], V[6][6], w[6];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        LD hr = 0.0L, hi = 0.0L;   // (G G^*)_ab = sum_k G_ak conj(G_bk)
+        for (int k = 0; k < 3; ++k) {
+          hr += Gr[a][k] * Gr[b][k] + Gi[a][k] * Gi[b][k];
+          hi += Gi[a][k] * Gr[b][k] - Gr[a][k] * Gi[b][k];
+        }
+        hr *= (LD)c * c;
+        hi *= (LD)c * c;
+        A[a][b] = hr;
+        A[a + 3][b + 3] = hr;
+        A[a][b + 3] = -hi;
+        A[a + 3][b] = hi;
+      }
+    jacobi6(A, V, w);
+    for (int b = 0; b < 6; ++b) shifts[(size_t)m * 6 + b] = w[b] > 0.0L ? w[b] : 0.0L;
+    for (int r = 0; r < 6; ++r)
+      for (int b = 0; b < 6; ++b) vtab[(size_t)m * 36 + r * 6 + b] = (T)V[r][b];
+  }
+  std::vector<FacRow<T>> rows;
+  std::vector<int> off, last;
+  build_factor_rows_shifts<T>(h->prob, shifts, rows, off, last);
+  if (h->d_fac_rows) hipFree(h->d_fac_rows);
+  if (h->d_fac_off) hipFree(h->d_fac_off);
+  if (h->d_fac_last) hipFree(h->d_fac_last);
+  if (h->d_vtab) hipFree(h->d_vtab);
+  h->d_fac_rows = h->d_vtab = nullptr;
+  h->d_fac_off = h->d_fac_last = nullptr;
+  HIP_TRY(hipMalloc(&h->d_fac_rows, rows.size() * sizeof(FacRow<T>)));
+  HIP_TRY(hipMalloc((void**)&h->d_fac_off, off.size() * sizeof(int)));
+  HIP_TRY(hipMalloc((void**)&h->d_fac_last, last.size() * sizeof(int)));
+  HIP_TRY(hipMalloc(&h->d_vtab, vtab.size() * sizeof(T)));
+  HIP_TRY(hipMemcpy(h->d_fac_rows, rows.data(), rows.size() * sizeof(FacRow<T>), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_fac_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_fac_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_vtab, vtab.data(), vtab.size() * sizeof(T), hipMemcpyHostToDevice));
+  h->fac_c = c;
+  h->fac_g = 0.0;
+  return PDHG_OK;
+}
+
 template <typename T>
 int upload_twiddles(pdhg_handle* h) {
   const int n = h->prob.nx;
@@ -262,7 +397,10 @@ template <typename T>
 int max_abs_dflux(pdhg_handle* h, const T* u0, void* ws, hipStream_t st, double* out) {
   const WsLayout L = layout_for(h->prob, h->esz);
   double* part = (double*)wsp(ws, L.part_rp);
-  HIP_TRY(launch_maxabs_dflux<T>(u0, (size_t)h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
+  if (h->prob.space == PDHG_DG_P2_LLF)   // DG: over the cell-edge traces of u0_h
+    HIP_TRY(launch_dg_maxabs_trace<T>(u0, h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
+  else
+    HIP_TRY(launch_maxabs_dflux<T>(u0, (size_t)h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
   HIP_TRY(hipMemcpyAsync(h->h_scal, part, 64 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   double m = 0.0;
@@ -287,7 +425,12 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
   h->lf = lf;
   h->c = c;
   h->consts_valid = true;
-  if (!h->d_fac_rows || h->fac_c != c || h->fac_g != p.precond_gamma_hat) {
+  if (p.space == PDHG_DG_P2_LLF) {
+    if (!h->d_fac_rows || h->fac_c != c) {
+      int rc = upload_factors_dg<T>(h, c);
+      if (rc) return rc;
+    }
+  } else if (!h->d_fac_rows || h->fac_c != c || h->fac_g != p.precond_gamma_hat) {
     int rc = upload_factors<T>(h, c, p.precond_gamma_hat);
     if (rc) return rc;
   }
@@ -298,6 +441,14 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
 template <typename T>
 int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
   const pdhg_problem& p = h->prob;
+  if (p.space == PDHG_DG_P2_LLF) {   // 3 nt coefficient rows; per-mode eigenbasis in the column solve
+    const int nr = 3 * p.nt;
+    HIP_TRY(launch_rows_fwd<T>(r, nr, spec, nr, h->lqb, p.nx, h->d_tw, nullptr, st));
+    HIP_TRY(launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
+                                  h->lqb, nullptr, st));
+    HIP_TRY(launch_rows_inv<T>(spec, nr, h->lqb, s, nr, p.nx, h->d_tw, nullptr, st));
+    return PDHG_OK;
+  }
   HIP_TRY(launch_rows_fwd<T>(r, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st));
   HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st));
   HIP_TRY(launch_rows_inv<T>(spec, p.nt, h->lqb, s, p.nt, p.nx, h->d_tw, nullptr, st));
@@ -310,7 +461,8 @@ int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int it
   const pdhg_problem& p = h->prob;
   const WsLayout L = layout_for(p, h->esz);
   const Scheme s = scheme_of(h);
-  const size_t n = (size_t)p.nt * p.nx;
+  const bool dg = p.space == PDHG_DG_P2_LLF;
+  const size_t n = (size_t)p.nt * p.nx * planes(p);
   T* v = (T*)wsp(ws, L.srow);
   T* w = (T*)wsp(ws, L.phibar);
   T* t = (T*)wsp(ws, L.spec1);
@@ -329,10 +481,12 @@ int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int it
   HIP_TRY(launch_normalize<T>(v, n, scal, st));
   double lam = 0.0;
   for (int it = 0; it < iters; ++it) {
-    HIP_TRY(launch_apply_j<T>(s, u, v, w, st));                  // w = J v
+    if (dg) HIP_TRY(launch_dg_apply_j<T>(s, u, v, w, st));       // w = J v
+    else HIP_TRY(launch_apply_j<T>(s, u, v, w, st));
     int rc = precond_apply<T>(h, w, w, spec, st);                 // w = K_d^{-1} w
     if (rc) return rc;
-    HIP_TRY(launch_apply_jt<T>(s, u, w, t, nullptr, st, nullptr)); // t = J^T w
+    if (dg) HIP_TRY(launch_dg_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));   // t = J^T w
+    else HIP_TRY(launch_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));
     HIP_TRY(launch_dot<T>(t, v, n, part, scal, st));             // scal[0] = <t, v>
     HIP_TRY(launch_dot<T>(t, nullptr, n, part, scal + 1, st));   // scal[1] = |t|^2
     HIP_TRY(launch_normalize<T>(t, n, scal + 1, st));
@@ -372,9 +526,11 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   if (!is_pow2(p.nx) || p.nx < 8 || p.nx > 4096 || p.nt < 1) return PDHG_EINVAL;
   if (!(p.length > 0) || !(p.t_final > 0) || p.gamma < 0 || p.precond_gamma_hat < 0) return PDHG_EINVAL;
   if (p.time != PDHG_BE && p.time != PDHG_BDF2) return PDHG_EINVAL;
-  if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF) return PDHG_EINVAL;
+  if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF && p.space != PDHG_DG_P2_LLF) return PDHG_EINVAL;
   if (p.dtype != PDHG_F32 && p.dtype != PDHG_F64) return PDHG_EINVAL;
   if (p.nt > 2048) return PDHG_EUNSUPPORTED;   // column solve: <= 32 segments of <= 64 levels
+  // DG: nx cells >= 16 (8 spectrum columns per column block), nt <= 512 (8 levels per lane), no viscosity
+  if (p.space == PDHG_DG_P2_LLF && (p.nx < 16 || p.nt > 512 || p.gamma != 0.0)) return PDHG_EUNSUPPORTED;
   pdhg_handle* h = new (std::nothrow) pdhg_handle();
   if (!h) return PDHG_EINVAL;
   h->prob = p;
@@ -412,6 +568,7 @@ void pdhg_destroy(pdhg_handle* h) {
   if (h->d_fac_rows) hipFree(h->d_fac_rows);
   if (h->d_fac_off) hipFree(h->d_fac_off);
   if (h->d_fac_last) hipFree(h->d_fac_last);
+  if (h->d_vtab) hipFree(h->d_vtab);
   if (h->own_ws) hipFree(h->own_ws);
   if (h->h_ctrl) hipHostFree(h->h_ctrl);
   if (h->h_scal) hipHostFree(h->h_scal);
@@ -491,6 +648,41 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
   return PDHG_OK;
 }
 
+// One DG loop body: A (inverse FFT + dual step over the 3 nt coefficient rows),
+// primal step + dual residual, implicit residual, forward FFT, column solve in
+// the per-mode eigenbasis, norms and stopping decision.
+template <typename T>
+int enqueue_body_dg(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist,
+                    hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  const WsLayout L = layout_for(p, h->esz);
+  const Scheme s = scheme_of(h);
+  T* u_alt = (T*)wsp(ws, L.u_alt);
+  T* spec = (T*)wsp(ws, L.spec0);
+  T* srow = (T*)wsp(ws, L.srow);
+  T* phibar = (T*)wsp(ws, L.phibar);
+  double* prp = (double*)wsp(ws, L.part_rp);
+  double* prd = (double*)wsp(ws, L.part_rd);
+  Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
+  T* uin = odd ? u : u_alt;
+  T* uout = odd ? u_alt : u;
+  const int nr = 3 * p.nt;
+  int nb_rd = 0, nb_rp = 0;
+  if (p.nx >= 64) {
+    HIP_TRY(launch_dual_fft<T>(spec, nr, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
+  } else {
+    HIP_TRY(launch_rows_inv<T>(spec, nr, h->lqb, srow, nr, p.nx, h->d_tw, ctrl, st));
+    HIP_TRY(launch_dual<T>(phi, phibar, srow, (size_t)nr * p.nx, tau_phi, ctrl, st));
+  }
+  HIP_TRY(launch_dg_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
+  HIP_TRY(launch_dg_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
+  HIP_TRY(launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, ctrl, st));
+  HIP_TRY(launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
+                                h->lqb, ctrl, st));
+  HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
+  return PDHG_OK;
+}
+
 template <typename T>
 int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist) {
   if (h->gexec && h->gkey == key) return PDHG_OK;
@@ -499,7 +691,9 @@ int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T t
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = PDHG_OK;
   for (int b = 0; b < key.chunk && rc == PDHG_OK; ++b) {
-    if (key.variant == 1)
+    if (key.variant == 4)
+      rc = enqueue_body_dg<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
+    else if (key.variant == 1)
       rc = enqueue_body_unfused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
     else
       rc = enqueue_body_fused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
@@ -521,15 +715,17 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   int rc = ensure_workspace(h, ws);
   if (rc) return rc;
   const WsLayout L = layout_for(p, h->esz);
-  const size_t nlev = (size_t)(p.nt + 1) * p.nx, n = (size_t)p.nt * p.nx;
+  const int row = p.nx * planes(p);   // elements per level
+  const bool dg = p.space == PDHG_DG_P2_LLF;
+  const size_t nlev = (size_t)(p.nt + 1) * row, n = (size_t)p.nt * row;
   T* u_alt = (T*)wsp(ws, L.u_alt);
   T* spec = (T*)wsp(ws, L.spec0);
   Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
   // initial guess (Section 3.3): u^l = u0, phi = 0 unless warm start; u^0 = u0 always
   if (prm->warm_start) {
-    HIP_TRY(launch_copy<T>(u, u0, (size_t)p.nx, st));
+    HIP_TRY(launch_copy<T>(u, u0, (size_t)row, st));
   } else {
-    HIP_TRY(launch_broadcast_levels<T>(u, u0, p.nx, p.nt + 1, st));
+    HIP_TRY(launch_broadcast_levels<T>(u, u0, row, p.nt + 1, st));
     HIP_TRY(launch_fill<T>(phi, n, T(0), st));
   }
   rc = resolve_constants<T>(h, u0, ws, st);
@@ -537,7 +733,7 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
   if (tau_u <= 0.0 || tau_phi <= 0.0) {
     // power iteration at the constant extension u^l = u0 (u_alt used as scratch)
-    HIP_TRY(launch_broadcast_levels<T>(u_alt, u0, p.nx, p.nt + 1, st));
+    HIP_TRY(launch_broadcast_levels<T>(u_alt, u0, row, p.nt + 1, st));
     rc = power_iteration<T>(h, u_alt, ws, st, 200, &nu);
     if (rc) return rc;
     if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
@@ -553,9 +749,10 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   GraphKey key;
   key.u = u; key.phi = phi; key.ws = ws; key.hist = prm->history;
   key.tau_u = tau_u; key.tau_phi = tau_phi; key.lf = h->lf; key.c = h->c;
-  // fused passes need at least one full wavefront per row (nx >= 64)
-  if (prm->variant == 2 && p.nx < 64) return PDHG_EUNSUPPORTED;
-  key.variant = (prm->variant == 1 || p.nx < 64) ? 1 : 2;
+  // fused passes need at least one full wavefront per row (nx >= 64); DG has its own body
+  if (prm->variant == 2 && p.nx < 64 && !dg) return PDHG_EUNSUPPORTED;
+  if (dg && prm->variant != 0 && prm->variant != 4) return PDHG_EUNSUPPORTED;
+  key.variant = dg ? 4 : ((prm->variant == 1 || p.nx < 64) ? 1 : 2);
   key.chunk = chunk;
   h->last = key;
   const long long bodies = prm->max_iter + 1;
@@ -592,7 +789,7 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   double drift = 0.0;
   {
     double* lev = (double*)wsp(ws, L.part_rp);   // nt+1 <= max_parts
-    HIP_TRY(launch_level_sums<T>(u, p.nx, p.nt + 1, lev, st));
+    HIP_TRY(launch_level_sums<T>(u, p.nx, (size_t)row, p.nt + 1, lev, st));   // DG: cell averages (plane 0)
     std::vector<double> m(p.nt + 1);
     HIP_TRY(hipMemcpyAsync(m.data(), lev, m.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -651,8 +848,13 @@ int residual_impl(pdhg_handle* h, const T* u, const T* phi, T* Au, T* JTphi, dou
   double* prp = (double*)wsp(ws, L.part_rp);
   double* prd = (double*)wsp(ws, L.part_rd);
   int nb1 = 0, nb2 = 0;
-  HIP_TRY(launch_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
-  if (phi) HIP_TRY(launch_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  if (h->prob.space == PDHG_DG_P2_LLF) {
+    HIP_TRY(launch_dg_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
+    if (phi) HIP_TRY(launch_dg_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  } else {
+    HIP_TRY(launch_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
+    if (phi) HIP_TRY(launch_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  }
   if (res) {
     // reduce the partials on the host (few thousand doubles)
     std::vector<double> a(nb1), b(nb2);
@@ -675,7 +877,8 @@ int precond_impl(pdhg_handle* h, const T* r, T* s, hipStream_t st) {
   if (rc) return rc;
   if (!h->d_fac_rows) {
     if (h->prob.precond_c < 0.0) return PDHG_EINVAL;
-    rc = upload_factors<T>(h, h->prob.precond_c, h->prob.precond_gamma_hat);
+    rc = (h->prob.space == PDHG_DG_P2_LLF) ? upload_factors_dg<T>(h, h->prob.precond_c)
+                                          : upload_factors<T>(h, h->prob.precond_c, h->prob.precond_gamma_hat);
     if (rc) return rc;
   }
   const WsLayout L = layout_for(h->prob, h->esz);
@@ -691,11 +894,14 @@ int adjoint_impl(pdhg_handle* h, int mode, const T* u, const T* in, T* out, T* m
     if (rc) return rc;
   }
   const Scheme s = scheme_of(h);
+  const bool dg = h->prob.space == PDHG_DG_P2_LLF;
   if (mode == PDHG_ADJ_APPLY) {
-    HIP_TRY(launch_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
+    if (dg) HIP_TRY(launch_dg_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
+    else HIP_TRY(launch_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
     return PDHG_OK;
   }
   if (mode != PDHG_ADJ_SOLVE) return PDHG_EINVAL;
+  if (dg) return PDHG_EUNSUPPORTED;   // the backward march is implemented for finite differences
   HIP_TRY(launch_adjoint_march<T>(s, u, in, mu, out, st));
   return PDHG_OK;
 }
@@ -716,11 +922,27 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
   T* phibar = (T*)wsp(ws, L.phibar);
   double* prp = (double*)wsp(ws, L.part_rp);
   double* prd = (double*)wsp(ws, L.part_rd);
-  const size_t n = (size_t)p.nt * p.nx;
+  const size_t n = (size_t)p.nt * p.nx * planes(p);
   const T tu = (T)h->last.tau_u, tp = (T)h->last.tau_phi;
   Ctrl* ctrl_t = (Ctrl*)wsp(ws, L.ctrl_t);
   if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, st));
+  const int nr = 3 * p.nt;
+  auto launch_dg = [&]() -> hipError_t {
+    switch (kernel) {
+      case 1: return launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1,
+                                           p.nt, p.nx, h->lqb, nullptr, st);
+      case 4: return launch_dg_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
+      case 5: return launch_dg_residual<T>(s, u_alt, srow, prp, nullptr, st, nullptr);
+      case 6: return launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, nullptr, st);
+      case 7: return launch_dual_fft<T>(spec, nr, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
+      case 8: return launch_copy<T>(srow, phibar, n, st);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  if (p.space == PDHG_DG_P2_LLF && !(kernel == 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
+  if (p.space == PDHG_DG_P2_LLF && kernel == 7 && p.nx < 64) return PDHG_EUNSUPPORTED;
   auto launch = [&]() -> hipError_t {
+    if (p.space == PDHG_DG_P2_LLF) return launch_dg();
     switch (kernel) {
       case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);

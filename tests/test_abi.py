@@ -91,3 +91,16 @@ def test_batch_setup_rejects_before_touching_the_device(bad, code):
     assert lib.pdhg_batch_setup(arr, 2, C.byref(h)) == getattr(B, code)
     assert not h.value
     assert lib.pdhg_batch_setup(arr, 0, C.byref(h)) == B.PDHG_EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(nx=8), dict(nt=1024), dict(gamma=1e-3)])
+def test_dg_setup_limits(bad):
+    B, lib = _lib()
+    p = B.pdhg_problem()
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 64, 16, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype = B.PDHG_BE, B.PDHG_DG_P2_LLF, B.PDHG_F32
+    for k, v in bad.items():
+        setattr(p, k, v)
+    h = C.c_void_p()
+    assert lib.pdhg_setup(C.byref(p), C.byref(h)) == B.PDHG_EUNSUPPORTED
+    assert not h.value
