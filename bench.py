@@ -13,6 +13,7 @@ bounded sample of iterations of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload batch [--batch-iters N] [--ttr-problems M]
+    python bench.py --workload dg [--dg-iters N] [--dtype f32|f64]
 """
 import argparse
 import json
@@ -240,6 +241,112 @@ def batch_time_to_residual(pk, count, dev):
     return res
 
 
+DG_NX, DG_NT, DG_ITERS = 4096, 512, 2000
+DG_KERNELS = {   # kernel id: (name, algorithmic words per DOF; DOF = 3 coefficients x cells x levels)
+    7: ("A: inverse FFT + dual step", 4),
+    4: ("DG primal step + dual residual", 4),
+    5: ("DG implicit residual", 2),
+    6: ("forward row FFT", 2),
+    1: ("DG column solve (per-mode eigenbasis, banded Cholesky in t)", 2),
+}
+
+
+DG_CPU_NT = 64
+
+
+def dg_cpu_baseline(sample_iters: int):
+    """FP64 oracle Algorithm 1 with the DG P2 discretisation on a bounded sample of the workload: all
+    4096 cells, the first DG_CPU_NT levels (same h_t = 3 h_x), `sample_iters` iterations (the oracle's
+    dense per-mode solves make one full-size iteration take minutes)."""
+    import numpy as np
+
+    import synthetic as syn
+    from oracle import dg as odg
+    from oracle import pdhg as opdhg
+    from oracle.problem import Problem as OProblem, default_constants
+    u0 = odg.p2_project(lambda x: syn.fourier_u0_at(SEED, x), DG_NX)
+    op = default_constants(OProblem(nx=DG_NX, nt=DG_CPU_NT, t_final=3.0 * DG_CPU_NT / DG_NX, alpha=0.5, beta=0.0,
+                                    space="dg_p2_llf", time="be"), u0)
+    c0, t0 = time.process_time(), time.perf_counter()
+    opdhg.run(op, u0, 0.6, 0.6, eps=0.0, max_iter=sample_iters)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {"value": 3 * DG_NX * DG_CPU_NT * sample_iters / wall, "unit": "DOF-iterations/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1, DG P2) on the "
+                      f"workload's {DG_NX} cells and first {DG_CPU_NT} levels (h_t = 3 h_x); {wall:.1f} s wall, "
+                      f"host has {os.cpu_count()} CPUs"}
+
+
+def run_dg(args):
+    """Burgers with DG P2 (Legendre, local Lax-Friedrichs), 4096 cells x 512 levels, h_t = 3 h_x,
+    backward Euler, seeded Fourier u0 projected on P2; FP32 by default, fixed iteration budget."""
+    import torch
+
+    import paper_2207_07234_amd as pk
+    import synthetic as syn
+    from oracle import dg as odg   # projection of the initial data onto P2 (input preparation)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dtype = torch.float32 if args.dtype in (None, "f32") else torch.float64
+    esz = 4 if dtype == torch.float32 else 8
+    T = 3.0 * DG_NT / DG_NX
+    prob = pk.Problem(nx=DG_NX, nt=DG_NT, t_final=T, alpha=0.5, beta=0.0, time="be", space="dg_p2_llf",
+                      dtype=dtype)
+    solver = pk.Solver(prob)
+    u0 = torch.tensor(odg.p2_project(lambda x: syn.fourier_u0_at(SEED, x), DG_NX), dtype=dtype, device=dev)
+    u = torch.empty((DG_NT + 1, 3, DG_NX), dtype=dtype, device=dev)
+    phi = torch.empty((DG_NT, 3, DG_NX), dtype=dtype, device=dev)
+    ws = torch.empty(solver.workspace_bytes, dtype=torch.uint8, device=dev)
+    iters = args.dg_iters
+    kw = dict(u=u, phi=phi, workspace=ws, check_every=128, eps=args.dg_eps, max_iter=iters)
+    first = solver.solve(u0, **kw)
+    tau = first.stats["tau_u"]
+    log(f"DG warm-up: nu_max {first.stats['nu_max']:.4f} tau {tau:.4f} Rp {first.stats['res_primal']:.3e}")
+    for _ in range(max(0, args.warmup - 1)):
+        solver.solve(u0, tau_u=tau, tau_phi=tau, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for k in range(args.steps):
+        r = solver.solve(u0, tau_u=tau, tau_phi=tau, **kw)
+        done += r.stats["iters"]
+        log(f"DG step {k}: status {r.status} iters {r.stats['iters']} Rp {r.stats['res_primal']:.3e} "
+            f"Rd {r.stats['res_dual']:.3e} loop {r.stats['seconds']*1e3:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dof = 3 * DG_NX * DG_NT
+    value = dof * done / wall
+    iters = r.stats["iters"]
+    kern = {}
+    for kid, (name, words) in DG_KERNELS.items():
+        ms = solver.time_kernel(kid, reps=30)
+        kern[kid] = (name, words, ms, words * esz * dof / (ms * 1e-3) / 1e9)
+        log(f"DG kernel {kid} {name}: {ms*1e3:.1f} us/launch, {kern[kid][3]:.0f} GB/s algorithmic")
+    dom = max(kern, key=lambda k: kern[k][2])
+    name, words, ms, gbs = kern[dom]
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if dtype == torch.float32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Burgers, DG P2 Legendre with local Lax-Friedrichs flux, backward Euler, "
+                               f"{DG_NX} cells x {DG_NT} levels, h_t = 3 h_x (T = {T}), seeded Fourier u0 projected "
+                               f"on P2, {iters} iterations per solve",
+                   "cells": DG_NX, "nt": DG_NT, "dof": dof, "iterations_per_solve": iters, "tau": tau,
+                   "res_primal": r.stats["res_primal"], "res_dual": r.stats["res_dual"],
+                   "us_per_iteration_wall": wall / done * 1e6, "eps": args.dg_eps,
+                   "time_to_residual_s": wall / args.steps if args.dg_eps > 0 else None, "status": r.status,
+                   "kernel_sum_us_per_iteration": sum(v[2] for v in kern.values()) * 1e3},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "DG " + name,
+                     "bytes_per_launch": words * esz * dof, "ms_per_launch": ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = dg_cpu_baseline(args.dg_cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,7 +359,11 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None,
                     help="compute type (default f64 for the single workload, f32 for the batch)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto (fused), 1 unfused, 2 fused")
-    ap.add_argument("--workload", choices=["burgers", "batch"], default="burgers")
+    ap.add_argument("--workload", choices=["burgers", "batch", "dg"], default="burgers")
+    ap.add_argument("--dg-iters", type=int, default=DG_ITERS)
+    ap.add_argument("--dg-cpu-iters", type=int, default=2)
+    ap.add_argument("--dg-eps", type=float, default=0.0,
+                    help="DG workload: solve to this residual (max --dg-iters iterations) instead of a fixed count")
     ap.add_argument("--batch-iters", type=int, default=BATCH_ITERS)
     ap.add_argument("--ttr-problems", type=int, default=32,
                     help="batch workload: FP64 time-to-residual comparison on this many problems (0 = skip)")
@@ -263,6 +374,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "dg":
+        run_dg(args)
         return
     if args.dtype is None:
         args.dtype = "f64"
