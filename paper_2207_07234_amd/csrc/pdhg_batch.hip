@@ -133,7 +133,7 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
 
 // ------------------------------------------------------------------ C
 template <typename T>
-__global__ void __launch_bounds__(64 * kColWaves)
+__global__ void __launch_bounds__(64 * kFdColWaves)
 kb_colsolve(const BatchProb* __restrict__ probs, Ctrl* ctrls, const int2* __restrict__ tiles,
             const int* __restrict__ counts, T* __restrict__ spec, const double* __restrict__ part, int rd_base) {
   extern __shared__ char smem[];
@@ -359,7 +359,7 @@ hipError_t batch_occupancy(int which, int max_nx, int* blocks_per_cu) {
   }
   const size_t lds = batch_col_lds<T>();
   if ((e = allow_lds(kb_colsolve<T>, lds)) != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kb_colsolve<T>, 64 * kColWaves, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kb_colsolve<T>, 64 * kFdColWaves, lds);
 }
 
 template <typename T>
@@ -391,7 +391,7 @@ hipError_t launch_batch_colsolve(const BatchLaunch& L, int grid, T* spec, const 
   const size_t lds = batch_col_lds<T>();
   hipError_t e = allow_lds(kb_colsolve<T>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_colsolve<T>, dim3(grid), dim3(64 * kColWaves), lds, st, L.probs, L.ctrls, L.col_tiles,
+  hipLaunchKernelGGL(kb_colsolve<T>, dim3(grid), dim3(64 * kFdColWaves), lds, st, L.probs, L.ctrls, L.col_tiles,
                      L.counts, spec, part, rd_base);
   return hipGetLastError();
 }

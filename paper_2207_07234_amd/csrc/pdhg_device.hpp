@@ -287,6 +287,22 @@ __device__ __forceinline__ double from_lane_above(double v, double fill) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Generic DPP move with control word CTRL (all rows and banks enabled): lanes
+// whose source lane is invalid for CTRL receive `fill`.  Row shifts within rows
+// of 16 lanes: row_shr:n = 0x110 + n (from lane l - n), row_shl:n = 0x100 + n
+// (from lane l + n).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v, float fill) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v, double fill) {
+  const long long a = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffll), (int)(a & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(a >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Value of v in lane `src` (uniform result).
 __device__ __forceinline__ float read_lane(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));

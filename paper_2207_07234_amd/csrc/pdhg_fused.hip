@@ -25,10 +25,13 @@
 namespace pdhg {
 
 constexpr int kRowThreadsMax = 512;
-// Row-pair blocks of the primal pass: up to 1024 threads in FP32 (E = 4 points
-// per thread for every nx <= 4096), 512 in FP64 (register budget).
-template <typename T>
-constexpr int row_threads_max() { return sizeof(T) == 4 ? 1024 : 512; }
+// Row-pair blocks of the primal pass.  The pass holds about 18 E values per
+// thread (four u levels twice, six phibar rows, four phi rows), so blocks of up
+// to 1024 threads (4 waves per SIMD, <= 128 VGPRs) are possible while E values
+// of type T fit in 16 bytes per row (FP32 E <= 4, FP64 E <= 2); larger E keeps
+// 512-thread blocks.
+template <typename T, int E>
+constexpr int row_threads_max() { return E * (int)sizeof(T) <= 16 ? 1024 : 512; }
 
 // A: one block per pair of dual rows, W = nx / EPT threads.
 template <typename T, int EPT>
@@ -48,7 +51,7 @@ k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __r
 // per-block partial sums go to part[blk] and part[gridDim + blk]; the column
 // solve of the same iteration reduces them.
 template <typename T, int E>
-__global__ void __launch_bounds__(row_threads_max<T>())
+__global__ void __launch_bounds__((row_threads_max<T, E>()))
 k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
              const T* __restrict__ phi, T tau_u, T* __restrict__ spec, int lqb, const C2<T>* __restrict__ tw,
              double* __restrict__ part, const Ctrl* ctrl) {
@@ -59,7 +62,7 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(nx);
   T* edge = reinterpret_cast<T*>(twl + lds_fft_points(nx));   // [2 rows][first, last][nw]
-  __shared__ double red[row_threads_max<T>() / 64];
+  __shared__ double red[row_threads_max<T, E>() / 64];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   double rp, rd;
   primal_res_pair<T, E>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
@@ -72,11 +75,11 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   }
 }
 
-// C: 4 waves per block, 8 spectrum columns per block.  With part != NULL the
+// C: 8 waves per block, one spectrum column each.  With part != NULL the
 // first wave of block 0 first reduces the iteration's partial sums and takes
 // the stopping decision.
 template <typename T, int BW, int LPL>
-__global__ void __launch_bounds__(64 * kColWaves)
+__global__ void __launch_bounds__(64 * kFdColWaves)
 k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
                 int nparts, double wscale, double* hist) {
   if (ctrl && ctrl->status != 0) return;
@@ -129,12 +132,15 @@ static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, 
   return hipGetLastError();
 }
 
-// B: W = 64 * clamp(nx / 256, 1, row_threads_max / 64) threads, E = nx / W points
-// per thread (nx >= 64).
+// B: E = 4 points per thread in FP32 (W = nx / 4 <= 1024 threads); in FP64
+// E = 2 up to nx = 2048 (W = nx / 2 <= 1024), E = 8 at nx = 4096 (W = 512);
+// W >= 64 (nx >= 64).
 template <typename T>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
                              T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st) {
-  const int W = 64 * clampi(s.nx / 256, 1, row_threads_max<T>() / 64);
+  int W;
+  if (sizeof(T) == 4) W = clampi(s.nx / 4, 64, 1024);
+  else W = s.nx <= 2048 ? clampi(s.nx / 2, 64, 1024) : 512;
   switch (s.nx / W) {
     case 1: return launch_primal_res_e<T, 1>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
     case 2: return launch_primal_res_e<T, 2>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
@@ -151,7 +157,7 @@ static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, 
   const size_t lds = sizeof(T) * (size_t)kColCols * LPL * 65;
   hipError_t e = allow_lds(k_colsolve_wave<T, BW, LPL>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_colsolve_wave<T, BW, LPL>), dim3(nx / kColCols), dim3(64 * kColWaves), lds, st, spec, fac,
+  hipLaunchKernelGGL((k_colsolve_wave<T, BW, LPL>), dim3(nx / kColCols), dim3(64 * kFdColWaves), lds, st, spec, fac,
                      nt, nx, lqb, ctrl, part, nparts, wscale, hist);
   return hipGetLastError();
 }

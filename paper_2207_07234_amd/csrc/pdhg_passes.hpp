@@ -270,22 +270,18 @@ __device__ __forceinline__ double subgroup_sum(double v, double* red, int w0, in
 }
 
 // ------------------------------------------------------------------ C
-// Banded Cholesky solve along t.  One wavefront per Fourier mode k handles the
-// two halfcomplex columns of that mode (Re and Im share the factor; the first
-// wave of the spectrum handles the real columns of modes 0 and nx/2).  Lane j
-// owns levels [j LPL, (j+1) LPL).  Each lane computes the affine map of its
-// segment (particular solution and the responses to the two incoming values),
-// an inclusive scan of the maps across the 64 lanes (shuffles, no barriers)
-// gives every lane its incoming state, and the segment is re-run from it.
-// The block stages a [nt][8-column] tile of the spectrum through LDS (lane-major,
-// padded) so that global accesses are coalesced and LDS accesses conflict-free.
-constexpr int kColWaves = 4;
-constexpr int kColCols = 2 * kColWaves;
-
-template <typename T>
-__device__ __forceinline__ T shfl_up_T(T v, int d) { return __shfl_up(v, d, 64); }
-template <typename T>
-__device__ __forceinline__ T shfl_down_T(T v, int d) { return __shfl_down(v, d, 64); }
+// Banded Cholesky solve along t.  One wavefront per halfcomplex column (the
+// column's Fourier mode selects the factor; columns 0 and 1 are the real
+// columns of modes 0 and nx/2).  Lane j owns levels [j LPL, (j+1) LPL).  Each
+// lane computes the affine map of its segment (particular solution and the
+// responses to the two incoming values), an inclusive scan of the maps across
+// the 64 lanes (shuffles, no barriers) gives every lane its incoming state, and
+// the segment is re-run from it.  The block stages a [nt][8-column] tile of the
+// spectrum through LDS (lane-major, padded) so that global accesses are
+// coalesced and LDS accesses conflict-free.
+constexpr int kColCols = 8;                // spectrum columns per block
+constexpr int kFdColWaves = kColCols;      // finite differences: one wave per column
+constexpr int kColWaves = 4;               // DG: one wave per mode (its Re and Im columns)
 
 // (H, P) <- (H, P) o (H', P') : apply (H', P') first, then (H, P).
 template <typename T>
@@ -300,22 +296,57 @@ __device__ __forceinline__ void compose(T* H, T* P, const T* H2, const T* P2) {
   P[0] = p0; P[1] = p1;
 }
 
-// Inclusive scan of segment maps over the lanes, forward (from lane 0) or
+// One Kogge-Stone step inside rows of 16 lanes by DPP: compose with the map of
+// lane l - D (forward) or l + D (backward); lanes without such a lane in their
+// row compose with the identity map.
+template <typename T, bool FWD, int D>
+__device__ __forceinline__ void scan_step_row(T* H, T* P) {
+  constexpr int CTRL = FWD ? (0x110 + D) : (0x100 + D);
+  T H2[4], P2[2];
+  H2[0] = dpp_move<CTRL>(H[0], T(1));
+  H2[1] = dpp_move<CTRL>(H[1], T(0));
+  H2[2] = dpp_move<CTRL>(H[2], T(0));
+  H2[3] = dpp_move<CTRL>(H[3], T(1));
+  P2[0] = dpp_move<CTRL>(P[0], T(0));
+  P2[1] = dpp_move<CTRL>(P[1], T(0));
+  compose(H, P, H2, P2);
+}
+
+// Combine row `row` with the prefix held by lane `src` (read as a uniform value).
+template <typename T>
+__device__ __forceinline__ void scan_step_cross(T* H, T* P, int lane, int row, int src) {
+  T H2[4], P2[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) H2[k] = read_lane(H[k], src);
+  P2[0] = read_lane(P[0], src);
+  P2[1] = read_lane(P[1], src);
+  if ((lane >> 4) == row) compose(H, P, H2, P2);
+}
+
+// Inclusive scan of segment maps over the 64 lanes, forward (from lane 0) or
 // backward (from lane 63); returns the state entering this lane's segment.
+// Within each row of 16 lanes: DPP row shifts by 1, 2, 4, 8 (VALU, no LDS);
+// across rows: each row in turn composes with the full prefix of the rows
+// before it (forward) or after it (backward), read from one lane.
 template <typename T, bool FWD>
 __device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& in1) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    T H2[4], P2[2];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) H2[k] = FWD ? shfl_up_T(H[k], d) : shfl_down_T(H[k], d);
-    P2[0] = FWD ? shfl_up_T(P[0], d) : shfl_down_T(P[0], d);
-    P2[1] = FWD ? shfl_up_T(P[1], d) : shfl_down_T(P[1], d);
-    if (FWD ? (lane >= d) : (lane + d < 64)) compose(H, P, H2, P2);
+  scan_step_row<T, FWD, 1>(H, P);
+  scan_step_row<T, FWD, 2>(H, P);
+  scan_step_row<T, FWD, 4>(H, P);
+  scan_step_row<T, FWD, 8>(H, P);
+  if (FWD) {
+    scan_step_cross(H, P, lane, 1, 15);
+    scan_step_cross(H, P, lane, 2, 31);
+    scan_step_cross(H, P, lane, 3, 47);
+    in2 = from_lane_below(P[0], T(0));
+    in1 = from_lane_below(P[1], T(0));
+  } else {
+    scan_step_cross(H, P, lane, 2, 48);
+    scan_step_cross(H, P, lane, 1, 32);
+    scan_step_cross(H, P, lane, 0, 16);
+    in2 = from_lane_above(P[0], T(0));
+    in1 = from_lane_above(P[1], T(0));
   }
-  in2 = FWD ? shfl_up_T(P[0], 1) : shfl_down_T(P[0], 1);
-  in1 = FWD ? shfl_up_T(P[1], 1) : shfl_down_T(P[1], 1);
-  if (FWD ? (lane == 0) : (lane == 63)) { in2 = T(0); in1 = T(0); }
 }
 
 // Solve L L^T y = z in place for NC columns sharing the factor rows; z[c][i]
@@ -411,68 +442,54 @@ __device__ __forceinline__ void finalize_wave(Ctrl* ctrl, const double* __restri
   if (lane == 0) finalize_body(ctrl, a, b, wscale, hist);
 }
 
-// Column solve of spectrum columns q0..q0+7 (q0 a multiple of 8) by the 4
-// waves of the calling block.  tile: kColCols * LPL * 65 elements of LDS.
+// Column solve of spectrum columns q0..q0+7 (q0 a multiple of 8) by the 8
+// waves of the calling block, one column each.  tile: kColCols * LPL * 65
+// elements of LDS.
 template <typename T, int BW, int LPL>
 __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx, int lqb,
                                                int q0, T* tile) {
   const int QB = 1 << lqb;
   T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
   const int tid = threadIdx.x;
-  constexpr int kPer = 64 * LPL * kColCols / (64 * kColWaves);   // tile elements per thread
+  constexpr int kThreads = 64 * kFdColWaves;
+  constexpr int kPer = 64 * LPL * kColCols / kThreads;   // tile elements per thread
   const int wv = tid >> 6, lane = tid & 63;
-  const int qa = q0 + 2 * wv, qb = qa + 1;
-  const int ka = spec_mode(qa, nx), kb = spec_mode(qb, nx);
+  const int kmode = spec_mode(q0 + wv, nx);
   const int l0 = lane * LPL;
   // factor rows of this wave's mode first, so their latency overlaps the tile loads
   T invd[LPL], e1[LPL + 1], e2[LPL + 2];
-  load_factor_rows<T, LPL>(fac, ka, l0, invd, e1, e2);
+  load_factor_rows<T, LPL>(fac, kmode, l0, invd, e1, e2);
   // all tile loads in flight before the first LDS write
   T stage[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * 64 * kColWaves;
+    const int idx = tid + r * kThreads;
     const int l = idx / kColCols, c = idx % kColCols;
     stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * 64 * kColWaves;
+    const int idx = tid + r * kThreads;
     const int l = idx / kColCols, c = idx % kColCols;
     tile[(c * LPL + l % LPL) * 65 + l / LPL] = stage[r];
   }
   __syncthreads();
-  T z[2][LPL];
+  T z[1][LPL];
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int i = 0; i < LPL; ++i) z[0][i] = tile[(wv * LPL + i) * 65 + lane];
+  cholesky_solve_wave<T, BW, LPL, 1>(z, invd, e1, e2, lane, l0, nt);
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) z[c][i] = tile[((2 * wv + c) * LPL + i) * 65 + lane];
-  if (ka == kb) {
-    cholesky_solve_wave<T, BW, LPL, 2>(z, invd, e1, e2, lane, l0, nt);
-  } else {   // real columns of modes 0 and nx/2
-    T za[1][LPL], zb[1][LPL];
-#pragma unroll
-    for (int i = 0; i < LPL; ++i) { za[0][i] = z[0][i]; zb[0][i] = z[1][i]; }
-    cholesky_solve_wave<T, BW, LPL, 1>(za, invd, e1, e2, lane, l0, nt);
-    load_factor_rows<T, LPL>(fac, kb, l0, invd, e1, e2);
-    cholesky_solve_wave<T, BW, LPL, 1>(zb, invd, e1, e2, lane, l0, nt);
-#pragma unroll
-    for (int i = 0; i < LPL; ++i) { z[0][i] = za[0][i]; z[1][i] = zb[0][i]; }
-  }
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int i = 0; i < LPL; ++i) tile[((2 * wv + c) * LPL + i) * 65 + lane] = z[c][i];
+  for (int i = 0; i < LPL; ++i) tile[(wv * LPL + i) * 65 + lane] = z[0][i];
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * 64 * kColWaves;
+    const int idx = tid + r * kThreads;
     const int l = idx / kColCols, c = idx % kColCols;
     stage[r] = tile[(c * LPL + l % LPL) * 65 + l / LPL];
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * 64 * kColWaves;
+    const int idx = tid + r * kThreads;
     const int l = idx / kColCols, c = idx % kColCols;
     if (l < nt) base[(size_t)l * QB + c] = stage[r];
   }
