@@ -245,8 +245,7 @@ DG_NX, DG_NT, DG_ITERS = 4096, 512, 2000
 DG_KERNELS = {   # kernel id: (name, algorithmic words per DOF; DOF = 3 coefficients x cells x levels)
     7: ("A: inverse FFT + dual step", 4),
     4: ("DG primal step + dual residual", 4),
-    5: ("DG implicit residual", 2),
-    6: ("forward row FFT", 2),
+    0: ("DG residual + forward FFT", 2),
     1: ("DG column solve (per-mode eigenbasis, banded Cholesky in t)", 2),
 }
 

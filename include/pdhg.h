@@ -103,7 +103,7 @@ typedef struct {
                                <= 0: 1e6                                                 */
   int32_t variant;          /* 0 = auto (2; DG: 4), 1 = unfused reference kernels (7 per
                                iteration), 2 = fused passes (3 kernels per iteration),
-                               4 = the DG loop body (6 kernels per iteration)            */
+                               4 = the DG loop body (5 kernels per iteration)            */
   int32_t reserved;
   double* history;          /* nullable DEVICE buffer [max_iter+2][2] of doubles: entry n holds
                                (||A(u^n)||, ||J(u^n)^T phi^n||) for n = 0..n*; entry 0 is
@@ -178,7 +178,8 @@ int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, vo
  * overwritten).  kernel: 0 = fused primal/residual/FFT pass, 1 = column solve,
  * 2 = inverse row FFT, 3 = dual update, 4 = primal update, 5 = residual,
  * 6 = forward row FFT, 7 = fused inverse-FFT/dual pass, 8 = plain device copy
- * (DG: 1 = column solve in the per-mode eigenbasis, 4 = primal step with the
+ * (DG: 0 = residual of two levels + forward FFT of their six coefficient rows,
+ * 1 = column solve in the per-mode eigenbasis, 4 = primal step with the
  * dual residual, 5 = residual, 6 = forward row FFT of the 3 nt coefficient
  * rows, 7 = inverse FFT + dual step, 8 = copy; others PDHG_EUNSUPPORTED)
  * of N_t*N_x elements (one read and one write per element; the reference point

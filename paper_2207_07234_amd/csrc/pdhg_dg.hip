@@ -303,6 +303,76 @@ k_dg_maxabs_trace(const T* __restrict__ u0, int nx, double a2, double b, double*
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Residual of levels l = 2w and 2w + 1 (3 planes each) and the forward FFT of
+// those 6 coefficient rows of the 3 nt-row spectrum, as the three complex
+// FFTs of row pairs (6w, 6w+1), (6w+2, 6w+3), (6w+4, 6w+5).  W = nx / E
+// threads; thread owns cells j = tid + e W.  Per-block partial sums of r^2.
+template <typename T, int E>
+__global__ void __launch_bounds__(512)
+k_dg_residual_fft(Scheme s, const T* __restrict__ u, T* __restrict__ spec, int lqb, const C2<T>* __restrict__ tw,
+                  double* __restrict__ part, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  extern __shared__ char smem[];
+  __shared__ double red[512 / 64];
+  const Consts<T> C(s);
+  const int nx = s.nx, nt = s.nt, nr = 3 * nt, W = blockDim.x, tid = threadIdx.x;
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* twl = buf + lds_fft_points(nx);
+  const int w = xcd_block(blockIdx.x, gridDim.x);
+  const size_t L3 = (size_t)3 * nx;
+  C2<T> twv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) twv[e] = tw[tid + e * W];
+  // residual rows: R[lv][p][e] for level 2w + lv
+  T R[2][3][E];
+  double rp = 0.0;
+#pragma unroll
+  for (int lv = 0; lv < 2; ++lv) {
+    const int l = 2 * w + lv;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      R[lv][0][e] = R[lv][1][e] = R[lv][2][e] = T(0);
+      if (l < nt) {
+        const int j = tid + e * W;
+        const int jm = (j - 1) & (nx - 1), jp = (j + 1) & (nx - 1);
+        const T* up1 = u + (size_t)(l + 1) * L3;
+        T v[3], vm[3], vp[3], F[3];
+        load_cell(up1, nx, j, v);
+        load_cell(up1, nx, jm, vm);
+        load_cell(up1, nx, jp, vp);
+        dg_spatial(C, v, vm[0] + vm[1] + vm[2], vp[0] - vp[1] + vp[2], F);
+        const T c0 = C.c0(l), c1 = C.c1(l), c2 = C.c2(l);
+        const bool use2 = l >= 1 && C.time == kTimeBDF2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          T t = c0 * v[k] + c1 * u[(size_t)l * L3 + (size_t)k * nx + j];
+          if (use2) t += c2 * u[(size_t)(l - 1) * L3 + (size_t)k * nx + j];
+          const T val = t * C.inv_ht + F[k];
+          R[lv][k][e] = val;
+          rp += (double)val * (double)val;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) twl[lpad(tid + e * W)] = twv[e];
+  // three complex FFTs: row 6w + 2i + h is (level 2w + (2i + h) / 3, plane (2i + h) % 3)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int ra = 6 * w + 2 * i;
+    if (i > 0) __syncthreads();   // the previous round's spectrum reads of buf are done
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int qa = 2 * i, qb = 2 * i + 1;
+      buf[lpad(tid + e * W)] = {R[qa / 3][qa % 3][e], R[qb / 3][qb % 3][e]};
+    }
+    fft_lds<false, E>(buf, nx, twl, tid, W);
+    if (ra < nr) store_halfcomplex_pair(buf, nx, spec, nr, lqb, ra, ra + 1 < nr, tid, W);
+  }
+  const double srp = block_sum_waves(rp, red);
+  if (tid == 0) part[blockIdx.x] = srp;
+}
+
 // ------------------------------------------------------------------ column solve
 // Block of 4 waves = 8 spectrum columns = 4 Fourier modes (the first wave of
 // block 0 holds the real columns of modes 0 and nx/2).  The spectrum has 3 nt
@@ -455,6 +525,34 @@ hipError_t launch_dg_maxabs_trace(const T* u0, int nx, double a2, double b, doub
   return hipGetLastError();
 }
 
+template <typename T, int E>
+static hipError_t launch_dg_residual_fft_e(const Scheme& s, const T* u, T* spec, int lqb, const void* tw,
+                                           double* part, const Ctrl* ctrl, hipStream_t st, int* nblocks) {
+  const int W = s.nx / E;
+  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(s.nx);
+  hipError_t e = allow_lds(k_dg_residual_fft<T, E>, lds);
+  if (e != hipSuccess) return e;
+  const int g = (s.nt + 1) / 2;
+  if (nblocks) *nblocks = g;
+  hipLaunchKernelGGL((k_dg_residual_fft<T, E>), dim3(g), dim3(W), lds, st, s, u, spec, lqb, (const C2<T>*)tw, part,
+                     ctrl);
+  return hipGetLastError();
+}
+
+// Residual + forward FFT for DG: W = min(512, nx) threads, E = nx / W (nx >= 64).
+template <typename T>
+hipError_t launch_dg_residual_fft(const Scheme& s, const T* u, T* spec, int lqb, const void* tw, double* part,
+                                  const Ctrl* ctrl, hipStream_t st, int* nblocks) {
+  const int W = s.nx < 512 ? s.nx : 512;
+  switch (s.nx / W) {
+    case 1: return launch_dg_residual_fft_e<T, 1>(s, u, spec, lqb, tw, part, ctrl, st, nblocks);
+    case 2: return launch_dg_residual_fft_e<T, 2>(s, u, spec, lqb, tw, part, ctrl, st, nblocks);
+    case 4: return launch_dg_residual_fft_e<T, 4>(s, u, spec, lqb, tw, part, ctrl, st, nblocks);
+    case 8: return launch_dg_residual_fft_e<T, 8>(s, u, spec, lqb, tw, part, ctrl, st, nblocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int BW, int LPL>
 static hipError_t launch_dg_colsolve_l(T* spec, const FacTab<T>& fac, const T* vtab, int nt, int nx, int lqb,
                                        const Ctrl* ctrl, hipStream_t st) {
@@ -494,6 +592,8 @@ hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int 
   template hipError_t launch_dg_primal<T>(const Scheme&, const T*, T*, const T*, const T*, T, double*, const Ctrl*, \
                                           hipStream_t, int*);                                                    \
   template hipError_t launch_dg_maxabs_trace<T>(const T*, int, double, double, double*, hipStream_t);             \
+  template hipError_t launch_dg_residual_fft<T>(const Scheme&, const T*, T*, int, const void*, double*,           \
+                                                const Ctrl*, hipStream_t, int*);                                 \
   template hipError_t launch_dg_colsolve<T>(T*, const FacTab<T>&, const T*, int, int, int, int, const Ctrl*,      \
                                             hipStream_t);
 

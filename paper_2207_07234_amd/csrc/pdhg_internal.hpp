@@ -161,6 +161,9 @@ hipError_t launch_dg_primal(const Scheme& s, const T* u_in, T* u_out, const T* p
 template <typename T>
 hipError_t launch_dg_maxabs_trace(const T* u0, int nx, double a2, double b, double* part, hipStream_t st);
 template <typename T>
+hipError_t launch_dg_residual_fft(const Scheme& s, const T* u, T* spec, int lqb, const void* tw, double* part,
+                                  const Ctrl* ctrl, hipStream_t st, int* nblocks);
+template <typename T>
 hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
                               const Ctrl* ctrl, hipStream_t st);
 }  // namespace pdhg

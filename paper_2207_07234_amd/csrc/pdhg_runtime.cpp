@@ -675,8 +675,12 @@ int enqueue_body_dg(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T
     HIP_TRY(launch_dual<T>(phi, phibar, srow, (size_t)nr * p.nx, tau_phi, ctrl, st));
   }
   HIP_TRY(launch_dg_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
-  HIP_TRY(launch_dg_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
-  HIP_TRY(launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, ctrl, st));
+  if (p.nx >= 64) {   // residual of two levels + forward FFT of their six coefficient rows, fused
+    HIP_TRY(launch_dg_residual_fft<T>(s, uout, spec, h->lqb, h->d_tw, prp, ctrl, st, &nb_rp));
+  } else {
+    HIP_TRY(launch_dg_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
+    HIP_TRY(launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, ctrl, st));
+  }
   HIP_TRY(launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
                                 h->lqb, ctrl, st));
   HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
@@ -932,6 +936,7 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
       case 1: return launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1,
                                            p.nt, p.nx, h->lqb, nullptr, st);
       case 4: return launch_dg_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
+      case 0: return launch_dg_residual_fft<T>(s, u_alt, spec, h->lqb, h->d_tw, prp, nullptr, st, nullptr);
       case 5: return launch_dg_residual<T>(s, u_alt, srow, prp, nullptr, st, nullptr);
       case 6: return launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, nullptr, st);
       case 7: return launch_dual_fft<T>(spec, nr, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
@@ -939,8 +944,8 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
       default: return hipErrorInvalidValue;
     }
   };
-  if (p.space == PDHG_DG_P2_LLF && !(kernel == 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
-  if (p.space == PDHG_DG_P2_LLF && kernel == 7 && p.nx < 64) return PDHG_EUNSUPPORTED;
+  if (p.space == PDHG_DG_P2_LLF && !(kernel <= 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
+  if (p.space == PDHG_DG_P2_LLF && (kernel == 7 || kernel == 0) && p.nx < 64) return PDHG_EUNSUPPORTED;
   auto launch = [&]() -> hipError_t {
     if (p.space == PDHG_DG_P2_LLF) return launch_dg();
     switch (kernel) {

@@ -74,7 +74,7 @@ def test_precond_matches_oracle(gpu_lib, dtype, nx, nt, time):
 
 
 @pytest.mark.parametrize("n_iter", [1, 10, 100])
-@pytest.mark.parametrize("nx,nt,time", [(16, 6, "be"), (32, 8, "bdf2")])
+@pytest.mark.parametrize("nx,nt,time", [(16, 6, "be"), (32, 8, "bdf2"), (64, 10, "be"), (128, 9, "bdf2")])
 def test_trajectory_matches_oracle_fp64(gpu_lib, nx, nt, time, n_iter):
     u0, op, gp = _case(gpu_lib, nx, nt, time, torch.float64)
     tau = 0.6
