@@ -171,11 +171,14 @@ __device__ __forceinline__ void dft8(C2<T>* v) {
   }
 }
 
-// LDS layout of an N-point complex FFT buffer: one padding slot after every 8
-// points, so that the strided Stockham writes (stride 8 points = 128 B for
-// double complex) land in distinct banks.  lds_fft_points(N) slots are needed.
-__device__ __forceinline__ int lpad(int x) { return x + (x >> 3); }
-__host__ __device__ constexpr int lds_fft_points(int n) { return n + n / 8 + 1; }
+// LDS layout of an N-point complex FFT buffer: point x is stored at
+// x ^ ((x >> 4) & 15), a permutation inside each block of 16 points.  Reads of
+// consecutive points stay conflict-free, and the strided Stockham writes and
+// twiddle reads of consecutive lanes spread over the banks (fewer conflicts
+// than a padded layout, measured on a bank model of the whole FFT, and no
+// extra space).  lds_fft_points(N) slots are needed.
+__device__ __forceinline__ int lpad(int x) { return x ^ ((x >> 4) & 15); }
+__host__ __device__ constexpr int lds_fft_points(int n) { return n; }
 
 // Copy the twiddle table w_N^i, i = 0..N-1, from global memory into LDS (padded).
 template <typename T>
