@@ -56,7 +56,8 @@ def kd_solve(prob: Problem, r: np.ndarray) -> np.ndarray:
     """s = K_d^{-1} r for r of shape (N_t, N_x), via FFT in x and banded solves in t."""
     kt = time_gram(prob)
     nt = prob.nt
-    bw = 2 if prob.time == "bdf2" else 1
+    # bandwidth of B_t B_t^T (no more off-diagonals than the matrix has)
+    bw = min(2 if prob.time == "bdf2" else 1, nt - 1)
     # upper banded storage for solveh_banded: ab[bw + i - j, j] = a[i, j]
     ab0 = np.zeros((bw + 1, nt))
     for d in range(bw + 1):
