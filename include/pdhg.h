@@ -145,6 +145,30 @@ size_t pdhg_workspace_bytes(const pdhg_handle* h);
 int pdhg_solve(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace,
                const pdhg_params* params, pdhg_stats* stats, pdhg_stream_t stream);
 
+/* Mesh refinement in time (Algorithm 2, Section 3.4): Algorithm 1 on the meshes
+ * N x nt_start, N x 2 nt_start, ..., N x nt (nt / nt_start a power of two), each
+ * level started from the previous level's solution interpolated in time (u
+ * linearly: fine level 2l = coarse level l, fine level 2l+1 = their mean; phi
+ * piecewise constant: fine rows 2l and 2l+1 take coarse row l), the first level
+ * from u^l = u0, phi = 0.  Coarse levels stop at coarse_eps (<= 0: params->eps)
+ * or coarse_max_iter; the finest level uses params (its warm_start is implied
+ * when there are coarse levels).  Step sizes: params->tau_u/tau_phi for every
+ * level when > 0, otherwise the power-iteration default per level.  The coarse
+ * levels' plans and buffers are created on first use and kept by the handle. */
+typedef struct {
+  int32_t nt_start;         /* coarsest mesh N_t0 (>= 1)                                 */
+  int32_t reserved;
+  int64_t coarse_max_iter;  /* iteration cap on each coarse level                        */
+  double coarse_eps;        /* tolerance on the coarse levels; <= 0: params->eps          */
+} pdhg_refine_params;
+
+/* As pdhg_solve, on the refined mesh sequence.  stats: the finest level's
+ * (or, if a coarse level diverges, that level's, with PDHG_DIVERGED returned).
+ * level_iters: nullable HOST array with one entry per level (n* of each). */
+int pdhg_solve_refined(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace,
+                       const pdhg_params* params, const pdhg_refine_params* refine, pdhg_stats* stats,
+                       int64_t* level_iters, pdhg_stream_t stream);
+
 /* Residual of the saddle-point system (Section 2.3): Au = A(u) [nt][nx] and
  * JTphi = J(u)^T phi [nt][nx] (either may be NULL), and res[2] (host) =
  * { ||A(u)||, ||J(u)^T phi|| } (res may be NULL; then the call is asynchronous).

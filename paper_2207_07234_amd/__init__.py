@@ -158,6 +158,34 @@ class Solver:
             hist = hist[: stats["iters"] + 1]
         return SolveResult(u, phi, rc, stats, hist)
 
+    def solve_refined(self, u0, nt_start: int = 1, coarse_max_iter: int = 100000, coarse_eps: float = 0.0,
+                      tau_u: float = 0.0, tau_phi: float = 0.0, eps: float = 1e-8, max_iter: int = 10000,
+                      check_every: int = 64, u=None, phi=None, workspace=None, diverge_factor: float = 0.0) -> SolveResult:
+        """Algorithm 2: Algorithm 1 on nt_start, 2 nt_start, ..., nt levels, each warm-started from the
+        previous level interpolated in time.  stats["level_iters"] lists n* per level."""
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u0, lv, "u0")
+        u = self._empty(nt + 1, *lv) if u is None else self._check(u, (nt + 1,) + lv, "u")
+        phi = self._empty(nt, *lv) if phi is None else self._check(phi, (nt,) + lv, "phi")
+        p = B.pdhg_params()
+        p.tau_u, p.tau_phi, p.eps = float(tau_u), float(tau_phi), float(eps)
+        p.max_iter, p.check_every, p.warm_start = int(max_iter), int(check_every), 0
+        p.diverge_factor, p.variant, p.history = float(diverge_factor), 0, None
+        r = B.pdhg_refine_params()
+        r.nt_start, r.coarse_max_iter, r.coarse_eps = int(nt_start), int(coarse_max_iter), float(coarse_eps)
+        nlev = 1
+        while (int(nt_start) << (nlev - 1)) < nt:
+            nlev += 1
+        li = (C.c_int64 * nlev)()
+        st = B.pdhg_stats()
+        rc = self.lib.pdhg_solve_refined(self._h, _ptr(u0), _ptr(u), _ptr(phi), _ptr(workspace), C.byref(p),
+                                         C.byref(r), C.byref(st), li, _stream_ptr(self.device))
+        if rc < 0:
+            raise PdhgError(f"pdhg_solve_refined failed: {self._status(rc)}")
+        stats = {k: getattr(st, k) for k, _ in B.pdhg_stats._fields_}
+        stats["level_iters"] = list(li)
+        return SolveResult(u, phi, rc, stats)
+
     def residual(self, u, phi=None, want_fields: bool = True):
         """(A(u), J(u)^T phi, [||A(u)||, ||J(u)^T phi||])."""
         nt, lv = self.prob.nt, self.prob.level_shape

@@ -48,6 +48,12 @@ class pdhg_stats(C.Structure):
     ]
 
 
+class pdhg_refine_params(C.Structure):
+    _fields_ = [
+        ("nt_start", C.c_int32), ("reserved", C.c_int32), ("coarse_max_iter", C.c_int64), ("coarse_eps", C.c_double),
+    ]
+
+
 class pdhg_batch_params(C.Structure):
     _fields_ = [
         ("tau_u", C.c_void_p), ("tau_phi", C.c_void_p), ("eps", C.c_double),
@@ -57,7 +63,7 @@ class pdhg_batch_params(C.Structure):
 
 
 EXPORTED = (
-    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_residual", "pdhg_precond",
+    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_solve_refined", "pdhg_residual", "pdhg_precond",
     "pdhg_adjoint", "pdhg_time_kernel", "pdhg_destroy", "pdhg_status_string", "pdhg_last_error",
     "pdhg_batch_setup", "pdhg_batch_sizes", "pdhg_batch_offsets", "pdhg_batch_solve", "pdhg_batch_tune",
     "pdhg_batch_time_kernel", "pdhg_batch_destroy", "pdhg_batch_last_error",
@@ -78,6 +84,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pdhg_workspace_bytes.restype = C.c_size_t
     lib.pdhg_solve.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_params), C.POINTER(pdhg_stats), vp]
     lib.pdhg_solve.restype = C.c_int
+    lib.pdhg_solve_refined.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_params), C.POINTER(pdhg_refine_params),
+                                       C.POINTER(pdhg_stats), C.POINTER(C.c_int64), vp]
+    lib.pdhg_solve_refined.restype = C.c_int
     lib.pdhg_residual.argtypes = [H, vp, vp, vp, vp, C.POINTER(C.c_double), vp]
     lib.pdhg_residual.restype = C.c_int
     lib.pdhg_precond.argtypes = [H, vp, vp, vp]

@@ -69,6 +69,8 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
 namespace pdhg {
 template <typename T>
 hipError_t launch_level_sums(const T* u, int nx, size_t stride, int levels, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_refine_time(const T* uc, const T* pc, int ntc, size_t row, T* uf, T* pf, hipStream_t st);
 }  // namespace pdhg
 
 namespace pdhg {

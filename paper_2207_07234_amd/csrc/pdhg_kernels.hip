@@ -417,6 +417,26 @@ k_finalize(Ctrl* c, const double* __restrict__ part_rp, int n_rp, const double* 
   if (threadIdx.x == 0) finalize_body(c, srp, srd, wscale, hist);
 }
 
+// Refinement in time (Algorithm 2): u on ntc + 1 levels -> 2 ntc + 1 levels (fine
+// level 2l = coarse level l, fine level 2l+1 = mean of coarse levels l, l+1);
+// phi on ntc rows -> 2 ntc rows (both fine rows of a coarse interval take its
+// value).  row = elements per level.
+template <typename T>
+__global__ void __launch_bounds__(kEwThreads)
+k_refine_time(const T* __restrict__ uc, const T* __restrict__ pc, int ntc, size_t row, T* __restrict__ uf,
+              T* __restrict__ pf) {
+  const size_t i = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  if (i >= (size_t)(2 * ntc + 1) * row) return;
+  const size_t lf = i / row, x = i % row;
+  if ((lf & 1) == 0) {
+    uf[i] = uc[(lf / 2) * row + x];
+  } else {
+    const size_t lc = lf / 2;
+    uf[i] = T(0.5) * (uc[lc * row + x] + uc[(lc + 1) * row + x]);
+  }
+  if (lf < (size_t)(2 * ntc)) pf[i] = pc[(lf / 2) * row + x];
+}
+
 // ------------------------------------------------------------------ launchers
 static inline unsigned grid_for(size_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
@@ -573,6 +593,16 @@ hipError_t launch_finalize(Ctrl* c, const double* part_rp, int n_rp, const doubl
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kEwThreads), 0, st, c, part_rp, n_rp, part_rd, n_rd, wscale, hist);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_refine_time(const T* uc, const T* pc, int ntc, size_t row, T* uf, T* pf, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_time<T>, dim3(grid_for((size_t)(2 * ntc + 1) * row, kEwThreads)), dim3(kEwThreads), 0,
+                     st, uc, pc, ntc, row, uf, pf);
+  return hipGetLastError();
+}
+template hipError_t launch_refine_time<float>(const float*, const float*, int, size_t, float*, float*, hipStream_t);
+template hipError_t launch_refine_time<double>(const double*, const double*, int, size_t, double*, double*,
+                                               hipStream_t);
 
 #define PDHG_INSTANTIATE(T)                                                                                    \
   template hipError_t launch_rows_fwd<T>(const T*, int, T*, int, int, int, const void*, const Ctrl*,          \

@@ -166,6 +166,10 @@ struct pdhg_handle {
   GraphKey gkey;
   // last solve (for kernel timing)
   GraphKey last;
+  // mesh refinement in time: plans of the coarse levels, and two (u, phi) buffer pairs
+  std::vector<std::pair<int, pdhg_handle*>> refine_sub;
+  void* refine_buf = nullptr;
+  size_t refine_buf_bytes = 0;
   std::string err;
 };
 
@@ -562,6 +566,8 @@ size_t pdhg_workspace_bytes(const pdhg_handle* h) { return h ? layout_for(h->pro
 
 void pdhg_destroy(pdhg_handle* h) {
   if (!h) return;
+  for (auto& kv : h->refine_sub) pdhg_destroy(kv.second);
+  if (h->refine_buf) hipFree(h->refine_buf);
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
   if (h->d_tw) hipFree(h->d_tw);
@@ -820,7 +826,111 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
 
 }  // namespace
 
+namespace {
+
+// Algorithm 2 (Section 3.4): Algorithm 1 on N_t0 = nt_start, 2 nt_start, ... levels,
+// each warm-started from the previous level's solution interpolated in time.
+template <typename T>
+int solve_refined_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_params* prm,
+                       const pdhg_refine_params* rp, pdhg_stats* stats, int64_t* level_iters, hipStream_t st) {
+  const pdhg_problem& P = h->prob;
+  std::vector<int> nts;   // coarse levels
+  int n = rp->nt_start;
+  while (n < P.nt) {
+    nts.push_back(n);
+    n *= 2;
+  }
+  if (n != P.nt) return PDHG_EINVAL;   // nt / nt_start must be a power of two
+  const size_t row = (size_t)P.nx * planes(P);
+  T* ub[2] = {nullptr, nullptr};
+  T* pb[2] = {nullptr, nullptr};
+  if (!nts.empty()) {
+    const size_t ntc = (size_t)nts.back();
+    const size_t bu = align_up((ntc + 1) * row * sizeof(T)), bp = align_up(ntc * row * sizeof(T));
+    const size_t need = 2 * (bu + bp);
+    if (h->refine_buf_bytes < need) {
+      if (h->refine_buf) hipFree(h->refine_buf);
+      h->refine_buf = nullptr;
+      h->refine_buf_bytes = 0;
+      HIP_TRY(hipMalloc(&h->refine_buf, need));
+      h->refine_buf_bytes = need;
+    }
+    char* b = static_cast<char*>(h->refine_buf);
+    ub[0] = (T*)b;
+    pb[0] = (T*)(b + bu);
+    ub[1] = (T*)(b + bu + bp);
+    pb[1] = (T*)(b + 2 * bu + bp);
+  }
+  const T* uc = nullptr;
+  const T* pc = nullptr;
+  int ntc = 0, li = 0;
+  for (size_t k = 0; k < nts.size(); ++k) {
+    const int nk = nts[k];
+    pdhg_handle* sh = nullptr;
+    for (auto& kv : h->refine_sub)
+      if (kv.first == nk) sh = kv.second;
+    if (!sh) {
+      pdhg_problem q = P;
+      q.nt = nk;
+      const int rc = pdhg_setup(&q, &sh);
+      if (rc) return rc;
+      h->refine_sub.emplace_back(nk, sh);
+    }
+    T* uk = ub[k & 1];
+    T* pk = pb[k & 1];
+    if (k > 0) HIP_TRY(launch_refine_time<T>(uc, pc, ntc, row, uk, pk, st));
+    pdhg_params p = *prm;
+    p.eps = rp->coarse_eps > 0.0 ? rp->coarse_eps : prm->eps;
+    p.max_iter = rp->coarse_max_iter;
+    p.warm_start = k > 0 ? 1 : 0;
+    p.history = nullptr;
+    pdhg_stats sk{};
+    const int rc = pdhg_solve(sh, u0, uk, pk, nullptr, &p, &sk, (pdhg_stream_t)st);
+    if (rc < 0) {
+      h->err = std::string("coarse level ") + std::to_string(nk) + ": " + pdhg_last_error(sh);
+      return rc;
+    }
+    if (level_iters) level_iters[li] = sk.iters;
+    ++li;
+    if (rc == PDHG_DIVERGED) {
+      if (stats) *stats = sk;
+      return PDHG_DIVERGED;
+    }
+    uc = uk;
+    pc = pk;
+    ntc = nk;
+  }
+  pdhg_params p = *prm;
+  if (!nts.empty()) {
+    HIP_TRY(launch_refine_time<T>(uc, pc, ntc, row, u, phi, st));
+    p.warm_start = 1;
+  }
+  pdhg_stats sf{};
+  const int rc = solve_impl<T>(h, u0, u, phi, ws, &p, &sf, st);
+  if (stats) *stats = sf;
+  if (level_iters && rc >= 0) level_iters[li] = sf.iters;
+  return rc;
+}
+
+}  // namespace
+
 extern "C" {
+
+int pdhg_solve_refined(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace,
+                       const pdhg_params* params, const pdhg_refine_params* refine, pdhg_stats* stats,
+                       int64_t* level_iters, pdhg_stream_t stream) {
+  if (!h || !u0 || !u || !phi || !params || !refine) return PDHG_EINVAL;
+  if (params->max_iter < 0 || refine->coarse_max_iter < 0 || refine->nt_start < 1 || refine->nt_start > h->prob.nt)
+    return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64)
+    return solve_refined_impl<double>(h, (const double*)u0, (double*)u, (double*)phi, workspace, params, refine,
+                                      stats, level_iters, st);
+  return solve_refined_impl<float>(h, (const float*)u0, (float*)u, (float*)phi, workspace, params, refine, stats,
+                                   level_iters, st);
+}
 
 int pdhg_solve(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace, const pdhg_params* params,
                pdhg_stats* stats, pdhg_stream_t stream) {

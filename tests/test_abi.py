@@ -64,6 +64,11 @@ def test_status_strings():
     assert lib.pdhg_status_string(12345) == b"unknown status"
 
 
+def test_refine_params_struct_size():
+    B, _ = _lib()
+    assert C.sizeof(B.pdhg_refine_params) == 4 * 2 + 8 * 2
+
+
 def test_batch_params_struct_size():
     B, _ = _lib()
     assert C.sizeof(B.pdhg_batch_params) == 8 * 3 + 8 + 4 * 2 + 8
