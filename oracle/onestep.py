@@ -1,0 +1,136 @@
+"""One-time-step primal-dual solver (Algorithm 3, Section 3.5) -- oracle, test infrastructure only.
+
+The implicit scheme is marched one step at a time.  Step l (l = 0..N_t-1)
+is the initial-value problem on [l h_t, (l+1) h_t] discretised with one
+implicit level: with u^l (and u^{l-1} for BDF2) known, the unknown
+v = u^{l+1} solves
+
+    A_l(v) = (c0 v + c1 u^l + c2 u^{l-1}) / h_t + F(v) = 0,
+
+(c0, c1, c2) the coefficients of row l (BDF2 starts with backward Euler).
+Algorithm 1 is applied to this N_x x 1 problem, started from v = u^l and
+phi = phibar = 0, and stops when both residuals, measured in the L2 norm
+over the time slice, sqrt(h_x sum z^2), are <= eps.
+
+Readings (the paper states the algorithm only in words and pseudocode):
+
+* The preconditioner of a step is the Gram reading of K_d with a single
+  unknown level: B_t is the scalar c0/h_t, so
+  K_l = (c0/h_t)^2 I + c^2 L_x + ghat^2 L_x^2, inverted by the FFT in x.
+  For backward Euler this is K_d of the N_t = 1 space-time problem.
+* phi restarts from zero at every step (the paper sets only the initial
+  guess of u).
+* One pair of step sizes serves the whole march; the default is
+  sqrt(0.95 / nu_max) with nu_max the largest eigenvalue of J^T K^{-1} J
+  at u0 over the step operators the scheme uses (c0 = 1, and c0 = 3/2 for
+  BDF2).  A step with c0 is the backward-Euler step of length h_t / c0.
+* A step that reaches max_iter without meeting eps keeps its last iterate
+  and the march goes on; a non-finite residual stops the march.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fd
+from . import pdhg as opdhg
+from .precond import mode_shifts
+from .problem import Problem, time_coeffs
+
+
+@dataclass
+class OneStepResult:
+    u: np.ndarray                      # (N_t+1, N_x), u[0] = u0
+    phi: np.ndarray                    # (N_t, N_x): the dual of step l at its n*
+    step_iters: list                   # n*_l
+    step_res: list                     # (Rp, Rd) of step l at n*_l
+    converged: bool                    # every step met eps
+    diverged: bool = False
+    history: list = field(default_factory=list)
+
+
+def slice_norm(prob: Problem, z: np.ndarray) -> float:
+    """L2 norm over one time slice: sqrt(h_x sum_j z_j^2)."""
+    return float(np.sqrt(prob.hx * np.sum(np.asarray(z) ** 2)))
+
+
+def step_precond_symbol(prob: Problem, c0: float) -> np.ndarray:
+    """Eigenvalues of K_l per FFT mode: (c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2."""
+    return (c0 / prob.ht) ** 2 + mode_shifts(prob)
+
+
+def solve_step(prob: Problem, row: int, u_prev: np.ndarray, u_prev2, tau_u: float, tau_phi: float,
+               eps: float, max_iter: int, v_init=None, hist=None):
+    """Algorithm 1 on the one-level problem of step `row`, started from v = u_prev (or v_init);
+    returns (v, phi, n*, Rp, Rd).  hist: optional list that receives (n, Rp, Rd) per iteration."""
+    c0, c1, c2 = time_coeffs(prob.time, row)
+    known = c1 * u_prev + (c2 * u_prev2 if c2 != 0.0 else 0.0)
+    ht = prob.ht
+    sym = step_precond_symbol(prob, c0)
+    v = np.array(u_prev if v_init is None else v_init, dtype=np.float64)
+    phi = np.zeros_like(v)
+    phibar = np.zeros_like(v)
+
+    def jt(vv, psi):
+        # J_l(v)^T psi with J_l(v) = (c0/h_t) I + dF(v)
+        return c0 / ht * psi + fd.flux_jacobian(prob, vv).T @ psi
+
+    rp = rd = float("inf")
+    n = 0
+    for n in range(1, max_iter + 1):
+        v = v - tau_u * jt(v, phibar)
+        r = (c0 * v + known) / ht + fd.flux_operator(prob, v)
+        s = np.fft.ifft(np.fft.fft(r) / sym).real
+        phibar = phi + 2.0 * tau_phi * s
+        phi = phi + tau_phi * s
+        rp = slice_norm(prob, r)
+        rd = slice_norm(prob, jt(v, phi))
+        if hist is not None:
+            hist.append((n, rp, rd))
+        if not (np.isfinite(rp) and np.isfinite(rd)):
+            break
+        if max(rp, rd) <= eps:
+            break
+    return v, phi, n, rp, rd
+
+
+def auto_steps(prob: Problem, u0: np.ndarray, safety: float = 0.95, iters: int = 200):
+    """sigma = tau = sqrt(safety / nu_max) over the step operators at u0.
+
+    The step with coefficient c0 is the backward-Euler N_t = 1 problem with
+    time step h_t / c0, whose nu_max Algorithm 1's power iteration gives."""
+    c0s = [1.0] + ([1.5] if prob.time == "bdf2" and prob.nt > 1 else [])
+    nm = 0.0
+    for c0 in c0s:
+        q = prob.with_(nt=1, time="be", t_final=prob.ht / c0)
+        u = np.stack([u0, u0])
+        nm = max(nm, opdhg.nu_max(q, u, iters))
+    t = float(np.sqrt(safety / nm))
+    return t, t, nm
+
+
+def run(prob: Problem, u0: np.ndarray, eps: float, max_iter: int = 10000, tau_u: float = None,
+        tau_phi: float = None) -> OneStepResult:
+    """Algorithm 3 over l = 0..N_t-1."""
+    if prob.space == "dg_p2_llf":
+        raise ValueError("the one-step oracle covers the finite-difference schemes")
+    if tau_u is None or tau_phi is None:
+        tu, tp, _ = auto_steps(prob, u0)
+        tau_u = tu if tau_u is None else tau_u
+        tau_phi = tp if tau_phi is None else tau_phi
+    u = np.empty((prob.nt + 1, prob.nx))
+    u[0] = u0
+    phi = np.zeros((prob.nt, prob.nx))
+    its, res = [], []
+    ok = True
+    for l in range(prob.nt):
+        v, ph, n, rp, rd = solve_step(prob, l, u[l], u[l - 1] if l >= 1 else None, tau_u, tau_phi, eps, max_iter)
+        u[l + 1] = v
+        phi[l] = ph
+        its.append(n)
+        res.append((rp, rd))
+        if not (np.isfinite(rp) and np.isfinite(rd)):
+            return OneStepResult(u, phi, its, res, False, True)
+        ok = ok and max(rp, rd) <= eps
+    return OneStepResult(u, phi, its, res, ok)
