@@ -169,6 +169,30 @@ int pdhg_solve_refined(pdhg_handle* h, const void* u0, void* u, void* phi, void*
                        const pdhg_params* params, const pdhg_refine_params* refine, pdhg_stats* stats,
                        int64_t* level_iters, pdhg_stream_t stream);
 
+/* One-time-step solver (Algorithm 3, Section 3.5).  The scheme is marched one
+ * implicit step at a time: step l (l = 0..nt-1) runs Algorithm 1 on the N_x x 1
+ * problem A_l(v) = (c0 v + c1 u^l + c2 u^{l-1})/h_t + F(v) = 0 for v = u^{l+1},
+ * (c0, c1, c2) the coefficients of row l, started from v = u^l, phi = 0.  Its
+ * preconditioner is K_l = (c0/h_t)^2 I + c^2 L_x + ghat^2 L_x^2 (the Gram form
+ * with one unknown level, inverted by the FFT), and it stops when both
+ * residuals, in the L2 norm of the time slice sqrt(h_x sum z^2), are <= eps or
+ * after max_iter iterations; the march then goes on from that step's iterate.
+ *   params: tau_u, tau_phi (<= 0: sqrt(0.95 / nu_max), nu_max the largest
+ *   power-iteration eigenvalue of J^T K^{-1} J at u0 over the step operators,
+ *   c0 = 1 and, for BDF2, 3/2), eps and max_iter per step, diverge_factor as
+ *   for pdhg_solve; check_every, warm_start, variant and history are ignored.
+ *   u [nt+1][nx] receives u^0 = u0 and every step's solution; phi [nt][nx] row l
+ *   receives the dual of step l at its n*.  A step that diverges stops the
+ *   march: PDHG_DIVERGED, and the rows after it are left unwritten.
+ *   stats: iters = sum of the steps' n*, res_primal/res_dual = the largest final
+ *   step residuals, variant = 5.  step_iters: nullable HOST [nt] (n* per step);
+ *   step_res: nullable HOST [nt][2] (final residuals per step).
+ * Finite differences with nx >= 64 only (PDHG_EUNSUPPORTED otherwise).  One
+ * workgroup per step: the call is latency-bound by design and leaves the rest
+ * of the GPU to other streams.  Synchronous on `stream`. */
+int pdhg_solve_onestep(pdhg_handle* h, const void* u0, void* u, void* phi, const pdhg_params* params,
+                       pdhg_stats* stats, int64_t* step_iters, double* step_res, pdhg_stream_t stream);
+
 /* Residual of the saddle-point system (Section 2.3): Au = A(u) [nt][nx] and
  * JTphi = J(u)^T phi [nt][nx] (either may be NULL), and res[2] (host) =
  * { ||A(u)||, ||J(u)^T phi|| } (res may be NULL; then the call is asynchronous).

@@ -186,6 +186,31 @@ class Solver:
         stats["level_iters"] = list(li)
         return SolveResult(u, phi, rc, stats)
 
+    def solve_onestep(self, u0, tau_u: float = 0.0, tau_phi: float = 0.0, eps: float = 1e-8,
+                      max_iter: int = 10000, u=None, phi=None, diverge_factor: float = 0.0) -> SolveResult:
+        """Algorithm 3: Algorithm 1 on one implicit step at a time (eps and max_iter per step, residuals in
+        the norm of the time slice).  stats["step_iters"] lists n* per step, stats["step_res"] the final
+        (Rp, Rd) per step."""
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u0, lv, "u0")
+        u = self._empty(nt + 1, *lv) if u is None else self._check(u, (nt + 1,) + lv, "u")
+        phi = self._empty(nt, *lv) if phi is None else self._check(phi, (nt,) + lv, "phi")
+        p = B.pdhg_params()
+        p.tau_u, p.tau_phi, p.eps = float(tau_u), float(tau_phi), float(eps)
+        p.max_iter, p.check_every, p.warm_start = int(max_iter), 1, 0
+        p.diverge_factor, p.variant, p.history = float(diverge_factor), 0, None
+        its = (C.c_int64 * nt)()
+        res = (C.c_double * (2 * nt))()
+        st = B.pdhg_stats()
+        rc = self.lib.pdhg_solve_onestep(self._h, _ptr(u0), _ptr(u), _ptr(phi), C.byref(p), C.byref(st), its, res,
+                                         _stream_ptr(self.device))
+        if rc < 0:
+            raise PdhgError(f"pdhg_solve_onestep failed: {self._status(rc)}")
+        stats = {k: getattr(st, k) for k, _ in B.pdhg_stats._fields_}
+        stats["step_iters"] = list(its)
+        stats["step_res"] = [(res[2 * i], res[2 * i + 1]) for i in range(nt)]
+        return SolveResult(u, phi, rc, stats)
+
     def residual(self, u, phi=None, want_fields: bool = True):
         """(A(u), J(u)^T phi, [||A(u)||, ||J(u)^T phi||])."""
         nt, lv = self.prob.nt, self.prob.level_shape

@@ -63,7 +63,7 @@ class pdhg_batch_params(C.Structure):
 
 
 EXPORTED = (
-    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_solve_refined", "pdhg_residual", "pdhg_precond",
+    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_solve_refined", "pdhg_solve_onestep", "pdhg_residual", "pdhg_precond",
     "pdhg_adjoint", "pdhg_time_kernel", "pdhg_destroy", "pdhg_status_string", "pdhg_last_error",
     "pdhg_batch_setup", "pdhg_batch_sizes", "pdhg_batch_offsets", "pdhg_batch_solve", "pdhg_batch_tune",
     "pdhg_batch_time_kernel", "pdhg_batch_destroy", "pdhg_batch_last_error",
@@ -87,6 +87,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pdhg_solve_refined.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_params), C.POINTER(pdhg_refine_params),
                                        C.POINTER(pdhg_stats), C.POINTER(C.c_int64), vp]
     lib.pdhg_solve_refined.restype = C.c_int
+    lib.pdhg_solve_onestep.argtypes = [H, vp, vp, vp, C.POINTER(pdhg_params), C.POINTER(pdhg_stats),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_double), vp]
+    lib.pdhg_solve_onestep.restype = C.c_int
     lib.pdhg_residual.argtypes = [H, vp, vp, vp, vp, C.POINTER(C.c_double), vp]
     lib.pdhg_residual.restype = C.c_int
     lib.pdhg_precond.argtypes = [H, vp, vp, vp]

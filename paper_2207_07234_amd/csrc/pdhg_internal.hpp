@@ -71,6 +71,17 @@ template <typename T>
 hipError_t launch_level_sums(const T* u, int nx, size_t stride, int levels, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_refine_time(const T* uc, const T* pc, int ntc, size_t row, T* uf, T* pf, hipStream_t st);
+
+// One-time-step solver (Algorithm 3): record of step l, written by its launch.
+struct StepStat {
+  long long iters;   // n*_l
+  double rp, rd;     // residuals of the step at n*_l (L2 norm over the time slice)
+  int status;        // 0 converged, 1 max_iter reached, 2 diverged
+  int pad;
+};
+template <typename T>
+hipError_t launch_onestep(const Scheme& s, const void* tw, const T* sym, T* u, T* phi, int l, T tau_u, T tau_phi,
+                          double eps, long long max_iter, double dfac, StepStat* stat, int* flag, hipStream_t st);
 }  // namespace pdhg
 
 namespace pdhg {

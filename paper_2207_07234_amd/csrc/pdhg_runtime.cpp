@@ -170,6 +170,12 @@ struct pdhg_handle {
   std::vector<std::pair<int, pdhg_handle*>> refine_sub;
   void* refine_buf = nullptr;
   size_t refine_buf_bytes = 0;
+  // one-time-step solver: device tables and per-step records, and the N_t = 1 plans
+  // whose power iteration gives the step sizes (c0 = 1 and c0 = 3/2)
+  void* os_buf = nullptr;
+  size_t os_buf_bytes = 0;
+  double os_c = -1.0;
+  pdhg_handle* os_sub[2] = {nullptr, nullptr};
   std::string err;
 };
 
@@ -396,11 +402,9 @@ int ensure_workspace(pdhg_handle* h, void*& ws) {
 
 inline char* wsp(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
-// max |f'(u0)| on the device, read back (synchronous).
+// max |f'(u0)| on the device, read back (synchronous).  part: >= 64 doubles of device scratch.
 template <typename T>
-int max_abs_dflux(pdhg_handle* h, const T* u0, void* ws, hipStream_t st, double* out) {
-  const WsLayout L = layout_for(h->prob, h->esz);
-  double* part = (double*)wsp(ws, L.part_rp);
+int max_abs_dflux(pdhg_handle* h, const T* u0, double* part, hipStream_t st, double* out) {
   if (h->prob.space == PDHG_DG_P2_LLF)   // DG: over the cell-edge traces of u0_h
     HIP_TRY(launch_dg_maxabs_trace<T>(u0, h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
   else
@@ -413,14 +417,15 @@ int max_abs_dflux(pdhg_handle* h, const T* u0, void* ws, hipStream_t st, double*
   return PDHG_OK;
 }
 
-// Resolve lf_speed and c from u0 when they default, and (re)build the factors.
+// Resolve lf_speed and c from u0 when they default (part: >= 64 doubles of
+// device scratch); with factors, also (re)build the banded factor tables.
 template <typename T>
-int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
+int resolve_constants_p(pdhg_handle* h, const T* u0, double* part, hipStream_t st, bool factors) {
   const pdhg_problem& p = h->prob;
   double lf = p.lf_speed, c = p.precond_c;
   if ((p.space == PDHG_FD_LF && lf < 0.0) || c < 0.0) {
     double m = 0.0;
-    int rc = max_abs_dflux<T>(h, u0, ws, st, &m);
+    int rc = max_abs_dflux<T>(h, u0, part, st, &m);
     if (rc) return rc;
     if (lf < 0.0) lf = m;
     if (c < 0.0) c = m;
@@ -429,6 +434,7 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
   h->lf = lf;
   h->c = c;
   h->consts_valid = true;
+  if (!factors) return PDHG_OK;
   if (p.space == PDHG_DG_P2_LLF) {
     if (!h->d_fac_rows || h->fac_c != c) {
       int rc = upload_factors_dg<T>(h, c);
@@ -439,6 +445,12 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
     if (rc) return rc;
   }
   return PDHG_OK;
+}
+
+template <typename T>
+int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
+  const WsLayout L = layout_for(h->prob, h->esz);
+  return resolve_constants_p<T>(h, u0, (double*)wsp(ws, L.part_rp), st, true);
 }
 
 // s = K_d^{-1} r through the workspace spectrum buffer spec.
@@ -568,6 +580,8 @@ void pdhg_destroy(pdhg_handle* h) {
   if (!h) return;
   for (auto& kv : h->refine_sub) pdhg_destroy(kv.second);
   if (h->refine_buf) hipFree(h->refine_buf);
+  for (pdhg_handle* sub : h->os_sub) pdhg_destroy(sub);
+  if (h->os_buf) hipFree(h->os_buf);
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
   if (h->d_tw) hipFree(h->d_tw);
@@ -912,9 +926,169 @@ int solve_refined_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, cons
   return rc;
 }
 
+// Algorithm 3 (Section 3.5): one launch of k_onestep per implicit step, all
+// enqueued at once; a diverged step sets a device flag that makes the later
+// launches return at once.
+template <typename T>
+int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* prm, pdhg_stats* stats,
+                 int64_t* step_iters, double* step_res, hipStream_t st) {
+  const pdhg_problem& P = h->prob;
+  if (P.space == PDHG_DG_P2_LLF || P.nx < 64) return PDHG_EUNSUPPORTED;
+  const int nx = P.nx, nt = P.nt;
+  // sym [2][nx] | stat [nt] | flag | part (level sums, max |f'|) | u [2][nx], phi [nx] of the step-size plans
+  const size_t b_sym = align_up(2 * (size_t)nx * sizeof(T));
+  const size_t b_stat = align_up((size_t)nt * sizeof(StepStat));
+  const size_t b_flag = align_up(sizeof(int));
+  const size_t b_part = align_up(sizeof(double) * std::max<size_t>(64, (size_t)nt + 1));
+  const size_t b_sub = align_up(3 * (size_t)nx * sizeof(T));
+  const size_t need = b_sym + b_stat + b_flag + b_part + b_sub;
+  if (h->os_buf_bytes < need) {
+    if (h->os_buf) hipFree(h->os_buf);
+    h->os_buf = nullptr;
+    h->os_buf_bytes = 0;
+    h->os_c = -1.0;
+    HIP_TRY(hipMalloc(&h->os_buf, need));
+    h->os_buf_bytes = need;
+  }
+  char* b = static_cast<char*>(h->os_buf);
+  T* sym = (T*)b;
+  StepStat* stat = (StepStat*)(b + b_sym);
+  int* flag = (int*)(b + b_sym + b_stat);
+  double* part = (double*)(b + b_sym + b_stat + b_flag);
+  T* sub_u = (T*)(b + b_sym + b_stat + b_flag + b_part);
+  T* sub_phi = sub_u + 2 * (size_t)nx;
+
+  HIP_TRY(launch_copy<T>(u, u0, (size_t)nx, st));   // u^0 = u0
+  int rc = resolve_constants_p<T>(h, u0, part, st, false);
+  if (rc) return rc;
+  const double ht = P.t_final / nt, hx = P.length / nx;
+  double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
+  if (tau_u <= 0.0 || tau_phi <= 0.0) {
+    // the step with coefficient c0 is the backward-Euler N_t = 1 problem with time step h_t / c0
+    const int nc0 = (P.time == PDHG_BDF2 && nt > 1) ? 2 : 1;
+    for (int i = 0; i < nc0; ++i) {
+      pdhg_problem q = P;
+      q.nt = 1;
+      q.time = PDHG_BE;
+      q.t_final = ht / (i ? 1.5 : 1.0);
+      if (P.space == PDHG_FD_LF) q.lf_speed = h->lf;
+      q.precond_c = h->c;
+      pdhg_handle*& sub = h->os_sub[i];
+      if (sub && (sub->prob.lf_speed != q.lf_speed || sub->prob.precond_c != q.precond_c)) {
+        pdhg_destroy(sub);
+        sub = nullptr;
+      }
+      if (!sub) {
+        rc = pdhg_setup(&q, &sub);
+        if (rc) return rc;
+      }
+      pdhg_params qp{};
+      qp.max_iter = 0;
+      qp.check_every = 1;
+      pdhg_stats sst{};
+      rc = pdhg_solve(sub, u0, sub_u, sub_phi, nullptr, &qp, &sst, (pdhg_stream_t)st);
+      if (rc < 0) {
+        h->err = std::string("step-size estimate: ") + pdhg_last_error(sub);
+        return rc;
+      }
+      nu = std::max(nu, sst.nu_max);
+    }
+    if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
+    tau_u = tau_phi = std::sqrt(0.95 / nu);
+  }
+  if (h->os_c != h->c) {
+    // 1 / (N_x ((c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2)), mu_k = 4 sin^2(pi k / N_x) / h_x^2 (FFT index k)
+    typedef long double LD;
+    const LD PI = 3.141592653589793238462643383279502884L;
+    const LD c = h->c, g = P.precond_gamma_hat;
+    std::vector<T> hs(2 * (size_t)nx);
+    for (int r = 0; r < 2; ++r) {
+      const LD a = (r ? 1.5L : 1.0L) / (LD)ht;
+      for (int k = 0; k < nx; ++k) {
+        const LD sn = sinl(PI * k / nx);
+        const LD mu = 4.0L * sn * sn / ((LD)hx * (LD)hx);
+        hs[(size_t)r * nx + k] = (T)(1.0L / ((LD)nx * (a * a + c * c * mu + g * g * mu * mu)));
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(sym, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    h->os_c = h->c;
+  }
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(stat, 0, (size_t)nt * sizeof(StepStat), st));
+  const Scheme s = scheme_of(h);
+  const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
+  auto t0 = std::chrono::steady_clock::now();
+  for (int l = 0; l < nt; ++l)
+    HIP_TRY(launch_onestep<T>(s, h->d_tw, sym, u, phi, l, (T)tau_u, (T)tau_phi, prm->eps, (long long)prm->max_iter,
+                              div, stat, flag, st));
+  std::vector<StepStat> rec(nt);
+  HIP_TRY(hipMemcpyAsync(rec.data(), stat, (size_t)nt * sizeof(StepStat), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  long long total = 0;
+  double mrp = 0.0, mrd = 0.0;
+  int status = PDHG_OK, done = nt;
+  for (int l = 0; l < nt; ++l) {
+    const bool ran = l < done;
+    if (ran) {
+      total += rec[l].iters;
+      mrp = std::max(mrp, rec[l].rp);
+      mrd = std::max(mrd, rec[l].rd);
+      if (rec[l].status == 2) {
+        status = PDHG_DIVERGED;
+        done = l + 1;
+      } else if (rec[l].status == 1 && status == PDHG_OK) {
+        status = PDHG_NOT_CONVERGED;
+      }
+    }
+    if (step_iters) step_iters[l] = ran ? rec[l].iters : 0;
+    if (step_res) {
+      step_res[2 * l] = ran ? rec[l].rp : NAN;
+      step_res[2 * l + 1] = ran ? rec[l].rd : NAN;
+    }
+  }
+  double drift = 0.0;
+  {
+    HIP_TRY(launch_level_sums<T>(u, nx, (size_t)nx, done + 1, part, st));
+    std::vector<double> m(done + 1);
+    HIP_TRY(hipMemcpyAsync(m.data(), part, m.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int l = 1; l <= done; ++l) drift = std::max(drift, std::fabs(m[l] - m[0]) * hx);
+  }
+  if (stats) {
+    stats->iters = total;
+    stats->res_primal = mrp;
+    stats->res_dual = mrd;
+    stats->tau_u = tau_u;
+    stats->tau_phi = tau_phi;
+    stats->nu_max = nu;
+    stats->lf_speed = h->lf;
+    stats->precond_c = h->c;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->mass_drift = drift;
+    stats->status = status;
+    stats->variant = 5;
+  }
+  return status;
+}
+
 }  // namespace
 
 extern "C" {
+
+int pdhg_solve_onestep(pdhg_handle* h, const void* u0, void* u, void* phi, const pdhg_params* params,
+                       pdhg_stats* stats, int64_t* step_iters, double* step_res, pdhg_stream_t stream) {
+  if (!h || !u0 || !u || !phi || !params) return PDHG_EINVAL;
+  if (params->max_iter < 0) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64)
+    return onestep_impl<double>(h, (const double*)u0, (double*)u, (double*)phi, params, stats, step_iters, step_res,
+                                st);
+  return onestep_impl<float>(h, (const float*)u0, (float*)u, (float*)phi, params, stats, step_iters, step_res, st);
+}
 
 int pdhg_solve_refined(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace,
                        const pdhg_params* params, const pdhg_refine_params* refine, pdhg_stats* stats,
