@@ -201,7 +201,7 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * W;
-    if (j < nbf) {
+    if (tid < W && j < nbf) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b * R + r] = buf[lpad(j + r * nbf)];
     }
@@ -211,7 +211,7 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * W;
-    if (j < nbf) {
+    if (tid < W && j < nbf) {
       const int k = j & (Ns - 1);
       C2<T>* vb = v + b * R;
       if (Ns > 1) {
@@ -232,7 +232,8 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
 // Unnormalised DFT of the N points in buf (natural order in and out, padded
 // layout): X_k = sum_x z_x e^{-2 pi i x k / N} (forward) or e^{+...} (inverse).
 // twl: LDS twiddle table from load_twiddles_lds.  Requires N = 2^m, 2 <= N <=
-// EPT W, and all W threads of the block (tid = 0..W-1) to call it.
+// EPT W, and every thread of the block to call it; threads tid = 0..W-1 do the
+// work, any others take part in the barriers only.
 template <bool INV, int EPT, typename T>
 __device__ void fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int tid, int W) {
   __syncthreads();

@@ -79,9 +79,23 @@ struct StepStat {
   int status;        // 0 converged, 1 max_iter reached, 2 diverged
   int pad;
 };
+// One problem of a one-step launch (device table entry).
 template <typename T>
-hipError_t launch_onestep(const Scheme& s, const void* tw, const T* sym, T* u, T* phi, int l, T tau_u, T tau_phi,
-                          double eps, long long max_iter, double dfac, StepStat* stat, int* flag, hipStream_t st);
+struct OneStepProb {
+  Scheme s;            // grid, scheme and resolved flux constants
+  const C2<T>* tw;     // [nx] twiddles e^{-2 pi i j / nx}
+  const T* sym;        // [2][nx] preconditioner symbol reciprocals (c0 = 1, c0 = 3/2), 1/M folded in
+  T* u;                // [nt+1][nx]; level 0 (and every level before the first step marched) is read
+  T* phi;              // [nt][nx]
+  StepStat* stat;      // [nt]
+  int* flag;           // 0 while the march runs, 2 after a step diverged
+  double tau_u, tau_phi;
+};
+// Threads per problem: one radix-8 butterfly per thread in each stage of the half-length FFT.
+__host__ __device__ inline int onestep_threads(int nx) { return nx / 8 < 64 ? 64 : nx / 8; }
+template <typename T>
+hipError_t launch_onestep(const OneStepProb<T>* probs, int nprob, int max_nx, int l_begin, int l_end, double eps,
+                          long long max_iter, double dfac, hipStream_t st);
 }  // namespace pdhg
 
 namespace pdhg {

@@ -926,9 +926,9 @@ int solve_refined_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, cons
   return rc;
 }
 
-// Algorithm 3 (Section 3.5): one launch of k_onestep per implicit step, all
-// enqueued at once; a diverged step sets a device flag that makes the later
-// launches return at once.
+// Algorithm 3 (Section 3.5): one launch of k_onestep marches every step (one
+// workgroup; u^l stays in registers between steps).  A diverged step stops
+// the march and sets the problem's device flag.
 template <typename T>
 int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* prm, pdhg_stats* stats,
                  int64_t* step_iters, double* step_res, hipStream_t st) {
@@ -936,12 +936,13 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   if (P.space == PDHG_DG_P2_LLF || P.nx < 64) return PDHG_EUNSUPPORTED;
   const int nx = P.nx, nt = P.nt;
   // sym [2][nx] | stat [nt] | flag | part (level sums, max |f'|) | u [2][nx], phi [nx] of the step-size plans
+  // | problem table
   const size_t b_sym = align_up(2 * (size_t)nx * sizeof(T));
   const size_t b_stat = align_up((size_t)nt * sizeof(StepStat));
   const size_t b_flag = align_up(sizeof(int));
   const size_t b_part = align_up(sizeof(double) * std::max<size_t>(64, (size_t)nt + 1));
   const size_t b_sub = align_up(3 * (size_t)nx * sizeof(T));
-  const size_t need = b_sym + b_stat + b_flag + b_part + b_sub;
+  const size_t need = b_sym + b_stat + b_flag + b_part + b_sub + align_up(sizeof(OneStepProb<T>));
   if (h->os_buf_bytes < need) {
     if (h->os_buf) hipFree(h->os_buf);
     h->os_buf = nullptr;
@@ -957,6 +958,7 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   double* part = (double*)(b + b_sym + b_stat + b_flag);
   T* sub_u = (T*)(b + b_sym + b_stat + b_flag + b_part);
   T* sub_phi = sub_u + 2 * (size_t)nx;
+  OneStepProb<T>* tab = (OneStepProb<T>*)(b + b_sym + b_stat + b_flag + b_part + b_sub);
 
   HIP_TRY(launch_copy<T>(u, u0, (size_t)nx, st));   // u^0 = u0
   int rc = resolve_constants_p<T>(h, u0, part, st, false);
@@ -997,7 +999,8 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
     tau_u = tau_phi = std::sqrt(0.95 / nu);
   }
   if (h->os_c != h->c) {
-    // 1 / (N_x ((c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2)), mu_k = 4 sin^2(pi k / N_x) / h_x^2 (FFT index k)
+    // 1 / (M ((c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2)), M = N_x / 2, mu_k = 4 sin^2(pi k / N_x) / h_x^2
+    // (FFT index k; the 1/M normalises the half-length inverse FFT)
     typedef long double LD;
     const LD PI = 3.141592653589793238462643383279502884L;
     const LD c = h->c, g = P.precond_gamma_hat;
@@ -1007,7 +1010,7 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
       for (int k = 0; k < nx; ++k) {
         const LD sn = sinl(PI * k / nx);
         const LD mu = 4.0L * sn * sn / ((LD)hx * (LD)hx);
-        hs[(size_t)r * nx + k] = (T)(1.0L / ((LD)nx * (a * a + c * c * mu + g * g * mu * mu)));
+        hs[(size_t)r * nx + k] = (T)(2.0L / ((LD)nx * (a * a + c * c * mu + g * g * mu * mu)));
       }
     }
     HIP_TRY(hipMemcpyAsync(sym, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -1016,12 +1019,21 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   }
   HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
   HIP_TRY(hipMemsetAsync(stat, 0, (size_t)nt * sizeof(StepStat), st));
-  const Scheme s = scheme_of(h);
+  OneStepProb<T> tp{};
+  tp.s = scheme_of(h);
+  tp.tw = (const C2<T>*)h->d_tw;
+  tp.sym = sym;
+  tp.u = u;
+  tp.phi = phi;
+  tp.stat = stat;
+  tp.flag = flag;
+  tp.tau_u = tau_u;
+  tp.tau_phi = tau_phi;
+  HIP_TRY(hipMemcpyAsync(tab, &tp, sizeof(tp), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
   auto t0 = std::chrono::steady_clock::now();
-  for (int l = 0; l < nt; ++l)
-    HIP_TRY(launch_onestep<T>(s, h->d_tw, sym, u, phi, l, (T)tau_u, (T)tau_phi, prm->eps, (long long)prm->max_iter,
-                              div, stat, flag, st));
+  HIP_TRY(launch_onestep<T>(tab, 1, nx, 0, nt, prm->eps, (long long)prm->max_iter, div, st));
   std::vector<StepStat> rec(nt);
   HIP_TRY(hipMemcpyAsync(rec.data(), stat, (size_t)nt * sizeof(StepStat), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
