@@ -294,6 +294,20 @@ int pdhg_batch_offsets(const pdhg_batch* b, int32_t i, int64_t* u0_off, int64_t*
 int pdhg_batch_solve(pdhg_batch* b, const void* u0, void* u, void* phi, void* workspace,
                      const pdhg_batch_params* params, pdhg_stats* stats, pdhg_stream_t stream);
 
+/* The one-time-step solver (Algorithm 3, Section 3.5; see pdhg_solve_onestep)
+ * for every problem of the batch: one workgroup marches each problem, all in
+ * one launch.  u0, u, phi: packed DEVICE arrays as above (no workspace).
+ * params: tau_u/tau_phi per problem (<= 0 or NULL: the one-step power-iteration
+ * default), eps and max_iter per step, diverge_factor; check_every and
+ * warm_start are ignored.  stats: HOST [nprob] (iters = sum of the steps' n*,
+ * res_primal/res_dual = largest final step residuals, mass_drift = -1: not
+ * computed, variant = 5, seconds = wall time of the march launch).
+ * step_iters: nullable HOST array [sum of nt_i], problem i's steps at the
+ * exclusive prefix sum of the nt_j.  A diverged step stops only its own
+ * problem's march.  Synchronises the stream.  Returns as pdhg_batch_solve. */
+int pdhg_batch_solve_onestep(pdhg_batch* b, const void* u0, void* u, void* phi, const pdhg_batch_params* params,
+                             pdhg_stats* stats, int64_t* step_iters, pdhg_stream_t stream);
+
 /* Autotuner: times each of the three batched passes on this batch (buffers as
  * for pdhg_batch_solve; their contents are overwritten) for every candidate
  * persistent grid size (1, 2, 4, 8 blocks per compute unit up to the occupancy

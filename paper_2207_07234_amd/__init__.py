@@ -377,6 +377,34 @@ class BatchSolver:
         vu, vp = self._views(u, phi)
         return BatchResult(u, phi, rc, stats, vu, vp)
 
+    def solve_onestep(self, u0, tau_u=None, tau_phi=None, eps: float = 1e-8, max_iter: int = 10000, u=None,
+                      phi=None, diverge_factor: float = 0.0, want_steps: bool = False) -> BatchResult:
+        """Algorithm 3 for every problem (one workgroup per problem, one launch).  With want_steps,
+        stats[i]["step_iters"] lists problem i's n* per step."""
+        import torch
+        if u0.dtype != self.dtype or u0.numel() != self.u0_elems or not u0.is_contiguous():
+            raise PdhgError(f"u0: need a contiguous tensor of {self.u0_elems} {self.dtype} elements")
+        if u is None:
+            u = torch.empty(self.u_elems, dtype=self.dtype, device=self.device)
+        if phi is None:
+            phi = torch.empty(self.phi_elems, dtype=self.dtype, device=self.device)
+        p = self._params(tau_u, tau_phi, eps, max_iter, 0, False, diverge_factor)
+        st = (B.pdhg_stats * len(self.probs))()
+        nst = sum(q.nt for q in self.probs)
+        its = (C.c_int64 * nst)() if want_steps else None
+        rc = self.lib.pdhg_batch_solve_onestep(self._h, _ptr(u0), _ptr(u), _ptr(phi), C.byref(p), st, its,
+                                               _stream_ptr(self.device))
+        if rc < 0:
+            raise PdhgError(f"pdhg_batch_solve_onestep failed: {self._status(rc)}")
+        stats = [{k: getattr(s, k) for k, _ in B.pdhg_stats._fields_} for s in st]
+        if want_steps:
+            o = 0
+            for q, d in zip(self.probs, stats):
+                d["step_iters"] = list(its[o:o + q.nt])
+                o += q.nt
+        vu, vp = self._views(u, phi)
+        return BatchResult(u, phi, rc, stats, vu, vp)
+
     def tune(self, u0, tau_u=None, tau_phi=None, u=None, phi=None, workspace=None):
         """Autotune the persistent grid sizes of the three passes; returns them."""
         u, phi, workspace = self._buffers(u, phi, workspace)

@@ -65,7 +65,7 @@ class pdhg_batch_params(C.Structure):
 EXPORTED = (
     "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_solve_refined", "pdhg_solve_onestep", "pdhg_residual", "pdhg_precond",
     "pdhg_adjoint", "pdhg_time_kernel", "pdhg_destroy", "pdhg_status_string", "pdhg_last_error",
-    "pdhg_batch_setup", "pdhg_batch_sizes", "pdhg_batch_offsets", "pdhg_batch_solve", "pdhg_batch_tune",
+    "pdhg_batch_setup", "pdhg_batch_sizes", "pdhg_batch_offsets", "pdhg_batch_solve", "pdhg_batch_solve_onestep", "pdhg_batch_tune",
     "pdhg_batch_time_kernel", "pdhg_batch_destroy", "pdhg_batch_last_error",
 )
 
@@ -113,6 +113,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pdhg_batch_offsets.restype = C.c_int
     lib.pdhg_batch_solve.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_batch_params), C.POINTER(pdhg_stats), vp]
     lib.pdhg_batch_solve.restype = C.c_int
+    lib.pdhg_batch_solve_onestep.argtypes = [H, vp, vp, vp, C.POINTER(pdhg_batch_params), C.POINTER(pdhg_stats),
+                                             C.POINTER(C.c_int64), vp]
+    lib.pdhg_batch_solve_onestep.restype = C.c_int
     lib.pdhg_batch_tune.argtypes = [H, vp, vp, vp, vp, C.POINTER(pdhg_batch_params), C.POINTER(C.c_int32), vp]
     lib.pdhg_batch_tune.restype = C.c_int
     lib.pdhg_batch_time_kernel.argtypes = [H, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]

@@ -68,6 +68,10 @@ struct pdhg_batch {
   const void* gk_phi = nullptr;
   const void* gk_ws = nullptr;
   int gk_chunk = 0, gk_grid[3] = {0, 0, 0};
+  // one-time-step solver: symbols, per-step records, flags, nu, problem table
+  void* os_buf = nullptr;
+  size_t os_buf_bytes = 0;
+  std::vector<double> os_c;
   // buffers of the last solve (kernel timing)
   const void* last_u0 = nullptr;
   void* last_u = nullptr;
@@ -286,26 +290,34 @@ int build_factors_b(pdhg_batch* b) {
 
 // Constants, factor tables and step sizes of every problem; uploads the table.
 // nu[i] receives the power-iteration estimate (0 where steps were given).
+// Each problem's lf_speed and c from its u0 where they default (one launch for the batch).
 template <typename T>
-int prepare(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batch_params* prm, std::vector<double>& tau_u,
-            std::vector<double>& tau_phi, std::vector<double>& nu, hipStream_t st) {
+int resolve_b(pdhg_batch* b, const T* u0, hipStream_t st) {
   const int P = b->nprob;
-  const BatchLaunch L = launch_of(b);
-  BHIP_TRY(launch_batch_maxabs_dflux<T>(L, u0, b->d_scal, st));
+  BHIP_TRY(launch_batch_maxabs_dflux<T>(launch_of(b), u0, b->d_scal, st));
   BHIP_TRY(hipMemcpyAsync(b->h_scal, b->d_scal, sizeof(double) * P, hipMemcpyDeviceToHost, st));
   BHIP_TRY(hipStreamSynchronize(st));
-  bool refactor = b->d_fac_rows == nullptr;
   for (int i = 0; i < P; ++i) {
     const pdhg_problem& p = b->probs[i];
     const double m = b->h_scal[i];
     double lf = p.lf_speed < 0.0 ? m : p.lf_speed;
     if (p.space != PDHG_FD_LF) lf = 0.0;
-    const double c = p.precond_c < 0.0 ? m : p.precond_c;
     b->lf[i] = lf;
-    b->c[i] = c;
+    b->c[i] = p.precond_c < 0.0 ? m : p.precond_c;
     b->table[i].s.lf = lf;
-    if (b->fac_c[i] != c || b->fac_g[i] != p.precond_gamma_hat) refactor = true;
   }
+  return PDHG_OK;
+}
+
+template <typename T>
+int prepare(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batch_params* prm, std::vector<double>& tau_u,
+            std::vector<double>& tau_phi, std::vector<double>& nu, hipStream_t st) {
+  const int P = b->nprob;
+  int rc0 = resolve_b<T>(b, u0, st);
+  if (rc0) return rc0;
+  bool refactor = b->d_fac_rows == nullptr;
+  for (int i = 0; i < P; ++i)
+    if (b->fac_c[i] != b->c[i] || b->fac_g[i] != b->probs[i].precond_gamma_hat) refactor = true;
   if (refactor) {
     int rc = build_factors_b<T>(b);
     if (rc) return rc;
@@ -478,6 +490,121 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
   return worst;
 }
 
+// Algorithm 3 for every problem of the batch: one launch of the one-step march
+// with a block per problem (after one power-iteration launch where step sizes
+// are not given).  Problems are tabled in decreasing N_t N_x order so that the
+// longest marches start first when there are more problems than compute units.
+template <typename T>
+int batch_onestep_impl(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batch_params* prm, pdhg_stats* stats,
+                       int64_t* step_iters, hipStream_t st) {
+  const int P = b->nprob;
+  int rc = resolve_b<T>(b, u0, st);
+  if (rc) return rc;
+  std::vector<size_t> sym_off(P), st_off(P);
+  size_t nsym = 0, nst = 0;
+  int max_nt = 0;
+  for (int i = 0; i < P; ++i) {
+    sym_off[i] = nsym;
+    st_off[i] = nst;
+    nsym += 2 * (size_t)b->probs[i].nx;
+    nst += (size_t)b->probs[i].nt;
+    max_nt = std::max(max_nt, b->probs[i].nt);
+  }
+  const size_t b_sym = align_b(nsym * sizeof(T)), b_stat = align_b(nst * sizeof(StepStat));
+  const size_t b_flag = align_b(P * sizeof(int)), b_nu = align_b(P * sizeof(double));
+  const size_t need = b_sym + b_stat + b_flag + b_nu + align_b(P * sizeof(OneStepProb<T>));
+  if (b->os_buf_bytes < need) {
+    if (b->os_buf) hipFree(b->os_buf);
+    b->os_buf = nullptr;
+    b->os_buf_bytes = 0;
+    b->os_c.clear();
+    BHIP_TRY(hipMalloc(&b->os_buf, need));
+    b->os_buf_bytes = need;
+  }
+  char* base = static_cast<char*>(b->os_buf);
+  T* sym = (T*)base;
+  StepStat* stat = (StepStat*)(base + b_sym);
+  int* flag = (int*)(base + b_sym + b_stat);
+  double* nu_d = (double*)(base + b_sym + b_stat + b_flag);
+  OneStepProb<T>* tab = (OneStepProb<T>*)(base + b_sym + b_stat + b_flag + b_nu);
+  if (b->os_c != b->c) {
+    std::vector<T> hs(nsym);
+    for (int i = 0; i < P; ++i) onestep_symbol<T>(b->probs[i], b->c[i], hs.data() + sym_off[i]);
+    BHIP_TRY(hipMemcpyAsync(sym, hs.data(), nsym * sizeof(T), hipMemcpyHostToDevice, st));
+    BHIP_TRY(hipStreamSynchronize(st));
+    b->os_c = b->c;
+  }
+  BHIP_TRY(hipMemsetAsync(flag, 0, P * sizeof(int), st));
+  BHIP_TRY(hipMemsetAsync(stat, 0, nst * sizeof(StepStat), st));
+  std::vector<int> order(P);
+  for (int i = 0; i < P; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (long long)b->probs[x].nt * b->probs[x].nx > (long long)b->probs[y].nt * b->probs[y].nx;
+  });
+  std::vector<OneStepProb<T>> tp(P);
+  bool any_auto = false;
+  for (int r = 0; r < P; ++r) {
+    const int i = order[r];
+    OneStepProb<T>& e = tp[r];
+    e.s = b->table[i].s;
+    e.tw = (const C2<T>*)b->d_tw.at(b->probs[i].nx);
+    e.sym = sym + sym_off[i];
+    e.u0 = u0 + b->u0_off[i];
+    e.u = u + b->u_off[i];
+    e.phi = phi + b->f_off[i];
+    e.stat = stat + st_off[i];
+    e.flag = flag + i;
+    const double tu = prm->tau_u ? prm->tau_u[i] : 0.0, tq = prm->tau_phi ? prm->tau_phi[i] : 0.0;
+    const bool given = tu > 0.0 && tq > 0.0;
+    e.tau_u = given ? tu : 0.0;
+    e.tau_phi = given ? tq : 0.0;
+    any_auto = any_auto || !given;
+  }
+  BHIP_TRY(hipMemcpyAsync(tab, tp.data(), P * sizeof(OneStepProb<T>), hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemsetAsync(nu_d, 0, P * sizeof(double), st));
+  if (any_auto) BHIP_TRY(launch_onestep_power<T>(tab, P, b->max_nx, 200, nu_d, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+  const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
+  auto t0 = std::chrono::steady_clock::now();
+  BHIP_TRY(launch_onestep<T>(tab, P, b->max_nx, 0, max_nt, prm->eps, (long long)prm->max_iter, div, st));
+  std::vector<StepStat> rec(nst);
+  std::vector<double> nu(P);
+  BHIP_TRY(hipMemcpyAsync(rec.data(), stat, nst * sizeof(StepStat), hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipMemcpyAsync(tp.data(), tab, P * sizeof(OneStepProb<T>), hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipMemcpyAsync(nu.data(), nu_d, P * sizeof(double), hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  const double secs = std::chrono::duration<double>(t1 - t0).count();
+  int worst = PDHG_OK;
+  for (int r = 0; r < P; ++r) {
+    const int i = order[r];
+    const OneStepSummary sm = summarize_steps(rec.data() + st_off[i], b->probs[i].nt,
+                                              step_iters ? step_iters + st_off[i] : nullptr, nullptr);
+    if (!(tp[r].tau_u > 0.0)) {
+      b->err = std::string("step-size estimate of problem ") + std::to_string(i) + " failed";
+      return PDHG_EINVAL;
+    }
+    if (sm.status == PDHG_DIVERGED) worst = PDHG_DIVERGED;
+    else if (sm.status == PDHG_NOT_CONVERGED && worst == PDHG_OK) worst = PDHG_NOT_CONVERGED;
+    if (stats) {
+      pdhg_stats& s = stats[i];
+      s.iters = sm.total;
+      s.res_primal = sm.rp;
+      s.res_dual = sm.rd;
+      s.tau_u = tp[r].tau_u;
+      s.tau_phi = tp[r].tau_phi;
+      s.nu_max = nu[r];
+      s.lf_speed = b->lf[i];
+      s.precond_c = b->c[i];
+      s.seconds = secs;
+      s.mass_drift = -1.0;
+      s.status = sm.status;
+      s.variant = 5;
+    }
+  }
+  return worst;
+}
+
 // Average device time of one launch of pass k with `grid` blocks (events per
 // launch; for the column pass a primal pass refills the spectrum before each
 // timed launch).
@@ -631,6 +758,18 @@ int pdhg_batch_solve(pdhg_batch* b, const void* u0, void* u, void* phi, void* wo
   return batch_solve_impl<float>(b, (const float*)u0, (float*)u, (float*)phi, workspace, params, stats, st);
 }
 
+int pdhg_batch_solve_onestep(pdhg_batch* b, const void* u0, void* u, void* phi, const pdhg_batch_params* params,
+                             pdhg_stats* stats, int64_t* step_iters, pdhg_stream_t stream) {
+  if (!b || !u0 || !u || !phi || !params || params->max_iter < 0) return PDHG_EINVAL;
+  if (b->max_nx < 64) return PDHG_EUNSUPPORTED;
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return bset_hip_error(b, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (b->dtype == PDHG_F64)
+    return batch_onestep_impl<double>(b, (const double*)u0, (double*)u, (double*)phi, params, stats, step_iters, st);
+  return batch_onestep_impl<float>(b, (const float*)u0, (float*)u, (float*)phi, params, stats, step_iters, st);
+}
+
 int pdhg_batch_tune(pdhg_batch* b, const void* u0, void* u, void* phi, void* workspace,
                     const pdhg_batch_params* params, int32_t* grids, pdhg_stream_t stream) {
   if (!b || !u0 || !u || !phi || !workspace || !params) return PDHG_EINVAL;
@@ -659,6 +798,7 @@ void pdhg_batch_destroy(pdhg_batch* b) {
   if (b->d_corder) hipFree(b->d_corder);
   if (b->d_part) hipFree(b->d_part);
   if (b->d_scal) hipFree(b->d_scal);
+  if (b->os_buf) hipFree(b->os_buf);
   if (b->h_ctrls) hipHostFree(b->h_ctrls);
   if (b->h_counts) hipHostFree(b->h_counts);
   if (b->h_scal) hipHostFree(b->h_scal);

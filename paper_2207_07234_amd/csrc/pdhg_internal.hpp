@@ -85,14 +85,26 @@ struct OneStepProb {
   Scheme s;            // grid, scheme and resolved flux constants
   const C2<T>* tw;     // [nx] twiddles e^{-2 pi i j / nx}
   const T* sym;        // [2][nx] preconditioner symbol reciprocals (c0 = 1, c0 = 3/2), 1/M folded in
-  T* u;                // [nt+1][nx]; level 0 (and every level before the first step marched) is read
+  const T* u0;         // [nx] or null; a march from step 0 reads u0 here and writes it to level 0 of u
+  T* u;                // [nt+1][nx]; otherwise the levels before the first step marched are read
   T* phi;              // [nt][nx]
   StepStat* stat;      // [nt]
   int* flag;           // 0 while the march runs, 2 after a step diverged
   double tau_u, tau_phi;
 };
+template <typename T>
+void onestep_symbol(const pdhg_problem& p, double c, T* out);   // host: [2][nx]
+struct OneStepSummary {
+  long long total;   // sum of the steps' n*
+  double rp, rd;     // largest final step residuals
+  int status;        // PDHG_OK / PDHG_NOT_CONVERGED / PDHG_DIVERGED
+  int done;          // steps marched (the march stops after a diverged step)
+};
+OneStepSummary summarize_steps(const StepStat* rec, int nt, int64_t* step_iters, double* step_res);
 // Threads per problem: one radix-8 butterfly per thread in each stage of the half-length FFT.
 __host__ __device__ inline int onestep_threads(int nx) { return nx / 8 < 64 ? 64 : nx / 8; }
+template <typename T>
+hipError_t launch_onestep_power(OneStepProb<T>* probs, int nprob, int max_nx, int iters, double* nu, hipStream_t st);
 template <typename T>
 hipError_t launch_onestep(const OneStepProb<T>* probs, int nprob, int max_nx, int l_begin, int l_end, double eps,
                           long long max_iter, double dfac, hipStream_t st);

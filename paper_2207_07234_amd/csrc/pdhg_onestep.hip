@@ -79,6 +79,83 @@ __device__ __forceinline__ void precond_pair(C2<T>* buf, int k, int q, T a, T b,
   if (q != k) buf[lpad(q)] = C2<T>{sex + soy, sox - sey};            // Y_q = conj(SE) + i conj(SO)
 }
 
+// Per-thread constants of the spectral pairs k = tid + j W < M/2 for one symbol row.
+template <typename T, int KP>
+struct PairConsts {
+  T a[KP], b[KP];   // d_k, d_{k+M}
+  C2<T> w[KP];      // e^{-2 pi i k / N}
+  T mid;            // d_{M/2}
+};
+
+template <typename T, int KP>
+__device__ __forceinline__ void load_pair_symbol(PairConsts<T, KP>& pc, const T* symr, bool act, int tid, int W,
+                                                 int M) {
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int k = tid + j * W;
+    const bool ok = act && k < (M >> 1);
+    pc.a[j] = ok ? symr[k] : T(0);
+    pc.b[j] = ok ? symr[k + M] : T(0);
+  }
+  pc.mid = symr[M >> 1];
+}
+
+// row <- K_l^{-1} row for the slice held in lane-cyclic order (block-wide; the
+// caller separates consecutive calls by at least one barrier).
+template <typename T, int EPT, int KP>
+__device__ __forceinline__ void kinv_slice(T (&row)[EPT], const PairConsts<T, KP>& pc, bool act, int seg, int lane,
+                                           int tid, int W, int M, C2<T>* buf, const C2<T>* twl) {
+  T* bufr = reinterpret_cast<T*>(buf);
+  if (act) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int x = seg + lane + 64 * e;
+      bufr[2 * lpad(x >> 1) + (x & 1)] = row[e];   // z_m = r_{2m} + i r_{2m+1}
+    }
+  }
+  fft_lds<false, (EPT + 1) / 2>(buf, M, twl, tid, W);
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const int k = tid + j * W;
+      if (k < (M >> 1)) precond_pair(buf, k, (M - k) & (M - 1), pc.a[j], pc.b[j], pc.w[j]);
+    }
+  }
+  if (tid == 0) {   // k = M/2: Y = d_{M/2} Z
+    C2<T> z = buf[lpad(M >> 1)];
+    z.x *= pc.mid;
+    z.y *= pc.mid;
+    buf[lpad(M >> 1)] = z;
+  }
+  fft_lds<true, (EPT + 1) / 2>(buf, M, twl, tid, W);
+  if (act) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int x = seg + lane + 64 * e;
+      row[e] = bufr[2 * lpad(x >> 1) + (x & 1)];
+    }
+  }
+}
+
+// Block sums of two per-thread values in a fixed order, returned to every thread.
+__device__ __forceinline__ void block_sum2(double& a, double& b, bool act, int wv, int nw, int lane,
+                                           double (*red)[kOneStepWavesMax]) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (act && lane == 0) {
+    red[0][wv] = a;
+    red[1][wv] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    sa += red[0][i];
+    sb += red[1][i];
+  }
+  a = sa;
+  b = sb;
+}
+
 // Steps [l_begin, l_end) of problem P on a block whose first W = nx / EPT threads are active.
 template <typename T, int EPT>
 __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, int l_begin, int l_end, double eps,
@@ -92,42 +169,35 @@ __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, in
   const int seg = wv * 64 * EPT;
   const T tau_u = (T)P.tau_u, tau_phi = (T)P.tau_phi;
   for (int i = tid; i < M; i += blockDim.x) twl[lpad(i)] = P.tw[2 * i];   // e^{-2 pi i i' / M}
-  T* bufr = reinterpret_cast<T*>(buf);
   // spectral pairs k = tid + j W < M/2 (and k = M/2, self-paired, on thread 0)
   constexpr int KP = EPT >= 4 ? EPT / 4 : 1;
-  C2<T> pw[KP];
+  PairConsts<T, KP> pc;
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
     const int k = tid + j * W;
-    pw[j] = (act && k < (M >> 1)) ? P.tw[k] : C2<T>{T(1), T(0)};
+    pc.w[j] = (act && k < (M >> 1)) ? P.tw[k] : C2<T>{T(1), T(0)};
   }
-  // cur = u^l, known = (c1 u^l + c2 u^{l-1}) / h_t at the first step
+  // cur = u^l, known = (c1 u^l + c2 u^{l-1}) / h_t at the first step; from u0 (also written to
+  // level 0) when the march starts at step 0 with P.u0 given
   T cur[EPT], known[EPT];
   {
     const T c1 = C.c1(l_begin), c2 = C.c2(l_begin);
-    const T* ul = P.u + (size_t)l_begin * nx;
+    const bool from_u0 = l_begin == 0 && P.u0 != nullptr;
+    const T* ul = from_u0 ? P.u0 : P.u + (size_t)l_begin * nx;
     const T* ulm = ul - (l_begin >= 1 ? nx : 0);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int x = seg + lane + 64 * e;
       cur[e] = act ? ul[x] : T(0);
       known[e] = act ? (c1 * cur[e] + c2 * ulm[x]) * C.inv_ht : T(0);
+      if (act && from_u0) P.u[x] = cur[e];
     }
   }
   const double hx = sch.hx;
   for (int l = l_begin; l < l_end; ++l) {
     const T c0 = C.c0(l);
     const T a0 = c0 * C.inv_ht;
-    const T* symr = P.sym + (c0 != T(1) ? nx : 0);
-    T pa[KP], pq[KP];
-#pragma unroll
-    for (int j = 0; j < KP; ++j) {
-      const int k = tid + j * W;
-      const bool ok = act && k < (M >> 1);
-      pa[j] = ok ? symr[k] : T(0);
-      pq[j] = ok ? symr[k + M] : T(0);
-    }
-    const T dmid = symr[M >> 1];
+    load_pair_symbol(pc, P.sym + (c0 != T(1) ? nx : 0), act, tid, W, M);
     // initial guess v = u^l, phi = phibar = 0 (so the first primal step is void)
     T v[1][EPT], ph[2][EPT], g[EPT];
 #pragma unroll
@@ -143,44 +213,22 @@ __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, in
       // primal step with J_l(v^{n-1})^T phibar^{n-1} (g, from the previous iteration)
 #pragma unroll
       for (int e = 0; e < EPT; ++e) v[0][e] -= tau_u * g[e];
-      // implicit residual A_l(v^n) into the FFT buffer
+      // implicit residual A_l(v^n)
       T vm[1][EPT], vp[1][EPT];
       slice_neighbours<T, EPT, 1>(v, vm, vp, ends, act, wv, nw, lane);
       double srp = 0.0;
-      if (act) {
+      T r[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int x = seg + lane + 64 * e;
-          const T r = a0 * v[0][e] + known[e] + C.F(vm[0][e], v[0][e], vp[0][e]);
-          srp += (double)r * (double)r;
-          bufr[2 * lpad(x >> 1) + (x & 1)] = r;   // z_m = r_{2m} + i r_{2m+1}
-        }
+      for (int e = 0; e < EPT; ++e) {
+        r[e] = a0 * v[0][e] + known[e] + C.F(vm[0][e], v[0][e], vp[0][e]);
+        if (act) srp += (double)r[e] * (double)r[e];
       }
-      // s = K_l^{-1} r: half-length forward FFT, spectral pairs, half-length inverse FFT
-      fft_lds<false, (EPT + 1) / 2>(buf, M, twl, tid, W);
-      if (act) {
+      // s = K_l^{-1} r (in place), then the dual step and extrapolation: ph[0] = phi, ph[1] = phibar
+      kinv_slice<T, EPT, KP>(r, pc, act, seg, lane, tid, W, M, buf, twl);
 #pragma unroll
-        for (int j = 0; j < KP; ++j) {
-          const int k = tid + j * W;
-          if (k < (M >> 1)) precond_pair(buf, k, (M - k) & (M - 1), pa[j], pq[j], pw[j]);
-        }
-      }
-      if (tid == 0) {   // k = M/2: Y = d_{M/2} Z
-        C2<T> z = buf[lpad(M >> 1)];
-        z.x *= dmid;
-        z.y *= dmid;
-        buf[lpad(M >> 1)] = z;
-      }
-      fft_lds<true, (EPT + 1) / 2>(buf, M, twl, tid, W);
-      // dual step and extrapolation: ph[0] = phi, ph[1] = phibar
-      if (act) {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int x = seg + lane + 64 * e;
-          const T s = bufr[2 * lpad(x >> 1) + (x & 1)];
-          ph[1][e] = ph[0][e] + T(2) * tau_phi * s;
-          ph[0][e] = ph[0][e] + tau_phi * s;
-        }
+      for (int e = 0; e < EPT; ++e) {
+        ph[1][e] = ph[0][e] + T(2) * tau_phi * r[e];
+        ph[0][e] = ph[0][e] + tau_phi * r[e];
       }
       // J_l(v^n)^T phi^n (dual residual) and J_l(v^n)^T phibar^n (next primal step)
       T pm[2][EPT], pp[2][EPT];
@@ -195,20 +243,9 @@ __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, in
         }
       }
       // block sums in a fixed order, read by every thread: a uniform decision
-      srp = wave_sum(srp);
-      srd = wave_sum(srd);
-      if (act && lane == 0) {
-        red[0][wv] = srp;
-        red[1][wv] = srd;
-      }
-      __syncthreads();
-      double sp = 0.0, sd = 0.0;
-      for (int i = 0; i < nw; ++i) {
-        sp += red[0][i];
-        sd += red[1][i];
-      }
-      rp = sqrt(hx * sp);
-      rd = sqrt(hx * sd);
+      block_sum2(srp, srd, act, wv, nw, lane, red);
+      rp = sqrt(hx * srp);
+      rd = sqrt(hx * srd);
       const double m = fmax(rp, rd);
       if (!(isfinite(rp) && isfinite(rd)) || (m > dfac * best)) {
         status = 2;
@@ -247,6 +284,127 @@ __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, in
     }
   }
 }
+
+// Largest eigenvalue of J_l(u0)^T K_l^{-1} J_l(u0) over the step operators of
+// problem P (c0 = 1, and c0 = 3/2 for BDF2 with nt > 1) by `iters` power
+// iterations from a fixed pseudo-random start; u0 is level 0 of P.u (or P.u0).
+template <typename T, int EPT>
+__device__ __forceinline__ double onestep_power(const OneStepProb<T>& P, int W, int iters, C2<T>* buf, C2<T>* twl,
+                                                T (*ends)[2 * kOneStepWavesMax], double (*red)[kOneStepWavesMax]) {
+  const Scheme& sch = P.s;
+  const Consts<T> C(sch);
+  const int nx = sch.nx, M = nx >> 1, tid = threadIdx.x;
+  const bool act = tid < W;
+  const int nw = W >> 6, wv = tid >> 6, lane = tid & 63;
+  const int seg = wv * 64 * EPT;
+  for (int i = tid; i < M; i += blockDim.x) twl[lpad(i)] = P.tw[2 * i];
+  constexpr int KP = EPT >= 4 ? EPT / 4 : 1;
+  PairConsts<T, KP> pc;
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int k = tid + j * W;
+    pc.w[j] = (act && k < (M >> 1)) ? P.tw[k] : C2<T>{T(1), T(0)};
+  }
+  const T* u0 = P.u0 ? P.u0 : P.u;
+  T uu[1][EPT], um[1][EPT], up[1][EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) uu[0][e] = act ? u0[seg + lane + 64 * e] : T(0);
+  slice_neighbours<T, EPT, 1>(uu, um, up, ends, act, wv, nw, lane);
+  double nu = 0.0;
+  const int nc0 = (sch.time == kTimeBDF2 && sch.nt > 1) ? 2 : 1;
+  for (int ci = 0; ci < nc0; ++ci) {
+    const T a0 = T(ci ? 1.5 : 1.0) * C.inv_ht;
+    load_pair_symbol(pc, P.sym + (ci ? nx : 0), act, tid, W, M);
+    T v[1][EPT];
+    double s2 = 0.0, dummy = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {   // xorshift-hashed start in [-1/2, 1/2)
+      unsigned long long h = 0x9E3779B97F4A7C15ull * (unsigned long long)(seg + lane + 64 * e + 1);
+      h ^= h >> 31;
+      h *= 0xBF58476D1CE4E5B9ull;
+      h ^= h >> 27;
+      v[0][e] = act ? T((double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5) : T(0);
+      s2 += (double)v[0][e] * (double)v[0][e];
+    }
+    block_sum2(s2, dummy, act, wv, nw, lane, red);
+    {
+      const T sc = T(1.0 / sqrt(s2));
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[0][e] *= sc;
+    }
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+      T vm[1][EPT], vp[1][EPT];
+      slice_neighbours<T, EPT, 1>(v, vm, vp, ends + 1, act, wv, nw, lane);
+      T w[1][EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e)   // J v = a0 v + dF(u0) v
+        w[0][e] = a0 * v[0][e] + C.JF(um[0][e], uu[0][e], up[0][e], vm[0][e], v[0][e], vp[0][e]);
+      kinv_slice<T, EPT, KP>(w[0], pc, act, seg, lane, tid, W, M, buf, twl);
+      T wm[1][EPT], wp[1][EPT];
+      slice_neighbours<T, EPT, 1>(w, wm, wp, ends + 2, act, wv, nw, lane);
+      double tv = 0.0, tt = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {   // t = J^T w
+        const T t = a0 * w[0][e] + C.JtF(uu[0][e], wm[0][e], w[0][e], wp[0][e]);
+        if (act) {
+          tv += (double)t * (double)v[0][e];
+          tt += (double)t * (double)t;
+        }
+        w[0][e] = t;
+      }
+      block_sum2(tv, tt, act, wv, nw, lane, red);
+      lam = tv;
+      const T sc = T(1.0 / sqrt(tt));
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[0][e] = w[0][e] * sc;
+    }
+    nu = fmax(nu, lam);
+  }
+  return nu;
+}
+
+// Block b estimates nu_max of problem probs[b] into nu[b]; where the problem's
+// step sizes are not positive it sets both to sqrt(0.95 / nu_max) in the table.
+template <typename T>
+__global__ void __launch_bounds__(kOneStepThreadsMax)
+k_onestep_power(OneStepProb<T>* __restrict__ probs, int iters, double* __restrict__ nu) {
+  const OneStepProb<T> P = probs[blockIdx.x];
+  extern __shared__ char smem[];
+  __shared__ T ends[3][2 * kOneStepWavesMax];
+  __shared__ double red[2][kOneStepWavesMax];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* twl = buf + lds_fft_points(P.s.nx >> 1);
+  const int W = onestep_threads(P.s.nx);
+  double v;
+  switch (P.s.nx / W) {
+    case 8: v = onestep_power<T, 8>(P, W, iters, buf, twl, ends, red); break;
+    case 4: v = onestep_power<T, 4>(P, W, iters, buf, twl, ends, red); break;
+    case 2: v = onestep_power<T, 2>(P, W, iters, buf, twl, ends, red); break;
+    default: v = onestep_power<T, 1>(P, W, iters, buf, twl, ends, red); break;
+  }
+  if (threadIdx.x == 0) {
+    nu[blockIdx.x] = v;
+    if (!(P.tau_u > 0.0) || !(P.tau_phi > 0.0)) {
+      const double t = (v > 0.0 && isfinite(v)) ? sqrt(0.95 / v) : 0.0;
+      probs[blockIdx.x].tau_u = t;
+      probs[blockIdx.x].tau_phi = t;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_onestep_power(OneStepProb<T>* probs, int nprob, int max_nx, int iters, double* nu, hipStream_t st) {
+  if (max_nx < 64 || max_nx > 4096 || (max_nx & (max_nx - 1)) || nprob < 1) return hipErrorInvalidValue;
+  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(max_nx / 2);
+  hipError_t e = allow_lds(k_onestep_power<T>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_onestep_power<T>), dim3(nprob), dim3(onestep_threads(max_nx)), lds, st, probs, iters, nu);
+  return hipGetLastError();
+}
+
+template hipError_t launch_onestep_power<float>(OneStepProb<float>*, int, int, int, double*, hipStream_t);
+template hipError_t launch_onestep_power<double>(OneStepProb<double>*, int, int, int, double*, hipStream_t);
 
 // Block b marches problem probs[b] over steps [l_begin, min(l_end, nt)).
 template <typename T>

@@ -105,6 +105,53 @@ template void build_factor_rows<float>(const pdhg_problem&, double, double, std:
                                         std::vector<int>&, std::vector<int>&);
 template void build_factor_rows<double>(const pdhg_problem&, double, double, std::vector<FacRow<double>>&,
                                          std::vector<int>&, std::vector<int>&);
+// Symbol of the one-step preconditioner per FFT index k, row r for c0 = 1 (r = 0)
+// and c0 = 3/2 (r = 1): 1 / (M ((c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2)),
+// mu_k = 4 sin^2(pi k / N_x) / h_x^2, M = N_x / 2 (the 1/M normalises the
+// half-length inverse FFT).  Computed in long double.
+template <typename T>
+void onestep_symbol(const pdhg_problem& p, double c, T* out) {
+  typedef long double LD;
+  const LD PI = 3.141592653589793238462643383279502884L;
+  const int nx = p.nx;
+  const LD ht = (LD)p.t_final / p.nt, hx = (LD)p.length / nx, cc = c, g = p.precond_gamma_hat;
+  for (int r = 0; r < 2; ++r) {
+    const LD a = (r ? 1.5L : 1.0L) / ht;
+    for (int k = 0; k < nx; ++k) {
+      const LD sn = sinl(PI * k / nx);
+      const LD mu = 4.0L * sn * sn / (hx * hx);
+      out[(size_t)r * nx + k] = (T)(2.0L / ((LD)nx * (a * a + cc * cc * mu + g * g * mu * mu)));
+    }
+  }
+}
+template void onestep_symbol<float>(const pdhg_problem&, double, float*);
+template void onestep_symbol<double>(const pdhg_problem&, double, double*);
+
+// Totals of a one-step march from its per-step records; the march stops after a diverged step.
+OneStepSummary summarize_steps(const StepStat* rec, int nt, int64_t* step_iters, double* step_res) {
+  OneStepSummary sm{0, 0.0, 0.0, PDHG_OK, nt};
+  for (int l = 0; l < nt; ++l) {
+    const bool ran = l < sm.done;
+    if (ran) {
+      sm.total += rec[l].iters;
+      sm.rp = std::max(sm.rp, rec[l].rp);
+      sm.rd = std::max(sm.rd, rec[l].rd);
+      if (rec[l].status == 2) {
+        sm.status = PDHG_DIVERGED;
+        sm.done = l + 1;
+      } else if (rec[l].status == 1 && sm.status == PDHG_OK) {
+        sm.status = PDHG_NOT_CONVERGED;
+      }
+    }
+    if (step_iters) step_iters[l] = ran ? rec[l].iters : 0;
+    if (step_res) {
+      step_res[2 * l] = ran ? rec[l].rp : NAN;
+      step_res[2 * l + 1] = ran ? rec[l].rd : NAN;
+    }
+  }
+  return sm;
+}
+
 template void build_factor_rows_shifts<float>(const pdhg_problem&, const std::vector<long double>&,
                                               std::vector<FacRow<float>>&, std::vector<int>&, std::vector<int>&);
 template void build_factor_rows_shifts<double>(const pdhg_problem&, const std::vector<long double>&,
@@ -170,12 +217,10 @@ struct pdhg_handle {
   std::vector<std::pair<int, pdhg_handle*>> refine_sub;
   void* refine_buf = nullptr;
   size_t refine_buf_bytes = 0;
-  // one-time-step solver: device tables and per-step records, and the N_t = 1 plans
-  // whose power iteration gives the step sizes (c0 = 1 and c0 = 3/2)
+  // one-time-step solver: symbol table, per-step records, flag and problem table
   void* os_buf = nullptr;
   size_t os_buf_bytes = 0;
   double os_c = -1.0;
-  pdhg_handle* os_sub[2] = {nullptr, nullptr};
   std::string err;
 };
 
@@ -580,7 +625,6 @@ void pdhg_destroy(pdhg_handle* h) {
   if (!h) return;
   for (auto& kv : h->refine_sub) pdhg_destroy(kv.second);
   if (h->refine_buf) hipFree(h->refine_buf);
-  for (pdhg_handle* sub : h->os_sub) pdhg_destroy(sub);
   if (h->os_buf) hipFree(h->os_buf);
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
@@ -935,14 +979,12 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   const pdhg_problem& P = h->prob;
   if (P.space == PDHG_DG_P2_LLF || P.nx < 64) return PDHG_EUNSUPPORTED;
   const int nx = P.nx, nt = P.nt;
-  // sym [2][nx] | stat [nt] | flag | part (level sums, max |f'|) | u [2][nx], phi [nx] of the step-size plans
-  // | problem table
+  // sym [2][nx] | stat [nt] | flag | part (max |f'|, nu, level sums) | problem table
   const size_t b_sym = align_up(2 * (size_t)nx * sizeof(T));
   const size_t b_stat = align_up((size_t)nt * sizeof(StepStat));
   const size_t b_flag = align_up(sizeof(int));
   const size_t b_part = align_up(sizeof(double) * std::max<size_t>(64, (size_t)nt + 1));
-  const size_t b_sub = align_up(3 * (size_t)nx * sizeof(T));
-  const size_t need = b_sym + b_stat + b_flag + b_part + b_sub + align_up(sizeof(OneStepProb<T>));
+  const size_t need = b_sym + b_stat + b_flag + b_part + align_up(sizeof(OneStepProb<T>));
   if (h->os_buf_bytes < need) {
     if (h->os_buf) hipFree(h->os_buf);
     h->os_buf = nullptr;
@@ -956,81 +998,46 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   StepStat* stat = (StepStat*)(b + b_sym);
   int* flag = (int*)(b + b_sym + b_stat);
   double* part = (double*)(b + b_sym + b_stat + b_flag);
-  T* sub_u = (T*)(b + b_sym + b_stat + b_flag + b_part);
-  T* sub_phi = sub_u + 2 * (size_t)nx;
-  OneStepProb<T>* tab = (OneStepProb<T>*)(b + b_sym + b_stat + b_flag + b_part + b_sub);
+  OneStepProb<T>* tab = (OneStepProb<T>*)(b + b_sym + b_stat + b_flag + b_part);
 
-  HIP_TRY(launch_copy<T>(u, u0, (size_t)nx, st));   // u^0 = u0
   int rc = resolve_constants_p<T>(h, u0, part, st, false);
   if (rc) return rc;
   const double ht = P.t_final / nt, hx = P.length / nx;
-  double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
-  if (tau_u <= 0.0 || tau_phi <= 0.0) {
-    // the step with coefficient c0 is the backward-Euler N_t = 1 problem with time step h_t / c0
-    const int nc0 = (P.time == PDHG_BDF2 && nt > 1) ? 2 : 1;
-    for (int i = 0; i < nc0; ++i) {
-      pdhg_problem q = P;
-      q.nt = 1;
-      q.time = PDHG_BE;
-      q.t_final = ht / (i ? 1.5 : 1.0);
-      if (P.space == PDHG_FD_LF) q.lf_speed = h->lf;
-      q.precond_c = h->c;
-      pdhg_handle*& sub = h->os_sub[i];
-      if (sub && (sub->prob.lf_speed != q.lf_speed || sub->prob.precond_c != q.precond_c)) {
-        pdhg_destroy(sub);
-        sub = nullptr;
-      }
-      if (!sub) {
-        rc = pdhg_setup(&q, &sub);
-        if (rc) return rc;
-      }
-      pdhg_params qp{};
-      qp.max_iter = 0;
-      qp.check_every = 1;
-      pdhg_stats sst{};
-      rc = pdhg_solve(sub, u0, sub_u, sub_phi, nullptr, &qp, &sst, (pdhg_stream_t)st);
-      if (rc < 0) {
-        h->err = std::string("step-size estimate: ") + pdhg_last_error(sub);
-        return rc;
-      }
-      nu = std::max(nu, sst.nu_max);
-    }
-    if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
-    tau_u = tau_phi = std::sqrt(0.95 / nu);
-  }
   if (h->os_c != h->c) {
-    // 1 / (M ((c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2)), M = N_x / 2, mu_k = 4 sin^2(pi k / N_x) / h_x^2
-    // (FFT index k; the 1/M normalises the half-length inverse FFT)
-    typedef long double LD;
-    const LD PI = 3.141592653589793238462643383279502884L;
-    const LD c = h->c, g = P.precond_gamma_hat;
     std::vector<T> hs(2 * (size_t)nx);
-    for (int r = 0; r < 2; ++r) {
-      const LD a = (r ? 1.5L : 1.0L) / (LD)ht;
-      for (int k = 0; k < nx; ++k) {
-        const LD sn = sinl(PI * k / nx);
-        const LD mu = 4.0L * sn * sn / ((LD)hx * (LD)hx);
-        hs[(size_t)r * nx + k] = (T)(2.0L / ((LD)nx * (a * a + c * c * mu + g * g * mu * mu)));
-      }
-    }
+    onestep_symbol<T>(P, h->c, hs.data());
     HIP_TRY(hipMemcpyAsync(sym, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     h->os_c = h->c;
   }
+  (void)ht;
   HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
   HIP_TRY(hipMemsetAsync(stat, 0, (size_t)nt * sizeof(StepStat), st));
+  const bool auto_tau = !(prm->tau_u > 0.0 && prm->tau_phi > 0.0);
   OneStepProb<T> tp{};
   tp.s = scheme_of(h);
   tp.tw = (const C2<T>*)h->d_tw;
   tp.sym = sym;
+  tp.u0 = u0;
   tp.u = u;
   tp.phi = phi;
   tp.stat = stat;
   tp.flag = flag;
-  tp.tau_u = tau_u;
-  tp.tau_phi = tau_phi;
+  tp.tau_u = auto_tau ? 0.0 : prm->tau_u;
+  tp.tau_phi = auto_tau ? 0.0 : prm->tau_phi;
   HIP_TRY(hipMemcpyAsync(tab, &tp, sizeof(tp), hipMemcpyHostToDevice, st));
+  double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
+  if (auto_tau) {
+    // nu_max over the step operators at u0 (200 power iterations); the kernel sets the table's steps
+    HIP_TRY(launch_onestep_power<T>(tab, 1, nx, 200, part, st));
+    HIP_TRY(hipMemcpyAsync(h->h_scal, part, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   HIP_TRY(hipStreamSynchronize(st));
+  if (auto_tau) {
+    nu = h->h_scal[0];
+    if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
+    tau_u = tau_phi = std::sqrt(0.95 / nu);
+  }
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
   auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(launch_onestep<T>(tab, 1, nx, 0, nt, prm->eps, (long long)prm->max_iter, div, st));
@@ -1038,40 +1045,19 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   HIP_TRY(hipMemcpyAsync(rec.data(), stat, (size_t)nt * sizeof(StepStat), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   auto t1 = std::chrono::steady_clock::now();
-  long long total = 0;
-  double mrp = 0.0, mrd = 0.0;
-  int status = PDHG_OK, done = nt;
-  for (int l = 0; l < nt; ++l) {
-    const bool ran = l < done;
-    if (ran) {
-      total += rec[l].iters;
-      mrp = std::max(mrp, rec[l].rp);
-      mrd = std::max(mrd, rec[l].rd);
-      if (rec[l].status == 2) {
-        status = PDHG_DIVERGED;
-        done = l + 1;
-      } else if (rec[l].status == 1 && status == PDHG_OK) {
-        status = PDHG_NOT_CONVERGED;
-      }
-    }
-    if (step_iters) step_iters[l] = ran ? rec[l].iters : 0;
-    if (step_res) {
-      step_res[2 * l] = ran ? rec[l].rp : NAN;
-      step_res[2 * l + 1] = ran ? rec[l].rd : NAN;
-    }
-  }
+  OneStepSummary sm = summarize_steps(rec.data(), nt, step_iters, step_res);
   double drift = 0.0;
   {
-    HIP_TRY(launch_level_sums<T>(u, nx, (size_t)nx, done + 1, part, st));
-    std::vector<double> m(done + 1);
+    HIP_TRY(launch_level_sums<T>(u, nx, (size_t)nx, sm.done + 1, part, st));
+    std::vector<double> m(sm.done + 1);
     HIP_TRY(hipMemcpyAsync(m.data(), part, m.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    for (int l = 1; l <= done; ++l) drift = std::max(drift, std::fabs(m[l] - m[0]) * hx);
+    for (int l = 1; l <= sm.done; ++l) drift = std::max(drift, std::fabs(m[l] - m[0]) * hx);
   }
   if (stats) {
-    stats->iters = total;
-    stats->res_primal = mrp;
-    stats->res_dual = mrd;
+    stats->iters = sm.total;
+    stats->res_primal = sm.rp;
+    stats->res_dual = sm.rd;
     stats->tau_u = tau_u;
     stats->tau_phi = tau_phi;
     stats->nu_max = nu;
@@ -1079,10 +1065,10 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
     stats->precond_c = h->c;
     stats->seconds = std::chrono::duration<double>(t1 - t0).count();
     stats->mass_drift = drift;
-    stats->status = status;
+    stats->status = sm.status;
     stats->variant = 5;
   }
-  return status;
+  return sm.status;
 }
 
 }  // namespace

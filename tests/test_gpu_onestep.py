@@ -145,3 +145,81 @@ def test_unsupported_cases(gpu_lib):
     gd = gpu_lib.Problem(nx=64, nt=4, t_final=0.5, alpha=0.5, beta=0.0, time="be", space="dg_p2_llf")
     with pytest.raises(gpu_lib.PdhgError):
         gpu_lib.Solver(gd).solve_onestep(_dev(np.zeros((3, 64))))
+
+
+# ------------------------------------------------------------------ batched one-step solver
+MIXED = [
+    dict(nx=256, nt=9, t_final=0.1, alpha=0.5, beta=0.0, gamma=0.0, time="bdf2", space="fd_lf", seed=0),
+    dict(nx=512, nt=5, t_final=0.05, alpha=0.5, beta=0.0, gamma=1e-3, precond_gamma_hat=1e-3, time="be",
+         space="fd_lf", seed=2),
+    dict(nx=1024, nt=6, t_final=0.2, alpha=0.0, beta=1.0, gamma=0.0, time="be", space="fd_upwind", seed=3),
+    dict(nx=2048, nt=4, t_final=0.02, alpha=0.5, beta=0.0, gamma=0.0, time="bdf2", space="fd_lf", seed=4),
+    dict(nx=4096, nt=3, t_final=0.01, alpha=0.5, beta=0.0, gamma=5e-4, precond_gamma_hat=5e-4, time="bdf2",
+         space="fd_lf", seed=6),
+]
+
+
+def _batch(pk, cfgs, dtype):
+    probs, u0s = [], []
+    for c in cfgs:
+        c = dict(c)
+        seed = c.pop("seed")
+        probs.append(pk.Problem(dtype=dtype, **c))
+        u0s.append(syn.fourier_u0(seed, c["nx"]))
+    return probs, u0s
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_matches_single_solves_bitwise(gpu_lib, dtype):
+    """Every problem of a batch (block size set by the widest problem, idle threads past each problem's
+    width) reproduces its single solve bit for bit, with given and with automatic step sizes."""
+    probs, u0s = _batch(gpu_lib, MIXED, dtype)
+    bs = gpu_lib.BatchSolver(probs)
+    taus = [0.6, 0.5, 0.7, 0.55, 0.6]
+    for tau in (taus, None):
+        res = bs.solve_onestep(bs.pack_u0(u0s), tau_u=tau, tau_phi=tau, eps=1e-9 if dtype == torch.float64 else 0.0,
+                               max_iter=400 if dtype == torch.float64 else 30, want_steps=True)
+        for i, (p, u0) in enumerate(zip(probs, u0s)):
+            st = res.stats[i]
+            ref = gpu_lib.Solver(p).solve_onestep(_dev(u0, dtype), tau_u=st["tau_u"], tau_phi=st["tau_phi"],
+                                                  eps=1e-9 if dtype == torch.float64 else 0.0,
+                                                  max_iter=400 if dtype == torch.float64 else 30)
+            if tau is None:
+                assert st["nu_max"] > 0 and st["tau_u"] == pytest.approx(np.sqrt(0.95 / st["nu_max"]))
+            assert st["step_iters"] == ref.stats["step_iters"]
+            assert st["status"] == ref.status == (0 if dtype == torch.float64 else 1)
+            assert torch.equal(res.views_u[i], ref.u) and torch.equal(res.views_phi[i], ref.phi)
+    _say(f"  {len(probs)} problems bitwise equal to their single solves")
+
+
+def test_batch_against_oracle(gpu_lib):
+    probs, u0s = _batch(gpu_lib, MIXED[:3], torch.float64)
+    bs = gpu_lib.BatchSolver(probs)
+    res = bs.solve_onestep(bs.pack_u0(u0s), tau_u=[0.6] * 3, tau_phi=[0.6] * 3, eps=0.0, max_iter=20)
+    for i, (c, u0) in enumerate(zip(MIXED[:3], u0s)):
+        c = dict(c)
+        c.pop("seed")
+        op = default_constants(OProblem(**c), u0)
+        ref = oos.run(op, u0, eps=0.0, max_iter=20, tau_u=0.6, tau_phi=0.6)
+        assert _err(res.views_u[i], ref.u, f"batch problem {i} u") < 1e-10
+        assert _err(res.views_phi[i], ref.phi, f"batch problem {i} phi") < 1e-10
+
+
+def test_batch_workload_family_converges(gpu_lib):
+    """Eight problems of the 256-problem Burgers family (BDF2, LF, T = 0.5; Algorithm 1 diverges on most of
+    this family) in FP64: the batched one-step march converges on every one to its Newton march."""
+    shapes = syn.batch_shapes(0, 256)
+    pick = [0, 1, 2, 3, 43, 86, 129, 172]
+    cfg = [shapes[i] for i in pick]
+    probs = [gpu_lib.Problem(nx=nx, nt=nt, t_final=0.5, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf",
+                             dtype=torch.float64) for nx, nt, _ in cfg]
+    u0s = [syn.fourier_u0(s, nx) for nx, _, s in cfg]
+    bs = gpu_lib.BatchSolver(probs)
+    res = bs.solve_onestep(bs.pack_u0(u0s), eps=1e-9, max_iter=2000)
+    _say(f"  status {res.status}; iterations {[s['iters'] for s in res.stats]}; {res.stats[0]['seconds']:.3f} s")
+    assert res.status == 0
+    for i, ((nx, nt, _), u0) in enumerate(zip(cfg, u0s)):
+        op = default_constants(OProblem(nx=nx, nt=nt, t_final=0.5, alpha=0.5, beta=0.0, time="bdf2",
+                                        space="fd_lf"), u0)
+        # slice residual <= eps per step: error <= T eps sqrt(N_x) (see the full-size test)
+        assert _err(res.views_u[i], onewton.march(op, u0), f"{nx}x{nt} vs newton") < 0.5 * 1e-9 * np.sqrt(nx)
