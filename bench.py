@@ -14,6 +14,14 @@ bounded sample of iterations of the same workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload batch [--batch-iters N] [--ttr-problems M]
     python bench.py --workload dg [--dg-iters N] [--dtype f32|f64]
+
+The single workload also reports the paper's three variants side by side
+(Section 4, comparison of the variants): Algorithm 1, mesh refinement in time
+(Algorithm 2, levels N_t = 1, 2, ..., 512) and the one-time-step solver
+(Algorithm 3, step residual 1e-8 in the slice norm, so the space-time residual
+is at most sqrt(T) 1e-8), each with its iterations, "world time" (iterations
+in sequence) and work in units of N_x (sum over levels of iterations times
+N_t + 1 levels; two levels per one-step iteration), and measured seconds.
 """
 import argparse
 import json
@@ -45,12 +53,12 @@ COPY_KERNEL = 8   # plain copy of N_t*N_x elements: one read and one write per e
 # only for the kernel sources they were taken on (SHA-256 below); after any change to those
 # sources the traffic field is reported as null until the counters are taken again.
 # Summary and commands: profiles/primal_res_burgers_2048x512_f64_pmc.md.
-COUNTER_SOURCES = ("paper_2207_07234_amd/csrc/pdhg_fused.hip", "paper_2207_07234_amd/csrc/pdhg_device.hpp",
-                   "paper_2207_07234_amd/csrc/pdhg_internal.hpp")
+COUNTER_SOURCES = ("paper_2207_07234_amd/csrc/pdhg_fused.hip", "paper_2207_07234_amd/csrc/pdhg_passes.hpp",
+                   "paper_2207_07234_amd/csrc/pdhg_device.hpp")
 COUNTERS = {
     # (dtype, variant, kernel id): per-dispatch KiB of the kernel and of the copy kernel
-    ("f64", 2, 0): {"fetch_kib": 13002.5, "write_kib": 16388.0, "copy_fetch_kib": 4105.5, "copy_write_kib": 8192.0,
-                    "sha": "e3e0c148445f1197e4185b506f808a21476ac17f0fa19e98f311e760308c409e"},
+    ("f64", 2, 0): {"fetch_kib": 12972.8, "write_kib": 16388.0, "copy_fetch_kib": 4102.5, "copy_write_kib": 8192.0,
+                    "sha": "11012316df0cf1b623462155c8ee2df51220743116971b57d9ad71efabafa943"},
 }
 
 KERNELS_UNFUSED = {
@@ -184,6 +192,7 @@ def run_batch(args):
     ttr = None
     if args.ttr_problems > 0:
         ttr = batch_time_to_residual(pk, args.ttr_problems, dev)
+    onestep = batch_onestep_time_to_residual(pk, dev)
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-iterations/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
@@ -195,12 +204,71 @@ def run_batch(args):
             "problems": len(probs), "dof": dof, "iterations_per_solve": iters, "diverged": ndiv,
             "grids": grids, "per_instance_value": value_s, "speedup_vs_per_instance": value / value_s,
             "time_to_residual_1e-8": ttr,
+            "one_step_time_to_residual_1e-8": onestep,
         },
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "batched " + name,
                      "bytes_per_launch": words * esz * dof, "ms_per_launch": ms},
     }
     print(json.dumps(out), flush=True)
+
+
+def variant_comparison(pk, solver, prob, u0, tau, vanilla):
+    """Algorithms 1, 2 and 3 on the single workload (FP64, 1e-8); `vanilla` = (iterations, seconds)."""
+    import torch
+    out = {"algorithm_1": {"iterations": vanilla[0], "world_time": vanilla[0],
+                           "work_N": vanilla[0] * (NT + 1), "seconds": vanilla[1], "status": 0}}
+    # Algorithm 2 from N_t0 = 1; every level to 1e-8 (the first call builds the coarse plans)
+    kw = dict(nt_start=1, coarse_eps=EPS, coarse_max_iter=200000, eps=EPS, max_iter=200000, check_every=128)
+    solver.solve_refined(u0, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = solver.solve_refined(u0, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lv = r.stats["level_iters"]
+    nts = [1 << k for k in range(len(lv))]
+    out["mesh_refinement"] = {"iterations": lv, "world_time": sum(lv),
+                              "work_N": sum(n * (m + 1) for n, m in zip(lv, nts)), "seconds": wall,
+                              "status": r.status}
+    log(f"Algorithm 2: status {r.status}, iterations per level {lv}, {wall:.3f} s")
+    # Algorithm 3, step residual 1e-8
+    solver.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = solver.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, _, res = solver.residual(r.u, r.phi, want_fields=False)
+    n = r.stats["iters"]
+    out["one_step"] = {"iterations": n, "world_time": n, "work_N": 2 * n, "seconds": wall, "status": r.status,
+                       "space_time_residual": list(res), "steps": NT,
+                       "us_per_iteration": r.stats["seconds"] / n * 1e6}
+    log(f"Algorithm 3: status {r.status}, {n} iterations ({min(r.stats['step_iters'])}.."
+        f"{max(r.stats['step_iters'])} per step), {wall:.3f} s, space-time residual {res[0]:.2e} / {res[1]:.2e}")
+    return out
+
+
+def batch_onestep_time_to_residual(pk, dev):
+    """FP64, every problem of the batch workload by the batched one-step solver (Algorithm 3), step
+    residual 1e-8."""
+    import torch
+    probs, u0s = batch_problems(pk, torch.float64)
+    bs = pk.BatchSolver(probs)
+    u0 = bs.pack_u0(u0s)
+    bs.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = bs.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    slice_its = sum(p.nx * s["iters"] for p, s in zip(probs, r.stats))
+    res = {"problems": len(probs), "dtype": "f64", "eps_step": EPS, "seconds": wall,
+           "converged": sum(s["status"] == 0 for s in r.stats), "diverged": sum(s["status"] == 2 for s in r.stats),
+           "max_iterations": max(s["iters"] for s in r.stats), "slice_dof_iterations_per_s": slice_its / wall}
+    log(f"batched one-step (FP64, all {len(probs)} problems, step residual 1e-8): {wall:.3f} s, "
+        f"{res['converged']} converged, {res['diverged']} diverged")
+    return res
 
 
 def batch_time_to_residual(pk, count, dev):
@@ -355,6 +423,7 @@ def main():
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run exactly this many iterations per solve instead of solving to 1e-8 (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Algorithm 2 / Algorithm 3 comparison")
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None,
                     help="compute type (default f64 for the single workload, f32 for the batch)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto (fused), 1 unfused, 2 fused")
@@ -444,6 +513,10 @@ def main():
             "bytes_per_launch": words * esz * dof, "ms_per_launch": ms,
             "copy_GBs": copy_bytes / (copy_ms * 1e-3) / 1e9}
 
+    variants = None
+    if eps > 0 and not args.no_variants:
+        variants = variant_comparison(pk, solver, prob, u0, tau, (iters[-1], ms_per_step / 1e3))
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -465,6 +538,7 @@ def main():
             "kernel_sum_us_per_iteration": iter_us, "variant": stats["variant"],
             "us_per_iteration_wall": wall / sum(iters) * 1e6,
             "effective_GBs_all_kernels": sum(w for _, w, _, _ in kern.values()) * esz * dof * sum(iters) / wall / 1e9,
+            "variants": variants,
         },
         "roofline": roof,
     }
