@@ -23,6 +23,9 @@ def march(prob: Problem, u0: np.ndarray, tol: float = 1e-14, max_newton: int = 5
     if prob.space == "dg_p2_llf":
         from . import dg
         return dg.p2_newton_march(prob, u0, tol, max_newton)
+    if prob.space == "dg_p1_upwind":
+        from . import dg1
+        return dg1.p1_newton_march(prob, u0, tol, max_newton)
     nt, n, ht = prob.nt, prob.nx, prob.ht
     u = np.empty((nt + 1, n))
     u[0] = u0

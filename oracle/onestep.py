@@ -113,7 +113,7 @@ def auto_steps(prob: Problem, u0: np.ndarray, safety: float = 0.95, iters: int =
 def run(prob: Problem, u0: np.ndarray, eps: float, max_iter: int = 10000, tau_u: float = None,
         tau_phi: float = None) -> OneStepResult:
     """Algorithm 3 over l = 0..N_t-1."""
-    if prob.space == "dg_p2_llf":
+    if prob.space in ("dg_p2_llf", "dg_p1_upwind"):
         raise ValueError("the one-step oracle covers the finite-difference schemes")
     if tau_u is None or tau_phi is None:
         tu, tp, _ = auto_steps(prob, u0)

@@ -46,6 +46,9 @@ def _ops(prob: Problem):
     if prob.space == "dg_p2_llf":
         from . import dg
         return dg.p2_residual, dg.p2_apply_jt, dg.p2_wnorm
+    if prob.space == "dg_p1_upwind":
+        from . import dg1
+        return dg1.p1_residual, dg1.p1_apply_jt, dg1.p1_wnorm
     return fd.residual, fd.apply_jt, fd.wnorm
 
 
@@ -95,6 +98,10 @@ def jt_operator(prob: Problem, u: np.ndarray):
     if prob.space == "dg_p2_llf":
         from . import dg
         return lambda phi: dg.p2_apply_jt(prob, u, phi)
+    if prob.space == "dg_p1_upwind":
+        from . import dg1
+        jt = dg1.p1_jacobian(prob, u).T.tocsr()
+        return lambda phi: (jt @ phi.ravel()).reshape(phi.shape)
     jt = fd.jacobian(prob, u).T.tocsr()
     return lambda phi: (jt @ phi.ravel()).reshape(phi.shape)
 
@@ -103,6 +110,9 @@ def kd_solve_any(prob: Problem, r: np.ndarray) -> np.ndarray:
     if prob.space == "dg_p2_llf":
         from . import dg
         return dg.p2_kd_solve(prob, r)
+    if prob.space == "dg_p1_upwind":
+        from . import dg1
+        return dg1.p1_kd_solve(prob, r)
     return kd_solve(prob, r)
 
 
@@ -112,7 +122,11 @@ def nu_max(prob: Problem, u: np.ndarray, iters: int = 200, seed: int = 0) -> flo
     Proposition 2.1 requires sigma * tau * nu < 1 for every eigenvalue nu.
     """
     residual, apply_jt, _ = _ops(prob)
-    J = fd.jacobian(prob, u) if prob.space != "dg_p2_llf" else None
+    if prob.space == "dg_p1_upwind":
+        from . import dg1
+        J = dg1.p1_jacobian(prob, u)
+    else:
+        J = fd.jacobian(prob, u) if prob.space != "dg_p2_llf" else None
     rng = np.random.default_rng(seed)
     v = rng.standard_normal((prob.nt,) + np.shape(u[0]))
     v /= np.linalg.norm(v)

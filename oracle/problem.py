@@ -25,7 +25,7 @@ class Problem:
     beta: float = 1.0
     gamma: float = 0.0                 # constant viscosity (centred diffusion)
     time: str = "be"                   # "be" | "bdf2"
-    space: str = "fd_upwind"           # "fd_upwind" | "fd_lf" | "heat_var" | "dg_p2_llf"
+    space: str = "fd_upwind"           # "fd_upwind" | "fd_lf" | "heat_var" | "dg_p2_llf" | "dg_p1_upwind"
     lf_speed: float = 0.0              # global Lax-Friedrichs constant (fd_lf)
     precond_c: float = 0.0             # c in K = -d_tt - c^2 d_xx + ghat^2 d_xxxx
     precond_gamma_hat: float = 0.0     # ghat
@@ -43,8 +43,8 @@ class Problem:
 
     @property
     def p(self) -> int:
-        """Degrees of freedom per cell: 1 for finite differences, 3 for DG P2."""
-        return 3 if self.space == "dg_p2_llf" else 1
+        """Degrees of freedom per cell: 1 for finite differences, 3 for DG P2, 2 for DG P1."""
+        return {"dg_p2_llf": 3, "dg_p1_upwind": 2}.get(self.space, 1)
 
     def f(self, u):
         return self.alpha * u * u + self.beta * u
@@ -79,6 +79,11 @@ def default_constants(prob: Problem, u0: np.ndarray) -> Problem:
       the initial data (Section 3.3); default max |f'(u0)|.
     """
     kw = {}
+    if prob.space == "dg_p1_upwind":
+        from .dg1 import default_speed
+        if prob.precond_c <= 0.0:
+            kw["precond_c"] = default_speed(prob, u0)
+        return prob.with_(**kw) if kw else prob
     if prob.space == "dg_p2_llf":
         # DG: u0 is the (3, N_x) coefficient array; the speed is taken over the
         # cell-edge traces of u0_h (the states the local Lax-Friedrichs flux sees)
