@@ -72,8 +72,16 @@ typedef enum { PDHG_BE = 0, PDHG_BDF2 = 1 } pdhg_time;
  *                  precond_gamma_hat are not used; the default precond_c is
  *                  max |f'| over the cell-edge traces of u0.  The preconditioner
  *                  couples the three planes through the unit-speed upwind DG
- *                  operator G: K_d = (B_t B_t^T) (x) I + I_t (x) c^2 G G^T. */
-typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1, PDHG_DG_P2_LLF = 2 } pdhg_space;
+ *                  operator G: K_d = (B_t B_t^T) (x) I + I_t (x) c^2 G G^T.
+ *  PDHG_DG_P1_UPWIND: the paper's DG example (Sections 3.2.2, 3.2.3): piecewise
+ *                  linear on nx cells, stored by the nodal values at x_c - h/4 and
+ *                  x_c + h/4 (x_c the cell centre), upwind flux f(u^-) (requires
+ *                  f' >= 0), volume integrals by 2-point Gauss.  Arrays: u [nt+1][2][nx],
+ *                  phi [nt][2][nx], u0 [2][nx] (nodal values of the initial data).
+ *                  Limits as for PDHG_DG_P2_LLF; the default precond_c is max |f'|
+ *                  over the nodal values and edge traces of u0; K_d as above with
+ *                  the P1 operator G. */
+typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1, PDHG_DG_P2_LLF = 2, PDHG_DG_P1_UPWIND = 3 } pdhg_space;
 
 typedef struct {
   int32_t nx, nt;

@@ -30,7 +30,8 @@ __all__ = ["Problem", "Solver", "SolveResult", "BatchSolver", "BatchResult", "Pd
 
 lib_path = B.LIB_PATH
 _TIME = {"be": B.PDHG_BE, "bdf2": B.PDHG_BDF2}
-_SPACE = {"fd_upwind": B.PDHG_FD_UPWIND, "fd_lf": B.PDHG_FD_LF, "dg_p2_llf": B.PDHG_DG_P2_LLF}
+_SPACE = {"fd_upwind": B.PDHG_FD_UPWIND, "fd_lf": B.PDHG_FD_LF, "dg_p2_llf": B.PDHG_DG_P2_LLF,
+          "dg_p1_upwind": B.PDHG_DG_P1_UPWIND}
 
 
 class PdhgError(RuntimeError):
@@ -74,8 +75,8 @@ class Problem:
 
     @property
     def level_shape(self):
-        """Shape of one time level: (nx,) for finite differences, (3, nx) coefficient planes for DG."""
-        return (3, self.nx) if self.space == "dg_p2_llf" else (self.nx,)
+        """Shape of one time level: (nx,) for finite differences, (3, nx) for DG P2, (2, nx) for DG P1."""
+        return {"dg_p2_llf": (3, self.nx), "dg_p1_upwind": (2, self.nx)}.get(self.space, (self.nx,))
 
 
 @dataclass

@@ -506,7 +506,7 @@ int batch_onestep_impl(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batc
   for (int i = 0; i < P; ++i) {
     sym_off[i] = nsym;
     st_off[i] = nst;
-    nsym += 2 * (size_t)b->probs[i].nx;
+    nsym += 2 * (size_t)b->probs[i].nx + 32;   // symbol [2][nx], cyclic-reduction coefficients [2][16]
     nst += (size_t)b->probs[i].nt;
     max_nt = std::max(max_nt, b->probs[i].nt);
   }
@@ -527,9 +527,18 @@ int batch_onestep_impl(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batc
   int* flag = (int*)(base + b_sym + b_stat);
   double* nu_d = (double*)(base + b_sym + b_stat + b_flag);
   OneStepProb<T>* tab = (OneStepProb<T>*)(base + b_sym + b_stat + b_flag + b_nu);
+  std::vector<int> pk(2 * (size_t)P, 0);
+  std::vector<double> pcr(32 * (size_t)P, 0.0);
+  for (int i = 0; i < P; ++i)
+    if (!onestep_pcr(b->probs[i], b->c[i], sizeof(T) == 8 ? 1e-17 : 1e-9, &pcr[32 * (size_t)i], &pk[2 * (size_t)i]))
+      pk[2 * (size_t)i] = pk[2 * (size_t)i + 1] = 0;
   if (b->os_c != b->c) {
-    std::vector<T> hs(nsym);
-    for (int i = 0; i < P; ++i) onestep_symbol<T>(b->probs[i], b->c[i], hs.data() + sym_off[i]);
+    std::vector<T> hs(nsym, T(0));
+    for (int i = 0; i < P; ++i) {
+      const size_t nx2 = 2 * (size_t)b->probs[i].nx;
+      onestep_symbol<T>(b->probs[i], b->c[i], hs.data() + sym_off[i]);
+      for (int q = 0; q < 32; ++q) hs[sym_off[i] + nx2 + q] = (T)pcr[32 * (size_t)i + q];
+    }
     BHIP_TRY(hipMemcpyAsync(sym, hs.data(), nsym * sizeof(T), hipMemcpyHostToDevice, st));
     BHIP_TRY(hipStreamSynchronize(st));
     b->os_c = b->c;
@@ -549,6 +558,9 @@ int batch_onestep_impl(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batc
     e.s = b->table[i].s;
     e.tw = (const C2<T>*)b->d_tw.at(b->probs[i].nx);
     e.sym = sym + sym_off[i];
+    e.pcr = e.sym + 2 * (size_t)b->probs[i].nx;
+    e.pcr_k[0] = pk[2 * (size_t)i];
+    e.pcr_k[1] = pk[2 * (size_t)i + 1];
     e.u0 = u0 + b->u0_off[i];
     e.u = u + b->u_off[i];
     e.phi = phi + b->f_off[i];

@@ -18,6 +18,8 @@ constexpr int kTimeBE = 0;
 constexpr int kTimeBDF2 = 1;
 constexpr int kSpaceUpwind = 0;
 constexpr int kSpaceLF = 1;
+constexpr int kSpaceDgP2 = 2;
+constexpr int kSpaceDgP1 = 3;
 
 // Host-filled description of one problem (all in double; kernels convert).
 struct Scheme {

@@ -375,109 +375,120 @@ k_dg_residual_fft(Scheme s, const T* __restrict__ u, T* __restrict__ spec, int l
 
 // ------------------------------------------------------------------ column solve
 // Block of 4 waves = 8 spectrum columns = 4 Fourier modes (the first wave of
-// block 0 holds the real columns of modes 0 and nx/2).  The spectrum has 3 nt
-// rows, row 3l + p for level l and coefficient plane p.  The [3 nt][8] tile is
-// staged in LDS; slot (c, p) of level l is column c, plane p.  Wave w owns
-// columns 2w (Re) and 2w+1 (Im): the 6 components r = 3 ri + p of its mode.
-//   1. rotate every level's 6-vector by V^T in LDS (one level per lane at a time)
+// block 0 holds the real columns of modes 0 and nx/2).  With NP coefficient
+// planes (3 for P2, 2 for P1) the spectrum has NP nt rows, row NP l + p for
+// level l and plane p.  The [NP nt][8] tile is staged in LDS; slot (c, p) of
+// level l is column c, plane p.  Wave w owns columns 2w (Re) and 2w+1 (Im):
+// the 2 NP components r = NP ri + p of its mode.
+//   1. rotate every level's 2NP-vector by V^T in LDS (one level per lane at a time)
 //   2. per eigen-branch b: banded Cholesky solve along t (lane owns LPL levels)
 //   3. rotate back by V
-// vtab: 36 values per mode (V row-major, columns = eigenvectors of the real 6x6
-// form); the factor table of branch b of mode m has index 6 m + b.  For the real
-// modes 0 and nx/2 the 6x6 form is block-diagonal (Im H = 0): branches 0..2 act on
-// the real parts, which are the only nonzero ones.
-template <int LPL>
+// vtab: 36 values per mode (V row-major with row stride 6, columns = eigenvectors
+// of the real 2NP x 2NP form); the factor table of branch b of mode m has index
+// 6 m + b.  For the real modes 0 and nx/2 the real form is block-diagonal
+// (Im H = 0): branches 0..NP-1 act on the real parts, the only nonzero ones.
+template <int LPL, int NP>
 __device__ __forceinline__ int dg_slot(int c, int p, int l) {
-  return ((c * 3 + p) * LPL + l % LPL) * 65 + l / LPL;
+  return ((c * NP + p) * LPL + l % LPL) * 65 + l / LPL;
 }
 
-template <typename T, int LPL>
+template <typename T, int LPL, int NP>
 __device__ __forceinline__ void dg_rotate(T* tile, const T* __restrict__ V, const int* cs, const int* ps, int ncomp,
                                           bool transpose, int lane, int nt) {
   for (int l = lane; l < nt; l += 64) {
     T x[6], y[6];
-    for (int r = 0; r < ncomp; ++r) x[r] = tile[dg_slot<LPL>(cs[r], ps[r], l)];
+    for (int r = 0; r < ncomp; ++r) x[r] = tile[dg_slot<LPL, NP>(cs[r], ps[r], l)];
     for (int b = 0; b < ncomp; ++b) {
       T acc = T(0);
       for (int r = 0; r < ncomp; ++r) acc += (transpose ? V[r * 6 + b] : V[b * 6 + r]) * x[r];
       y[b] = acc;
     }
-    for (int b = 0; b < ncomp; ++b) tile[dg_slot<LPL>(cs[b], ps[b], l)] = y[b];
+    for (int b = 0; b < ncomp; ++b) tile[dg_slot<LPL, NP>(cs[b], ps[b], l)] = y[b];
   }
 }
 
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, int NP>
 __device__ __forceinline__ void dg_solve_mode(T* tile, const FacTab<T>& fac, const T* __restrict__ vtab, int mode,
                                               const int* cs, const int* ps, int ncomp, int lane, int nt) {
   const T* V = vtab + (size_t)mode * 36;
   const int l0 = lane * LPL;
-  dg_rotate<T, LPL>(tile, V, cs, ps, ncomp, true, lane, nt);            // y = V^T x
+  dg_rotate<T, LPL, NP>(tile, V, cs, ps, ncomp, true, lane, nt);        // y = V^T x
   for (int b = 0; b < ncomp; ++b) {
     T invd[LPL], e1[LPL + 1], e2[LPL + 2];
     load_factor_rows<T, LPL>(fac, mode * 6 + b, l0, invd, e1, e2);
     T z[1][LPL];
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) z[0][i] = tile[dg_slot<LPL>(cs[b], ps[b], l0 + i)];
+    for (int i = 0; i < LPL; ++i) z[0][i] = tile[dg_slot<LPL, NP>(cs[b], ps[b], l0 + i)];
     cholesky_solve_wave<T, BW, LPL, 1>(z, invd, e1, e2, lane, l0, nt);
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) tile[dg_slot<LPL>(cs[b], ps[b], l0 + i)] = z[0][i];
+    for (int i = 0; i < LPL; ++i) tile[dg_slot<LPL, NP>(cs[b], ps[b], l0 + i)] = z[0][i];
   }
-  dg_rotate<T, LPL>(tile, V, cs, ps, ncomp, false, lane, nt);           // x = V y
+  dg_rotate<T, LPL, NP>(tile, V, cs, ps, ncomp, false, lane, nt);       // x = V y
 }
 
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, int NP>
 __global__ void __launch_bounds__(64 * kColWaves)
 k_dg_colsolve(T* __restrict__ spec, FacTab<T> fac, const T* __restrict__ vtab, int nt, int nx, int lqb,
               const Ctrl* ctrl) {
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
-  T* tile = reinterpret_cast<T*>(smem);   // [8 cols][3 planes][LPL][65]
-  const int QB = 1 << lqb, nr = 3 * nt;
+  T* tile = reinterpret_cast<T*>(smem);   // [8 cols][NP planes][LPL][65]
+  const int QB = 1 << lqb, nr = NP * nt;
   const int q0 = xcd_block(blockIdx.x, gridDim.x) * kColCols;
   T* base = spec + (size_t)(q0 >> lqb) * nr * QB + (q0 & (QB - 1));
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   constexpr int kPer = 64 * LPL * kColCols / (64 * kColWaves);   // per plane
-  // stage the [3 nt][8] tile through registers, one plane at a time
-  for (int p = 0; p < 3; ++p) {
+  // stage the [NP nt][8] tile through registers, one plane at a time
+  for (int p = 0; p < NP; ++p) {
     T stage[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       const int idx = tid + r * 64 * kColWaves;
       const int l = idx / kColCols, c = idx % kColCols;
-      stage[r] = (l < nt) ? base[(size_t)(3 * l + p) * QB + c] : T(0);
+      stage[r] = (l < nt) ? base[(size_t)(NP * l + p) * QB + c] : T(0);
     }
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       const int idx = tid + r * 64 * kColWaves;
       const int l = idx / kColCols, c = idx % kColCols;
-      tile[dg_slot<LPL>(c, p, l)] = stage[r];
+      tile[dg_slot<LPL, NP>(c, p, l)] = stage[r];
     }
   }
   __syncthreads();
   const int qa = q0 + 2 * wv;
-  if (qa != 0) {   // one complex mode: components (Re, planes 0..2), (Im, planes 0..2)
-    const int cs[6] = {2 * wv, 2 * wv, 2 * wv, 2 * wv + 1, 2 * wv + 1, 2 * wv + 1};
-    const int ps[6] = {0, 1, 2, 0, 1, 2};
-    dg_solve_mode<T, BW, LPL>(tile, fac, vtab, spec_mode(qa, nx), cs, ps, 6, lane, nt);
+  if (qa != 0) {   // one complex mode: components (Re, planes 0..NP-1), (Im, planes 0..NP-1)
+    int cs[6], ps[6];
+#pragma unroll
+    for (int r = 0; r < 2 * NP; ++r) {
+      cs[r] = 2 * wv + r / NP;
+      ps[r] = r % NP;
+    }
+    dg_solve_mode<T, BW, LPL, NP>(tile, fac, vtab, spec_mode(qa, nx), cs, ps, 2 * NP, lane, nt);
   } else {         // real columns 0 (mode 0) and 1 (mode nx/2)
-    const int cs0[3] = {0, 0, 0}, cs1[3] = {1, 1, 1}, ps[3] = {0, 1, 2};
-    dg_solve_mode<T, BW, LPL>(tile, fac, vtab, 0, cs0, ps, 3, lane, nt);
-    dg_solve_mode<T, BW, LPL>(tile, fac, vtab, nx / 2, cs1, ps, 3, lane, nt);
+    int cs0[3], cs1[3], ps[3];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      cs0[r] = 0;
+      cs1[r] = 1;
+      ps[r] = r;
+    }
+    dg_solve_mode<T, BW, LPL, NP>(tile, fac, vtab, 0, cs0, ps, NP, lane, nt);
+    dg_solve_mode<T, BW, LPL, NP>(tile, fac, vtab, nx / 2, cs1, ps, NP, lane, nt);
   }
   __syncthreads();
-  for (int p = 0; p < 3; ++p) {
+  for (int p = 0; p < NP; ++p) {
     T stage[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       const int idx = tid + r * 64 * kColWaves;
       const int l = idx / kColCols, c = idx % kColCols;
-      stage[r] = tile[dg_slot<LPL>(c, p, l)];
+      stage[r] = tile[dg_slot<LPL, NP>(c, p, l)];
     }
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       const int idx = tid + r * 64 * kColWaves;
       const int l = idx / kColCols, c = idx % kColCols;
-      if (l < nt) base[(size_t)(3 * l + p) * QB + c] = stage[r];
+      if (l < nt) base[(size_t)(NP * l + p) * QB + c] = stage[r];
     }
   }
 }
@@ -553,23 +564,22 @@ hipError_t launch_dg_residual_fft(const Scheme& s, const T* u, T* spec, int lqb,
   }
 }
 
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, int NP>
 static hipError_t launch_dg_colsolve_l(T* spec, const FacTab<T>& fac, const T* vtab, int nt, int nx, int lqb,
                                        const Ctrl* ctrl, hipStream_t st) {
-  const size_t lds = sizeof(T) * (size_t)kColCols * 3 * LPL * 65;
-  hipError_t e = allow_lds(k_dg_colsolve<T, BW, LPL>, lds);
+  const size_t lds = sizeof(T) * (size_t)kColCols * NP * LPL * 65;
+  hipError_t e = allow_lds(k_dg_colsolve<T, BW, LPL, NP>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dg_colsolve<T, BW, LPL>), dim3(nx / kColCols), dim3(64 * kColWaves), lds, st, spec, fac,
+  hipLaunchKernelGGL((k_dg_colsolve<T, BW, LPL, NP>), dim3(nx / kColCols), dim3(64 * kColWaves), lds, st, spec, fac,
                      vtab, nt, nx, lqb, ctrl);
   return hipGetLastError();
 }
 
-// nt <= 512 (LPL <= 8), nx >= 16.
-template <typename T>
-hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
-                              const Ctrl* ctrl, hipStream_t st) {
+template <typename T, int NP>
+static hipError_t launch_dg_colsolve_np(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
+                                        const Ctrl* ctrl, hipStream_t st) {
   const int lpl = (nt + 63) / 64;
-#define PDHG_DGC(B, L) return launch_dg_colsolve_l<T, B, L>(spec, fac, vtab, nt, nx, lqb, ctrl, st)
+#define PDHG_DGC(B, L) return launch_dg_colsolve_l<T, B, L, NP>(spec, fac, vtab, nt, nx, lqb, ctrl, st)
   if (bw == 2) {
     if (lpl <= 1) PDHG_DGC(2, 1);
     if (lpl <= 2) PDHG_DGC(2, 2);
@@ -585,6 +595,15 @@ hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int 
   return hipErrorInvalidValue;
 }
 
+// np coefficient planes (3: P2, 2: P1); nt <= 512 (LPL <= 8), nx >= 16.
+template <typename T>
+hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
+                              const Ctrl* ctrl, hipStream_t st, int np) {
+  if (np == 2) return launch_dg_colsolve_np<T, 2>(spec, fac, vtab, bw, nt, nx, lqb, ctrl, st);
+  if (np == 3) return launch_dg_colsolve_np<T, 3>(spec, fac, vtab, bw, nt, nx, lqb, ctrl, st);
+  return hipErrorInvalidValue;
+}
+
 #define PDHG_DG_INSTANTIATE(T)                                                                                   \
   template hipError_t launch_dg_residual<T>(const Scheme&, const T*, T*, double*, const Ctrl*, hipStream_t, int*); \
   template hipError_t launch_dg_apply_jt<T>(const Scheme&, const T*, const T*, T*, double*, hipStream_t, int*);    \
@@ -595,7 +614,7 @@ hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int 
   template hipError_t launch_dg_residual_fft<T>(const Scheme&, const T*, T*, int, const void*, double*,           \
                                                 const Ctrl*, hipStream_t, int*);                                 \
   template hipError_t launch_dg_colsolve<T>(T*, const FacTab<T>&, const T*, int, int, int, int, const Ctrl*,      \
-                                            hipStream_t);
+                                            hipStream_t, int);
 
 PDHG_DG_INSTANTIATE(float)
 PDHG_DG_INSTANTIATE(double)

@@ -91,7 +91,15 @@ struct OneStepProb {
   StepStat* stat;      // [nt]
   int* flag;           // 0 while the march runs, 2 after a step diverged
   double tau_u, tau_phi;
+  // K_l^{-1} by cyclic reduction instead of the FFT when pcr_k[r] > 0 (row r as for sym): pcr [2][16]
+  // holds the reduction ratios rho_0..rho_{k-1} and, in entry 15, the final scale
+  const T* pcr;
+  int pcr_k[2];
 };
+// Cyclic-reduction coefficients of the periodic tridiagonal K_l = (c0/h_t)^2 I + c^2 L_x (ghat = 0),
+// rows c0 = 1 and c0 = 3/2, into out [2][16]; returns false (FFT path) when ghat != 0 or when a row
+// would need the wrap-around step (the coupling ratio does not fall below tol within log2(nx) - 1 steps).
+bool onestep_pcr(const pdhg_problem& p, double c, double tol, double* out, int* k);
 template <typename T>
 void onestep_symbol(const pdhg_problem& p, double c, T* out);   // host: [2][nx]
 struct OneStepSummary {
@@ -202,7 +210,47 @@ hipError_t launch_dg_maxabs_trace(const T* u0, int nx, double a2, double b, doub
 template <typename T>
 hipError_t launch_dg_residual_fft(const Scheme& s, const T* u, T* spec, int lqb, const void* tw, double* part,
                                   const Ctrl* ctrl, hipStream_t st, int* nblocks);
+// np coefficient planes: 3 (P2) or 2 (P1).
 template <typename T>
 hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
-                              const Ctrl* ctrl, hipStream_t st);
+                              const Ctrl* ctrl, hipStream_t st, int np);
+
+// DG P1 nodal upwind space discretisation (pdhg_dg1.hip).
+template <typename T>
+hipError_t launch_dg1_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,
+                               int* nblocks);
+template <typename T>
+hipError_t launch_dg1_apply_jt(const Scheme& s, const T* u, const T* psi, T* out, double* part, hipStream_t st,
+                               int* nblocks);
+template <typename T>
+hipError_t launch_dg1_apply_j(const Scheme& s, const T* u, const T* v, T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_dg1_primal(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
+                             double* part, const Ctrl* ctrl, hipStream_t st, int* nblocks);
+template <typename T>
+hipError_t launch_dg1_maxabs(const T* u0, int nx, double a2, double b, double* part, hipStream_t st);
+
+// Either DG discretisation, chosen by the scheme's space.
+template <typename T>
+inline hipError_t dgx_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,
+                               int* nblocks) {
+  return s.space == kSpaceDgP1 ? launch_dg1_residual<T>(s, u, r, part, ctrl, st, nblocks)
+                               : launch_dg_residual<T>(s, u, r, part, ctrl, st, nblocks);
+}
+template <typename T>
+inline hipError_t dgx_apply_jt(const Scheme& s, const T* u, const T* psi, T* out, double* part, hipStream_t st,
+                               int* nblocks) {
+  return s.space == kSpaceDgP1 ? launch_dg1_apply_jt<T>(s, u, psi, out, part, st, nblocks)
+                               : launch_dg_apply_jt<T>(s, u, psi, out, part, st, nblocks);
+}
+template <typename T>
+inline hipError_t dgx_apply_j(const Scheme& s, const T* u, const T* v, T* out, hipStream_t st) {
+  return s.space == kSpaceDgP1 ? launch_dg1_apply_j<T>(s, u, v, out, st) : launch_dg_apply_j<T>(s, u, v, out, st);
+}
+template <typename T>
+inline hipError_t dgx_primal(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
+                             double* part, const Ctrl* ctrl, hipStream_t st, int* nblocks) {
+  return s.space == kSpaceDgP1 ? launch_dg1_primal<T>(s, u_in, u_out, phibar, phi, tau_u, part, ctrl, st, nblocks)
+                               : launch_dg_primal<T>(s, u_in, u_out, phibar, phi, tau_u, part, ctrl, st, nblocks);
+}
 }  // namespace pdhg

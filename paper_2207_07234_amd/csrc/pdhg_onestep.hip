@@ -34,6 +34,16 @@
 // back, Y_k = (S_k + S_{k+M})/2 + i (S_k - S_{k+M}) conj(w^k)/2, makes
 // IFFT_M(Y) = M (s_{2m} + i s_{2m+1}); d carries the 1/M.  The pair (k, M-k)
 // is handled by one thread, which writes both Y_k and Y_{M-k}.
+//
+// Without the fourth-order term (ghat = 0) K_l is the constant-coefficient
+// periodic tridiagonal d x_i - e (x_{i-1} + x_{i+1}) = r_i, d = (c0/h_t)^2 + 2 c^2/h_x^2,
+// e = c^2/h_x^2, and cyclic reduction solves it with no FFT: step k replaces
+// r_i by r_i + rho_k (r_{i-2^k} + r_{i+2^k}), rho_k = e_k/d_k, with
+// d_{k+1} = d_k - 2 e_k^2/d_k, e_{k+1} = e_k^2/d_k; rho_k falls quadratically, and
+// once it is below the rounding level x_i = r_i / d_k.  The host computes the
+// ratios (long double) and chooses this path only when it ends before the
+// wrap-around distance N_x/2 (otherwise the FFT path is used).  Each step is
+// one LDS pass over the slice (double-buffered, one barrier).
 #include "pdhg_internal.hpp"
 #include "pdhg_passes.hpp"
 
@@ -85,11 +95,18 @@ struct PairConsts {
   T a[KP], b[KP];   // d_k, d_{k+M}
   C2<T> w[KP];      // e^{-2 pi i k / N}
   T mid;            // d_{M/2}
+  int pcr_k;        // > 0: cyclic reduction with pcr[0..pcr_k-1] and scale pcr[15] instead of the FFT
+  const T* pcr;
 };
 
+// Symbol (or cyclic-reduction coefficients) of row r (0: c0 = 1, 1: c0 = 3/2).
 template <typename T, int KP>
-__device__ __forceinline__ void load_pair_symbol(PairConsts<T, KP>& pc, const T* symr, bool act, int tid, int W,
-                                                 int M) {
+__device__ __forceinline__ void load_pair_symbol(PairConsts<T, KP>& pc, const OneStepProb<T>& P, int r, bool act,
+                                                 int tid, int W, int M) {
+  pc.pcr_k = P.pcr_k[r];
+  pc.pcr = P.pcr + 16 * r;
+  if (pc.pcr_k > 0) return;
+  const T* symr = P.sym + (size_t)r * 2 * M;
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
     const int k = tid + j * W;
@@ -104,8 +121,32 @@ __device__ __forceinline__ void load_pair_symbol(PairConsts<T, KP>& pc, const T*
 // caller separates consecutive calls by at least one barrier).
 template <typename T, int EPT, int KP>
 __device__ __forceinline__ void kinv_slice(T (&row)[EPT], const PairConsts<T, KP>& pc, bool act, int seg, int lane,
-                                           int tid, int W, int M, C2<T>* buf, const C2<T>* twl) {
+                                           int tid, int W, int M, C2<T>* buf, C2<T>* twl) {
   T* bufr = reinterpret_cast<T*>(buf);
+  if (pc.pcr_k > 0) {   // cyclic reduction: LDS arrays buf and twl (N reals each), alternating
+    const int nm = 2 * M - 1;
+    for (int k = 0; k < pc.pcr_k; ++k) {
+      T* A = (k & 1) ? reinterpret_cast<T*>(twl) : bufr;
+      const int D = 1 << k;
+      const T rho = pc.pcr[k];
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) A[seg + lane + 64 * e] = row[e];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int x = seg + lane + 64 * e;
+          row[e] += rho * (A[(x - D) & nm] + A[(x + D) & nm]);
+        }
+      }
+    }
+    const T fin = pc.pcr[15];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) row[e] *= fin;
+    return;
+  }
   if (act) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -168,7 +209,8 @@ __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, in
   const int nw = W >> 6, wv = tid >> 6, lane = tid & 63;
   const int seg = wv * 64 * EPT;
   const T tau_u = (T)P.tau_u, tau_phi = (T)P.tau_phi;
-  for (int i = tid; i < M; i += blockDim.x) twl[lpad(i)] = P.tw[2 * i];   // e^{-2 pi i i' / M}
+  if (P.pcr_k[0] == 0)   // FFT path: twiddles e^{-2 pi i i' / M} in LDS
+    for (int i = tid; i < M; i += blockDim.x) twl[lpad(i)] = P.tw[2 * i];
   // spectral pairs k = tid + j W < M/2 (and k = M/2, self-paired, on thread 0)
   constexpr int KP = EPT >= 4 ? EPT / 4 : 1;
   PairConsts<T, KP> pc;
@@ -197,7 +239,7 @@ __device__ __forceinline__ void onestep_march(const OneStepProb<T>& P, int W, in
   for (int l = l_begin; l < l_end; ++l) {
     const T c0 = C.c0(l);
     const T a0 = c0 * C.inv_ht;
-    load_pair_symbol(pc, P.sym + (c0 != T(1) ? nx : 0), act, tid, W, M);
+    load_pair_symbol(pc, P, c0 != T(1) ? 1 : 0, act, tid, W, M);
     // initial guess v = u^l, phi = phibar = 0 (so the first primal step is void)
     T v[1][EPT], ph[2][EPT], g[EPT];
 #pragma unroll
@@ -297,7 +339,8 @@ __device__ __forceinline__ double onestep_power(const OneStepProb<T>& P, int W, 
   const bool act = tid < W;
   const int nw = W >> 6, wv = tid >> 6, lane = tid & 63;
   const int seg = wv * 64 * EPT;
-  for (int i = tid; i < M; i += blockDim.x) twl[lpad(i)] = P.tw[2 * i];
+  if (P.pcr_k[0] == 0)
+    for (int i = tid; i < M; i += blockDim.x) twl[lpad(i)] = P.tw[2 * i];
   constexpr int KP = EPT >= 4 ? EPT / 4 : 1;
   PairConsts<T, KP> pc;
 #pragma unroll
@@ -314,7 +357,7 @@ __device__ __forceinline__ double onestep_power(const OneStepProb<T>& P, int W, 
   const int nc0 = (sch.time == kTimeBDF2 && sch.nt > 1) ? 2 : 1;
   for (int ci = 0; ci < nc0; ++ci) {
     const T a0 = T(ci ? 1.5 : 1.0) * C.inv_ht;
-    load_pair_symbol(pc, P.sym + (ci ? nx : 0), act, tid, W, M);
+    load_pair_symbol(pc, P, ci, act, tid, W, M);
     T v[1][EPT];
     double s2 = 0.0, dummy = 0.0;
 #pragma unroll

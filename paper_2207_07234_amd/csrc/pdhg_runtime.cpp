@@ -124,6 +124,31 @@ void onestep_symbol(const pdhg_problem& p, double c, T* out) {
     }
   }
 }
+bool onestep_pcr(const pdhg_problem& p, double c, double tol, double* out, int* k) {
+  typedef long double LD;
+  if (p.precond_gamma_hat != 0.0) return false;
+  int m = 0;
+  while ((1 << (m + 1)) <= p.nx) ++m;   // log2(nx)
+  const LD ht = (LD)p.t_final / p.nt, hx = (LD)p.length / p.nx, e0 = (LD)c * c / (hx * hx);
+  for (int r = 0; r < 2; ++r) {
+    const LD a = (r ? 1.5L : 1.0L) / ht;
+    LD d = a * a + 2.0L * e0, e = e0;
+    int n = 0;
+    for (int i = 0; i < 16; ++i) out[r * 16 + i] = 0.0;
+    while (e / d >= (LD)tol) {
+      if (n >= m - 1 || n >= 15) return false;   // the wrap-around step would be needed: use the FFT
+      out[r * 16 + n] = (double)(e / d);
+      const LD d1 = d - 2.0L * e * e / d, e1 = e * e / d;
+      d = d1;
+      e = e1;
+      ++n;
+    }
+    out[r * 16 + 15] = (double)(1.0L / d);
+    k[r] = n;
+  }
+  return true;
+}
+
 template void onestep_symbol<float>(const pdhg_problem&, double, float*);
 template void onestep_symbol<double>(const pdhg_problem&, double, double*);
 
@@ -242,7 +267,11 @@ int set_hip_error(pdhg_handle* h, hipError_t e, const char* what) {
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // Coefficients per cell: 3 for DG P2, 1 for finite differences.
-inline int planes(const pdhg_problem& p) { return p.space == PDHG_DG_P2_LLF ? 3 : 1; }
+inline int planes(const pdhg_problem& p) {
+  return p.space == PDHG_DG_P2_LLF ? 3 : (p.space == PDHG_DG_P1_UPWIND ? 2 : 1);
+}
+// Either DG discretisation (coefficient planes, per-mode eigenbasis in the column solve).
+inline bool is_dg(const pdhg_problem& p) { return p.space == PDHG_DG_P2_LLF || p.space == PDHG_DG_P1_UPWIND; }
 
 WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   WsLayout L{};
@@ -304,60 +333,74 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
   return PDHG_OK;
 }
 
-// Eigen-decomposition of a real symmetric 6x6 matrix by cyclic Jacobi rotations
-// (long double): A = V diag(w) V^T, columns of V the eigenvectors.
-void jacobi6(long double A[6][6], long double V[6][6], long double w[6]) {
+// Eigen-decomposition of the leading n x n block (n <= 6) of a real symmetric
+// matrix by cyclic Jacobi rotations (long double): A = V diag(w) V^T, columns
+// of V the eigenvectors.
+void jacobi6(long double A[6][6], long double V[6][6], long double w[6], int n = 6) {
   typedef long double LD;
   for (int i = 0; i < 6; ++i)
     for (int j = 0; j < 6; ++j) V[i][j] = (i == j) ? 1.0L : 0.0L;
   LD scale = 0.0L;
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) scale += A[i][j] * A[i][j];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) scale += A[i][j] * A[i][j];
   for (int sweep = 0; sweep < 100; ++sweep) {
     LD off = 0.0L;
-    for (int p = 0; p < 6; ++p)
-      for (int q = p + 1; q < 6; ++q) off += A[p][q] * A[p][q];
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p][q] * A[p][q];
     if (off <= 1e-36L * scale) break;
-    for (int p = 0; p < 6; ++p)
-      for (int q = p + 1; q < 6; ++q) {
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
         if (A[p][q] == 0.0L) continue;
         const LD th = (A[q][q] - A[p][p]) / (2.0L * A[p][q]);
         const LD t = (th >= 0.0L ? 1.0L : -1.0L) / (fabsl(th) + sqrtl(th * th + 1.0L));
         const LD c = 1.0L / sqrtl(t * t + 1.0L), sn = t * c;
-        for (int k = 0; k < 6; ++k) {   // columns p, q
+        for (int k = 0; k < n; ++k) {   // columns p, q
           const LD akp = A[k][p], akq = A[k][q];
           A[k][p] = c * akp - sn * akq;
           A[k][q] = sn * akp + c * akq;
         }
-        for (int k = 0; k < 6; ++k) {   // rows p, q
+        for (int k = 0; k < n; ++k) {   // rows p, q
           const LD apk = A[p][k], aqk = A[q][k];
           A[p][k] = c * apk - sn * aqk;
           A[q][k] = sn * apk + c * aqk;
         }
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < n; ++k) {
           const LD vkp = V[k][p], vkq = V[k][q];
           V[k][p] = c * vkp - sn * vkq;
           V[k][q] = sn * vkp + c * vkq;
         }
       }
   }
-  for (int i = 0; i < 6; ++i) w[i] = A[i][i];
+  for (int i = 0; i < 6; ++i) w[i] = i < n ? A[i][i] : 0.0L;
 }
 
 // DG preconditioner data: for each Fourier mode m = 0..nx/2 over the cells, the
-// unit-speed upwind DG symbol G(theta) = G_0 + G_-1 e^{-i theta} (theta = 2 pi m / nx),
-// G_0 = [1 1 1; -3 3 3; 5 -5 5] / h_x, G_-1 = [-1 -1 -1; 3 3 3; -5 -5 -5] / h_x, the
-// Hermitian coupling H = c^2 G G^*, and the eigen-decomposition of its real 6x6
-// form [Re H, -Im H; Im H, Re H] (acting on (Re, Im) of the three coefficient
-// planes).  Uploads the factor tables of B_t B_t^T + lambda (6 per mode) and the
-// eigenvector matrices (36 values per mode).
+// unit-speed upwind DG symbol G(theta) = G_0 + G_-1 e^{-i theta} (theta = 2 pi m / nx)
+// of the NP coefficient planes, the Hermitian coupling H = c^2 G G^*, and the
+// eigen-decomposition of its real 2NP x 2NP form [Re H, -Im H; Im H, Re H] (acting
+// on (Re, Im) of the planes).
+//   P2 Legendre: G_0 = [1 1 1; -3 3 3; 5 -5 5] / h_x, G_-1 = [-1 -1 -1; 3 3 3; -5 -5 -5] / h_x.
+//   P1 nodal:    G_0 = [7 3; -11 9] / (4 h_x), G_-1 = [5 -15; -1 3] / (4 h_x)
+//                (minus the printed A_1, A_2 of Section 3.2.2 at unit speed).
+// Uploads the factor tables of B_t B_t^T + lambda (6 per mode, the unused ones
+// with lambda = 0 for P1) and the eigenvector matrices (36 values per mode, row
+// stride 6).
 template <typename T>
 int upload_factors_dg(pdhg_handle* h, double c) {
   typedef long double LD;
   const int nx = h->prob.nx, nmodes = nx / 2 + 1;
+  const int np = planes(h->prob), n2 = 2 * np;
   const LD hx = (LD)h->prob.length / nx, PI = 3.141592653589793238462643383279502884L;
-  const LD g0[3][3] = {{1, 1, 1}, {-3, 3, 3}, {5, -5, 5}};
-  const LD gm[3][3] = {{-1, -1, -1}, {3, 3, 3}, {-5, -5, -5}};
+  LD g0[3][3] = {{1, 1, 1}, {-3, 3, 3}, {5, -5, 5}};
+  LD gm[3][3] = {{-1, -1, -1}, {3, 3, 3}, {-5, -5, -5}};
+  if (np == 2) {
+    const LD a0[2][2] = {{1.75L, 0.75L}, {-2.75L, 2.25L}}, am[2][2] = {{1.25L, -3.75L}, {-0.25L, 0.75L}};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        g0[a][b] = (a < 2 && b < 2) ? a0[a][b] : 0.0L;
+        gm[a][b] = (a < 2 && b < 2) ? am[a][b] : 0.0L;
+      }
+  }
   std::vector<long double> shifts((size_t)nmodes * 6);
   std::vector<T> vtab((size_t)nmodes * 36);
   for (int m = 0; m < nmodes; ++m) {
@@ -366,27 +409,27 @@ int upload_factors_dg(pdhg_handle* h, double c) {
     const LD cr = (m == 0) ? 1.0L : (2 * m == nx ? -1.0L : cosl(th));
     const LD ci = (m == 0 || 2 * m == nx) ? 0.0L : -sinl(th);
     LD Gr[3][3], Gi[3][3];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < np; ++b) {
         Gr[a][b] = (g0[a][b] + gm[a][b] * cr) / hx;
         Gi[a][b] = (gm[a][b] * ci) / hx;
       }
-    LD A[6][6], V[6][6], w[6];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
+    LD A[6][6] = {}, V[6][6], w[6];
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < np; ++b) {
         LD hr = 0.0L, hi = 0.0L;   // (G G^*)_ab = sum_k G_ak conj(G_bk)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < np; ++k) {
           hr += Gr[a][k] * Gr[b][k] + Gi[a][k] * Gi[b][k];
           hi += Gi[a][k] * Gr[b][k] - Gr[a][k] * Gi[b][k];
         }
         hr *= (LD)c * c;
         hi *= (LD)c * c;
         A[a][b] = hr;
-        A[a + 3][b + 3] = hr;
-        A[a][b + 3] = -hi;
-        A[a + 3][b] = hi;
+        A[a + np][b + np] = hr;
+        A[a][b + np] = -hi;
+        A[a + np][b] = hi;
       }
-    jacobi6(A, V, w);
+    jacobi6(A, V, w, n2);
     for (int b = 0; b < 6; ++b) shifts[(size_t)m * 6 + b] = w[b] > 0.0L ? w[b] : 0.0L;
     for (int r = 0; r < 6; ++r)
       for (int b = 0; b < 6; ++b) vtab[(size_t)m * 36 + r * 6 + b] = (T)V[r][b];
@@ -452,6 +495,8 @@ template <typename T>
 int max_abs_dflux(pdhg_handle* h, const T* u0, double* part, hipStream_t st, double* out) {
   if (h->prob.space == PDHG_DG_P2_LLF)   // DG: over the cell-edge traces of u0_h
     HIP_TRY(launch_dg_maxabs_trace<T>(u0, h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
+  else if (h->prob.space == PDHG_DG_P1_UPWIND)   // over the nodal values and edge traces
+    HIP_TRY(launch_dg1_maxabs<T>(u0, h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
   else
     HIP_TRY(launch_maxabs_dflux<T>(u0, (size_t)h->prob.nx, 2.0 * h->prob.alpha, h->prob.beta, part, st));
   HIP_TRY(hipMemcpyAsync(h->h_scal, part, 64 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -480,7 +525,7 @@ int resolve_constants_p(pdhg_handle* h, const T* u0, double* part, hipStream_t s
   h->c = c;
   h->consts_valid = true;
   if (!factors) return PDHG_OK;
-  if (p.space == PDHG_DG_P2_LLF) {
+  if (is_dg(p)) {
     if (!h->d_fac_rows || h->fac_c != c) {
       int rc = upload_factors_dg<T>(h, c);
       if (rc) return rc;
@@ -502,11 +547,11 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
 template <typename T>
 int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
   const pdhg_problem& p = h->prob;
-  if (p.space == PDHG_DG_P2_LLF) {   // 3 nt coefficient rows; per-mode eigenbasis in the column solve
-    const int nr = 3 * p.nt;
+  if (is_dg(p)) {   // planes x nt coefficient rows; per-mode eigenbasis in the column solve
+    const int nr = planes(p) * p.nt;
     HIP_TRY(launch_rows_fwd<T>(r, nr, spec, nr, h->lqb, p.nx, h->d_tw, nullptr, st));
     HIP_TRY(launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
-                                  h->lqb, nullptr, st));
+                                  h->lqb, nullptr, st, planes(p)));
     HIP_TRY(launch_rows_inv<T>(spec, nr, h->lqb, s, nr, p.nx, h->d_tw, nullptr, st));
     return PDHG_OK;
   }
@@ -522,7 +567,7 @@ int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int it
   const pdhg_problem& p = h->prob;
   const WsLayout L = layout_for(p, h->esz);
   const Scheme s = scheme_of(h);
-  const bool dg = p.space == PDHG_DG_P2_LLF;
+  const bool dg = is_dg(p);
   const size_t n = (size_t)p.nt * p.nx * planes(p);
   T* v = (T*)wsp(ws, L.srow);
   T* w = (T*)wsp(ws, L.phibar);
@@ -542,11 +587,11 @@ int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int it
   HIP_TRY(launch_normalize<T>(v, n, scal, st));
   double lam = 0.0;
   for (int it = 0; it < iters; ++it) {
-    if (dg) HIP_TRY(launch_dg_apply_j<T>(s, u, v, w, st));       // w = J v
+    if (dg) HIP_TRY(dgx_apply_j<T>(s, u, v, w, st));             // w = J v
     else HIP_TRY(launch_apply_j<T>(s, u, v, w, st));
     int rc = precond_apply<T>(h, w, w, spec, st);                 // w = K_d^{-1} w
     if (rc) return rc;
-    if (dg) HIP_TRY(launch_dg_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));   // t = J^T w
+    if (dg) HIP_TRY(dgx_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));         // t = J^T w
     else HIP_TRY(launch_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));
     HIP_TRY(launch_dot<T>(t, v, n, part, scal, st));             // scal[0] = <t, v>
     HIP_TRY(launch_dot<T>(t, nullptr, n, part, scal + 1, st));   // scal[1] = |t|^2
@@ -587,11 +632,11 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   if (!is_pow2(p.nx) || p.nx < 8 || p.nx > 4096 || p.nt < 1) return PDHG_EINVAL;
   if (!(p.length > 0) || !(p.t_final > 0) || p.gamma < 0 || p.precond_gamma_hat < 0) return PDHG_EINVAL;
   if (p.time != PDHG_BE && p.time != PDHG_BDF2) return PDHG_EINVAL;
-  if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF && p.space != PDHG_DG_P2_LLF) return PDHG_EINVAL;
+  if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF && !is_dg(p)) return PDHG_EINVAL;
   if (p.dtype != PDHG_F32 && p.dtype != PDHG_F64) return PDHG_EINVAL;
   if (p.nt > 2048) return PDHG_EUNSUPPORTED;   // column solve: <= 32 segments of <= 64 levels
   // DG: nx cells >= 16 (8 spectrum columns per column block), nt <= 512 (8 levels per lane), no viscosity
-  if (p.space == PDHG_DG_P2_LLF && (p.nx < 16 || p.nt > 512 || p.gamma != 0.0)) return PDHG_EUNSUPPORTED;
+  if (is_dg(p) && (p.nx < 16 || p.nt > 512 || p.gamma != 0.0)) return PDHG_EUNSUPPORTED;
   pdhg_handle* h = new (std::nothrow) pdhg_handle();
   if (!h) return PDHG_EINVAL;
   h->prob = p;
@@ -730,7 +775,8 @@ int enqueue_body_dg(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T
   Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
   T* uin = odd ? u : u_alt;
   T* uout = odd ? u_alt : u;
-  const int nr = 3 * p.nt;
+  const int nr = planes(p) * p.nt;
+  const bool p2 = p.space == PDHG_DG_P2_LLF;
   int nb_rd = 0, nb_rp = 0;
   if (p.nx >= 64) {
     HIP_TRY(launch_dual_fft<T>(spec, nr, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
@@ -738,15 +784,15 @@ int enqueue_body_dg(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T
     HIP_TRY(launch_rows_inv<T>(spec, nr, h->lqb, srow, nr, p.nx, h->d_tw, ctrl, st));
     HIP_TRY(launch_dual<T>(phi, phibar, srow, (size_t)nr * p.nx, tau_phi, ctrl, st));
   }
-  HIP_TRY(launch_dg_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
-  if (p.nx >= 64) {   // residual of two levels + forward FFT of their six coefficient rows, fused
+  HIP_TRY(dgx_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
+  if (p2 && p.nx >= 64) {   // P2: residual of two levels + forward FFT of their six coefficient rows, fused
     HIP_TRY(launch_dg_residual_fft<T>(s, uout, spec, h->lqb, h->d_tw, prp, ctrl, st, &nb_rp));
   } else {
-    HIP_TRY(launch_dg_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
+    HIP_TRY(dgx_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
     HIP_TRY(launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, ctrl, st));
   }
   HIP_TRY(launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
-                                h->lqb, ctrl, st));
+                                h->lqb, ctrl, st, planes(p)));
   HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
   return PDHG_OK;
 }
@@ -784,7 +830,7 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   if (rc) return rc;
   const WsLayout L = layout_for(p, h->esz);
   const int row = p.nx * planes(p);   // elements per level
-  const bool dg = p.space == PDHG_DG_P2_LLF;
+  const bool dg = is_dg(p);
   const size_t nlev = (size_t)(p.nt + 1) * row, n = (size_t)p.nt * row;
   T* u_alt = (T*)wsp(ws, L.u_alt);
   T* spec = (T*)wsp(ws, L.spec0);
@@ -857,11 +903,13 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   double drift = 0.0;
   {
     double* lev = (double*)wsp(ws, L.part_rp);   // nt+1 <= max_parts
-    HIP_TRY(launch_level_sums<T>(u, p.nx, (size_t)row, p.nt + 1, lev, st));   // DG: cell averages (plane 0)
+    // mass h_x sum_j of the cell averages: plane 0 for P2 Legendre, (v_1 + v_2) / 2 for P1 nodal
+    const bool p1 = p.space == PDHG_DG_P1_UPWIND;
+    HIP_TRY(launch_level_sums<T>(u, p1 ? 2 * p.nx : p.nx, (size_t)row, p.nt + 1, lev, st));
     std::vector<double> m(p.nt + 1);
     HIP_TRY(hipMemcpyAsync(m.data(), lev, m.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const double hx = p.length / p.nx;
+    const double hx = (p1 ? 0.5 : 1.0) * p.length / p.nx;
     for (int l = 1; l <= p.nt; ++l) drift = std::max(drift, std::fabs(m[l] - m[0]) * hx);
   }
   if (stats) {
@@ -977,10 +1025,10 @@ template <typename T>
 int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* prm, pdhg_stats* stats,
                  int64_t* step_iters, double* step_res, hipStream_t st) {
   const pdhg_problem& P = h->prob;
-  if (P.space == PDHG_DG_P2_LLF || P.nx < 64) return PDHG_EUNSUPPORTED;
+  if (is_dg(P) || P.nx < 64) return PDHG_EUNSUPPORTED;
   const int nx = P.nx, nt = P.nt;
-  // sym [2][nx] | stat [nt] | flag | part (max |f'|, nu, level sums) | problem table
-  const size_t b_sym = align_up(2 * (size_t)nx * sizeof(T));
+  // sym [2][nx], pcr [2][16] | stat [nt] | flag | part (max |f'|, nu, level sums) | problem table
+  const size_t b_sym = align_up((2 * (size_t)nx + 32) * sizeof(T));
   const size_t b_stat = align_up((size_t)nt * sizeof(StepStat));
   const size_t b_flag = align_up(sizeof(int));
   const size_t b_part = align_up(sizeof(double) * std::max<size_t>(64, (size_t)nt + 1));
@@ -1003,9 +1051,15 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   int rc = resolve_constants_p<T>(h, u0, part, st, false);
   if (rc) return rc;
   const double ht = P.t_final / nt, hx = P.length / nx;
+  double pcr[32];
+  int pcr_k[2] = {0, 0};
+  const bool use_pcr = onestep_pcr(P, h->c, sizeof(T) == 8 ? 1e-17 : 1e-9, pcr, pcr_k);
+  if (!use_pcr) pcr_k[0] = pcr_k[1] = 0;
   if (h->os_c != h->c) {
-    std::vector<T> hs(2 * (size_t)nx);
+    std::vector<T> hs(2 * (size_t)nx + 32, T(0));
     onestep_symbol<T>(P, h->c, hs.data());
+    if (use_pcr)
+      for (int i = 0; i < 32; ++i) hs[2 * (size_t)nx + i] = (T)pcr[i];
     HIP_TRY(hipMemcpyAsync(sym, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     h->os_c = h->c;
@@ -1025,6 +1079,9 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   tp.flag = flag;
   tp.tau_u = auto_tau ? 0.0 : prm->tau_u;
   tp.tau_phi = auto_tau ? 0.0 : prm->tau_phi;
+  tp.pcr = sym + 2 * (size_t)nx;
+  tp.pcr_k[0] = pcr_k[0];
+  tp.pcr_k[1] = pcr_k[1];
   HIP_TRY(hipMemcpyAsync(tab, &tp, sizeof(tp), hipMemcpyHostToDevice, st));
   double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
   if (auto_tau) {
@@ -1134,9 +1191,9 @@ int residual_impl(pdhg_handle* h, const T* u, const T* phi, T* Au, T* JTphi, dou
   double* prp = (double*)wsp(ws, L.part_rp);
   double* prd = (double*)wsp(ws, L.part_rd);
   int nb1 = 0, nb2 = 0;
-  if (h->prob.space == PDHG_DG_P2_LLF) {
-    HIP_TRY(launch_dg_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
-    if (phi) HIP_TRY(launch_dg_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  if (is_dg(h->prob)) {
+    HIP_TRY(dgx_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
+    if (phi) HIP_TRY(dgx_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
   } else {
     HIP_TRY(launch_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
     if (phi) HIP_TRY(launch_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
@@ -1163,7 +1220,7 @@ int precond_impl(pdhg_handle* h, const T* r, T* s, hipStream_t st) {
   if (rc) return rc;
   if (!h->d_fac_rows) {
     if (h->prob.precond_c < 0.0) return PDHG_EINVAL;
-    rc = (h->prob.space == PDHG_DG_P2_LLF) ? upload_factors_dg<T>(h, h->prob.precond_c)
+    rc = is_dg(h->prob) ? upload_factors_dg<T>(h, h->prob.precond_c)
                                           : upload_factors<T>(h, h->prob.precond_c, h->prob.precond_gamma_hat);
     if (rc) return rc;
   }
@@ -1180,9 +1237,9 @@ int adjoint_impl(pdhg_handle* h, int mode, const T* u, const T* in, T* out, T* m
     if (rc) return rc;
   }
   const Scheme s = scheme_of(h);
-  const bool dg = h->prob.space == PDHG_DG_P2_LLF;
+  const bool dg = is_dg(h->prob);
   if (mode == PDHG_ADJ_APPLY) {
-    if (dg) HIP_TRY(launch_dg_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
+    if (dg) HIP_TRY(dgx_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
     else HIP_TRY(launch_apply_jt<T>(s, u, in, out, nullptr, st, nullptr));
     return PDHG_OK;
   }
@@ -1212,24 +1269,25 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
   const T tu = (T)h->last.tau_u, tp = (T)h->last.tau_phi;
   Ctrl* ctrl_t = (Ctrl*)wsp(ws, L.ctrl_t);
   if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, st));
-  const int nr = 3 * p.nt;
+  const int nr = planes(p) * p.nt;
   auto launch_dg = [&]() -> hipError_t {
     switch (kernel) {
       case 1: return launch_dg_colsolve<T>(spec, factab<T>(h), (const T*)h->d_vtab, p.time == PDHG_BDF2 ? 2 : 1,
-                                           p.nt, p.nx, h->lqb, nullptr, st);
-      case 4: return launch_dg_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
+                                           p.nt, p.nx, h->lqb, nullptr, st, planes(p));
+      case 4: return dgx_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
       case 0: return launch_dg_residual_fft<T>(s, u_alt, spec, h->lqb, h->d_tw, prp, nullptr, st, nullptr);
-      case 5: return launch_dg_residual<T>(s, u_alt, srow, prp, nullptr, st, nullptr);
+      case 5: return dgx_residual<T>(s, u_alt, srow, prp, nullptr, st, nullptr);
       case 6: return launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, nullptr, st);
       case 7: return launch_dual_fft<T>(spec, nr, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
       case 8: return launch_copy<T>(srow, phibar, n, st);
       default: return hipErrorInvalidValue;
     }
   };
-  if (p.space == PDHG_DG_P2_LLF && !(kernel <= 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
-  if (p.space == PDHG_DG_P2_LLF && (kernel == 7 || kernel == 0) && p.nx < 64) return PDHG_EUNSUPPORTED;
+  if (is_dg(p) && !(kernel <= 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
+  if (is_dg(p) && (kernel == 7 || kernel == 0) && p.nx < 64) return PDHG_EUNSUPPORTED;
+  if (p.space == PDHG_DG_P1_UPWIND && kernel == 0) return PDHG_EUNSUPPORTED;   // fused residual + FFT: P2 only
   auto launch = [&]() -> hipError_t {
-    if (p.space == PDHG_DG_P2_LLF) return launch_dg();
+    if (is_dg(p)) return launch_dg();
     switch (kernel) {
       case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);

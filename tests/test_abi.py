@@ -29,6 +29,21 @@ def test_header_declares_the_core_entry_points():
         assert name in syms
 
 
+def test_binding_enum_values_match_header():
+    """Every enumerator the binding mirrors has the value the header gives it."""
+    B, _ = _lib()
+    src = open(os.path.join(ROOT, "include", "pdhg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {}
+    for body in re.findall(r"typedef enum\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"(PDHG_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            vals[name] = int(val)
+    assert vals["PDHG_DG_P1_UPWIND"] == 3
+    for name, val in vals.items():
+        if hasattr(B, name):
+            assert getattr(B, name) == val, name
+
+
 def test_library_exports_every_declared_symbol():
     _, lib = _lib()
     for name in _declared_symbols():
@@ -98,12 +113,13 @@ def test_batch_setup_rejects_before_touching_the_device(bad, code):
     assert lib.pdhg_batch_setup(arr, 0, C.byref(h)) == B.PDHG_EINVAL
 
 
+@pytest.mark.parametrize("space", ["PDHG_DG_P2_LLF", "PDHG_DG_P1_UPWIND"])
 @pytest.mark.parametrize("bad", [dict(nx=8), dict(nt=1024), dict(gamma=1e-3)])
-def test_dg_setup_limits(bad):
+def test_dg_setup_limits(bad, space):
     B, lib = _lib()
     p = B.pdhg_problem()
     p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 64, 16, 1.0, 0.5, 0.5, 0.0
-    p.time, p.space, p.dtype = B.PDHG_BE, B.PDHG_DG_P2_LLF, B.PDHG_F32
+    p.time, p.space, p.dtype = B.PDHG_BE, getattr(B, space), B.PDHG_F32
     for k, v in bad.items():
         setattr(p, k, v)
     h = C.c_void_p()
