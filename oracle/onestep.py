@@ -56,7 +56,11 @@ def slice_norm(prob: Problem, z: np.ndarray) -> float:
 
 
 def step_precond_symbol(prob: Problem, c0: float) -> np.ndarray:
-    """Eigenvalues of K_l per FFT mode: (c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2."""
+    """Eigenvalues of K_l per FFT mode: (c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2, or, for the full-symbol
+    preconditioner, |c0/h_t + g_k|^2 (the one-level form of L_k L_k^*)."""
+    if prob.precond_kind == "full":
+        from .precond import full_symbol
+        return np.abs(c0 / prob.ht + full_symbol(prob)) ** 2
     return (c0 / prob.ht) ** 2 + mode_shifts(prob)
 
 

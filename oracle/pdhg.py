@@ -113,6 +113,9 @@ def kd_solve_any(prob: Problem, r: np.ndarray) -> np.ndarray:
     if prob.space == "dg_p1_upwind":
         from . import dg1
         return dg1.p1_kd_solve(prob, r)
+    if prob.precond_kind == "full":
+        from .precond import kd_full_solve
+        return kd_full_solve(prob, r)
     return kd_solve(prob, r)
 
 

@@ -72,6 +72,40 @@ def kd_solve(prob: Problem, r: np.ndarray) -> np.ndarray:
     return np.fft.ifft(shat, axis=1).real
 
 
+# ------------------------------------------------------------------ full symbol
+# Reading (beyond the paper, which drops the cross term d_t d_x of A^T A when it
+# forms K in Section 2.2): K_full = J_c J_c^T with J_c = B_t (x) I + I (x) G_c the
+# scheme's own Jacobian for the linear flux f(u) = c u (c the constant speed
+# estimate; same Lax-Friedrichs constant, ghat in place of the viscosity).  G_c is
+# circulant with symbol g_k, so per FFT mode K_k = L_k L_k^* with the lower
+# triangular banded L_k = B_t + g_k I: one forward and one backward substitution.
+def full_symbol(prob: Problem) -> np.ndarray:
+    """g_k, k = 0..N_x-1: eigenvalues of the linear-flux spatial operator G_c."""
+    th = 2.0 * np.pi * np.arange(prob.nx) / prob.nx
+    c = prob.precond_c
+    if prob.space == "fd_upwind":
+        g = c * (1.0 - np.exp(-1j * th)) / prob.hx
+    elif prob.space == "fd_lf":
+        g = (1j * c * np.sin(th) + prob.lf_speed * (1.0 - np.cos(th))) / prob.hx
+    else:
+        raise ValueError("the full-symbol preconditioner covers the finite-difference fluxes")
+    mu = 4.0 * np.sin(th / 2.0) ** 2 / prob.hx ** 2
+    return g + prob.precond_gamma_hat * mu
+
+
+def kd_full_solve(prob: Problem, r: np.ndarray) -> np.ndarray:
+    """s = K_full^{-1} r for r of shape (N_t, N_x)."""
+    b = time_matrix(prob)
+    g = full_symbol(prob)
+    rhat = np.fft.fft(r, axis=1)
+    shat = np.empty_like(rhat)
+    for k in range(prob.nx):
+        L = b + g[k] * np.eye(prob.nt)
+        y = sla.solve_triangular(L, rhat[:, k], lower=True)
+        shat[:, k] = sla.solve_triangular(L.conj().T, y, lower=False)
+    return np.fft.ifft(shat, axis=1).real
+
+
 def kd_apply(prob: Problem, s: np.ndarray) -> np.ndarray:
     """K_d s (matrix-free; used to check kd_solve)."""
     kt = time_gram(prob)

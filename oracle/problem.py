@@ -29,6 +29,7 @@ class Problem:
     lf_speed: float = 0.0              # global Lax-Friedrichs constant (fd_lf)
     precond_c: float = 0.0             # c in K = -d_tt - c^2 d_xx + ghat^2 d_xxxx
     precond_gamma_hat: float = 0.0     # ghat
+    precond_kind: str = "gram"         # "gram": K_d of Section 3.3 | "full": the Gram of the linearised operator
     gamma_fn: Optional[Callable] = field(default=None, compare=False)  # heat_var only
 
     @property
@@ -94,5 +95,7 @@ def default_constants(prob: Problem, u0: np.ndarray) -> Problem:
     if prob.space == "fd_lf" and prob.lf_speed <= 0.0:
         kw["lf_speed"] = float(np.max(np.abs(prob.fp(np.asarray(u0)))))
     if prob.precond_c <= 0.0 and prob.space != "heat_var":
-        kw["precond_c"] = float(np.max(np.abs(prob.fp(np.asarray(u0)))))
+        # the full-symbol preconditioner keeps the signed transport term: the mean speed of u0
+        kw["precond_c"] = (float(np.mean(prob.fp(np.asarray(u0)))) if prob.precond_kind == "full"
+                           else float(np.max(np.abs(prob.fp(np.asarray(u0))))))
     return prob.with_(**kw) if kw else prob
