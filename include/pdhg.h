@@ -83,6 +83,20 @@ typedef enum { PDHG_BE = 0, PDHG_BDF2 = 1 } pdhg_time;
  *                  the P1 operator G. */
 typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1, PDHG_DG_P2_LLF = 2, PDHG_DG_P1_UPWIND = 3 } pdhg_space;
 
+/* Dual-step preconditioner K_d (Sections 2.2, 3.3):
+ *  PDHG_PRECOND_GRAM: K_d = (B_t B_t^T) (x) I + I_t (x) (c^2 L_x + ghat^2 L_x^2), the
+ *                  discrete form of the paper's K = -d_tt - c^2 d_xx + ghat^2 d_xxxx
+ *                  (default precond_c: max |f'(u0)|).
+ *  PDHG_PRECOND_FULL: K_d = J_c J_c^T with J_c = B_t (x) I + I (x) G_c the scheme's
+ *                  Jacobian for the linear flux f = c u (same Lax-Friedrichs constant,
+ *                  ghat as the viscosity): the Gram reading with the cross term of
+ *                  A^T A that the paper drops when it forms K.  Per Fourier mode k,
+ *                  K_k = L_k L_k^* with L_k = B_t + g_k I lower triangular (g_k the
+ *                  symbol of G_c), solved by two substitutions along t.  Default
+ *                  precond_c: the mean of f'(u0) (the signed transport speed).
+ *                  Finite differences only (PDHG_EUNSUPPORTED for DG and for batches). */
+typedef enum { PDHG_PRECOND_GRAM = 0, PDHG_PRECOND_FULL = 1 } pdhg_precond_kind;
+
 typedef struct {
   int32_t nx, nt;
   double length;            /* periodic domain [0, length)                                */
@@ -92,7 +106,7 @@ typedef struct {
   int32_t time;             /* pdhg_time                                                  */
   int32_t space;            /* pdhg_space                                                 */
   int32_t dtype;            /* pdhg_dtype                                                 */
-  int32_t reserved;
+  int32_t precond_kind;     /* pdhg_precond_kind                                          */
   double lf_speed;          /* Lax-Friedrichs constant; < 0: max |f'(u0)| at solve time    */
   double precond_c;         /* c of K (Section 2.2); < 0: max |f'(u0)| at solve time       */
   double precond_gamma_hat; /* ghat of K (>= 0)                                           */

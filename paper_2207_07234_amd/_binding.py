@@ -17,6 +17,7 @@ PDHG_EINVAL, PDHG_EHIP, PDHG_EUNSUPPORTED, PDHG_EWORKSPACE = -1, -2, -3, -4
 PDHG_F32, PDHG_F64 = 0, 1
 PDHG_BE, PDHG_BDF2 = 0, 1
 PDHG_FD_UPWIND, PDHG_FD_LF, PDHG_DG_P2_LLF, PDHG_DG_P1_UPWIND = 0, 1, 2, 3
+PDHG_PRECOND_GRAM, PDHG_PRECOND_FULL = 0, 1
 PDHG_ADJ_APPLY, PDHG_ADJ_SOLVE = 0, 1
 
 
@@ -25,7 +26,7 @@ class pdhg_problem(C.Structure):
         ("nx", C.c_int32), ("nt", C.c_int32),
         ("length", C.c_double), ("t_final", C.c_double),
         ("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
-        ("time", C.c_int32), ("space", C.c_int32), ("dtype", C.c_int32), ("reserved", C.c_int32),
+        ("time", C.c_int32), ("space", C.c_int32), ("dtype", C.c_int32), ("precond_kind", C.c_int32),
         ("lf_speed", C.c_double), ("precond_c", C.c_double), ("precond_gamma_hat", C.c_double),
     ]
 

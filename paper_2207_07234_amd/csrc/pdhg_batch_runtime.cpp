@@ -536,7 +536,7 @@ int batch_onestep_impl(pdhg_batch* b, const T* u0, T* u, T* phi, const pdhg_batc
     std::vector<T> hs(nsym, T(0));
     for (int i = 0; i < P; ++i) {
       const size_t nx2 = 2 * (size_t)b->probs[i].nx;
-      onestep_symbol<T>(b->probs[i], b->c[i], hs.data() + sym_off[i]);
+      onestep_symbol<T>(b->probs[i], b->c[i], b->lf[i], hs.data() + sym_off[i]);
       for (int q = 0; q < 32; ++q) hs[sym_off[i] + nx2 + q] = (T)pcr[32 * (size_t)i + q];
     }
     BHIP_TRY(hipMemcpyAsync(sym, hs.data(), nsym * sizeof(T), hipMemcpyHostToDevice, st));
@@ -708,6 +708,7 @@ int validate_batch_problem(const pdhg_problem& p, int dtype) {
   if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF) return PDHG_EINVAL;
   if (p.dtype != PDHG_F32 && p.dtype != PDHG_F64) return PDHG_EINVAL;
   if (p.dtype != dtype) return PDHG_EINVAL;
+  if (p.precond_kind != PDHG_PRECOND_GRAM) return PDHG_EUNSUPPORTED;   // batches use the Gram preconditioner
   if (p.nx < 256 || p.nx > 4096 || p.nt > 512) return PDHG_EUNSUPPORTED;
   return PDHG_OK;
 }

@@ -89,8 +89,153 @@ k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ct
   colsolve_group<T, BW, LPL>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile);
 }
 
+// C (full-symbol preconditioner): per Fourier mode k, K_k = L_k L_k^* with
+// L_k = B_t + g_k I lower triangular (row l: c0(l)/h_t + g_k on the diagonal,
+// c1(l)/h_t and c2(l)/h_t below it), g_k = (wr + vr)(1 - cos theta_k) + i ci sin theta_k
+// the symbol of the linear-flux spatial operator (theta_k = 2 pi k / nx, from the
+// twiddle table).  Forward substitution with L_k, backward with L_k^*.  Block of
+// 4 waves = 8 spectrum columns; wave w owns columns 2w (Re) and 2w+1 (Im) of one
+// mode as a complex column; the real columns 0 (mode 0) and 1 (mode nx/2) of
+// block 0 are solved one after the other as real columns.  With part != NULL the
+// first wave of block 0 first reduces the iteration's partial sums and takes the
+// stopping decision.
+template <typename T, int BW, int LPL>
+__device__ __forceinline__ void full_rows(const FullSym& F, const C2<T>* __restrict__ tw, int kmode, int l0,
+                                          Cx<T>* invd, Cx<T>* invb, T* e1, T* e2) {
+  const C2<T> w = tw[kmode];   // (cos theta, -sin theta)
+  const T omc = T(1) - w.x;
+  const Cx<T> g((T(F.wr) + T(F.vr)) * omc, -T(F.ci) * w.y);
+  const T iht = T(F.inv_ht);
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) {
+    const int l = l0 + i;
+    const T c0 = (F.bdf2 && l >= 1) ? T(1.5) : T(1);
+    const Cx<T> d(c0 * iht + g.re, g.im);
+    const T den = T(1) / (d.re * d.re + d.im * d.im);
+    invd[i] = Cx<T>(d.re * den, -d.im * den);
+    invb[i] = Cx<T>(d.re * den, d.im * den);
+  }
+#pragma unroll
+  for (int i = 0; i <= LPL; ++i) {
+    const int l = l0 + i;
+    e1[i] = (l >= 1) ? ((F.bdf2 ? T(-2) : T(-1)) * iht) : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i <= LPL + 1; ++i) {
+    const int l = l0 + i;
+    e2[i] = (F.bdf2 && l >= 2) ? T(0.5) * iht : T(0);
+  }
+}
+
+template <typename T, int BW, int LPL>
+__global__ void __launch_bounds__(64 * kColWaves)
+k_colsolve_full(T* __restrict__ spec, FullSym F, const C2<T>* __restrict__ tw, int nt, int nx, int lqb, Ctrl* ctrl,
+                const double* part, int nparts, double wscale, double* hist) {
+  if (ctrl && ctrl->status != 0) return;
+  if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
+  extern __shared__ char smem[];
+  T* tile = reinterpret_cast<T*>(smem);   // [8 cols][LPL][65]
+  const int QB = 1 << lqb;
+  const int q0 = xcd_block(blockIdx.x, gridDim.x) * kColCols;
+  T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
+  constexpr int kThreads = 64 * kColWaves;
+  constexpr int kPer = 64 * LPL * kColCols / kThreads;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int l0 = lane * LPL;
+  T stage[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    tile[(c * LPL + l % LPL) * 65 + l / LPL] = stage[r];
+  }
+  __syncthreads();
+  const int ca = 2 * wv, cb = 2 * wv + 1;
+  Cx<T> invd[LPL], invb[LPL];
+  T e1[LPL + 1], e2[LPL + 2];
+  Cx<T> z[1][LPL];
+  if (q0 + ca != 0) {   // complex mode (q0 + ca) / 2
+    full_rows<T, BW, LPL>(F, tw, (q0 + ca) >> 1, l0, invd, invb, e1, e2);
+#pragma unroll
+    for (int i = 0; i < LPL; ++i)
+      z[0][i] = Cx<T>(tile[(ca * LPL + i) * 65 + lane], tile[(cb * LPL + i) * 65 + lane]);
+    tri_solve_wave<Cx<T>, T, BW, LPL, 1>(z, invd, invb, e1, e2, lane, l0, nt);
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      tile[(ca * LPL + i) * 65 + lane] = z[0][i].re;
+      tile[(cb * LPL + i) * 65 + lane] = z[0][i].im;
+    }
+  } else {              // real columns: mode 0 in column 0, mode nx/2 in column 1
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = h;
+      full_rows<T, BW, LPL>(F, tw, h ? nx / 2 : 0, l0, invd, invb, e1, e2);
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) z[0][i] = Cx<T>(tile[(c * LPL + i) * 65 + lane], T(0));
+      tri_solve_wave<Cx<T>, T, BW, LPL, 1>(z, invd, invb, e1, e2, lane, l0, nt);
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) tile[(c * LPL + i) * 65 + lane] = z[0][i].re;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = tile[(c * LPL + l % LPL) * 65 + l / LPL];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    if (l < nt) base[(size_t)l * QB + c] = stage[r];
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 static inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <typename T, int BW, int LPL>
+static hipError_t launch_colsolve_full_l(T* spec, const FullSym& F, const void* tw, int nt, int nx, int lqb,
+                                         Ctrl* ctrl, const double* part, int nparts, double wscale, double* hist,
+                                         hipStream_t st) {
+  const size_t lds = sizeof(T) * (size_t)kColCols * LPL * 65;
+  hipError_t e = allow_lds(k_colsolve_full<T, BW, LPL>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_colsolve_full<T, BW, LPL>), dim3(nx / kColCols), dim3(64 * kColWaves), lds, st, spec, F,
+                     (const C2<T>*)tw, nt, nx, lqb, ctrl, part, nparts, wscale, hist);
+  return hipGetLastError();
+}
+
+// Full-symbol C: nt <= 1024, nx >= 8; part != NULL as for launch_colsolve_wave.
+template <typename T>
+hipError_t launch_colsolve_full(T* spec, const FullSym& F, const void* tw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                const double* part, int nparts, double wscale, double* hist, hipStream_t st) {
+  const int lpl = (nt + 63) / 64;
+#define PDHG_CF(B, L) \
+  return launch_colsolve_full_l<T, B, L>(spec, F, tw, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+  if (F.bdf2) {
+    if (lpl <= 1) PDHG_CF(2, 1);
+    if (lpl <= 2) PDHG_CF(2, 2);
+    if (lpl <= 4) PDHG_CF(2, 4);
+    if (lpl <= 8) PDHG_CF(2, 8);
+    if (lpl <= 16) PDHG_CF(2, 16);
+  } else {
+    if (lpl <= 1) PDHG_CF(1, 1);
+    if (lpl <= 2) PDHG_CF(1, 2);
+    if (lpl <= 4) PDHG_CF(1, 4);
+    if (lpl <= 8) PDHG_CF(1, 8);
+    if (lpl <= 16) PDHG_CF(1, 16);
+  }
+#undef PDHG_CF
+  return hipErrorInvalidValue;
+}
 
 template <typename T, int EPT>
 static hipError_t launch_dual_fft_e(const T* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
@@ -198,6 +343,10 @@ template hipError_t launch_primal_res<double>(const Scheme&, const double*, doub
                                               double, double*, int, const void*, double*, const Ctrl*, hipStream_t);
 template hipError_t launch_colsolve_wave<float>(float*, const FacTab<float>&, int, int, int, int, Ctrl*,
                                                 const double*, int, double, double*, hipStream_t);
+template hipError_t launch_colsolve_full<float>(float*, const FullSym&, const void*, int, int, int, Ctrl*,
+                                                const double*, int, double, double*, hipStream_t);
+template hipError_t launch_colsolve_full<double>(double*, const FullSym&, const void*, int, int, int, Ctrl*,
+                                                 const double*, int, double, double*, hipStream_t);
 template hipError_t launch_colsolve_wave<double>(double*, const FacTab<double>&, int, int, int, int, Ctrl*,
                                                  const double*, int, double, double*, hipStream_t);
 

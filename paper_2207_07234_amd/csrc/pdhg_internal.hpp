@@ -64,6 +64,17 @@ hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* 
 template <typename T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st);
+// Full-symbol preconditioner: g_k = (wr + vr)(1 - cos theta_k) + i ci sin theta_k per Fourier mode.
+struct FullSym {
+  double inv_ht;   // 1 / h_t
+  double wr;       // lf_speed / h_x (Lax-Friedrichs) or c / h_x (upwind)
+  double vr;       // 2 ghat / h_x^2 (viscosity of the linear-flux operator)
+  double ci;       // c / h_x
+  int bdf2;
+};
+template <typename T>
+hipError_t launch_colsolve_full(T* spec, const FullSym& F, const void* tw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                const double* part, int nparts, double wscale, double* hist, hipStream_t st);
 }  // namespace pdhg
 
 namespace pdhg {
@@ -101,7 +112,7 @@ struct OneStepProb {
 // would need the wrap-around step (the coupling ratio does not fall below tol within log2(nx) - 1 steps).
 bool onestep_pcr(const pdhg_problem& p, double c, double tol, double* out, int* k);
 template <typename T>
-void onestep_symbol(const pdhg_problem& p, double c, T* out);   // host: [2][nx]
+void onestep_symbol(const pdhg_problem& p, double c, double lf, T* out);   // host: [2][nx]
 struct OneStepSummary {
   long long total;   // sum of the steps' n*
   double rp, rd;     // largest final step residuals

@@ -284,6 +284,42 @@ constexpr int kFdColWaves = kColCols;      // finite differences: one wave per c
 constexpr int kColWaves = 4;               // DG: one wave per mode (its Re and Im columns)
 
 // (H, P) <- (H, P) o (H', P') : apply (H', P') first, then (H, P).
+// Complex value of the full-symbol column solve: the scan helpers below are
+// generic in the arithmetic type; cross-lane moves act per component.
+template <typename T>
+struct Cx {
+  T re, im;
+  __device__ __forceinline__ Cx() : re(T(0)), im(T(0)) {}
+  __device__ __forceinline__ Cx(T r) : re(r), im(T(0)) {}
+  __device__ __forceinline__ Cx(T r, T i) : re(r), im(i) {}
+};
+template <typename T>
+__device__ __forceinline__ Cx<T> operator+(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> operator-(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> operator-(Cx<T> a) { return {-a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> operator*(Cx<T> a, Cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> operator*(T a, Cx<T> b) { return {a * b.re, a * b.im}; }
+template <int CTRL, typename T>
+__device__ __forceinline__ Cx<T> dpp_move(Cx<T> v, Cx<T> fill) {
+  return {dpp_move<CTRL>(v.re, fill.re), dpp_move<CTRL>(v.im, fill.im)};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> read_lane(Cx<T> v, int src) { return {read_lane(v.re, src), read_lane(v.im, src)}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> from_lane_below(Cx<T> v, Cx<T> fill) {
+  return {from_lane_below(v.re, fill.re), from_lane_below(v.im, fill.im)};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> from_lane_above(Cx<T> v, Cx<T> fill) {
+  return {from_lane_above(v.re, fill.re), from_lane_above(v.im, fill.im)};
+}
+
 template <typename T>
 __device__ __forceinline__ void compose(T* H, T* P, const T* H2, const T* P2) {
   const T h0 = H[0] * H2[0] + H[1] * H2[2];
@@ -349,11 +385,15 @@ __device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& i
   }
 }
 
-// Solve L L^T y = z in place for NC columns sharing the factor rows; z[c][i]
-// is level l0 + i of column c.
-template <typename T, int BW, int LPL, int NC>
-__device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* invd, const T* e1, const T* e2,
-                                                    int lane, int l0, int nt) {
+// Solve L M y = z in place for NC columns sharing the coefficient rows, L lower
+// triangular (inverse diagonal invd, sub-diagonals e1, e2) and M = the upper
+// triangular with inverse diagonal invb and the transposed sub-diagonals; z[c][i]
+// is level l0 + i of column c.  L L^T (Cholesky factor) is invb = invd.  T is
+// the value type (real, or Cx for complex right-hand sides and diagonals), E
+// the type of the sub-diagonals.
+template <typename T, typename E, int BW, int LPL, int NC>
+__device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, const T* invb, const E* e1,
+                                               const E* e2, int lane, int l0, int nt) {
   // forward: z_l = invd_l (rhs_l - e1_l z_{l-1} - e2_l z_{l-2})
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -362,8 +402,8 @@ __device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* in
     for (int i = 0; i < LPL; ++i) {
       if (l0 + i < nt) {
         const T pz = invd[i] * (z[c][i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : T(0)));
-        const T az = invd[i] * (-e1[i] * a1 - (BW == 2 ? e2[i] * a2 : T(0)));
-        const T bz = invd[i] * (-e1[i] * b1 - (BW == 2 ? e2[i] * b2 : T(0)));
+        const T az = invd[i] * (-(e1[i] * a1) - (BW == 2 ? e2[i] * a2 : T(0)));
+        const T bz = invd[i] * (-(e1[i] * b1) - (BW == 2 ? e2[i] * b2 : T(0)));
         p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
       }
     }
@@ -379,7 +419,7 @@ __device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* in
       }
     }
   }
-  // backward: y_l = invd_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2})
+  // backward: y_l = invb_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2})
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
@@ -387,10 +427,10 @@ __device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* in
     for (int ii = 0; ii < LPL; ++ii) {
       const int i = LPL - 1 - ii;
       if (l0 + i < nt) {
-        const T f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : T(0);
-        const T pz = invd[i] * (z[c][i] - f1 * p1 - f2 * p2);
-        const T az = invd[i] * (-f1 * a1 - f2 * a2);
-        const T bz = invd[i] * (-f1 * b1 - f2 * b2);
+        const E f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : E(0);
+        const T pz = invb[i] * (z[c][i] - f1 * p1 - f2 * p2);
+        const T az = invb[i] * (-(f1 * a1) - f2 * a2);
+        const T bz = invb[i] * (-(f1 * b1) - f2 * b2);
         p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
       }
     }
@@ -401,13 +441,20 @@ __device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* in
     for (int ii = 0; ii < LPL; ++ii) {
       const int i = LPL - 1 - ii;
       if (l0 + i < nt) {
-        const T f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : T(0);
-        const T yy = invd[i] * (z[c][i] - f1 * ym1 - f2 * ym2);
+        const E f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : E(0);
+        const T yy = invb[i] * (z[c][i] - f1 * ym1 - f2 * ym2);
         z[c][i] = yy;
         ym2 = ym1; ym1 = yy;
       }
     }
   }
+}
+
+// Solve L L^T y = z in place (banded Cholesky factor L).
+template <typename T, int BW, int LPL, int NC>
+__device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* invd, const T* e1, const T* e2,
+                                                    int lane, int l0, int nt) {
+  tri_solve_wave<T, T, BW, LPL, NC>(z, invd, invd, e1, e2, lane, l0, nt);
 }
 
 template <typename T, int LPL>

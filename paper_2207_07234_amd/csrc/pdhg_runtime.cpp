@@ -106,27 +106,37 @@ template void build_factor_rows<float>(const pdhg_problem&, double, double, std:
 template void build_factor_rows<double>(const pdhg_problem&, double, double, std::vector<FacRow<double>>&,
                                          std::vector<int>&, std::vector<int>&);
 // Symbol of the one-step preconditioner per FFT index k, row r for c0 = 1 (r = 0)
-// and c0 = 3/2 (r = 1): 1 / (M ((c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2)),
-// mu_k = 4 sin^2(pi k / N_x) / h_x^2, M = N_x / 2 (the 1/M normalises the
-// half-length inverse FFT).  Computed in long double.
+// and c0 = 3/2 (r = 1): 1 / (M K_k), M = N_x / 2 (the 1/M normalises the half-length
+// inverse FFT), with K_k = (c0/h_t)^2 + c^2 mu_k + ghat^2 mu_k^2, mu_k = 4 sin^2(pi k / N_x) / h_x^2,
+// or, for the full-symbol preconditioner, K_k = |c0/h_t + g_k|^2 with
+// g_k = (w (1 - cos theta_k) + i c sin theta_k) / h_x + ghat mu_k (w = lf for Lax-Friedrichs,
+// c for upwind).  Computed in long double.
 template <typename T>
-void onestep_symbol(const pdhg_problem& p, double c, T* out) {
+void onestep_symbol(const pdhg_problem& p, double c, double lf, T* out) {
   typedef long double LD;
   const LD PI = 3.141592653589793238462643383279502884L;
   const int nx = p.nx;
   const LD ht = (LD)p.t_final / p.nt, hx = (LD)p.length / nx, cc = c, g = p.precond_gamma_hat;
+  const LD w = p.space == PDHG_FD_LF ? (LD)lf : cc;
   for (int r = 0; r < 2; ++r) {
     const LD a = (r ? 1.5L : 1.0L) / ht;
     for (int k = 0; k < nx; ++k) {
-      const LD sn = sinl(PI * k / nx);
+      const LD th = 2.0L * PI * k / nx, sn = sinl(0.5L * th);
       const LD mu = 4.0L * sn * sn / (hx * hx);
-      out[(size_t)r * nx + k] = (T)(2.0L / ((LD)nx * (a * a + cc * cc * mu + g * g * mu * mu)));
+      LD kk;
+      if (p.precond_kind == PDHG_PRECOND_FULL) {
+        const LD gr = a + w * (1.0L - cosl(th)) / hx + g * mu, gi = cc * sinl(th) / hx;
+        kk = gr * gr + gi * gi;
+      } else {
+        kk = a * a + cc * cc * mu + g * g * mu * mu;
+      }
+      out[(size_t)r * nx + k] = (T)(2.0L / ((LD)nx * kk));
     }
   }
 }
 bool onestep_pcr(const pdhg_problem& p, double c, double tol, double* out, int* k) {
   typedef long double LD;
-  if (p.precond_gamma_hat != 0.0) return false;
+  if (p.precond_gamma_hat != 0.0 || p.precond_kind == PDHG_PRECOND_FULL) return false;
   int m = 0;
   while ((1 << (m + 1)) <= p.nx) ++m;   // log2(nx)
   const LD ht = (LD)p.t_final / p.nt, hx = (LD)p.length / p.nx, e0 = (LD)c * c / (hx * hx);
@@ -149,8 +159,8 @@ bool onestep_pcr(const pdhg_problem& p, double c, double tol, double* out, int* 
   return true;
 }
 
-template void onestep_symbol<float>(const pdhg_problem&, double, float*);
-template void onestep_symbol<double>(const pdhg_problem&, double, double*);
+template void onestep_symbol<float>(const pdhg_problem&, double, double, float*);
+template void onestep_symbol<double>(const pdhg_problem&, double, double, double*);
 
 // Totals of a one-step march from its per-step records; the march stops after a diverged step.
 OneStepSummary summarize_steps(const StepStat* rec, int nt, int64_t* step_iters, double* step_res) {
@@ -272,6 +282,7 @@ inline int planes(const pdhg_problem& p) {
 }
 // Either DG discretisation (coefficient planes, per-mode eigenbasis in the column solve).
 inline bool is_dg(const pdhg_problem& p) { return p.space == PDHG_DG_P2_LLF || p.space == PDHG_DG_P1_UPWIND; }
+inline bool is_full(const pdhg_problem& p) { return p.precond_kind == PDHG_PRECOND_FULL; }
 
 WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   WsLayout L{};
@@ -310,6 +321,19 @@ Scheme scheme_of(const pdhg_handle* h) {
   s.gamma = p.gamma;
   s.lf = h->lf;
   return s;
+}
+
+// Symbol parameters of the full-symbol preconditioner from the resolved constants.
+FullSym full_sym_of(const pdhg_handle* h) {
+  const pdhg_problem& p = h->prob;
+  const double hx = p.length / p.nx;
+  FullSym F{};
+  F.inv_ht = p.nt / p.t_final;
+  F.wr = (p.space == PDHG_FD_LF ? h->lf : h->c) / hx;
+  F.vr = 2.0 * p.precond_gamma_hat / (hx * hx);
+  F.ci = h->c / hx;
+  F.bdf2 = p.time == PDHG_BDF2 ? 1 : 0;
+  return F;
 }
 
 template <typename T>
@@ -513,18 +537,24 @@ template <typename T>
 int resolve_constants_p(pdhg_handle* h, const T* u0, double* part, hipStream_t st, bool factors) {
   const pdhg_problem& p = h->prob;
   double lf = p.lf_speed, c = p.precond_c;
-  if ((p.space == PDHG_FD_LF && lf < 0.0) || c < 0.0) {
+  if ((p.space == PDHG_FD_LF && lf < 0.0) || (c < 0.0 && !is_full(p))) {
     double m = 0.0;
     int rc = max_abs_dflux<T>(h, u0, part, st, &m);
     if (rc) return rc;
     if (lf < 0.0) lf = m;
-    if (c < 0.0) c = m;
+    if (c < 0.0 && !is_full(p)) c = m;
+  }
+  if (c < 0.0 && is_full(p)) {   // the signed mean speed: f'(mean u0) = 2 alpha mean(u0) + beta
+    HIP_TRY(launch_level_sums<T>(u0, p.nx, (size_t)p.nx, 1, part, st));
+    HIP_TRY(hipMemcpyAsync(h->h_scal, part, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    c = 2.0 * p.alpha * h->h_scal[0] / p.nx + p.beta;
   }
   if (p.space != PDHG_FD_LF) lf = 0.0;
   h->lf = lf;
   h->c = c;
   h->consts_valid = true;
-  if (!factors) return PDHG_OK;
+  if (!factors || is_full(p)) return PDHG_OK;   // the full symbol needs no factor tables
   if (is_dg(p)) {
     if (!h->d_fac_rows || h->fac_c != c) {
       int rc = upload_factors_dg<T>(h, c);
@@ -556,7 +586,11 @@ int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
     return PDHG_OK;
   }
   HIP_TRY(launch_rows_fwd<T>(r, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st));
-  HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st));
+  if (is_full(p))
+    HIP_TRY(launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, nullptr, nullptr, 0, 0.0,
+                                    nullptr, st));
+  else
+    HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st));
   HIP_TRY(launch_rows_inv<T>(spec, p.nt, h->lqb, s, p.nt, p.nx, h->d_tw, nullptr, st));
   return PDHG_OK;
 }
@@ -637,6 +671,9 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   if (p.nt > 2048) return PDHG_EUNSUPPORTED;   // column solve: <= 32 segments of <= 64 levels
   // DG: nx cells >= 16 (8 spectrum columns per column block), nt <= 512 (8 levels per lane), no viscosity
   if (is_dg(p) && (p.nx < 16 || p.nt > 512 || p.gamma != 0.0)) return PDHG_EUNSUPPORTED;
+  if (p.precond_kind != PDHG_PRECOND_GRAM && p.precond_kind != PDHG_PRECOND_FULL) return PDHG_EINVAL;
+  // full symbol: finite differences, one wavefront per mode in the column solve (nt <= 1024)
+  if (is_full(p) && (is_dg(p) || p.nt > 1024)) return PDHG_EUNSUPPORTED;
   pdhg_handle* h = new (std::nothrow) pdhg_handle();
   if (!h) return PDHG_EINVAL;
   h->prob = p;
@@ -700,6 +737,9 @@ hipError_t colsolve_any(pdhg_handle* h, T* spec, Ctrl* ctrl, const double* part,
   const pdhg_problem& p = h->prob;
   const int bw = p.time == PDHG_BDF2 ? 2 : 1;
   const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
+  if (is_full(p))   // nt <= 1024 (checked at set-up)
+    return launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale,
+                                   hist, st);
   if (p.nt <= 1024)
     return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale, hist, st);
   hipError_t e = launch_colsolve<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
@@ -731,7 +771,11 @@ int enqueue_body_unfused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau
   HIP_TRY(launch_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
   HIP_TRY(launch_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
   HIP_TRY(launch_rows_fwd<T>(srow, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, ctrl, st));
-  HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, ctrl, st));
+  if (is_full(p))
+    HIP_TRY(launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, ctrl, nullptr, 0, 0.0,
+                                    nullptr, st));
+  else
+    HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, ctrl, st));
   HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
   return PDHG_OK;
 }
@@ -1057,7 +1101,7 @@ int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* p
   if (!use_pcr) pcr_k[0] = pcr_k[1] = 0;
   if (h->os_c != h->c) {
     std::vector<T> hs(2 * (size_t)nx + 32, T(0));
-    onestep_symbol<T>(P, h->c, hs.data());
+    onestep_symbol<T>(P, h->c, h->lf, hs.data());
     if (use_pcr)
       for (int i = 0; i < 32; ++i) hs[2 * (size_t)nx + i] = (T)pcr[i];
     HIP_TRY(hipMemcpyAsync(sym, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -1218,7 +1262,13 @@ int precond_impl(pdhg_handle* h, const T* r, T* s, hipStream_t st) {
   void* ws = nullptr;
   int rc = ensure_workspace(h, ws);
   if (rc) return rc;
-  if (!h->d_fac_rows) {
+  if (is_full(h->prob)) {
+    if (!h->consts_valid) {   // constants as given (no u0 to resolve them from)
+      if (h->prob.precond_c < 0.0 || (h->prob.space == PDHG_FD_LF && h->prob.lf_speed < 0.0)) return PDHG_EINVAL;
+      h->c = h->prob.precond_c;
+      h->lf = h->prob.space == PDHG_FD_LF ? h->prob.lf_speed : 0.0;
+    }
+  } else if (!h->d_fac_rows) {
     if (h->prob.precond_c < 0.0) return PDHG_EINVAL;
     rc = is_dg(h->prob) ? upload_factors_dg<T>(h, h->prob.precond_c)
                                           : upload_factors<T>(h, h->prob.precond_c, h->prob.precond_gamma_hat);
@@ -1292,7 +1342,7 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
       case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
       case 1:
-        if (h->last.variant == 2) return colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st);
+        if (h->last.variant == 2 || is_full(p)) return colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st);
         return launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st);
       case 2: return launch_rows_inv<T>(spec, p.nt, h->lqb, srow, p.nt, p.nx, h->d_tw, nullptr, st);
       case 3: return launch_dual<T>(phi, phibar, srow, n, tp, nullptr, st);

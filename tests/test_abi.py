@@ -125,3 +125,28 @@ def test_dg_setup_limits(bad, space):
     h = C.c_void_p()
     assert lib.pdhg_setup(C.byref(p), C.byref(h)) == B.PDHG_EUNSUPPORTED
     assert not h.value
+
+
+@pytest.mark.parametrize("kind,space,nt,code", [(7, "PDHG_FD_LF", 16, "PDHG_EINVAL"),
+                                                (1, "PDHG_DG_P2_LLF", 16, "PDHG_EUNSUPPORTED"),
+                                                (1, "PDHG_DG_P1_UPWIND", 16, "PDHG_EUNSUPPORTED"),
+                                                (1, "PDHG_FD_LF", 2048, "PDHG_EUNSUPPORTED")])
+def test_precond_kind_limits(kind, space, nt, code):
+    B, lib = _lib()
+    p = B.pdhg_problem()
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 64, nt, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype, p.precond_kind = B.PDHG_BE, getattr(B, space), B.PDHG_F64, kind
+    h = C.c_void_p()
+    assert lib.pdhg_setup(C.byref(p), C.byref(h)) == getattr(B, code)
+    assert not h.value
+
+
+def test_batch_rejects_the_full_symbol():
+    B, lib = _lib()
+    arr = (B.pdhg_problem * 1)()
+    p = arr[0]
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 256, 16, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype, p.precond_kind = B.PDHG_BE, B.PDHG_FD_LF, B.PDHG_F64, B.PDHG_PRECOND_FULL
+    h = C.c_void_p()
+    assert lib.pdhg_batch_setup(arr, 1, C.byref(h)) == B.PDHG_EUNSUPPORTED
+    assert not h.value
