@@ -246,6 +246,37 @@ def variant_comparison(pk, solver, prob, u0, tau, vanilla):
                        "us_per_iteration": r.stats["seconds"] / n * 1e6}
     log(f"Algorithm 3: status {r.status}, {n} iterations ({min(r.stats['step_iters'])}.."
         f"{max(r.stats['step_iters'])} per step), {wall:.3f} s, space-time residual {res[0]:.2e} / {res[1]:.2e}")
+    # the same two with the full-symbol preconditioner (the Gram of the linear-flux Jacobian)
+    fp = pk.Problem(nx=NX, nt=NT, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf",
+                    dtype=prob.dtype, precond_kind="full")
+    fs = pk.Solver(fp)
+    first = fs.solve(u0, eps=EPS, max_iter=200000, check_every=128)
+    tf = first.stats["tau_u"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fs.solve(u0, tau_u=tf, tau_phi=tf, eps=EPS, max_iter=200000, check_every=128)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = r.stats["iters"]
+    cms = fs.time_kernel(1, reps=50)
+    out["algorithm_1_full_symbol"] = {"iterations": n, "world_time": n, "work_N": n * (NT + 1), "seconds": wall,
+                                      "status": r.status, "precond_c": r.stats["precond_c"],
+                                      "us_per_iteration": wall / n * 1e6, "column_pass_us": cms * 1e3}
+    log(f"Algorithm 1, full symbol: status {r.status}, {n} iterations, {wall:.3f} s "
+        f"({wall / n * 1e6:.1f} us/iteration, column pass {cms * 1e3:.1f} us), c = {r.stats['precond_c']:.4f}")
+    fs.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fs.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, _, res = fs.residual(r.u, r.phi, want_fields=False)
+    n = r.stats["iters"]
+    out["one_step_full_symbol"] = {"iterations": n, "world_time": n, "work_N": 2 * n, "seconds": wall,
+                                   "status": r.status, "space_time_residual": list(res),
+                                   "us_per_iteration": r.stats["seconds"] / n * 1e6}
+    log(f"Algorithm 3, full symbol: status {r.status}, {n} iterations, {wall:.3f} s, "
+        f"space-time residual {res[0]:.2e} / {res[1]:.2e}")
     return out
 
 
