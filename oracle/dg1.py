@@ -104,15 +104,13 @@ def spatial_blocks(prob: Problem, v: np.ndarray):
     uq = P.T @ v
     P1, P_1 = basis(1.0), basis(-1.0)
     minv = np.linalg.inv(h * mass_unit())
-    D = np.empty((nx, 2, 2))
-    L = np.empty((nx, 2, 2))
-    for j in range(nx):
-        # d vol_k / d v_m = dphi_k sum_q f'(u_q) phi_m(x_q)
-        dvol = DBASIS[:, None] * (P @ prob.fp(uq[:, j]))[None, :]
-        dflux_r = prob.fp(a[j]) * np.outer(P1, P1)                 # d(fhat_{j+1/2} phi_k(1)) / d v_j
-        dflux_l = prob.fp(a[(j - 1) % nx]) * np.outer(P_1, P1)     # d(fhat_{j-1/2} phi_k(-1)) / d v_{j-1}
-        D[j] = -(minv @ (dvol - dflux_r))
-        L[j] = -(minv @ dflux_l)
+    # d vol_k / d v_m = dphi_k sum_q f'(u_q) phi_m(x_q), per cell j: (nx, k, m)
+    dvol = DBASIS[None, :, None] * (P @ prob.fp(uq)).T[:, None, :]
+    # d(fhat_{j+1/2} phi_k(1)) / d v_j  and  d(fhat_{j-1/2} phi_k(-1)) / d v_{j-1}
+    dflux_r = prob.fp(a)[:, None, None] * np.outer(P1, P1)[None]
+    dflux_l = prob.fp(np.roll(a, 1))[:, None, None] * np.outer(P_1, P1)[None]
+    D = -np.einsum("kl,jlm->jkm", minv, dvol - dflux_r)
+    L = -np.einsum("kl,jlm->jkm", minv, dflux_l)
     return D, L
 
 
@@ -120,14 +118,15 @@ def spatial_jacobian(prob: Problem, v: np.ndarray) -> sp.csr_matrix:
     """dF/dv as a sparse (2 nx) x (2 nx) matrix in (k, j) ordering (index k nx + j)."""
     nx = prob.nx
     D, L = spatial_blocks(prob, v)
+    j = np.arange(nx)
     rows, cols, vals = [], [], []
-    for j in range(nx):
-        for k in range(2):
-            for m in range(2):
-                rows += [k * nx + j, k * nx + j]
-                cols += [m * nx + j, m * nx + (j - 1) % nx]
-                vals += [D[j, k, m], L[j, k, m]]
-    return sp.csr_matrix((vals, (rows, cols)), shape=(2 * nx, 2 * nx))
+    for k in range(2):
+        for m in range(2):
+            rows += [k * nx + j, k * nx + j]
+            cols += [m * nx + j, m * nx + (j - 1) % nx]
+            vals += [D[:, k, m], L[:, k, m]]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(2 * nx, 2 * nx))
 
 
 def p1_residual(prob: Problem, u: np.ndarray) -> np.ndarray:
@@ -210,8 +209,8 @@ def unit_upwind_blocks(prob: Problem):
     return D[0], L[0]
 
 
-def symbol(prob: Problem, theta: float) -> np.ndarray:
-    g0, gm = unit_upwind_blocks(prob)
+def symbol(prob: Problem, theta: float, blocks=None) -> np.ndarray:
+    g0, gm = unit_upwind_blocks(prob) if blocks is None else blocks
     return g0 + gm * np.exp(-1j * theta)
 
 
@@ -219,8 +218,9 @@ def mode_eig(prob: Problem):
     """Per Fourier mode m = 0..nx-1: (lambda_m [2], Q_m [2x2]) of c^2 G(theta_m) G(theta_m)^*."""
     lam = np.empty((prob.nx, 2))
     Q = np.empty((prob.nx, 2, 2), dtype=np.complex128)
+    blocks = unit_upwind_blocks(prob)
     for m in range(prob.nx):
-        g = symbol(prob, 2.0 * np.pi * m / prob.nx)
+        g = symbol(prob, 2.0 * np.pi * m / prob.nx, blocks)
         w, q = np.linalg.eigh(prob.precond_c ** 2 * (g @ g.conj().T))
         lam[m], Q[m] = w, q
     return lam, Q
