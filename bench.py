@@ -213,6 +213,37 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def traffic_table3(pk):
+    """The traffic example of Section 4.3 (f(u) = u - u^2 on [0, 2), piecewise-constant density, 256 x 32,
+    T = 1, upwind, tau = 0.4, c = 1, tolerance 1e-3) through the three variants, in the columns of Table 3:
+    iterations, world time (iterations in sequence) and work in units of N_x (iterations x levels)."""
+    import torch
+    import synthetic as syn
+    u0 = torch.tensor(syn.traffic_u0(256, 2.0), dtype=torch.float64, device="cuda")
+    out = {}
+    for tm in ("be", "bdf2"):
+        s = pk.Solver(pk.Problem(nx=256, nt=32, length=2.0, t_final=1.0, alpha=-1.0, beta=1.0, time=tm,
+                                 space="fd_upwind", precond_c=1.0))
+        kw = dict(tau_u=0.4, tau_phi=0.4, eps=1e-3, max_iter=20000)
+        v = s.solve(u0, check_every=64, **kw)
+        rf = s.solve_refined(u0, nt_start=8, coarse_max_iter=1000, coarse_eps=1e-300, check_every=64, **kw)
+        os_ = s.solve_onestep(u0, **kw)
+        lv = rf.stats["level_iters"]
+        out[tm] = {
+            "vanilla": {"iterations": v.stats["iters"], "world_time": v.stats["iters"],
+                        "work_N": v.stats["iters"] * 33, "status": v.status},
+            "mesh_refinement": {"iterations": lv, "world_time": sum(lv),
+                                "work_N": sum(n * (m + 1) for n, m in zip(lv, (8, 16, 32))), "status": rf.status},
+            "one_step": {"iterations": os_.stats["iters"], "world_time": os_.stats["iters"],
+                         "work_N": 2 * os_.stats["iters"], "status": os_.status},
+        }
+        log(f"traffic example ({tm}): vanilla {v.stats['iters']}, refinement {lv}, "
+            f"one-step {os_.stats['iters']} iterations")
+    out["paper"] = {"vanilla": [4573, 4573, 150909], "mesh_refinement": [[1000, 1000, 3601], 5601, 144833],
+                    "one_step": [8627, 8627, 17254]}
+    return out
+
+
 def variant_comparison(pk, solver, prob, u0, tau, vanilla):
     """Algorithms 1, 2 and 3 on the single workload (FP64, 1e-8); `vanilla` = (iterations, seconds)."""
     import torch
@@ -547,6 +578,7 @@ def main():
     variants = None
     if eps > 0 and not args.no_variants:
         variants = variant_comparison(pk, solver, prob, u0, tau, (iters[-1], ms_per_step / 1e3))
+        variants["traffic_table3"] = traffic_table3(pk)
 
     out = {
         "metric": METRIC,

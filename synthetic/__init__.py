@@ -63,6 +63,17 @@ def sine_u0(nx: int, length: float = 1.0) -> np.ndarray:
     return np.sin(2.0 * np.pi * x / length)
 
 
+def traffic_u0_at(x: np.ndarray) -> np.ndarray:
+    """Piecewise-constant traffic density of Section 4.3 on [0, 2): 0.1 on [1, 2], 0.25 elsewhere."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where((x >= 1.0) & (x <= 2.0), 0.1, 0.25)
+
+
+def traffic_u0(nx: int, length: float = 2.0) -> np.ndarray:
+    """traffic_u0_at at the nodes x_j = j*length/nx."""
+    return traffic_u0_at(np.arange(nx, dtype=np.float64) * (length / nx))
+
+
 def gaussian_bump_u0(nx: int) -> np.ndarray:
     """u0 = exp(-64 (x - 1/2)^2) on [0,1) (heat example, Section 4.1)."""
     x = np.arange(nx, dtype=np.float64) / nx
