@@ -189,14 +189,15 @@ __device__ __forceinline__ void load_twiddles_lds(C2<T>* twl, const C2<T>* __res
   for (int i = tid; i < N; i += W) twl[lpad(i)] = tw[i];
 }
 
-// One Stockham radix-R stage on an LDS array of N points, in place: every
-// thread loads all inputs of its butterflies, the block synchronises, then
-// the outputs are stored.  Butterfly j (0 <= j < N/R) reads x[j + r N/R],
-// twiddles input r by w_N^{r k N/(Ns R)} with k = j mod Ns, and writes
-// output q to x[(j - k) R + k + q Ns].  EPT bounds N / W (points per thread).
+// One Stockham radix-R stage on LDS arrays of N points: every thread loads all
+// inputs of its butterflies from src, and stores the outputs to dst.  In place
+// (dst == src) the block synchronises between the loads and the stores.
+// Butterfly j (0 <= j < N/R) reads x[j + r N/R], twiddles input r by
+// w_N^{r k N/(Ns R)} with k = j mod Ns, and writes output q to
+// x[(j - k) R + k + q Ns].  EPT bounds N / W (points per thread).
 template <bool INV, int R, int EPT, typename T>
-__device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const C2<T>* __restrict__ twl,
-                                               int tid, int W) {
+__device__ __forceinline__ void stockham_stage(const C2<T>* src, C2<T>* dst, int N, int Ns,
+                                               const C2<T>* __restrict__ twl, int tid, int W) {
   constexpr int MAXB = (EPT + R - 1) / R;  // butterflies per thread
   const int nbf = N / R;
   C2<T> v[MAXB * R];
@@ -205,10 +206,10 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
     const int j = tid + b * W;
     if (tid < W && j < nbf) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b * R + r] = buf[lpad(j + r * nbf)];
+      for (int r = 0; r < R; ++r) v[b * R + r] = src[lpad(j + r * nbf)];
     }
   }
-  __syncthreads();
+  if (dst == src) __syncthreads();
   const int tstride = N / (Ns * R);
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
@@ -225,7 +226,7 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
       else dft2<INV>(vb);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[lpad(base + q * Ns)] = vb[q];
+      for (int q = 0; q < R; ++q) dst[lpad(base + q * Ns)] = vb[q];
     }
   }
   __syncthreads();
@@ -235,24 +236,35 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, int N, int Ns, const 
 // layout): X_k = sum_x z_x e^{-2 pi i x k / N} (forward) or e^{+...} (inverse).
 // twl: LDS twiddle table from load_twiddles_lds.  Requires N = 2^m, 2 <= N <=
 // EPT W, and every thread of the block to call it; threads tid = 0..W-1 do the
-// work, any others take part in the barriers only.
+// work, any others take part in the barriers only.  With a second LDS array
+// alt of N points the stages alternate between buf and alt (one barrier per
+// stage instead of two); the returned pointer (buf or alt) holds the result.
 template <bool INV, int EPT, typename T>
-__device__ void fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int tid, int W) {
+__device__ C2<T>* fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int tid, int W,
+                          C2<T>* alt = nullptr) {
   __syncthreads();
+  C2<T>* src = buf;
+  C2<T>* dst = alt ? alt : buf;
   int Ns = 1;
   while (Ns < N) {
     const int rem = N / Ns;
     if (rem >= 8) {
-      stockham_stage<INV, 8, EPT>(buf, N, Ns, twl, tid, W);
+      stockham_stage<INV, 8, EPT>(src, dst, N, Ns, twl, tid, W);
       Ns *= 8;
     } else if (rem == 4) {
-      stockham_stage<INV, 4, EPT>(buf, N, Ns, twl, tid, W);
+      stockham_stage<INV, 4, EPT>(src, dst, N, Ns, twl, tid, W);
       Ns *= 4;
     } else {
-      stockham_stage<INV, 2, EPT>(buf, N, Ns, twl, tid, W);
+      stockham_stage<INV, 2, EPT>(src, dst, N, Ns, twl, tid, W);
       Ns *= 2;
     }
+    if (alt) {
+      C2<T>* t = src;
+      src = dst;
+      dst = t;
+    }
   }
+  return src;
 }
 
 // ------------------------------------------------------------------ XCD-aware block order

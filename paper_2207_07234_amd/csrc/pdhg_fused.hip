@@ -33,6 +33,12 @@ constexpr int kRowThreadsMax = 512;
 template <typename T, int E>
 constexpr int row_threads_max() { return E * (int)sizeof(T) <= 16 ? 1024 : 512; }
 
+// A and B take a third N-point LDS array for the FFT (one barrier per stage
+// instead of two) when the three arrays fit in 96 KiB: up to nx = 2048 in FP64
+// and nx = 4096 in FP32.  The kernels and their launchers decide alike.
+template <typename T>
+__host__ __device__ constexpr bool fft_pingpong(int nx) { return 3 * (size_t)nx * sizeof(C2<T>) <= 98304; }
+
 // A: one block per pair of dual rows, W = nx / EPT threads.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(kRowThreadsMax)
@@ -44,12 +50,15 @@ k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __r
   C2<T>* twl = buf + lds_fft_points(nx);
   const int tid = threadIdx.x, W = blockDim.x;
   const int a = 2 * xcd_block(blockIdx.x, gridDim.x);
-  dual_fft_pair<T, EPT>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl);
+  C2<T>* alt = fft_pingpong<T>(nx) ? twl + lds_fft_points(nx) : nullptr;
+  dual_fft_pair<T, EPT>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl, alt);
 }
 
 // B: one block per pair of implicit rows, W = 64 nw threads, E = nx / W.  The
 // per-block partial sums go to part[blk] and part[gridDim + blk]; the column
-// solve of the same iteration reduces them.
+// solve of the same iteration reduces them.  The per-wave sums are taken
+// before the FFT, whose barriers publish them, and added up by thread 0 in
+// wave order at the end (the order of block_sum_waves).
 template <typename T, int E>
 __global__ void __launch_bounds__((row_threads_max<T, E>()))
 k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
@@ -61,15 +70,24 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   const int nx = sch.nx, W = blockDim.x, tid = threadIdx.x;
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(nx);
-  T* edge = reinterpret_cast<T*>(twl + lds_fft_points(nx));   // [2 rows][first, last][nw]
-  __shared__ double red[row_threads_max<T, E>() / 64];
+  const bool pp = fft_pingpong<T>(nx);
+  C2<T>* alt = pp ? twl + lds_fft_points(nx) : nullptr;
+  T* edge = reinterpret_cast<T*>(twl + (pp ? 2 : 1) * lds_fft_points(nx));   // [2 rows][first, last][nw]
+  constexpr int kMaxWaves = row_threads_max<T, E>() / 64;
+  __shared__ double wsum[2 * kMaxWaves];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   double rp, rd;
   primal_res_pair<T, E>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
-                        edge, rp, rd);
-  const double srp = block_sum_waves(rp, red);
-  const double srd = block_sum_waves(rd, red);
+                        edge, rp, rd, alt, wsum);
   if (tid == 0) {
+    const int nw = W >> 6;
+    double srp = 0.0, srd = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxWaves; ++i)
+      if (i < nw) srp += wsum[i];
+#pragma unroll
+    for (int i = 0; i < kMaxWaves; ++i)
+      if (i < nw) srd += wsum[nw + i];
     part[blk] = srp;
     part[gridDim.x + blk] = srd;
   }
@@ -241,7 +259,7 @@ template <typename T, int EPT>
 static hipError_t launch_dual_fft_e(const T* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
                                     const Ctrl* ctrl, hipStream_t st) {
   const int W = nx / EPT;
-  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(nx);
+  const size_t lds = sizeof(C2<T>) * (fft_pingpong<T>(nx) ? 3 : 2) * (size_t)lds_fft_points(nx);
   hipError_t e = allow_lds(k_dual_fft<T, EPT>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dual_fft<T, EPT>), dim3((nt + 1) / 2), dim3(W), lds, st, spec, nt, lqb, nx,
@@ -269,7 +287,8 @@ static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, 
                                       T tau_u, T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl,
                                       hipStream_t st) {
   const int W = s.nx / E;
-  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(s.nx) + sizeof(T) * 4 * (W / 64);
+  const size_t lds = sizeof(C2<T>) * (fft_pingpong<T>(s.nx) ? 3 : 2) * (size_t)lds_fft_points(s.nx) +
+                     sizeof(T) * 4 * (W / 64);
   hipError_t e = allow_lds(k_primal_res<T, E>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_primal_res<T, E>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out, phibar, phi,

@@ -29,7 +29,7 @@ template <typename T, int EPT>
 __device__ __forceinline__ void dual_fft_pair(const T* __restrict__ spec, int nt, int lqb, int nx,
                                               const C2<T>* __restrict__ tw, T* __restrict__ phi,
                                               T* __restrict__ phibar, T tau, int a, int tid, int W, int gtid, int TB,
-                                              C2<T>* buf, C2<T>* twl) {
+                                              C2<T>* buf, C2<T>* twl, C2<T>* alt = nullptr) {
   const int b = a + 1;
   const bool act = a < nt, hasb = b < nt;
   const int half = nx >> 1;
@@ -85,12 +85,12 @@ __device__ __forceinline__ void dual_fft_pair(const T* __restrict__ spec, int nt
       if (k != 0 && k != half) buf[lpad(nx - k)] = {sar[e] + sbi[e], sbr[e] - sai[e]};
     }
   }
-  fft_lds<true, EPT>(buf, nx, twl, tid, W);
+  const C2<T>* res = fft_lds<true, EPT>(buf, nx, twl, tid, W, alt);
   const T sc = T(1) / T(nx);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int x = tid + e * W;
-    const C2<T> z = buf[lpad(x)];
+    const C2<T> z = res[lpad(x)];
     if (act) {
       const T ta = tau * (z.x * sc);
       const T p = fa[e] + ta;
@@ -141,14 +141,16 @@ __device__ __forceinline__ void dual_op_regs(const Consts<T>& C, int m, const T*
 // row the pair needs is loaded up front: u^{n-1} on levels a-1..a+2, phibar on
 // rows a-2..a+3, phi on rows a..a+3.  Returns this thread's contributions to
 // ||A(u^n)||^2 (rows a, a+1) and ||J(u^{n-1})^T phi^{n-1}||^2 (levels a+1, a+2).
-// edge: 4 (W / 64) values of LDS for this sub-group.
+// edge: 4 (W / 64) values of LDS for this sub-group.  alt (optional): a second
+// N-point LDS array for the FFT.  wsum (optional, 2 W / 64 doubles of LDS): the
+// per-wave sums of the two contributions, stored before the FFT.
 template <typename T, int E>
 __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __restrict__ u_in,
                                                 T* __restrict__ u_out, const T* __restrict__ phibar,
                                                 const T* __restrict__ phi, T tau_u, T* __restrict__ spec, int lqb,
                                                 const C2<T>* __restrict__ tw, int a, int tid, int W, int gtid,
                                                 int TB, C2<T>* buf, C2<T>* twl, T* edge, double& rp_out,
-                                                double& rd_out) {
+                                                double& rd_out, C2<T>* alt = nullptr, double* wsum = nullptr) {
   const int nx = C.nx, nt = C.nt;
   const int lane = tid & 63, wv = tid >> 6, nw = W >> 6;
   const int seg0 = wv * 64 * E;
@@ -245,10 +247,24 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
       for (int e = 0; e < E; ++e) R[s][e] = T(0);
     }
   }
+  if (wsum) {
+    // per-wave sums now (the FFT's barriers publish them); the caller adds
+    // them up in wave order, as block_sum_waves would
+    double sp = rp, sd = rd;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      sp += __shfl_down(sp, off, 64);
+      sd += __shfl_down(sd, off, 64);
+    }
+    if (lane == 0) {
+      wsum[wv] = sp;
+      wsum[nw + wv] = sd;
+    }
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) buf[lpad(seg0 + lane + 64 * e)] = {R[0][e], R[1][e]};
-  fft_lds<false, E>(buf, nx, twl, tid, W);
-  if (act) store_halfcomplex_pair(buf, nx, spec, nt, lqb, a, b < nt, tid, W);
+  const C2<T>* res = fft_lds<false, E>(buf, nx, twl, tid, W, alt);
+  if (act) store_halfcomplex_pair(res, nx, spec, nt, lqb, a, b < nt, tid, W);
   rp_out = rp;
   rd_out = rd;
 }
