@@ -213,6 +213,36 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def large_single_sweep(pk):
+    """Per-kernel device time of the fused passes on single problems large enough to fill the GPU many
+    times over (N_t = 2048, the column solve's limit: 1024 row-pair blocks, four per CU), against the
+    HBM roofline; at 4096 x 2048 the working set (five arrays of N_x N_t values) exceeds the MALL."""
+    import torch
+    import synthetic as syn
+    out = []
+    for nx, nt, dt in ((2048, 2048, torch.float64), (4096, 2048, torch.float64), (4096, 2048, torch.float32)):
+        esz = 8 if dt == torch.float64 else 4
+        prob = pk.Problem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf", dtype=dt)
+        s = pk.Solver(prob)
+        u0 = torch.tensor(syn.fourier_u0(SEED, nx), dtype=dt, device="cuda")
+        s.solve(u0, tau_u=0.5, tau_phi=0.5, eps=0.0, max_iter=2, check_every=2)
+        dof = nx * nt
+        rec = {"nx": nx, "nt": nt, "dtype": "f64" if esz == 8 else "f32", "kernels": {}}
+        for kid, (name, words) in KERNELS_FUSED.items():
+            ms = s.time_kernel(kid, reps=20)
+            gbs = words * esz * dof / (ms * 1e-3) / 1e9
+            rec["kernels"][name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            log(f"large single {nx}x{nt} {rec['dtype']}: {name}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s "
+                f"({gbs / HBM_PEAK_GBS:.2f} of peak)")
+        ms = s.time_kernel(COPY_KERNEL, reps=20)
+        rec["copy_GBs"] = 2 * esz * dof / (ms * 1e-3) / 1e9
+        out.append(rec)
+        s.close()
+        del s, u0
+        torch.cuda.empty_cache()
+    return out
+
+
 def traffic_table3(pk):
     """The traffic example of Section 4.3 (f(u) = u - u^2 on [0, 2), piecewise-constant density, 256 x 32,
     T = 1, upwind, tau = 0.4, c = 1, tolerance 1e-3) through the three variants, in the columns of Table 3:
@@ -579,6 +609,7 @@ def main():
     if eps > 0 and not args.no_variants:
         variants = variant_comparison(pk, solver, prob, u0, tau, (iters[-1], ms_per_step / 1e3))
         variants["traffic_table3"] = traffic_table3(pk)
+        variants["large_single"] = large_single_sweep(pk)
 
     out = {
         "metric": METRIC,
