@@ -200,17 +200,24 @@ __device__ __forceinline__ void stockham_stage(const C2<T>* src, C2<T>* dst, int
                                                const C2<T>* __restrict__ twl, int tid, int W) {
   constexpr int MAXB = (EPT + R - 1) / R;  // butterflies per thread
   const int nbf = N / R;
-  C2<T> v[MAXB * R];
+  const int tstride = N / (Ns * R);
+  // inputs and twiddles of all butterflies are read before any is used, so that
+  // their LDS latencies overlap
+  C2<T> v[MAXB * R], w[MAXB * R];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * W;
     if (tid < W && j < nbf) {
+      const int k = j & (Ns - 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b * R + r] = src[lpad(j + r * nbf)];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b * R + r] = twl[lpad(r * k * tstride)];
+      }
     }
   }
   if (dst == src) __syncthreads();
-  const int tstride = N / (Ns * R);
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * W;
@@ -219,7 +226,7 @@ __device__ __forceinline__ void stockham_stage(const C2<T>* src, C2<T>* dst, int
       C2<T>* vb = v + b * R;
       if (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) vb[r] = cmul_tw<INV>(vb[r], twl[lpad(r * k * tstride)]);
+        for (int r = 1; r < R; ++r) vb[r] = cmul_tw<INV>(vb[r], w[b * R + r]);
       }
       if (R == 8) dft8<INV>(vb);
       else if (R == 4) dft4<INV>(vb);

@@ -120,8 +120,14 @@ struct OneStepSummary {
   int done;          // steps marched (the march stops after a diverged step)
 };
 OneStepSummary summarize_steps(const StepStat* rec, int nt, int64_t* step_iters, double* step_res);
-// Threads per problem: one radix-8 butterfly per thread in each stage of the half-length FFT.
-__host__ __device__ inline int onestep_threads(int nx) { return nx / 8 < 64 ? 64 : nx / 8; }
+// Threads per problem of the one-step march.
+template <typename T>
+__host__ __device__ inline int onestep_threads(int nx) {
+  // FP64: 4 points per thread up to nx = 2048 (8 at 4096, the 512-thread limit), which keeps the
+  // march's registers within the file; FP32: 8 points per thread
+  const int w = nx / (sizeof(T) == 8 ? 4 : 8);
+  return w < 64 ? 64 : (w > 512 ? 512 : w);
+}
 template <typename T>
 hipError_t launch_onestep_power(OneStepProb<T>* probs, int nprob, int max_nx, int iters, double* nu, hipStream_t st);
 template <typename T>

@@ -22,8 +22,8 @@
 // x = seg + q + 64 e): stencil neighbours inside a wave come from DPP lane
 // shifts, and only the two segment ends of each wave pass through LDS.  A
 // launch takes a table of problems, one block each (a batch, or a single
-// problem); threads beyond a problem's W = max(64, N_x/8) take part in the
-// barriers only.
+// problem); threads beyond a problem's W (onestep_threads: N_x/4 in FP64,
+// N_x/8 in FP32, within [64, 512]) take part in the barriers only.
 //
 // K_l^{-1} of a real row through a half-length complex FFT: the row r, read
 // as M = N_x/2 complex values z_m = r_{2m} + i r_{2m+1}, is exactly the LDS
@@ -418,7 +418,7 @@ k_onestep_power(OneStepProb<T>* __restrict__ probs, int iters, double* __restric
   __shared__ double red[2][kOneStepWavesMax];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(P.s.nx >> 1);
-  const int W = onestep_threads(P.s.nx);
+  const int W = onestep_threads<T>(P.s.nx);
   double v;
   switch (P.s.nx / W) {
     case 8: v = onestep_power<T, 8>(P, W, iters, buf, twl, ends, red); break;
@@ -442,7 +442,7 @@ hipError_t launch_onestep_power(OneStepProb<T>* probs, int nprob, int max_nx, in
   const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(max_nx / 2);
   hipError_t e = allow_lds(k_onestep_power<T>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_onestep_power<T>), dim3(nprob), dim3(onestep_threads(max_nx)), lds, st, probs, iters, nu);
+  hipLaunchKernelGGL((k_onestep_power<T>), dim3(nprob), dim3(onestep_threads<T>(max_nx)), lds, st, probs, iters, nu);
   return hipGetLastError();
 }
 
@@ -464,7 +464,7 @@ k_onestep(const OneStepProb<T>* __restrict__ probs, int l_begin, int l_end, doub
   const int M = P.s.nx >> 1;
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(M);
-  const int W = onestep_threads(P.s.nx);
+  const int W = onestep_threads<T>(P.s.nx);
   switch (P.s.nx / W) {
     case 8: onestep_march<T, 8>(P, W, l_begin, le, eps, max_iter, dfac, buf, twl, ends, red); break;
     case 4: onestep_march<T, 4>(P, W, l_begin, le, eps, max_iter, dfac, buf, twl, ends, red); break;
@@ -478,7 +478,7 @@ template <typename T>
 hipError_t launch_onestep(const OneStepProb<T>* probs, int nprob, int max_nx, int l_begin, int l_end, double eps,
                           long long max_iter, double dfac, hipStream_t st) {
   if (max_nx < 64 || max_nx > 4096 || (max_nx & (max_nx - 1)) || nprob < 1) return hipErrorInvalidValue;
-  const int W = onestep_threads(max_nx);
+  const int W = onestep_threads<T>(max_nx);
   const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(max_nx / 2);
   hipError_t e = allow_lds(k_onestep<T>, lds);
   if (e != hipSuccess) return e;
