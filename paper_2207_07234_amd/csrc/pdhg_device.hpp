@@ -355,10 +355,16 @@ __device__ __forceinline__ void wave_row_neighbours(const T* v, T prev_last, T n
 }
 
 // ------------------------------------------------------------------ reductions
+// Sum over the 64 lanes of a wavefront (all lanes active), the same value in
+// every lane: an inclusive scan inside each row of 16 lanes by DPP row shifts
+// (no LDS), then the four row totals (lanes 15, 31, 47, 63) added in a fixed
+// order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  v += dpp_move<0x111>(v, 0.0);   // row_shr:1
+  v += dpp_move<0x112>(v, 0.0);   // row_shr:2
+  v += dpp_move<0x114>(v, 0.0);   // row_shr:4
+  v += dpp_move<0x118>(v, 0.0);   // row_shr:8
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
 }
 
 // Sum over the block (W threads); result valid in thread 0.  Fixed order.

@@ -250,12 +250,7 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
   if (wsum) {
     // per-wave sums now (the FFT's barriers publish them); the caller adds
     // them up in wave order, as block_sum_waves would
-    double sp = rp, sd = rd;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      sp += __shfl_down(sp, off, 64);
-      sd += __shfl_down(sd, off, 64);
-    }
+    const double sp = wave_sum(rp), sd = wave_sum(rd);
     if (lane == 0) {
       wsum[wv] = sp;
       wsum[nw + wv] = sd;
