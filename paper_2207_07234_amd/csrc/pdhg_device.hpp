@@ -392,8 +392,15 @@ __device__ __forceinline__ double block_sum_waves(double v, double* red /* >= bl
   if (lane == 0) red[wid] = v;
   __syncthreads();
   double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < nw; ++i) s += red[i];
+  if (threadIdx.x == 0) {
+    // reads issued together (unrolled to 16 waves), added in wave order
+    double r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r[i] = i < nw ? red[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i < nw) s += r[i];
+  }
   return s;
 }
 

@@ -188,10 +188,20 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, bool act, int w
     red[1][wv] = b;
   }
   __syncthreads();
+  // all reads issued before the additions (unrolled to the largest wave count)
+  double ra[kOneStepWavesMax], rb[kOneStepWavesMax];
+#pragma unroll
+  for (int i = 0; i < kOneStepWavesMax; ++i) {
+    ra[i] = i < nw ? red[0][i] : 0.0;
+    rb[i] = i < nw ? red[1][i] : 0.0;
+  }
   double sa = 0.0, sb = 0.0;
-  for (int i = 0; i < nw; ++i) {
-    sa += red[0][i];
-    sb += red[1][i];
+#pragma unroll
+  for (int i = 0; i < kOneStepWavesMax; ++i) {
+    if (i < nw) {
+      sa += ra[i];
+      sb += rb[i];
+    }
   }
   a = sa;
   b = sb;

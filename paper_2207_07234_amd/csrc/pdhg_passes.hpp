@@ -275,8 +275,15 @@ __device__ __forceinline__ double subgroup_sum(double v, double* red, int w0, in
   if (lane == 0) red[wid] = v;
   __syncthreads();
   double s = 0.0;
-  if (wid == w0 && lane == 0)
-    for (int i = 0; i < nw; ++i) s += red[w0 + i];
+  if (wid == w0 && lane == 0) {
+    // reads issued together (unrolled to 16 waves), added in wave order
+    double r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r[i] = i < nw ? red[w0 + i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i < nw) s += r[i];
+  }
   return s;
 }
 
