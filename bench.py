@@ -444,7 +444,6 @@ def run_dg(args):
 
     import paper_2207_07234_amd as pk
     import synthetic as syn
-    from oracle import dg as odg   # projection of the initial data onto P2 (input preparation)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     dtype = torch.float32 if args.dtype in (None, "f32") else torch.float64
@@ -453,7 +452,7 @@ def run_dg(args):
     prob = pk.Problem(nx=DG_NX, nt=DG_NT, t_final=T, alpha=0.5, beta=0.0, time="be", space="dg_p2_llf",
                       dtype=dtype)
     solver = pk.Solver(prob)
-    u0 = torch.tensor(odg.p2_project(lambda x: syn.fourier_u0_at(SEED, x), DG_NX), dtype=dtype, device=dev)
+    u0 = torch.tensor(syn.fourier_u0_legendre(SEED, DG_NX), dtype=dtype, device=dev)
     u = torch.empty((DG_NT + 1, 3, DG_NX), dtype=dtype, device=dev)
     phi = torch.empty((DG_NT, 3, DG_NX), dtype=dtype, device=dev)
     ws = torch.empty(solver.workspace_bytes, dtype=torch.uint8, device=dev)

@@ -25,6 +25,7 @@ __all__ = [
     "fourier_coeffs",
     "fourier_u0",
     "fourier_u0_at",
+    "fourier_u0_legendre",
     "sine_u0",
     "gaussian_bump_u0",
     "heat_gamma_at",
@@ -55,6 +56,49 @@ def fourier_u0(seed: int, nx: int, length: float = 1.0) -> np.ndarray:
     """Seeded Fourier-sum initial data at the nodes x_j = j*length/nx."""
     x = np.arange(nx, dtype=np.float64) * (length / nx)
     return fourier_u0_at(seed, x, length)
+
+
+def _sph_bessel_012(t: np.ndarray):
+    """Spherical Bessel functions j_0, j_1, j_2 at t >= 0: the power series for t < 0.5
+    (no cancellation), the trigonometric forms above."""
+    t = np.asarray(t, dtype=np.float64)
+    js = []
+    for n in range(3):
+        # series: sum_m (-1)^m t^(2m+n) / (2^m m! (2m+2n+1)!!)
+        ser = np.zeros_like(t)
+        df = 1.0
+        for i in range(1, 2 * n + 2, 2):
+            df *= i                      # (2n+1)!!
+        term = t ** n / df
+        for m in range(12):
+            ser = ser + term
+            term = -term * t * t / (2.0 * (m + 1) * (2 * m + 2 * n + 3))
+        js.append(ser)
+    big = t >= 0.5
+    tb = np.where(big, t, 1.0)
+    s, c = np.sin(tb), np.cos(tb)
+    closed = [s / tb, s / tb ** 2 - c / tb, (3.0 / tb ** 2 - 1.0) * s / tb - 3.0 * c / tb ** 2]
+    return [np.where(big, closed[n], js[n]) for n in range(3)]
+
+
+def fourier_u0_legendre(seed: int, nx: int, length: float = 1.0) -> np.ndarray:
+    """Cell-wise L2 projection of the seeded Fourier sum onto the Legendre basis P_0, P_1, P_2
+    (cells [j h, (j+1) h], local coordinate xi in [-1, 1]), in closed form: for a mode
+    sin(w x + th) on a cell with centre x_c and t = w h / 2, the coefficient of P_n is
+    (2n+1) Im(i^n e^{i(w x_c + th)}) j_n(t).  Returns (3, nx): coefficient-planar."""
+    a, th = fourier_coeffs(seed)
+    h = length / nx
+    xc = (np.arange(nx, dtype=np.float64) + 0.5) * h
+    out = np.zeros((3, nx))
+    out[0] += 0.5
+    for k in range(4):
+        w = 2.0 * np.pi * (k + 1) / length
+        phi = w * xc + th[k]
+        j0, j1, j2 = _sph_bessel_012(np.array(w * h / 2.0))
+        out[0] += a[k] * np.sin(phi) * j0
+        out[1] += a[k] * 3.0 * np.cos(phi) * j1
+        out[2] += a[k] * -5.0 * np.sin(phi) * j2
+    return out
 
 
 def sine_u0(nx: int, length: float = 1.0) -> np.ndarray:

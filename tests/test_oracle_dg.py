@@ -173,3 +173,12 @@ def test_pdhg_limit_is_the_newton_march():
     res = opdhg.run(prob, u0, tu, tp, eps=1e-10, max_iter=20000)
     assert res.converged
     np.testing.assert_allclose(res.u, onewton.march(prob, u0), atol=1e-9)
+
+
+@pytest.mark.parametrize("nx", [16, 256, 4096])
+def test_projection_of_the_seeded_fourier_sum_matches_its_closed_form(nx):
+    """The quadrature projection against the exact Legendre coefficients of each sine mode
+    (spherical Bessel functions), which the benchmark uses as its DG initial data."""
+    a = dg.p2_project(lambda x: syn.fourier_u0_at(3, x), nx)
+    b = syn.fourier_u0_legendre(3, nx)
+    assert np.max(np.abs(a - b)) < 1e-13
