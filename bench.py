@@ -14,6 +14,7 @@ bounded sample of iterations of the same workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload batch [--batch-iters N] [--ttr-problems M]
     python bench.py --workload dg [--dg-iters N] [--dtype f32|f64]
+    python bench.py --workload adjoint [--dtype f32|f64]
 
 The single workload also reports the paper's three variants side by side
 (Section 4, comparison of the variants): Algorithm 1, mesh refinement in time
@@ -505,6 +506,72 @@ def run_dg(args):
     print(json.dumps(out), flush=True)
 
 
+def run_adjoint(args):
+    """Differentiable workload: viscous Burgers (gamma = 1e-3), 2048 x 512, T = 0.5, backward Euler,
+    Lax-Friedrichs flux with centred diffusion, loss h_x ||u^{N_t} - target||^2 with the target from
+    seed + 1.  The forward solve (FP32: a fixed budget of 15000 iterations, which reaches its rounding
+    floor; FP64: residual 1e-8), then the adjoint march for d loss / d u0, timed with HIP events."""
+    import torch
+
+    import paper_2207_07234_amd as pk
+    import synthetic as syn
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dtype = torch.float32 if args.dtype in (None, "f32") else torch.float64
+    esz = 4 if dtype == torch.float32 else 8
+    nx, nt = NX, NT
+    prob = pk.Problem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, gamma=1e-3, time="be", space="fd_lf",
+                      dtype=dtype, precond_gamma_hat=1e-3)
+    solver = pk.Solver(prob)
+    u0 = torch.tensor(syn.fourier_u0(SEED, nx), dtype=dtype, device=dev)
+    tgt = torch.tensor(syn.fourier_u0(SEED + 1, nx), dtype=dtype, device=dev)
+    eps, max_iter = (1e-8, 200000) if esz == 8 else (0.0, 15000)
+    first = solver.solve(u0, eps=eps, max_iter=max_iter, check_every=128)
+    tau = first.stats["tau_u"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = solver.solve(u0, tau_u=tau, tau_phi=tau, eps=eps, max_iter=max_iter, check_every=128)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / args.steps
+    n = r.stats["iters"]
+    log(f"forward: status {r.status}, {n} iterations, {fwd:.3f} s, Rp {r.stats['res_primal']:.3e} "
+        f"Rd {r.stats['res_dual']:.3e}")
+    g = torch.zeros((nt + 1, nx), dtype=dtype, device=dev)
+    g[-1] = (2.0 / nx) * (r.u[-1] - tgt)
+    grad = solver.adjoint_solve(r.u, g)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        grad = solver.adjoint_solve(r.u, g)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / reps
+    adj_bytes = (2 * (nt + 1) * nx + nx) * esz
+    adj_gbs = adj_bytes / (adj_ms * 1e-3) / 1e9
+    log(f"adjoint march: {adj_ms * 1e3:.1f} us ({adj_ms * 1e3 / nt:.2f} us per level), {adj_gbs:.1f} GB/s; "
+        f"|grad|max {float(grad.abs().max()):.3e}")
+    out = {
+        "metric": METRIC, "value": nx * nt * n / fwd, "unit": "DOF-iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": (fwd + adj_ms * 1e-3) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if esz == 4 else "f64", "data": "synthetic",
+        "config": {"workload": f"differentiable viscous Burgers (gamma 1e-3), FD Lax-Friedrichs + centred "
+                               f"diffusion, backward Euler, {nx}x{nt}, T={T_FINAL}, loss h_x|u(T)-target|^2, "
+                               f"seeds {SEED}/{SEED + 1}",
+                   "forward_iterations": n, "forward_s": fwd, "forward_status": r.status,
+                   "res_primal": r.stats["res_primal"], "res_dual": r.stats["res_dual"], "eps": eps,
+                   "adjoint_ms": adj_ms, "adjoint_us_per_level": adj_ms * 1e3 / nt,
+                   "backward_share": adj_ms * 1e-3 / (fwd + adj_ms * 1e-3)},
+        "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "adjoint march (N_t sequential periodic tridiagonal solves in one workgroup)",
+                     "bytes_per_launch": adj_bytes, "ms_per_launch": adj_ms},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,7 +585,7 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None,
                     help="compute type (default f64 for the single workload, f32 for the batch)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto (fused), 1 unfused, 2 fused")
-    ap.add_argument("--workload", choices=["burgers", "batch", "dg"], default="burgers")
+    ap.add_argument("--workload", choices=["burgers", "batch", "dg", "adjoint"], default="burgers")
     ap.add_argument("--dg-iters", type=int, default=DG_ITERS)
     ap.add_argument("--dg-cpu-iters", type=int, default=2)
     ap.add_argument("--dg-eps", type=float, default=0.0,
@@ -534,6 +601,8 @@ def main():
     if args.workload == "batch":
         run_batch(args)
         return
+    if args.workload == "adjoint":
+        return run_adjoint(args)
     if args.workload == "dg":
         run_dg(args)
         return
