@@ -133,7 +133,7 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
 
 // ------------------------------------------------------------------ C
 template <typename T>
-__global__ void __launch_bounds__(64 * kFdColWaves)
+__global__ void __launch_bounds__(kColHalfThreads)
 kb_colsolve(const BatchProb* __restrict__ probs, Ctrl* ctrls, const int2* __restrict__ tiles,
             const int* __restrict__ counts, T* __restrict__ spec, const double* __restrict__ part, int rd_base) {
   extern __shared__ char smem[];
@@ -155,17 +155,20 @@ kb_colsolve(const BatchProb* __restrict__ probs, Ctrl* ctrls, const int2* __rest
     const FacTab<T> fac{static_cast<const FacRow<T>*>(P.fac_rows), P.fac_off, P.fac_last};
     const int nt = P.s.nt, nx = P.s.nx, q0 = td.y * kColCols;
     T* sp = spec + P.f_off;
-    const int lpl = (nt + 63) / 64;
+    // nt <= 512 (checked at set-up): 32 lanes per column, LPL = ceil(nt / 32) <= 16
+    const int lpl = (nt + 31) / 32;
     if (P.s.time == kTimeBDF2) {
-      if (lpl <= 1) colsolve_group<T, 2, 1>(sp, fac, nt, nx, P.lqb, q0, tile);
-      else if (lpl <= 2) colsolve_group<T, 2, 2>(sp, fac, nt, nx, P.lqb, q0, tile);
-      else if (lpl <= 4) colsolve_group<T, 2, 4>(sp, fac, nt, nx, P.lqb, q0, tile);
-      else colsolve_group<T, 2, 8>(sp, fac, nt, nx, P.lqb, q0, tile);
+      if (lpl <= 1) colsolve_group_half<T, 2, 1>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else if (lpl <= 2) colsolve_group_half<T, 2, 2>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else if (lpl <= 4) colsolve_group_half<T, 2, 4>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else if (lpl <= 8) colsolve_group_half<T, 2, 8>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else colsolve_group_half<T, 2, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
     } else {
-      if (lpl <= 1) colsolve_group<T, 1, 1>(sp, fac, nt, nx, P.lqb, q0, tile);
-      else if (lpl <= 2) colsolve_group<T, 1, 2>(sp, fac, nt, nx, P.lqb, q0, tile);
-      else if (lpl <= 4) colsolve_group<T, 1, 4>(sp, fac, nt, nx, P.lqb, q0, tile);
-      else colsolve_group<T, 1, 8>(sp, fac, nt, nx, P.lqb, q0, tile);
+      if (lpl <= 1) colsolve_group_half<T, 1, 1>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else if (lpl <= 2) colsolve_group_half<T, 1, 2>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else if (lpl <= 4) colsolve_group_half<T, 1, 4>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else if (lpl <= 8) colsolve_group_half<T, 1, 8>(sp, fac, nt, nx, P.lqb, q0, tile);
+      else colsolve_group_half<T, 1, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
     }
   }
 }
@@ -341,7 +344,7 @@ template <typename T>
 size_t batch_row_lds(int max_nx) { return row_lds_bytes<T, batch_row_threads<T>()>(max_nx); }
 
 template <typename T>
-size_t batch_col_lds() { return sizeof(T) * (size_t)kColCols * 8 * 65; }
+size_t batch_col_lds() { return sizeof(T) * (size_t)kColCols * 16 * 33; }
 
 template <typename T>
 hipError_t batch_occupancy(int which, int max_nx, int* blocks_per_cu) {
@@ -359,7 +362,7 @@ hipError_t batch_occupancy(int which, int max_nx, int* blocks_per_cu) {
   }
   const size_t lds = batch_col_lds<T>();
   if ((e = allow_lds(kb_colsolve<T>, lds)) != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kb_colsolve<T>, 64 * kFdColWaves, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kb_colsolve<T>, kColHalfThreads, lds);
 }
 
 template <typename T>
@@ -391,7 +394,7 @@ hipError_t launch_batch_colsolve(const BatchLaunch& L, int grid, T* spec, const 
   const size_t lds = batch_col_lds<T>();
   hipError_t e = allow_lds(kb_colsolve<T>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_colsolve<T>, dim3(grid), dim3(64 * kFdColWaves), lds, st, L.probs, L.ctrls, L.col_tiles,
+  hipLaunchKernelGGL(kb_colsolve<T>, dim3(grid), dim3(kColHalfThreads), lds, st, L.probs, L.ctrls, L.col_tiles,
                      L.counts, spec, part, rd_base);
   return hipGetLastError();
 }

@@ -107,6 +107,18 @@ k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ct
   colsolve_group<T, BW, LPL>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile);
 }
 
+// C for N_t <= 512: 4 waves per block, two columns per wave (32 lanes each).
+template <typename T, int BW, int LPL>
+__global__ void __launch_bounds__(kColHalfThreads)
+k_colsolve_half(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                int nparts, double wscale, double* hist) {
+  if (ctrl && ctrl->status != 0) return;
+  if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
+  extern __shared__ char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  colsolve_group_half<T, BW, LPL>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile);
+}
+
 // C (full-symbol preconditioner): per Fourier mode k, K_k = L_k L_k^* with
 // L_k = B_t + g_k I lower triangular (row l: c0(l)/h_t + g_k on the diagonal,
 // c1(l)/h_t and c2(l)/h_t below it), g_k = (wr + vr)(1 - cos theta_k) + i ci sin theta_k
@@ -315,6 +327,18 @@ hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* 
 }
 
 template <typename T, int BW, int LPL>
+static hipError_t launch_colsolve_half_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+                                         const double* part, int nparts, double wscale, double* hist,
+                                         hipStream_t st) {
+  const size_t lds = sizeof(T) * (size_t)kColCols * LPL * 33;
+  hipError_t e = allow_lds(k_colsolve_half<T, BW, LPL>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_colsolve_half<T, BW, LPL>), dim3(nx / kColCols), dim3(kColHalfThreads), lds, st, spec,
+                     fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist);
+  return hipGetLastError();
+}
+
+template <typename T, int BW, int LPL>
 static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                          const double* part, int nparts, double wscale, double* hist,
                                          hipStream_t st) {
@@ -332,6 +356,25 @@ static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, 
 template <typename T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st) {
+  if (nt <= 512) {
+    const int lh = (nt + 31) / 32;
+#define PDHG_CH(B, L) \
+  return launch_colsolve_half_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+    if (bw == 2) {
+      if (lh <= 1) PDHG_CH(2, 1);
+      if (lh <= 2) PDHG_CH(2, 2);
+      if (lh <= 4) PDHG_CH(2, 4);
+      if (lh <= 8) PDHG_CH(2, 8);
+      PDHG_CH(2, 16);
+    } else {
+      if (lh <= 1) PDHG_CH(1, 1);
+      if (lh <= 2) PDHG_CH(1, 2);
+      if (lh <= 4) PDHG_CH(1, 4);
+      if (lh <= 8) PDHG_CH(1, 8);
+      PDHG_CH(1, 16);
+    }
+#undef PDHG_CH
+  }
   const int lpl = (nt + 63) / 64;
 #define PDHG_CW(B, L) \
   return launch_colsolve_wave_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)

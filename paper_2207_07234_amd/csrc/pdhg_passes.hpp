@@ -403,13 +403,57 @@ __device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& i
   }
 }
 
+// The same for two independent 32-lane columns per wavefront (lanes 0..31 and
+// 32..63): the row steps never cross a row, and across rows only row 1 (row 3)
+// composes with the prefix ending in lane 15 (47), forward, or row 0 (row 2)
+// with the suffix starting in lane 16 (48), backward.  The first lane of each
+// column (forward) or its last lane (backward) enters with zero.
+template <typename T>
+__device__ __forceinline__ void scan_cross_half(T* H, T* P, int lane, bool fwd) {
+  const int sa = fwd ? 15 : 16, sb = fwd ? 47 : 48;
+  T Ha[4], Pa[2], Hb[4], Pb[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    Ha[k] = read_lane(H[k], sa);
+    Hb[k] = read_lane(H[k], sb);
+  }
+  Pa[0] = read_lane(P[0], sa);
+  Pa[1] = read_lane(P[1], sa);
+  Pb[0] = read_lane(P[0], sb);
+  Pb[1] = read_lane(P[1], sb);
+  const int row = lane >> 4;
+  if (row == (fwd ? 1 : 0)) compose(H, P, Ha, Pa);
+  if (row == (fwd ? 3 : 2)) compose(H, P, Hb, Pb);
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void scan_incoming_half(T* H, T* P, int lane, T& in2, T& in1) {
+  scan_step_row<T, FWD, 1>(H, P);
+  scan_step_row<T, FWD, 2>(H, P);
+  scan_step_row<T, FWD, 4>(H, P);
+  scan_step_row<T, FWD, 8>(H, P);
+  scan_cross_half(H, P, lane, FWD);
+  const bool edge = FWD ? ((lane & 31) == 0) : ((lane & 31) == 31);
+  if (FWD) {
+    in2 = from_lane_below(P[0], T(0));
+    in1 = from_lane_below(P[1], T(0));
+  } else {
+    in2 = from_lane_above(P[0], T(0));
+    in1 = from_lane_above(P[1], T(0));
+  }
+  if (edge) {
+    in2 = T(0);
+    in1 = T(0);
+  }
+}
+
 // Solve L M y = z in place for NC columns sharing the coefficient rows, L lower
 // triangular (inverse diagonal invd, sub-diagonals e1, e2) and M = the upper
 // triangular with inverse diagonal invb and the transposed sub-diagonals; z[c][i]
 // is level l0 + i of column c.  L L^T (Cholesky factor) is invb = invd.  T is
 // the value type (real, or Cx for complex right-hand sides and diagonals), E
 // the type of the sub-diagonals.
-template <typename T, typename E, int BW, int LPL, int NC>
+template <typename T, typename E, int BW, int LPL, int NC, int CW = 64>
 __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, const T* invb, const E* e1,
                                                const E* e2, int lane, int l0, int nt) {
   // forward: z_l = invd_l (rhs_l - e1_l z_{l-1} - e2_l z_{l-2})
@@ -427,7 +471,8 @@ __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, c
     }
     T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
     T zm2, zm1;
-    scan_incoming<T, true>(H, P, lane, zm2, zm1);
+    if (CW == 64) scan_incoming<T, true>(H, P, lane, zm2, zm1);
+    else scan_incoming_half<T, true>(H, P, lane, zm2, zm1);
 #pragma unroll
     for (int i = 0; i < LPL; ++i) {
       if (l0 + i < nt) {
@@ -454,7 +499,8 @@ __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, c
     }
     T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
     T ym2, ym1;
-    scan_incoming<T, false>(H, P, lane, ym2, ym1);
+    if (CW == 64) scan_incoming<T, false>(H, P, lane, ym2, ym1);
+    else scan_incoming_half<T, false>(H, P, lane, ym2, ym1);
 #pragma unroll
     for (int ii = 0; ii < LPL; ++ii) {
       const int i = LPL - 1 - ii;
@@ -468,11 +514,11 @@ __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, c
   }
 }
 
-// Solve L L^T y = z in place (banded Cholesky factor L).
-template <typename T, int BW, int LPL, int NC>
+// Solve L L^T y = z in place (banded Cholesky factor L); CW lanes per column.
+template <typename T, int BW, int LPL, int NC, int CW = 64>
 __device__ __forceinline__ void cholesky_solve_wave(T (&z)[NC][LPL], const T* invd, const T* e1, const T* e2,
                                                     int lane, int l0, int nt) {
-  tri_solve_wave<T, T, BW, LPL, NC>(z, invd, invd, e1, e2, lane, l0, nt);
+  tri_solve_wave<T, T, BW, LPL, NC, CW>(z, invd, invd, e1, e2, lane, l0, nt);
 }
 
 template <typename T, int LPL>
@@ -555,6 +601,60 @@ __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTa
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int idx = tid + r * kThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    if (l < nt) base[(size_t)l * QB + c] = stage[r];
+  }
+}
+
+// The same for N_t <= 512 by 4 waves of the calling block, two columns per
+// wave and 32 lanes per column (LPL <= 16 levels per lane): a wave's scans run
+// over 32 lanes, and a SIMD holds one wave with two columns instead of two
+// waves with one each, which halves the scan work per column.  tile:
+// kColCols * LPL * 33 elements of LDS.
+constexpr int kColHalfThreads = 256;
+template <typename T, int BW, int LPL>
+__device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx,
+                                                    int lqb, int q0, T* tile) {
+  const int QB = 1 << lqb;
+  T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
+  const int tid = threadIdx.x;
+  constexpr int kPer = 32 * LPL * kColCols / kColHalfThreads;   // tile elements per thread
+  const int wv = tid >> 6, lane = tid & 63;
+  const int col = 2 * wv + (lane >> 5), q = lane & 31;
+  const int kmode = spec_mode(q0 + col, nx);
+  const int l0 = q * LPL;
+  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<T, LPL>(fac, kmode, l0, invd, e1, e2);
+  T stage[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kColHalfThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kColHalfThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    tile[(c * LPL + l % LPL) * 33 + l / LPL] = stage[r];
+  }
+  __syncthreads();
+  T z[1][LPL];
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) z[0][i] = tile[(col * LPL + i) * 33 + q];
+  cholesky_solve_wave<T, BW, LPL, 1, 32>(z, invd, e1, e2, lane, l0, nt);
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) tile[(col * LPL + i) * 33 + q] = z[0][i];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kColHalfThreads;
+    const int l = idx / kColCols, c = idx % kColCols;
+    stage[r] = tile[(c * LPL + l % LPL) * 33 + l / LPL];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kColHalfThreads;
     const int l = idx / kColCols, c = idx % kColCols;
     if (l < nt) base[(size_t)l * QB + c] = stage[r];
   }
