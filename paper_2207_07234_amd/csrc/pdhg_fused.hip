@@ -107,16 +107,18 @@ k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ct
   colsolve_group<T, BW, LPL>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile);
 }
 
-// C for N_t <= 512: 4 waves per block, two columns per wave (32 lanes each).
+// C for N_t <= 512: kColsHalf columns per block, two per wave (32 lanes each).
+constexpr int kColsHalf = 4;
 template <typename T, int BW, int LPL>
-__global__ void __launch_bounds__(kColHalfThreads)
+__global__ void __launch_bounds__(32 * kColsHalf)
 k_colsolve_half(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
                 int nparts, double wscale, double* hist) {
   if (ctrl && ctrl->status != 0) return;
   if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
   extern __shared__ char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  colsolve_group_half<T, BW, LPL>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile);
+  colsolve_group_half<T, BW, LPL, kColsHalf>(spec, fac, nt, nx, lqb,
+                                             xcd_block(blockIdx.x, gridDim.x) * kColsHalf, tile);
 }
 
 // C (full-symbol preconditioner): per Fourier mode k, K_k = L_k L_k^* with
@@ -330,10 +332,10 @@ template <typename T, int BW, int LPL>
 static hipError_t launch_colsolve_half_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                          const double* part, int nparts, double wscale, double* hist,
                                          hipStream_t st) {
-  const size_t lds = sizeof(T) * (size_t)kColCols * LPL * 33;
+  const size_t lds = sizeof(T) * (size_t)kColsHalf * LPL * 33;
   hipError_t e = allow_lds(k_colsolve_half<T, BW, LPL>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_colsolve_half<T, BW, LPL>), dim3(nx / kColCols), dim3(kColHalfThreads), lds, st, spec,
+  hipLaunchKernelGGL((k_colsolve_half<T, BW, LPL>), dim3(nx / kColsHalf), dim3(32 * kColsHalf), lds, st, spec,
                      fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist);
   return hipGetLastError();
 }

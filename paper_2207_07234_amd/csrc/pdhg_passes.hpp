@@ -606,19 +606,21 @@ __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTa
   }
 }
 
-// The same for N_t <= 512 by 4 waves of the calling block, two columns per
-// wave and 32 lanes per column (LPL <= 16 levels per lane): a wave's scans run
-// over 32 lanes, and a SIMD holds one wave with two columns instead of two
-// waves with one each, which halves the scan work per column.  tile:
-// kColCols * LPL * 33 elements of LDS.
+// The same for N_t <= 512 on NCOL columns q0..q0+NCOL-1 (q0 a multiple of
+// NCOL) by NCOL/2 waves of the calling block, two columns per wave and 32
+// lanes per column (LPL <= 16 levels per lane): a wave's scans run over 32
+// lanes, and a SIMD holds one wave with two columns instead of two waves with
+// one each, which halves the scan work per column.  tile: NCOL * LPL * 33
+// elements of LDS.
 constexpr int kColHalfThreads = 256;
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, int NCOL = kColCols>
 __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx,
                                                     int lqb, int q0, T* tile) {
+  constexpr int kThreads = 32 * NCOL;
   const int QB = 1 << lqb;
   T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
   const int tid = threadIdx.x;
-  constexpr int kPer = 32 * LPL * kColCols / kColHalfThreads;   // tile elements per thread
+  constexpr int kPer = LPL;   // tile elements per thread (32 LPL NCOL / kThreads)
   const int wv = tid >> 6, lane = tid & 63;
   const int col = 2 * wv + (lane >> 5), q = lane & 31;
   const int kmode = spec_mode(q0 + col, nx);
@@ -628,14 +630,14 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
   T stage[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * kColHalfThreads;
-    const int l = idx / kColCols, c = idx % kColCols;
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCOL, c = idx % NCOL;
     stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * kColHalfThreads;
-    const int l = idx / kColCols, c = idx % kColCols;
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCOL, c = idx % NCOL;
     tile[(c * LPL + l % LPL) * 33 + l / LPL] = stage[r];
   }
   __syncthreads();
@@ -648,14 +650,14 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * kColHalfThreads;
-    const int l = idx / kColCols, c = idx % kColCols;
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCOL, c = idx % NCOL;
     stage[r] = tile[(c * LPL + l % LPL) * 33 + l / LPL];
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int idx = tid + r * kColHalfThreads;
-    const int l = idx / kColCols, c = idx % kColCols;
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCOL, c = idx % NCOL;
     if (l < nt) base[(size_t)l * QB + c] = stage[r];
   }
 }
