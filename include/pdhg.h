@@ -209,7 +209,13 @@ int pdhg_solve_refined(pdhg_handle* h, const void* u0, void* u, void* phi, void*
  *   stats: iters = sum of the steps' n*, res_primal/res_dual = the largest final
  *   step residuals, variant = 5.  step_iters: nullable HOST [nt] (n* per step);
  *   step_res: nullable HOST [nt][2] (final residuals per step).
- * Finite differences with nx >= 64 only (PDHG_EUNSUPPORTED otherwise).  One
+ * Finite differences with nx >= 64, and the DG P1 nodal upwind scheme with
+ * 64 <= nx <= 4096 cells (PDHG_EUNSUPPORTED otherwise, including DG P2).  For
+ * DG P1 the unknowns are the two nodal planes: u0 [2][nx], u [nt+1][2][nx],
+ * phi [nt][2][nx]; K_l = (c0/h_t)^2 I + c^2 G G^T with G the unit-speed upwind
+ * P1 operator (a 2x2 block per Fourier mode over the cells), the slice norm
+ * sums both planes, nu_max comes from Algorithm 1's power iteration on the
+ * one-level problems, and stats.mass_drift is -1 (not measured).  One
  * workgroup per step: the call is latency-bound by design and leaves the rest
  * of the GPU to other streams.  Synchronous on `stream`. */
 int pdhg_solve_onestep(pdhg_handle* h, const void* u0, void* u, void* phi, const pdhg_params* params,

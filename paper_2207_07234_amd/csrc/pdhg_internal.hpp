@@ -95,10 +95,11 @@ template <typename T>
 struct OneStepProb {
   Scheme s;            // grid, scheme and resolved flux constants
   const C2<T>* tw;     // [nx] twiddles e^{-2 pi i j / nx}
-  const T* sym;        // [2][nx] preconditioner symbol reciprocals (c0 = 1, c0 = 3/2), 1/M folded in
+  const T* sym;        // [2][nx] preconditioner symbol reciprocals (c0 = 1, c0 = 3/2), 1/M folded in;
+                       // DG P1: [2][nx/2 + 1][4] per-mode inverses (onestep_dg1_kinv)
   const T* u0;         // [nx] or null; a march from step 0 reads u0 here and writes it to level 0 of u
   T* u;                // [nt+1][nx]; otherwise the levels before the first step marched are read
-  T* phi;              // [nt][nx]
+  T* phi;              // [nt][nx]  (DG P1: u0 [2][nx], u [nt+1][2][nx], phi [nt][2][nx])
   StepStat* stat;      // [nt]
   int* flag;           // 0 while the march runs, 2 after a step diverged
   double tau_u, tau_phi;
@@ -128,6 +129,17 @@ __host__ __device__ inline int onestep_threads(int nx) {
   const int w = nx / (sizeof(T) == 8 ? 4 : 8);
   return w < 64 ? 64 : (w > 512 ? 512 : w);
 }
+// Threads per problem of the DG P1 one-step march: two cells (four nodal values) per thread.
+__host__ __device__ inline int onestep_threads_dg1(int nx) {
+  const int w = nx / 2;
+  return w < 64 ? 64 : (w > 512 ? 512 : w);
+}
+// DG P1: per-mode inverse of the one-level preconditioner, [2 rows c0 = 1, 3/2][nx/2 + 1][a, Re b, Im b, d]
+template <typename T>
+void onestep_dg1_kinv(const pdhg_problem& p, double c, T* out);
+template <typename T>
+hipError_t launch_onestep_dg1(const OneStepProb<T>* probs, int nprob, int max_nx, int l_begin, int l_end,
+                              double eps, long long max_iter, double dfac, hipStream_t st);
 template <typename T>
 hipError_t launch_onestep_power(OneStepProb<T>* probs, int nprob, int max_nx, int iters, double* nu, hipStream_t st);
 template <typename T>

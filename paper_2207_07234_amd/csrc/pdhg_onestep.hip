@@ -46,6 +46,7 @@
 // one LDS pass over the slice (double-buffered, one barrier).
 #include "pdhg_internal.hpp"
 #include "pdhg_passes.hpp"
+#include "pdhg_dg1.hpp"
 
 namespace pdhg {
 
@@ -495,6 +496,257 @@ hipError_t launch_onestep(const OneStepProb<T>* probs, int nprob, int max_nx, in
   hipLaunchKernelGGL((k_onestep<T>), dim3(nprob), dim3(W), lds, st, probs, l_begin, l_end, eps, max_iter, dfac);
   return hipGetLastError();
 }
+
+// ------------------------------------------------------------------ DG P1
+// The one-level problem on the two nodal planes of the DG P1 scheme.  A step's
+// preconditioner is (c0/h_t)^2 I + c^2 G G^T with G the unit-speed upwind P1
+// operator: per Fourier mode m over the cells a Hermitian 2x2 matrix, whose
+// inverse [a b; conj(b) d] (the inverse FFT's 1/N folded in) the host tables
+// in P.sym as [2 rows c0 = 1, 3/2][N/2 + 1 modes][a, Re b, Im b, d].  The two
+// real planes are one complex row Z = r_1 + i r_2 for the FFT.
+
+// Spectral pair (m, q = N - m mod N): R_1 = (Z_m + conj Z_q)/2 and
+// R_2 = (Z_m - conj Z_q)/(2i) are the planes' spectra at m; S = K^{-1} R, and
+// Y_m = S_1 + i S_2, Y_q = conj(S_1) + i conj(S_2) (the planes are real).
+template <typename T>
+__device__ __forceinline__ void dg1_precond_pair(C2<T>* buf, int m, int q, T a, T br, T bi, T d) {
+  const C2<T> zm = buf[lpad(m)], zq = buf[lpad(q)];
+  const T r0x = T(0.5) * (zm.x + zq.x), r0y = T(0.5) * (zm.y - zq.y);
+  const T r1x = T(0.5) * (zm.y + zq.y), r1y = T(-0.5) * (zm.x - zq.x);
+  const T s0x = a * r0x + br * r1x - bi * r1y, s0y = a * r0y + br * r1y + bi * r1x;   // a R_1 + b R_2
+  const T s1x = br * r0x + bi * r0y + d * r1x, s1y = br * r0y - bi * r0x + d * r1y;   // conj(b) R_1 + d R_2
+  buf[lpad(m)] = C2<T>{s0x - s1y, s0y + s1x};
+  if (q != m) buf[lpad(q)] = C2<T>{s0x + s1y, s1x - s0y};
+}
+
+// Steps [l_begin, l_end) of a DG P1 problem; cell x = seg + lane + 64 e, both planes per thread.
+template <typename T, int EPT>
+__device__ __forceinline__ void onestep_march_dg1(const OneStepProb<T>& P, int W, int l_begin, int l_end,
+                                                  double eps, long long max_iter, double dfac, C2<T>* buf,
+                                                  C2<T>* twl, T (*ends)[2 * kOneStepWavesMax],
+                                                  double (*red)[kOneStepWavesMax]) {
+  const Scheme& sch = P.s;
+  const Consts<T> C(sch);
+  const int nx = sch.nx, tid = threadIdx.x, half = nx >> 1;
+  const bool act = tid < W;
+  const int nw = W >> 6, wv = tid >> 6, lane = tid & 63;
+  const int seg = wv * 64 * EPT;
+  const T tau_u = (T)P.tau_u, tau_phi = (T)P.tau_phi;
+  const size_t L2 = 2 * (size_t)nx;   // one level: two planes
+  for (int i = tid; i < nx; i += blockDim.x) twl[lpad(i)] = P.tw[i];
+  constexpr int KP = EPT / 2 + 1;     // modes m = tid + j W <= N/2
+  T cur[2][EPT], known[2][EPT];
+  {
+    const T c1 = C.c1(l_begin), c2 = C.c2(l_begin);
+    const bool from_u0 = l_begin == 0 && P.u0 != nullptr;
+    const T* ul = from_u0 ? P.u0 : P.u + (size_t)l_begin * L2;
+    const T* ulm = ul - (l_begin >= 1 ? L2 : 0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int x = seg + lane + 64 * e;
+        cur[k][e] = act ? ul[(size_t)k * nx + x] : T(0);
+        known[k][e] = act ? (c1 * cur[k][e] + c2 * ulm[(size_t)k * nx + x]) * C.inv_ht : T(0);
+        if (act && from_u0) P.u[(size_t)k * nx + x] = cur[k][e];
+      }
+  }
+  const double hx = sch.hx;
+  for (int l = l_begin; l < l_end; ++l) {
+    const T c0 = C.c0(l);
+    const T a0 = c0 * C.inv_ht;
+    const T* kt = P.sym + (size_t)(c0 != T(1) ? 1 : 0) * (half + 1) * 4;
+    T ka[KP], kbr[KP], kbi[KP], kd[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const int m = tid + j * W;
+      const bool ok = act && m <= half;
+      ka[j] = ok ? kt[4 * m] : T(0);
+      kbr[j] = ok ? kt[4 * m + 1] : T(0);
+      kbi[j] = ok ? kt[4 * m + 2] : T(0);
+      kd[j] = ok ? kt[4 * m + 3] : T(0);
+    }
+    // initial guess v = u^l, phi = phibar = 0
+    T v[2][EPT], ph[2][2][EPT], g[2][EPT];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        v[k][e] = cur[k][e];
+        ph[0][k][e] = ph[1][k][e] = g[k][e] = T(0);
+      }
+    double rp = 0.0, rd = 0.0, best = INFINITY;
+    long long n = 0;
+    int status = 1;
+    while (n < max_iter) {
+      ++n;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) v[k][e] -= tau_u * g[k][e];
+      // implicit residual A_l(v): the upwind flux of cell x needs the right trace of cell x - 1
+      T tr[1][EPT], trm[1][EPT], trp[1][EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const T vc[2] = {v[0][e], v[1][e]};
+        tr[0][e] = P1Cell<T>::trace(vc);
+      }
+      slice_neighbours<T, EPT, 1>(tr, trm, trp, ends, act, wv, nw, lane);
+      double srp = 0.0;
+      T r[2][EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const T vc[2] = {v[0][e], v[1][e]};
+        T F[2];
+        dg1_spatial(C, vc, trm[0][e], F);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          r[k][e] = a0 * v[k][e] + known[k][e] + F[k];
+          if (act) srp += (double)r[k][e] * (double)r[k][e];
+        }
+      }
+      // s = K_l^{-1} r over both planes
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) buf[lpad(seg + lane + 64 * e)] = C2<T>{r[0][e], r[1][e]};
+      }
+      fft_lds<false, EPT>(buf, nx, twl, tid, W);
+      if (act) {
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          const int m = tid + j * W;
+          if (m <= half) dg1_precond_pair(buf, m, (nx - m) & (nx - 1), ka[j], kbr[j], kbi[j], kd[j]);
+        }
+      }
+      fft_lds<true, EPT>(buf, nx, twl, tid, W);
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const C2<T> y = buf[lpad(seg + lane + 64 * e)];
+          r[0][e] = y.x;
+          r[1][e] = y.y;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          ph[1][k][e] = ph[0][k][e] + T(2) * tau_phi * r[k][e];
+          ph[0][k][e] = ph[0][k][e] + tau_phi * r[k][e];
+        }
+      // J_l(v)^T phi (dual residual) and J_l(v)^T phibar (next primal step): psi of cell x + 1
+      T pr[4][EPT], pl4[4][EPT], pn4[4][EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        pr[0][e] = ph[0][0][e];
+        pr[1][e] = ph[0][1][e];
+        pr[2][e] = ph[1][0][e];
+        pr[3][e] = ph[1][1][e];
+      }
+      slice_neighbours<T, EPT, 4>(pr, pl4, pn4, ends + 1, act, wv, nw, lane);
+      double srd = 0.0;
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const T vc[2] = {v[0][e], v[1][e]};
+          T o[2];
+          const T p0[2] = {pr[0][e], pr[1][e]}, pn[2] = {pn4[0][e], pn4[1][e]};
+          dg1_jt_cell(C, vc, p0, pn, o);
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const T hk = a0 * ph[0][k][e] + o[k];
+            srd += (double)hk * (double)hk;
+          }
+          const T q0[2] = {pr[2][e], pr[3][e]}, qn[2] = {pn4[2][e], pn4[3][e]};
+          dg1_jt_cell(C, vc, q0, qn, o);
+#pragma unroll
+          for (int k = 0; k < 2; ++k) g[k][e] = a0 * ph[1][k][e] + o[k];
+        }
+      }
+      block_sum2(srp, srd, act, wv, nw, lane, red);
+      rp = sqrt(hx * srp);
+      rd = sqrt(hx * srd);
+      const double mm = fmax(rp, rd);
+      if (!(isfinite(rp) && isfinite(rd)) || (mm > dfac * best)) {
+        status = 2;
+        break;
+      }
+      best = fmin(best, mm);
+      if (mm <= eps) {
+        status = 0;
+        break;
+      }
+    }
+    if (act) {
+      T* un = P.u + (size_t)(l + 1) * L2;
+      T* pl = P.phi + (size_t)l * L2;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int x = seg + lane + 64 * e;
+          un[(size_t)k * nx + x] = v[k][e];
+          pl[(size_t)k * nx + x] = ph[0][k][e];
+        }
+    }
+    if (tid == 0) {
+      P.stat[l].iters = n;
+      P.stat[l].rp = rp;
+      P.stat[l].rd = rd;
+      P.stat[l].status = status;
+      if (status == 2) *P.flag = 2;
+    }
+    if (status == 2) return;
+    const T c1n = C.c1(l + 1), c2n = C.c2(l + 1);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        known[k][e] = (c1n * v[k][e] + c2n * cur[k][e]) * C.inv_ht;
+        cur[k][e] = v[k][e];
+      }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kOneStepThreadsMax)
+k_onestep_dg1(const OneStepProb<T>* __restrict__ probs, int l_begin, int l_end, double eps, long long max_iter,
+              double dfac) {
+  const OneStepProb<T> P = probs[blockIdx.x];
+  if (*P.flag != 0) return;
+  const int le = l_end < P.s.nt ? l_end : P.s.nt;
+  if (l_begin >= le) return;
+  extern __shared__ char smem[];
+  __shared__ T ends[5][2 * kOneStepWavesMax];
+  __shared__ double red[2][kOneStepWavesMax];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* twl = buf + lds_fft_points(P.s.nx);
+  const int W = onestep_threads_dg1(P.s.nx);
+  switch (P.s.nx / W) {
+    case 8: onestep_march_dg1<T, 8>(P, W, l_begin, le, eps, max_iter, dfac, buf, twl, ends, red); break;
+    case 4: onestep_march_dg1<T, 4>(P, W, l_begin, le, eps, max_iter, dfac, buf, twl, ends, red); break;
+    case 2: onestep_march_dg1<T, 2>(P, W, l_begin, le, eps, max_iter, dfac, buf, twl, ends, red); break;
+    default: onestep_march_dg1<T, 1>(P, W, l_begin, le, eps, max_iter, dfac, buf, twl, ends, red); break;
+  }
+}
+
+template <typename T>
+hipError_t launch_onestep_dg1(const OneStepProb<T>* probs, int nprob, int max_nx, int l_begin, int l_end,
+                              double eps, long long max_iter, double dfac, hipStream_t st) {
+  if (max_nx < 64 || max_nx > 4096 || (max_nx & (max_nx - 1)) || nprob < 1) return hipErrorInvalidValue;
+  const int W = onestep_threads_dg1(max_nx);
+  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(max_nx);
+  hipError_t e = allow_lds(k_onestep_dg1<T>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_onestep_dg1<T>), dim3(nprob), dim3(W), lds, st, probs, l_begin, l_end, eps, max_iter,
+                     dfac);
+  return hipGetLastError();
+}
+
+template hipError_t launch_onestep_dg1<float>(const OneStepProb<float>*, int, int, int, int, double, long long,
+                                              double, hipStream_t);
+template hipError_t launch_onestep_dg1<double>(const OneStepProb<double>*, int, int, int, int, double, long long,
+                                               double, hipStream_t);
 
 template hipError_t launch_onestep<float>(const OneStepProb<float>*, int, int, int, int, double, long long, double,
                                           hipStream_t);

@@ -162,6 +162,57 @@ bool onestep_pcr(const pdhg_problem& p, double c, double tol, double* out, int* 
 template void onestep_symbol<float>(const pdhg_problem&, double, double, float*);
 template void onestep_symbol<double>(const pdhg_problem&, double, double, double*);
 
+// DG P1 one-step preconditioner per Fourier mode m = 0..nx/2 over the cells, rows
+// c0 = 1 (r = 0) and c0 = 3/2 (r = 1): K = (c0/h_t)^2 I + c^2 G G^*, with
+// G(theta) = G_0 + G_-1 e^{-i theta} the unit-speed upwind P1 operator
+// (G_0 = [7 3; -11 9] / (4 h_x), G_-1 = [5 -15; -1 3] / (4 h_x)); its Hermitian
+// inverse [a b; conj(b) d] divided by nx (the inverse FFT's normalisation) as
+// (a, Re b, Im b, d).  Computed in long double.
+template <typename T>
+void onestep_dg1_kinv(const pdhg_problem& p, double c, T* out) {
+  typedef long double LD;
+  const LD PI = 3.141592653589793238462643383279502884L;
+  const int nx = p.nx, nm = nx / 2 + 1;
+  const LD ht = (LD)p.t_final / p.nt, hx = (LD)p.length / nx, cc = c;
+  const LD g0[2][2] = {{1.75L, 0.75L}, {-2.75L, 2.25L}}, gm[2][2] = {{1.25L, -3.75L}, {-0.25L, 0.75L}};
+  for (int r = 0; r < 2; ++r) {
+    const LD a0 = (r ? 1.5L : 1.0L) / ht;
+    for (int m = 0; m < nm; ++m) {
+      const LD th = 2.0L * PI * m / nx;
+      const LD cr = (m == 0) ? 1.0L : (2 * m == nx ? -1.0L : cosl(th));
+      const LD ci = (m == 0 || 2 * m == nx) ? 0.0L : -sinl(th);
+      LD Gr[2][2], Gi[2][2];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          Gr[i][j] = (g0[i][j] + gm[i][j] * cr) / hx;
+          Gi[i][j] = gm[i][j] * ci / hx;
+        }
+      // H = G G^*: H_ij = sum_k G_ik conj(G_jk)
+      LD hr[2][2], hi[2][2];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          hr[i][j] = 0.0L;
+          hi[i][j] = 0.0L;
+          for (int k = 0; k < 2; ++k) {
+            hr[i][j] += Gr[i][k] * Gr[j][k] + Gi[i][k] * Gi[j][k];
+            hi[i][j] += Gi[i][k] * Gr[j][k] - Gr[i][k] * Gi[j][k];
+          }
+        }
+      const LD ka = a0 * a0 + cc * cc * hr[0][0], kd = a0 * a0 + cc * cc * hr[1][1];
+      const LD kbr = cc * cc * hr[0][1], kbi = cc * cc * hi[0][1];
+      const LD det = ka * kd - (kbr * kbr + kbi * kbi);
+      T* o = out + ((size_t)r * nm + m) * 4;
+      o[0] = (T)(kd / (det * nx));
+      o[1] = (T)(-kbr / (det * nx));
+      o[2] = (T)(-kbi / (det * nx));
+      o[3] = (T)(ka / (det * nx));
+    }
+  }
+}
+
+template void onestep_dg1_kinv<float>(const pdhg_problem&, double, float*);
+template void onestep_dg1_kinv<double>(const pdhg_problem&, double, double*);
+
 // Totals of a one-step march from its per-step records; the march stops after a diverged step.
 OneStepSummary summarize_steps(const StepStat* rec, int nt, int64_t* step_iters, double* step_res) {
   OneStepSummary sm{0, 0.0, 0.0, PDHG_OK, nt};
@@ -256,6 +307,9 @@ struct pdhg_handle {
   void* os_buf = nullptr;
   size_t os_buf_bytes = 0;
   double os_c = -1.0;
+  // DG P1 one-step: one-level plans (c0 = 1, 3/2) for the step-size power iteration, and their (u, phi)
+  pdhg_handle* os_sub[2] = {nullptr, nullptr};
+  void* os_sub_buf = nullptr;
   std::string err;
 };
 
@@ -708,6 +762,8 @@ void pdhg_destroy(pdhg_handle* h) {
   for (auto& kv : h->refine_sub) pdhg_destroy(kv.second);
   if (h->refine_buf) hipFree(h->refine_buf);
   if (h->os_buf) hipFree(h->os_buf);
+  for (int i = 0; i < 2; ++i) pdhg_destroy(h->os_sub[i]);
+  if (h->os_sub_buf) hipFree(h->os_sub_buf);
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
   if (h->d_tw) hipFree(h->d_tw);
@@ -1062,6 +1118,121 @@ int solve_refined_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, cons
   return rc;
 }
 
+// Algorithm 3 on the DG P1 scheme: the same march on the two nodal planes
+// (k_onestep_dg1).  Default step sizes: sqrt(0.95 / nu_max) with nu_max from the
+// power iteration of Algorithm 1 on the one-level problems (backward Euler,
+// N_t = 1, time step h_t / c0 for c0 = 1 and, with BDF2, 3/2), whose K_d is the
+// step preconditioner.
+template <typename T>
+int onestep_dg1_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* prm, pdhg_stats* stats,
+                     int64_t* step_iters, double* step_res, hipStream_t st) {
+  const pdhg_problem& P = h->prob;
+  const int nx = P.nx, nt = P.nt, nm = nx / 2 + 1;
+  if (nx < 64 || nx > 4096) return PDHG_EUNSUPPORTED;
+  const size_t row = 2 * (size_t)nx;
+  const size_t b_sym = align_up((size_t)2 * nm * 4 * sizeof(T));
+  const size_t b_stat = align_up((size_t)nt * sizeof(StepStat));
+  const size_t b_flag = align_up(sizeof(int));
+  const size_t b_part = align_up(sizeof(double) * std::max<size_t>(64, (size_t)nt + 1));
+  const size_t need = b_sym + b_stat + b_flag + b_part + align_up(sizeof(OneStepProb<T>));
+  if (h->os_buf_bytes < need) {
+    if (h->os_buf) hipFree(h->os_buf);
+    h->os_buf = nullptr;
+    h->os_buf_bytes = 0;
+    h->os_c = -1.0;
+    HIP_TRY(hipMalloc(&h->os_buf, need));
+    h->os_buf_bytes = need;
+  }
+  char* b = static_cast<char*>(h->os_buf);
+  T* sym = (T*)b;
+  StepStat* stat = (StepStat*)(b + b_sym);
+  int* flag = (int*)(b + b_sym + b_stat);
+  double* part = (double*)(b + b_sym + b_stat + b_flag);
+  OneStepProb<T>* tab = (OneStepProb<T>*)(b + b_sym + b_stat + b_flag + b_part);
+  int rc = resolve_constants_p<T>(h, u0, part, st, false);
+  if (rc) return rc;
+  if (h->os_c != h->c) {
+    std::vector<T> hs((size_t)2 * nm * 4);
+    onestep_dg1_kinv<T>(P, h->c, hs.data());
+    HIP_TRY(hipMemcpyAsync(sym, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    h->os_c = h->c;
+  }
+  double tau_u = prm->tau_u, tau_phi = prm->tau_phi, nu = 0.0;
+  const bool auto_tau = !(tau_u > 0.0 && tau_phi > 0.0);
+  if (auto_tau) {
+    if (!h->os_sub_buf)
+      HIP_TRY(hipMalloc(&h->os_sub_buf, 3 * row * sizeof(T)));   // u [2][2][nx], phi [1][2][nx]
+    T* su = (T*)h->os_sub_buf;
+    T* sp = su + 2 * row;
+    const int nrow = (P.time == PDHG_BDF2 && nt > 1) ? 2 : 1;
+    for (int r = 0; r < nrow; ++r) {
+      if (!h->os_sub[r]) {
+        pdhg_problem q = P;
+        q.nt = 1;
+        q.time = PDHG_BE;
+        q.t_final = (P.t_final / nt) / (r ? 1.5 : 1.0);
+        q.precond_c = h->c;
+        q.lf_speed = h->lf;
+        rc = pdhg_setup(&q, &h->os_sub[r]);
+        if (rc) return rc;
+      }
+      pdhg_params pp{};
+      pp.tau_u = pp.tau_phi = 0.0;
+      pp.eps = 0.0;
+      pp.max_iter = 2;
+      pp.check_every = 2;
+      pdhg_stats ss{};
+      rc = pdhg_solve(h->os_sub[r], u0, su, sp, nullptr, &pp, &ss, (pdhg_stream_t)st);
+      if (rc < 0) {
+        h->err = std::string("one-level step-size plan: ") + pdhg_last_error(h->os_sub[r]);
+        return rc;
+      }
+      nu = std::max(nu, ss.nu_max);
+    }
+    if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
+    tau_u = tau_phi = std::sqrt(0.95 / nu);
+  }
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(stat, 0, (size_t)nt * sizeof(StepStat), st));
+  OneStepProb<T> tp{};
+  tp.s = scheme_of(h);
+  tp.tw = (const C2<T>*)h->d_tw;
+  tp.sym = sym;
+  tp.u0 = u0;
+  tp.u = u;
+  tp.phi = phi;
+  tp.stat = stat;
+  tp.flag = flag;
+  tp.tau_u = tau_u;
+  tp.tau_phi = tau_phi;
+  tp.pcr = nullptr;
+  HIP_TRY(hipMemcpyAsync(tab, &tp, sizeof(tp), hipMemcpyHostToDevice, st));
+  const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
+  auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(launch_onestep_dg1<T>(tab, 1, nx, 0, nt, prm->eps, (long long)prm->max_iter, div, st));
+  std::vector<StepStat> rec(nt);
+  HIP_TRY(hipMemcpyAsync(rec.data(), stat, (size_t)nt * sizeof(StepStat), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  OneStepSummary sm = summarize_steps(rec.data(), nt, step_iters, step_res);
+  if (stats) {
+    stats->iters = sm.total;
+    stats->res_primal = sm.rp;
+    stats->res_dual = sm.rd;
+    stats->tau_u = tau_u;
+    stats->tau_phi = tau_phi;
+    stats->nu_max = nu;
+    stats->lf_speed = h->lf;
+    stats->precond_c = h->c;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->mass_drift = -1.0;
+    stats->status = sm.status;
+    stats->variant = 5;
+  }
+  return sm.status;
+}
+
 // Algorithm 3 (Section 3.5): one launch of k_onestep marches every step (one
 // workgroup; u^l stays in registers between steps).  A diverged step stops
 // the march and sets the problem's device flag.
@@ -1069,6 +1240,7 @@ template <typename T>
 int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* prm, pdhg_stats* stats,
                  int64_t* step_iters, double* step_res, hipStream_t st) {
   const pdhg_problem& P = h->prob;
+  if (P.space == PDHG_DG_P1_UPWIND) return onestep_dg1_impl<T>(h, u0, u, phi, prm, stats, step_iters, step_res, st);
   if (is_dg(P) || P.nx < 64) return PDHG_EUNSUPPORTED;
   const int nx = P.nx, nt = P.nt;
   // sym [2][nx], pcr [2][16] | stat [nt] | flag | part (max |f'|, nu, level sums) | problem table
