@@ -246,21 +246,28 @@ def large_single_sweep(pk):
 
 def traffic_table3(pk):
     """The traffic example of Section 4.3 (f(u) = u - u^2 on [0, 2), piecewise-constant density, 256 x 32,
-    T = 1, upwind, tau = 0.4, c = 1, tolerance 1e-3) through the three variants, in the columns of Table 3:
-    iterations, world time (iterations in sequence) and work in units of N_x (iterations x levels)."""
+    T = 1, upwind finite differences (BE, BDF2) and the DG P1 nodal upwind scheme (BE), tau = 0.4, c = 1,
+    tolerance 1e-3) through the three variants, in the columns of Table 3: iterations, world time
+    (iterations in sequence) and work in units of N_x (iterations x levels)."""
+    import numpy as np
     import torch
     import synthetic as syn
     u0 = torch.tensor(syn.traffic_u0(256, 2.0), dtype=torch.float64, device="cuda")
     out = {}
-    for tm in ("be", "bdf2"):
+    # DG P1 nodes x_c -/+ h/4 of the cells [2j/N, 2(j+1)/N)
+    xn = (np.arange(256) + 0.5) * (2.0 / 256)
+    u0_dg = torch.tensor(np.stack([syn.traffic_u0_at(xn - 0.5 / 256), syn.traffic_u0_at(xn + 0.5 / 256)]),
+                         dtype=torch.float64, device="cuda")
+    for key, space, tm in (("be", "fd_upwind", "be"), ("bdf2", "fd_upwind", "bdf2"), ("dg_p1_be", "dg_p1_upwind", "be")):
         s = pk.Solver(pk.Problem(nx=256, nt=32, length=2.0, t_final=1.0, alpha=-1.0, beta=1.0, time=tm,
-                                 space="fd_upwind", precond_c=1.0))
+                                 space=space, precond_c=1.0))
+        x0 = u0_dg if space == "dg_p1_upwind" else u0
         kw = dict(tau_u=0.4, tau_phi=0.4, eps=1e-3, max_iter=20000)
-        v = s.solve(u0, check_every=64, **kw)
-        rf = s.solve_refined(u0, nt_start=8, coarse_max_iter=1000, coarse_eps=1e-300, check_every=64, **kw)
-        os_ = s.solve_onestep(u0, **kw)
+        v = s.solve(x0, check_every=64, **kw)
+        rf = s.solve_refined(x0, nt_start=8, coarse_max_iter=1000, coarse_eps=1e-300, check_every=64, **kw)
+        os_ = s.solve_onestep(x0, **kw)
         lv = rf.stats["level_iters"]
-        out[tm] = {
+        out[key] = {
             "vanilla": {"iterations": v.stats["iters"], "world_time": v.stats["iters"],
                         "work_N": v.stats["iters"] * 33, "status": v.status},
             "mesh_refinement": {"iterations": lv, "world_time": sum(lv),
@@ -268,7 +275,7 @@ def traffic_table3(pk):
             "one_step": {"iterations": os_.stats["iters"], "world_time": os_.stats["iters"],
                          "work_N": 2 * os_.stats["iters"], "status": os_.status},
         }
-        log(f"traffic example ({tm}): vanilla {v.stats['iters']}, refinement {lv}, "
+        log(f"traffic example ({key}): vanilla {v.stats['iters']}, refinement {lv}, "
             f"one-step {os_.stats['iters']} iterations")
     out["paper"] = {"vanilla": [4573, 4573, 150909], "mesh_refinement": [[1000, 1000, 3601], 5601, 144833],
                     "one_step": [8627, 8627, 17254]}
