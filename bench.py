@@ -216,12 +216,14 @@ def run_batch(args):
 
 def large_single_sweep(pk):
     """Per-kernel device time of the fused passes on single problems large enough to fill the GPU many
-    times over (N_t = 2048, the column solve's limit: 1024 row-pair blocks, four per CU), against the
-    HBM roofline; at 4096 x 2048 the working set (five arrays of N_x N_t values) exceeds the MALL."""
+    times over (N_t = 2048: 1024 row-pair blocks, four per CU; N_t = 8192, the column solve's limit, with
+    each spectrum column spread over 8 wavefronts), against the HBM roofline; from 4096 x 2048 on, the
+    working set (five arrays of N_x N_t values) exceeds the MALL."""
     import torch
     import synthetic as syn
     out = []
-    for nx, nt, dt in ((2048, 2048, torch.float64), (4096, 2048, torch.float64), (4096, 2048, torch.float32)):
+    for nx, nt, dt in ((2048, 2048, torch.float64), (4096, 2048, torch.float64), (4096, 2048, torch.float32),
+                       (2048, 8192, torch.float64), (4096, 8192, torch.float32)):
         esz = 8 if dt == torch.float64 else 4
         prob = pk.Problem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf", dtype=dt)
         s = pk.Solver(prob)

@@ -24,7 +24,7 @@
  *     phi [nt][nx]     one dual row per implicit equation l = 0..nt-1
  *     r   [nt][nx]     implicit residual rows A(u)^l
  *     g   [nt][nx]     J(u)^T phi, row m-1 belongs to unknown level m = 1..nt
- * - nx must be a power of two, 8 <= nx <= 4096; 1 <= nt <= 2048.
+ * - nx must be a power of two, 8 <= nx <= 4096; 1 <= nt <= 8192.
  * - Calls are asynchronous on the given stream unless stated otherwise.  One
  *   handle must not be used from two streams at the same time.
  * - Functions return a pdhg_status; they never throw.  On PDHG_EHIP the HIP

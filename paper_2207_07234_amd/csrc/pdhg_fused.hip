@@ -121,6 +121,20 @@ k_colsolve_half(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ct
                                              xcd_block(blockIdx.x, gridDim.x) * kColsHalf, tile);
 }
 
+// C for 1024 < N_t <= 8192: WPC waves per column, 8 / WPC columns per block.
+template <typename T, int BW, int WPC>
+__global__ void __launch_bounds__(512)
+k_colsolve_long(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                int nparts, double wscale, double* hist) {
+  if (ctrl && ctrl->status != 0) return;
+  if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
+  extern __shared__ char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  T* xch = tile + 8 * kColLongLpl * 65;
+  colsolve_group_long<T, BW, kColLongLpl, WPC>(spec, fac, nt, nx, lqb,
+                                                xcd_block(blockIdx.x, gridDim.x) * (8 / WPC), tile, xch);
+}
+
 // C (full-symbol preconditioner): per Fourier mode k, K_k = L_k L_k^* with
 // L_k = B_t + g_k I lower triangular (row l: c0(l)/h_t + g_k on the diagonal,
 // c1(l)/h_t and c2(l)/h_t below it), g_k = (wr + vr)(1 - cos theta_k) + i ci sin theta_k
@@ -352,9 +366,23 @@ static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, 
   return hipGetLastError();
 }
 
-// C: nt <= 1024, nx >= 8 (one wavefront per Fourier mode).  With part != NULL the
+template <typename T, int BW, int WPC>
+static hipError_t launch_colsolve_long_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+                                         const double* part, int nparts, double wscale, double* hist,
+                                         hipStream_t st) {
+  const size_t lds = sizeof(T) * ((size_t)8 * kColLongLpl * 65 + 48);
+  hipError_t e = allow_lds(k_colsolve_long<T, BW, WPC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_colsolve_long<T, BW, WPC>), dim3(nx / (8 / WPC)), dim3(512), lds, st, spec, fac, nt, nx,
+                     lqb, ctrl, part, nparts, wscale, hist);
+  return hipGetLastError();
+}
+
+// C: nt <= 8192, nx >= 8.  With part != NULL the
 // first wave of block 0 also reduces the iteration's residual partial sums and
-// takes the stopping decision (ctrl must then be non-NULL).
+// takes the stopping decision (ctrl must then be non-NULL).  N_t <= 512: two
+// 32-lane columns per wave; up to 1024: one wavefront per column; beyond:
+// 2, 4 or 8 wavefronts per column.
 template <typename T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st) {
@@ -394,6 +422,19 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
     if (lpl <= 16) PDHG_CW(1, 16);
   }
 #undef PDHG_CW
+#define PDHG_CL(B, W) \
+  return launch_colsolve_long_l<T, B, W>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+  const int wpc = (nt + 64 * kColLongLpl - 1) / (64 * kColLongLpl);
+  if (bw == 2) {
+    if (wpc <= 2) PDHG_CL(2, 2);
+    if (wpc <= 4) PDHG_CL(2, 4);
+    if (wpc <= 8) PDHG_CL(2, 8);
+  } else {
+    if (wpc <= 2) PDHG_CL(1, 2);
+    if (wpc <= 4) PDHG_CL(1, 4);
+    if (wpc <= 8) PDHG_CL(1, 8);
+  }
+#undef PDHG_CL
   return hipErrorInvalidValue;
 }
 

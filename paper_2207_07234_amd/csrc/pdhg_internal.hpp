@@ -15,9 +15,6 @@ template <typename T>
 hipError_t launch_rows_inv(const T* spec, int nt_spec, int lqb, T* rows, int nrows, int nx, const void* tw,
                            const Ctrl* ctrl, hipStream_t st);
 template <typename T>
-hipError_t launch_colsolve(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, const Ctrl* ctrl,
-                           hipStream_t st);
-template <typename T>
 hipError_t launch_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,
                            int* nblocks);
 template <typename T>

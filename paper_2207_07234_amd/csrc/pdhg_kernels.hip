@@ -57,136 +57,6 @@ k_rows_inv(const T* __restrict__ spec, int nt_spec, int lqb, T* __restrict__ row
   }
 }
 
-// ------------------------------------------------------------------ column solves
-// Solve (B_t B_t^T + s_k I) y = rhs along t for every halfcomplex column of the
-// spectrum, in place, with the precomputed banded Cholesky factor L (L L^T):
-// forward substitution L z = rhs, then back substitution L^T y = z.  Each
-// column is split into nseg segments handled by different threads: a segment
-// first computes its affine map (particular solution and responses to the two
-// incoming values), the maps are chained sequentially per column, and the
-// segment is re-run from its true incoming state.  Block = QB columns x nseg
-// segments; thread (c, s) = threadIdx.x = s * QB + c.
-template <typename T, int BW, int GMAX>
-__global__ void __launch_bounds__(512)
-k_colsolve(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, int nseg, const Ctrl* ctrl) {
-  if (ctrl && ctrl->status != 0) return;
-  extern __shared__ char smem[];
-  const int QB = 1 << lqb;
-  const int c = threadIdx.x & (QB - 1);
-  const int sg = threadIdx.x >> lqb;
-  T* mapH = reinterpret_cast<T*>(smem);                 // [nseg][QB][4]
-  T* mapP = mapH + (size_t)nseg * QB * 4;               // [nseg][QB][2]
-  T* inst = mapP + (size_t)nseg * QB * 2;               // [nseg][QB][2]
-  const int q = (blockIdx.x << lqb) + c;
-  const int kmode = spec_mode(q, nx);
-  const FacRow<T>* rows = fac.rows + fac.off[kmode];
-  const int last = fac.last[kmode];
-  const int G = (nt + nseg - 1) / nseg;
-  const int l0 = min(nt, sg * G);
-  const int len = min(nt, l0 + G) - l0;
-  T* col = spec + (size_t)blockIdx.x * nt * QB + c;
-  T z[GMAX];
-#pragma unroll
-  for (int i = 0; i < GMAX; ++i) z[i] = (i < len) ? col[(size_t)(l0 + i) * QB] : T(0);
-
-  // ---- forward: z_l = invd_l (rhs_l - e1_l z_{l-1} - e2_l z_{l-2}); state (z_{l-2}, z_{l-1})
-  {
-    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;   // particular, response to z_{-2}, to z_{-1}
-#pragma unroll
-    for (int i = 0; i < GMAX; ++i) {
-      if (i < len) {
-        const FacRow<T> fr = rows[min(l0 + i, last)];
-        const T pz = fr.invd * (z[i] - fr.e1 * p1 - (BW == 2 ? fr.e2 * p2 : T(0)));
-        const T az = fr.invd * (-fr.e1 * a1 - (BW == 2 ? fr.e2 * a2 : T(0)));
-        const T bz = fr.invd * (-fr.e1 * b1 - (BW == 2 ? fr.e2 * b2 : T(0)));
-        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
-      }
-    }
-    T* H = mapH + ((size_t)sg * QB + c) * 4;
-    T* P = mapP + ((size_t)sg * QB + c) * 2;
-    H[0] = a2; H[1] = b2; H[2] = a1; H[3] = b1;
-    P[0] = p2; P[1] = p1;
-    __syncthreads();
-    if (sg == 0) {
-      T s2 = 0, s1 = 0;
-      for (int s = 0; s < nseg; ++s) {
-        T* Hs = mapH + ((size_t)s * QB + c) * 4;
-        T* Ps = mapP + ((size_t)s * QB + c) * 2;
-        inst[((size_t)s * QB + c) * 2 + 0] = s2;
-        inst[((size_t)s * QB + c) * 2 + 1] = s1;
-        const T n2 = Hs[0] * s2 + Hs[1] * s1 + Ps[0];
-        const T n1 = Hs[2] * s2 + Hs[3] * s1 + Ps[1];
-        s2 = n2; s1 = n1;
-      }
-    }
-    __syncthreads();
-    T zm2 = inst[((size_t)sg * QB + c) * 2 + 0], zm1 = inst[((size_t)sg * QB + c) * 2 + 1];
-#pragma unroll
-    for (int i = 0; i < GMAX; ++i) {
-      if (i < len) {
-        const FacRow<T> fr = rows[min(l0 + i, last)];
-        const T zz = fr.invd * (z[i] - fr.e1 * zm1 - (BW == 2 ? fr.e2 * zm2 : T(0)));
-        z[i] = zz;
-        zm2 = zm1; zm1 = zz;
-      }
-    }
-    __syncthreads();
-  }
-  // ---- backward: y_l = invd_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2}); state (y_{l+2}, y_{l+1})
-  {
-    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
-#pragma unroll
-    for (int ii = 0; ii < GMAX; ++ii) {
-      const int i = GMAX - 1 - ii;
-      if (i < len) {
-        const int l = l0 + i;
-        const FacRow<T> fr = rows[min(l, last)];
-        const T e1 = rows[min(l + 1, last)].e1;
-        const T e2 = (BW == 2) ? rows[min(l + 2, last)].e2 : T(0);
-        const T pz = fr.invd * (z[i] - e1 * p1 - e2 * p2);
-        const T az = fr.invd * (-e1 * a1 - e2 * a2);
-        const T bz = fr.invd * (-e1 * b1 - e2 * b2);
-        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
-      }
-    }
-    T* H = mapH + ((size_t)sg * QB + c) * 4;
-    T* P = mapP + ((size_t)sg * QB + c) * 2;
-    H[0] = a2; H[1] = b2; H[2] = a1; H[3] = b1;
-    P[0] = p2; P[1] = p1;
-    __syncthreads();
-    if (sg == 0) {
-      T s2 = 0, s1 = 0;
-      for (int s = nseg - 1; s >= 0; --s) {
-        T* Hs = mapH + ((size_t)s * QB + c) * 4;
-        T* Ps = mapP + ((size_t)s * QB + c) * 2;
-        inst[((size_t)s * QB + c) * 2 + 0] = s2;
-        inst[((size_t)s * QB + c) * 2 + 1] = s1;
-        const T n2 = Hs[0] * s2 + Hs[1] * s1 + Ps[0];
-        const T n1 = Hs[2] * s2 + Hs[3] * s1 + Ps[1];
-        s2 = n2; s1 = n1;
-      }
-    }
-    __syncthreads();
-    T ym2 = inst[((size_t)sg * QB + c) * 2 + 0], ym1 = inst[((size_t)sg * QB + c) * 2 + 1];
-#pragma unroll
-    for (int ii = 0; ii < GMAX; ++ii) {
-      const int i = GMAX - 1 - ii;
-      if (i < len) {
-        const int l = l0 + i;
-        const FacRow<T> fr = rows[min(l, last)];
-        const T e1 = rows[min(l + 1, last)].e1;
-        const T e2 = (BW == 2) ? rows[min(l + 2, last)].e2 : T(0);
-        const T yy = fr.invd * (z[i] - e1 * ym1 - e2 * ym2);
-        z[i] = yy;
-        ym2 = ym1; ym1 = yy;
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < GMAX; ++i)
-    if (i < len) col[(size_t)(l0 + i) * QB] = z[i];
-}
-
 // ------------------------------------------------------------------ stencil kernels
 // A(u): r^l_k for l = 0..nt-1 (u has nt+1 levels).  Optional partial sums of r^2.
 template <typename T>
@@ -470,36 +340,6 @@ hipError_t launch_rows_inv(const T* spec, int nt_spec, int lqb, T* rows, int nro
   return hipGetLastError();
 }
 
-template <typename T, int BW, int GMAX>
-static hipError_t launch_colsolve_g(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, int nseg,
-                                    const Ctrl* ctrl, hipStream_t st) {
-  const int QB = 1 << lqb;
-  const size_t lds = sizeof(T) * (size_t)nseg * QB * 8;
-  hipLaunchKernelGGL((k_colsolve<T, BW, GMAX>), dim3(nx / QB), dim3(QB * nseg), lds, st, spec, fac, nt, nx,
-                     lqb, nseg, ctrl);
-  return hipGetLastError();
-}
-
-// Segment count: smallest power of two with nt / nseg <= 16, and QB * nseg <= 512.
-template <typename T>
-hipError_t launch_colsolve(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, const Ctrl* ctrl,
-                           hipStream_t st) {
-  const int QB = 1 << lqb;
-  int nseg = 1;
-  while ((nt + nseg - 1) / nseg > 16 && QB * nseg * 2 <= 512) nseg *= 2;
-  const int G = (nt + nseg - 1) / nseg;
-  if (bw == 2) {
-    if (G <= 16) return launch_colsolve_g<T, 2, 16>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
-    if (G <= 32) return launch_colsolve_g<T, 2, 32>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
-    if (G <= 64) return launch_colsolve_g<T, 2, 64>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
-  } else {
-    if (G <= 16) return launch_colsolve_g<T, 1, 16>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
-    if (G <= 32) return launch_colsolve_g<T, 1, 32>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
-    if (G <= 64) return launch_colsolve_g<T, 1, 64>(spec, fac, nt, nx, lqb, nseg, ctrl, st);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename T>
 hipError_t launch_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,
                            int* nblocks) {
@@ -609,7 +449,6 @@ template hipError_t launch_refine_time<double>(const double*, const double*, int
                                          hipStream_t);                                                        \
   template hipError_t launch_rows_inv<T>(const T*, int, int, T*, int, int, const void*, const Ctrl*,          \
                                          hipStream_t);                                                        \
-  template hipError_t launch_colsolve<T>(T*, const FacTab<T>&, int, int, int, int, const Ctrl*, hipStream_t); \
   template hipError_t launch_residual<T>(const Scheme&, const T*, T*, double*, const Ctrl*, hipStream_t,      \
                                          int*);                                                               \
   template hipError_t launch_apply_jt<T>(const Scheme&, const T*, const T*, T*, double*, hipStream_t, int*);  \

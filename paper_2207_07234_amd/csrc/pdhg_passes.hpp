@@ -300,6 +300,7 @@ __device__ __forceinline__ double subgroup_sum(double v, double* red, int w0, in
 constexpr int kColCols = 8;                // spectrum columns per block
 constexpr int kFdColWaves = kColCols;      // finite differences: one wave per column
 constexpr int kColWaves = 4;               // DG: one wave per mode (its Re and Im columns)
+constexpr int kColLongLpl = 16;            // levels per lane when a column spans several waves
 
 // (H, P) <- (H, P) o (H', P') : apply (H', P') first, then (H, P).
 // Complex value of the full-symbol column solve: the scan helpers below are
@@ -383,7 +384,7 @@ __device__ __forceinline__ void scan_step_cross(T* H, T* P, int lane, int row, i
 // across rows: each row in turn composes with the full prefix of the rows
 // before it (forward) or after it (backward), read from one lane.
 template <typename T, bool FWD>
-__device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& in1) {
+__device__ __forceinline__ void scan_inclusive(T* H, T* P, int lane) {
   scan_step_row<T, FWD, 1>(H, P);
   scan_step_row<T, FWD, 2>(H, P);
   scan_step_row<T, FWD, 4>(H, P);
@@ -392,15 +393,74 @@ __device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& i
     scan_step_cross(H, P, lane, 1, 15);
     scan_step_cross(H, P, lane, 2, 31);
     scan_step_cross(H, P, lane, 3, 47);
-    in2 = from_lane_below(P[0], T(0));
-    in1 = from_lane_below(P[1], T(0));
   } else {
     scan_step_cross(H, P, lane, 2, 48);
     scan_step_cross(H, P, lane, 1, 32);
     scan_step_cross(H, P, lane, 0, 16);
+  }
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& in1) {
+  scan_inclusive<T, FWD>(H, P, lane);
+  if (FWD) {
+    in2 = from_lane_below(P[0], T(0));
+    in1 = from_lane_below(P[1], T(0));
+  } else {
     in2 = from_lane_above(P[0], T(0));
     in1 = from_lane_above(P[1], T(0));
   }
+}
+
+// The same over a column shared by WPC consecutive waves of the block (wave j
+// of the column holds lanes 64 j .. 64 j + 63 of it): each wave's inclusive
+// scan, then the wave totals (the map of its last lane forward, of its first
+// lane backward) are exchanged through LDS (xch: 6 values per wave of the
+// block) and each wave applies the totals of the waves before it (forward) or
+// after it (backward) to the zero state; the lane's exclusive prefix map,
+// applied to that state, gives the state entering its segment.
+template <typename T, bool FWD, int WPC>
+__device__ __forceinline__ void scan_incoming_multi(T* H, T* P, int lane, int wv, T* xch, T& in2, T& in1) {
+  scan_inclusive<T, FWD>(H, P, lane);
+  if (lane == (FWD ? 63 : 0)) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xch[wv * 6 + k] = H[k];
+    xch[wv * 6 + 4] = P[0];
+    xch[wv * 6 + 5] = P[1];
+  }
+  __syncthreads();
+  const int j = wv % WPC, w0 = wv - j;
+  T s2 = 0, s1 = 0;
+#pragma unroll
+  for (int jj = 0; jj < WPC; ++jj) {
+    const int src = FWD ? jj : WPC - 1 - jj;   // waves nearer the column's start first
+    if (FWD ? (src < j) : (src > j)) {
+      const T* X = xch + (w0 + src) * 6;
+      const T n2 = X[0] * s2 + X[1] * s1 + X[4];
+      const T n1 = X[2] * s2 + X[3] * s1 + X[5];
+      s2 = n2;
+      s1 = n1;
+    }
+  }
+  __syncthreads();   // xch is reused by the next scan
+  T E[4], F[2];
+  if (FWD) {
+    E[0] = from_lane_below(H[0], T(1));
+    E[1] = from_lane_below(H[1], T(0));
+    E[2] = from_lane_below(H[2], T(0));
+    E[3] = from_lane_below(H[3], T(1));
+    F[0] = from_lane_below(P[0], T(0));
+    F[1] = from_lane_below(P[1], T(0));
+  } else {
+    E[0] = from_lane_above(H[0], T(1));
+    E[1] = from_lane_above(H[1], T(0));
+    E[2] = from_lane_above(H[2], T(0));
+    E[3] = from_lane_above(H[3], T(1));
+    F[0] = from_lane_above(P[0], T(0));
+    F[1] = from_lane_above(P[1], T(0));
+  }
+  in2 = E[0] * s2 + E[1] * s1 + F[0];
+  in1 = E[2] * s2 + E[3] * s1 + F[1];
 }
 
 // The same for two independent 32-lane columns per wavefront (lanes 0..31 and
@@ -508,6 +568,64 @@ __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, c
         const E f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : E(0);
         const T yy = invb[i] * (z[c][i] - f1 * ym1 - f2 * ym2);
         z[c][i] = yy;
+        ym2 = ym1; ym1 = yy;
+      }
+    }
+  }
+}
+
+// Solve L L^T y = z in place (banded Cholesky factor L) for one column per
+// lane group of WPC waves (64 WPC lanes, LPL levels each); every wave of the
+// block takes part in both exchanges.
+template <typename T, int BW, int LPL, int WPC>
+__device__ __forceinline__ void cholesky_solve_multi(T (&z)[LPL], const T* invd, const T* e1, const T* e2, int lane,
+                                                     int wv, int l0, int nt, T* xch) {
+  {
+    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      if (l0 + i < nt) {
+        const T pz = invd[i] * (z[i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : T(0)));
+        const T az = invd[i] * (-(e1[i] * a1) - (BW == 2 ? e2[i] * a2 : T(0)));
+        const T bz = invd[i] * (-(e1[i] * b1) - (BW == 2 ? e2[i] * b2 : T(0)));
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
+    T zm2, zm1;
+    scan_incoming_multi<T, true, WPC>(H, P, lane, wv, xch, zm2, zm1);
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      if (l0 + i < nt) {
+        const T zz = invd[i] * (z[i] - e1[i] * zm1 - (BW == 2 ? e2[i] * zm2 : T(0)));
+        z[i] = zz;
+        zm2 = zm1; zm1 = zz;
+      }
+    }
+  }
+  {
+    T p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int ii = 0; ii < LPL; ++ii) {
+      const int i = LPL - 1 - ii;
+      if (l0 + i < nt) {
+        const T f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : T(0);
+        const T pz = invd[i] * (z[i] - f1 * p1 - f2 * p2);
+        const T az = invd[i] * (-(f1 * a1) - f2 * a2);
+        const T bz = invd[i] * (-(f1 * b1) - f2 * b2);
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
+    T ym2, ym1;
+    scan_incoming_multi<T, false, WPC>(H, P, lane, wv, xch, ym2, ym1);
+#pragma unroll
+    for (int ii = 0; ii < LPL; ++ii) {
+      const int i = LPL - 1 - ii;
+      if (l0 + i < nt) {
+        const T f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : T(0);
+        const T yy = invd[i] * (z[i] - f1 * ym1 - f2 * ym2);
+        z[i] = yy;
         ym2 = ym1; ym1 = yy;
       }
     }
@@ -658,6 +776,63 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
   for (int r = 0; r < kPer; ++r) {
     const int idx = tid + r * kThreads;
     const int l = idx / NCOL, c = idx % NCOL;
+    if (l < nt) base[(size_t)l * QB + c] = stage[r];
+  }
+}
+
+// The same for 1024 < N_t <= 64 WPC LPL on 8 / WPC columns q0.. (q0 a multiple
+// of 8 / WPC) by the block's 8 waves, WPC consecutive waves per column and
+// LPL levels per lane.  Wave v of the block holds levels 64 LPL (v % WPC) ..
+// of column v / WPC.  tile: 8 * LPL * 65 elements of LDS, xch: 48 more.
+template <typename T, int BW, int LPL, int WPC>
+__device__ __forceinline__ void colsolve_group_long(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx,
+                                                    int lqb, int q0, T* tile, T* xch) {
+  constexpr int kWaves = 8;
+  constexpr int kThreads = 64 * kWaves;
+  constexpr int NCB = kWaves / WPC;   // columns per block
+  constexpr int kPer = LPL;           // tile elements per thread (64 LPL kWaves / kThreads)
+  const int QB = 1 << lqb;
+  T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int col = wv / WPC;
+  const int kmode = spec_mode(q0 + col, nx);
+  const int l0 = ((wv % WPC) * 64 + lane) * LPL;
+  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<T, LPL>(fac, kmode, l0, invd, e1, e2);
+  T stage[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCB, c = idx % NCB;
+    stage[r] = (l < nt) ? base[(size_t)l * QB + c] : T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCB, c = idx % NCB;
+    const int g = l / LPL;   // lane of the column's lane group
+    tile[((c * WPC + (g >> 6)) * LPL + l % LPL) * 65 + (g & 63)] = stage[r];
+  }
+  __syncthreads();
+  T z[LPL];
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) z[i] = tile[(wv * LPL + i) * 65 + lane];
+  cholesky_solve_multi<T, BW, LPL, WPC>(z, invd, e1, e2, lane, wv, l0, nt, xch);
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) tile[(wv * LPL + i) * 65 + lane] = z[i];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCB, c = idx % NCB;
+    const int g = l / LPL;
+    stage[r] = tile[((c * WPC + (g >> 6)) * LPL + l % LPL) * 65 + (g & 63)];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int idx = tid + r * kThreads;
+    const int l = idx / NCB, c = idx % NCB;
     if (l < nt) base[(size_t)l * QB + c] = stage[r];
   }
 }

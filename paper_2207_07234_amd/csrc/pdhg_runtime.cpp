@@ -627,6 +627,21 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
   return resolve_constants_p<T>(h, u0, (double*)wsp(ws, L.part_rp), st, true);
 }
 
+// Column solve (Gram or full-symbol preconditioner).  With part != NULL it
+// also reduces the iteration's residual partial sums (nparts per norm) and
+// takes the stopping decision, in the first wavefront of block 0.
+template <typename T>
+hipError_t colsolve_any(pdhg_handle* h, T* spec, Ctrl* ctrl, const double* part, int nparts, double* hist,
+                        hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  const int bw = p.time == PDHG_BDF2 ? 2 : 1;
+  const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
+  if (is_full(p))   // nt <= 1024 (checked at set-up)
+    return launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale,
+                                   hist, st);
+  return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale, hist, st);
+}
+
 // s = K_d^{-1} r through the workspace spectrum buffer spec.
 template <typename T>
 int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
@@ -640,11 +655,7 @@ int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
     return PDHG_OK;
   }
   HIP_TRY(launch_rows_fwd<T>(r, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st));
-  if (is_full(p))
-    HIP_TRY(launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, nullptr, nullptr, 0, 0.0,
-                                    nullptr, st));
-  else
-    HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st));
+  HIP_TRY(colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st));
   HIP_TRY(launch_rows_inv<T>(spec, p.nt, h->lqb, s, p.nt, p.nx, h->d_tw, nullptr, st));
   return PDHG_OK;
 }
@@ -722,7 +733,7 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   if (p.time != PDHG_BE && p.time != PDHG_BDF2) return PDHG_EINVAL;
   if (p.space != PDHG_FD_UPWIND && p.space != PDHG_FD_LF && !is_dg(p)) return PDHG_EINVAL;
   if (p.dtype != PDHG_F32 && p.dtype != PDHG_F64) return PDHG_EINVAL;
-  if (p.nt > 2048) return PDHG_EUNSUPPORTED;   // column solve: <= 32 segments of <= 64 levels
+  if (p.nt > 8192) return PDHG_EUNSUPPORTED;   // column solve: <= 8 wavefronts of 64 x 16 levels per column
   // DG: nx cells >= 16 (8 spectrum columns per column block), nt <= 512 (8 levels per lane), no viscosity
   if (is_dg(p) && (p.nx < 16 || p.nt > 512 || p.gamma != 0.0)) return PDHG_EUNSUPPORTED;
   if (p.precond_kind != PDHG_PRECOND_GRAM && p.precond_kind != PDHG_PRECOND_FULL) return PDHG_EINVAL;
@@ -784,25 +795,6 @@ void pdhg_destroy(pdhg_handle* h) {
 
 namespace {
 
-// Column solve of the fused body.  With part != NULL it also reduces the
-// iteration's residual partial sums (nparts per norm) and takes the stopping
-// decision: inside the wave kernel (nt <= 1024) or in a separate finalize kernel.
-template <typename T>
-hipError_t colsolve_any(pdhg_handle* h, T* spec, Ctrl* ctrl, const double* part, int nparts, double* hist,
-                        hipStream_t st) {
-  const pdhg_problem& p = h->prob;
-  const int bw = p.time == PDHG_BDF2 ? 2 : 1;
-  const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
-  if (is_full(p))   // nt <= 1024 (checked at set-up)
-    return launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale,
-                                   hist, st);
-  if (p.nt <= 1024)
-    return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale, hist, st);
-  hipError_t e = launch_colsolve<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, st);
-  if (e != hipSuccess || !part) return e;
-  return launch_finalize(ctrl, part, nparts, part + nparts, nparts, wscale, hist, st);
-}
-
 // One unfused loop body (iteration n = ctrl->n_done + 1); `odd` selects the
 // ping-pong direction of u: odd n reads u and writes u_alt.
 template <typename T>
@@ -827,11 +819,7 @@ int enqueue_body_unfused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau
   HIP_TRY(launch_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
   HIP_TRY(launch_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
   HIP_TRY(launch_rows_fwd<T>(srow, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, ctrl, st));
-  if (is_full(p))
-    HIP_TRY(launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, ctrl, nullptr, 0, 0.0,
-                                    nullptr, st));
-  else
-    HIP_TRY(launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, ctrl, st));
+  HIP_TRY(colsolve_any<T>(h, spec, ctrl, nullptr, 0, nullptr, st));
   HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
   return PDHG_OK;
 }
@@ -1513,9 +1501,7 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
     switch (kernel) {
       case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
-      case 1:
-        if (h->last.variant == 2 || is_full(p)) return colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st);
-        return launch_colsolve<T>(spec, factab<T>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, nullptr, st);
+      case 1: return colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st);
       case 2: return launch_rows_inv<T>(spec, p.nt, h->lqb, srow, p.nt, p.nx, h->d_tw, nullptr, st);
       case 3: return launch_dual<T>(phi, phibar, srow, n, tp, nullptr, st);
       case 4: return launch_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);
