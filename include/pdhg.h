@@ -94,8 +94,19 @@ typedef enum { PDHG_FD_UPWIND = 0, PDHG_FD_LF = 1, PDHG_DG_P2_LLF = 2, PDHG_DG_P
  *                  K_k = L_k L_k^* with L_k = B_t + g_k I lower triangular (g_k the
  *                  symbol of G_c), solved by two substitutions along t.  Default
  *                  precond_c: the mean of f'(u0) (the signed transport speed).
- *                  Finite differences only (PDHG_EUNSUPPORTED for DG and for batches). */
-typedef enum { PDHG_PRECOND_GRAM = 0, PDHG_PRECOND_FULL = 1 } pdhg_precond_kind;
+ *                  Finite differences only (PDHG_EUNSUPPORTED for DG and for batches).
+ *  PDHG_PRECOND_GRAM_F32: K_d as PDHG_PRECOND_GRAM for an FP64 problem, with the
+ *                  spectral pass in single precision inside pdhg_solve: the residual
+ *                  rows are rounded to float before the forward FFT, and the FFTs,
+ *                  the spectrum in the workspace, the factor tables and the column
+ *                  solve are float; u, phi, phibar, the residuals and both norms stay
+ *                  FP64.  The rounding is relative to the residual, so the fixed point
+ *                  (A(u) = 0) and the stopping test are those of FP64.  Requires
+ *                  dtype PDHG_F64, finite differences, nx >= 64 and the fused loop
+ *                  body (variant 0 or 2); PDHG_EUNSUPPORTED otherwise, and for
+ *                  pdhg_solve_refined, pdhg_solve_onestep and batches.  pdhg_precond
+ *                  and the step-size power iteration apply the FP64 operator. */
+typedef enum { PDHG_PRECOND_GRAM = 0, PDHG_PRECOND_FULL = 1, PDHG_PRECOND_GRAM_F32 = 2 } pdhg_precond_kind;
 
 typedef struct {
   int32_t nx, nt;

@@ -54,7 +54,8 @@ class Problem:
     lf_speed: float = -1.0          # < 0: max |f'(u0)|
     precond_c: float = -1.0         # < 0: max |f'(u0)| ("gram") or mean f'(u0) ("full")
     precond_gamma_hat: float = 0.0
-    precond_kind: str = "gram"      # "gram" (Section 3.3) or "full" (with the cross term)
+    precond_kind: str = "gram"      # "gram" (Section 3.3), "full" (with the cross term), or "gram_f32"
+                                    # (FP64 problem, the Gram preconditioner's spectral pass in float)
 
     def to_c(self) -> B.pdhg_problem:
         import torch
@@ -67,7 +68,8 @@ class Problem:
         p.dtype = B.PDHG_F64 if dt == torch.float64 else B.PDHG_F32
         p.lf_speed, p.precond_c = float(self.lf_speed), float(self.precond_c)
         p.precond_gamma_hat = float(self.precond_gamma_hat)
-        p.precond_kind = {"gram": B.PDHG_PRECOND_GRAM, "full": B.PDHG_PRECOND_FULL}[self.precond_kind]
+        p.precond_kind = {"gram": B.PDHG_PRECOND_GRAM, "full": B.PDHG_PRECOND_FULL,
+                          "gram_f32": B.PDHG_PRECOND_GRAM_F32}[self.precond_kind]
         return p
 
     @property

@@ -17,7 +17,7 @@ PDHG_EINVAL, PDHG_EHIP, PDHG_EUNSUPPORTED, PDHG_EWORKSPACE = -1, -2, -3, -4
 PDHG_F32, PDHG_F64 = 0, 1
 PDHG_BE, PDHG_BDF2 = 0, 1
 PDHG_FD_UPWIND, PDHG_FD_LF, PDHG_DG_P2_LLF, PDHG_DG_P1_UPWIND = 0, 1, 2, 3
-PDHG_PRECOND_GRAM, PDHG_PRECOND_FULL = 0, 1
+PDHG_PRECOND_GRAM, PDHG_PRECOND_FULL, PDHG_PRECOND_GRAM_F32 = 0, 1, 2
 PDHG_ADJ_APPLY, PDHG_ADJ_SOLVE = 0, 1
 
 

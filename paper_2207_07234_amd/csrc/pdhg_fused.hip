@@ -39,19 +39,20 @@ constexpr int row_threads_max() { return E * (int)sizeof(T) <= 16 ? 1024 : 512; 
 template <typename T>
 __host__ __device__ constexpr bool fft_pingpong(int nx) { return 3 * (size_t)nx * sizeof(C2<T>) <= 98304; }
 
-// A: one block per pair of dual rows, W = nx / EPT threads.
-template <typename T, int EPT>
+// A: one block per pair of dual rows, W = nx / EPT threads; S is the type of
+// the spectrum and of the FFT.
+template <typename T, int EPT, typename S>
 __global__ void __launch_bounds__(kRowThreadsMax)
-k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __restrict__ tw, T* __restrict__ phi,
+k_dual_fft(const S* __restrict__ spec, int nt, int lqb, int nx, const C2<S>* __restrict__ tw, T* __restrict__ phi,
            T* __restrict__ phibar, T tau, const Ctrl* ctrl) {
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
-  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  C2<T>* twl = buf + lds_fft_points(nx);
+  C2<S>* buf = reinterpret_cast<C2<S>*>(smem);
+  C2<S>* twl = buf + lds_fft_points(nx);
   const int tid = threadIdx.x, W = blockDim.x;
   const int a = 2 * xcd_block(blockIdx.x, gridDim.x);
-  C2<T>* alt = fft_pingpong<T>(nx) ? twl + lds_fft_points(nx) : nullptr;
-  dual_fft_pair<T, EPT>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl, alt);
+  C2<S>* alt = fft_pingpong<S>(nx) ? twl + lds_fft_points(nx) : nullptr;
+  dual_fft_pair<T, EPT, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl, alt);
 }
 
 // B: one block per pair of implicit rows, W = 64 nw threads, E = nx / W.  The
@@ -59,25 +60,25 @@ k_dual_fft(const T* __restrict__ spec, int nt, int lqb, int nx, const C2<T>* __r
 // solve of the same iteration reduces them.  The per-wave sums are taken
 // before the FFT, whose barriers publish them, and added up by thread 0 in
 // wave order at the end (the order of block_sum_waves).
-template <typename T, int E>
+template <typename T, int E, typename S>
 __global__ void __launch_bounds__((row_threads_max<T, E>()))
 k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
-             const T* __restrict__ phi, T tau_u, T* __restrict__ spec, int lqb, const C2<T>* __restrict__ tw,
+             const T* __restrict__ phi, T tau_u, S* __restrict__ spec, int lqb, const C2<S>* __restrict__ tw,
              double* __restrict__ part, const Ctrl* ctrl) {
   if (ctrl->status != 0) return;
   extern __shared__ char smem[];
   const Consts<T> C(sch);
   const int nx = sch.nx, W = blockDim.x, tid = threadIdx.x;
-  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  C2<T>* twl = buf + lds_fft_points(nx);
-  const bool pp = fft_pingpong<T>(nx);
-  C2<T>* alt = pp ? twl + lds_fft_points(nx) : nullptr;
+  C2<S>* buf = reinterpret_cast<C2<S>*>(smem);
+  C2<S>* twl = buf + lds_fft_points(nx);
+  const bool pp = fft_pingpong<S>(nx);
+  C2<S>* alt = pp ? twl + lds_fft_points(nx) : nullptr;
   T* edge = reinterpret_cast<T*>(twl + (pp ? 2 : 1) * lds_fft_points(nx));   // [2 rows][first, last][nw]
   constexpr int kMaxWaves = row_threads_max<T, E>() / 64;
   __shared__ double wsum[2 * kMaxWaves];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   double rp, rd;
-  primal_res_pair<T, E>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
+  primal_res_pair<T, E, S>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
                         edge, rp, rd, alt, wsum);
   if (tid == 0) {
     const int nw = W >> 6;
@@ -283,61 +284,61 @@ hipError_t launch_colsolve_full(T* spec, const FullSym& F, const void* tw, int n
   return hipErrorInvalidValue;
 }
 
-template <typename T, int EPT>
-static hipError_t launch_dual_fft_e(const T* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
+template <typename T, int EPT, typename S>
+static hipError_t launch_dual_fft_e(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
                                     const Ctrl* ctrl, hipStream_t st) {
   const int W = nx / EPT;
-  const size_t lds = sizeof(C2<T>) * (fft_pingpong<T>(nx) ? 3 : 2) * (size_t)lds_fft_points(nx);
-  hipError_t e = allow_lds(k_dual_fft<T, EPT>, lds);
+  const size_t lds = sizeof(C2<S>) * (fft_pingpong<S>(nx) ? 3 : 2) * (size_t)lds_fft_points(nx);
+  hipError_t e = allow_lds(k_dual_fft<T, EPT, S>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dual_fft<T, EPT>), dim3((nt + 1) / 2), dim3(W), lds, st, spec, nt, lqb, nx,
-                     (const C2<T>*)tw, phi, phibar, tau, ctrl);
+  hipLaunchKernelGGL((k_dual_fft<T, EPT, S>), dim3((nt + 1) / 2), dim3(W), lds, st, spec, nt, lqb, nx,
+                     (const C2<S>*)tw, phi, phibar, tau, ctrl);
   return hipGetLastError();
 }
 
 // A: nx >= 64.
-template <typename T>
-hipError_t launch_dual_fft(const T* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
+template <typename T, typename S>
+hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
                            const Ctrl* ctrl, hipStream_t st) {
   // EPT = nx / W with W = min(512, nx / 2) threads for nx >= 128 (8 waves at nx = 2048)
   const int W = nx >= 1024 ? 512 : (nx >= 128 ? nx / 2 : nx);
   switch (nx / W) {
-    case 1: return launch_dual_fft_e<T, 1>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
-    case 2: return launch_dual_fft_e<T, 2>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
-    case 4: return launch_dual_fft_e<T, 4>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
-    case 8: return launch_dual_fft_e<T, 8>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
+    case 1: return launch_dual_fft_e<T, 1, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
+    case 2: return launch_dual_fft_e<T, 2, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
+    case 4: return launch_dual_fft_e<T, 4, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
+    case 8: return launch_dual_fft_e<T, 8, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T, int E>
+template <typename T, int E, typename S>
 static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi,
-                                      T tau_u, T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl,
+                                      T tau_u, S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl,
                                       hipStream_t st) {
   const int W = s.nx / E;
-  const size_t lds = sizeof(C2<T>) * (fft_pingpong<T>(s.nx) ? 3 : 2) * (size_t)lds_fft_points(s.nx) +
+  const size_t lds = sizeof(C2<S>) * (fft_pingpong<S>(s.nx) ? 3 : 2) * (size_t)lds_fft_points(s.nx) +
                      sizeof(T) * 4 * (W / 64);
-  hipError_t e = allow_lds(k_primal_res<T, E>, lds);
+  hipError_t e = allow_lds(k_primal_res<T, E, S>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_primal_res<T, E>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out, phibar, phi,
-                     tau_u, spec, lqb, (const C2<T>*)tw, part, ctrl);
+  hipLaunchKernelGGL((k_primal_res<T, E, S>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out, phibar, phi,
+                     tau_u, spec, lqb, (const C2<S>*)tw, part, ctrl);
   return hipGetLastError();
 }
 
 // B: E = 4 points per thread in FP32 (W = nx / 4 <= 1024 threads); in FP64
 // E = 2 up to nx = 2048 (W = nx / 2 <= 1024), E = 8 at nx = 4096 (W = 512);
 // W >= 64 (nx >= 64).
-template <typename T>
+template <typename T, typename S>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
-                             T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st) {
+                             S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st) {
   int W;
   if (sizeof(T) == 4) W = clampi(s.nx / 4, 64, 1024);
   else W = s.nx <= 2048 ? clampi(s.nx / 2, 64, 1024) : 512;
   switch (s.nx / W) {
-    case 1: return launch_primal_res_e<T, 1>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
-    case 2: return launch_primal_res_e<T, 2>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
-    case 4: return launch_primal_res_e<T, 4>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
-    case 8: return launch_primal_res_e<T, 8>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 1: return launch_primal_res_e<T, 1, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 2: return launch_primal_res_e<T, 2, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 4: return launch_primal_res_e<T, 4, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 8: return launch_primal_res_e<T, 8, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -438,14 +439,21 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_dual_fft<float>(const float*, int, int, int, const void*, float*, float*, float,
-                                           const Ctrl*, hipStream_t);
-template hipError_t launch_dual_fft<double>(const double*, int, int, int, const void*, double*, double*, double,
-                                            const Ctrl*, hipStream_t);
-template hipError_t launch_primal_res<float>(const Scheme&, const float*, float*, const float*, const float*, float,
-                                             float*, int, const void*, double*, const Ctrl*, hipStream_t);
-template hipError_t launch_primal_res<double>(const Scheme&, const double*, double*, const double*, const double*,
-                                              double, double*, int, const void*, double*, const Ctrl*, hipStream_t);
+template hipError_t launch_dual_fft<float, float>(const float*, int, int, int, const void*, float*, float*, float,
+                                                  const Ctrl*, hipStream_t);
+template hipError_t launch_dual_fft<double, double>(const double*, int, int, int, const void*, double*, double*,
+                                                    double, const Ctrl*, hipStream_t);
+template hipError_t launch_dual_fft<double, float>(const float*, int, int, int, const void*, double*, double*,
+                                                   double, const Ctrl*, hipStream_t);
+template hipError_t launch_primal_res<float, float>(const Scheme&, const float*, float*, const float*, const float*,
+                                                    float, float*, int, const void*, double*, const Ctrl*,
+                                                    hipStream_t);
+template hipError_t launch_primal_res<double, double>(const Scheme&, const double*, double*, const double*,
+                                                      const double*, double, double*, int, const void*, double*,
+                                                      const Ctrl*, hipStream_t);
+template hipError_t launch_primal_res<double, float>(const Scheme&, const double*, double*, const double*,
+                                                     const double*, double, float*, int, const void*, double*,
+                                                     const Ctrl*, hipStream_t);
 template hipError_t launch_colsolve_wave<float>(float*, const FacTab<float>&, int, int, int, int, Ctrl*,
                                                 const double*, int, double, double*, hipStream_t);
 template hipError_t launch_colsolve_full<float>(float*, const FullSym&, const void*, int, int, int, Ctrl*,

@@ -52,12 +52,14 @@ hipError_t launch_adjoint_march(const Scheme& s, const T* u, const T* g, T* mu, 
 }  // namespace pdhg
 
 namespace pdhg {
-template <typename T>
-hipError_t launch_dual_fft(const T* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
+// S: type of the spectrum, the FFT and the twiddle table tw (T, or float with
+// an FP64 state and the single-precision preconditioner).
+template <typename T, typename S = T>
+hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
                            const Ctrl* ctrl, hipStream_t st);
-template <typename T>
+template <typename T, typename S = T>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
-                             T* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st);
+                             S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st);
 template <typename T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st);

@@ -24,12 +24,13 @@ namespace pdhg {
 // ------------------------------------------------------------------ A
 // EPT = nx / W points per thread.  All global loads (twiddles, the two spectrum
 // rows and the two dual rows) are issued before the first LDS write so that
-// their latencies overlap.
-template <typename T, int EPT>
-__device__ __forceinline__ void dual_fft_pair(const T* __restrict__ spec, int nt, int lqb, int nx,
-                                              const C2<T>* __restrict__ tw, T* __restrict__ phi,
+// their latencies overlap.  S is the type of the spectrum and of the FFT (T,
+// or float under an FP64 state with a single-precision preconditioner).
+template <typename T, int EPT, typename S = T>
+__device__ __forceinline__ void dual_fft_pair(const S* __restrict__ spec, int nt, int lqb, int nx,
+                                              const C2<S>* __restrict__ tw, T* __restrict__ phi,
                                               T* __restrict__ phibar, T tau, int a, int tid, int W, int gtid, int TB,
-                                              C2<T>* buf, C2<T>* twl, C2<T>* alt = nullptr) {
+                                              C2<S>* buf, C2<S>* twl, C2<S>* alt = nullptr) {
   const int b = a + 1;
   const bool act = a < nt, hasb = b < nt;
   const int half = nx >> 1;
@@ -39,23 +40,23 @@ __device__ __forceinline__ void dual_fft_pair(const T* __restrict__ spec, int nt
   T* pb = phi + (size_t)br * nx;
   T* qb = phibar + (size_t)br * nx;
   // ---- loads
-  C2<T> twv[EPT];
+  C2<S> twv[EPT];
   T fa[EPT], fb[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int xt = gtid + e * TB;
-    twv[e] = (xt < nx) ? tw[xt] : C2<T>{T(0), T(0)};
+    twv[e] = (xt < nx) ? tw[xt] : C2<S>{S(0), S(0)};
     const int x = tid + e * W;
     fa[e] = act ? pa[x] : T(0);
     fb[e] = hasb ? pb[x] : T(0);
   }
   // halfcomplex pair: thread handles modes k = tid + e W, k <= nx/2 (EPT/2 + 1 of them)
   constexpr int KPT = EPT / 2 + 1;
-  T sar[KPT], sai[KPT], sbr[KPT], sbi[KPT];
+  S sar[KPT], sai[KPT], sbr[KPT], sbi[KPT];
 #pragma unroll
   for (int e = 0; e < KPT; ++e) {
     const int k = tid + e * W;
-    sar[e] = sai[e] = sbr[e] = sbi[e] = T(0);
+    sar[e] = sai[e] = sbr[e] = sbi[e] = S(0);
     if (act && k <= half) {
       if (k == 0 || k == half) {
         const int q = (k == 0) ? 0 : 1;
@@ -85,20 +86,20 @@ __device__ __forceinline__ void dual_fft_pair(const T* __restrict__ spec, int nt
       if (k != 0 && k != half) buf[lpad(nx - k)] = {sar[e] + sbi[e], sbr[e] - sai[e]};
     }
   }
-  const C2<T>* res = fft_lds<true, EPT>(buf, nx, twl, tid, W, alt);
-  const T sc = T(1) / T(nx);
+  const C2<S>* res = fft_lds<true, EPT>(buf, nx, twl, tid, W, alt);
+  const S sc = S(1) / S(nx);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int x = tid + e * W;
-    const C2<T> z = res[lpad(x)];
+    const C2<S> z = res[lpad(x)];
     if (act) {
-      const T ta = tau * (z.x * sc);
+      const T ta = tau * T(z.x * sc);
       const T p = fa[e] + ta;
       pa[x] = p;
       qa[x] = p + ta;
     }
     if (hasb) {
-      const T tb = tau * (z.y * sc);
+      const T tb = tau * T(z.y * sc);
       const T q = fb[e] + tb;
       pb[x] = q;
       qb[x] = q + tb;
@@ -144,13 +145,13 @@ __device__ __forceinline__ void dual_op_regs(const Consts<T>& C, int m, const T*
 // edge: 4 (W / 64) values of LDS for this sub-group.  alt (optional): a second
 // N-point LDS array for the FFT.  wsum (optional, 2 W / 64 doubles of LDS): the
 // per-wave sums of the two contributions, stored before the FFT.
-template <typename T, int E>
+template <typename T, int E, typename S = T>
 __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __restrict__ u_in,
                                                 T* __restrict__ u_out, const T* __restrict__ phibar,
-                                                const T* __restrict__ phi, T tau_u, T* __restrict__ spec, int lqb,
-                                                const C2<T>* __restrict__ tw, int a, int tid, int W, int gtid,
-                                                int TB, C2<T>* buf, C2<T>* twl, T* edge, double& rp_out,
-                                                double& rd_out, C2<T>* alt = nullptr, double* wsum = nullptr) {
+                                                const T* __restrict__ phi, T tau_u, S* __restrict__ spec, int lqb,
+                                                const C2<S>* __restrict__ tw, int a, int tid, int W, int gtid,
+                                                int TB, C2<S>* buf, C2<S>* twl, T* edge, double& rp_out,
+                                                double& rd_out, C2<S>* alt = nullptr, double* wsum = nullptr) {
   const int nx = C.nx, nt = C.nt;
   const int lane = tid & 63, wv = tid >> 6, nw = W >> 6;
   const int seg0 = wv * 64 * E;
@@ -158,11 +159,11 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
   const bool act = a < nt;
   const bool bdf2 = C.time == kTimeBDF2;
   // ---- all global loads first
-  C2<T> twv[E];
+  C2<S> twv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int xt = gtid + e * TB;
-    twv[e] = (xt < nx) ? tw[xt] : C2<T>{T(0), T(0)};
+    twv[e] = (xt < nx) ? tw[xt] : C2<S>{S(0), S(0)};
   }
   T U0[4][E], U[4][E];                 // u^{n-1} and u^n on levels a-1+i
   T PB[6][E], PBp[4], PBn[4];          // phibar rows a-2+j (edges for j = 0..3)
@@ -257,8 +258,8 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
     }
   }
 #pragma unroll
-  for (int e = 0; e < E; ++e) buf[lpad(seg0 + lane + 64 * e)] = {R[0][e], R[1][e]};
-  const C2<T>* res = fft_lds<false, E>(buf, nx, twl, tid, W, alt);
+  for (int e = 0; e < E; ++e) buf[lpad(seg0 + lane + 64 * e)] = {S(R[0][e]), S(R[1][e])};
+  const C2<S>* res = fft_lds<false, E>(buf, nx, twl, tid, W, alt);
   if (act) store_halfcomplex_pair(res, nx, spec, nt, lqb, a, b < nt, tid, W);
   rp_out = rp;
   rd_out = rd;

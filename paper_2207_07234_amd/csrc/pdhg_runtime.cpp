@@ -281,6 +281,12 @@ struct pdhg_handle {
   int* d_fac_off = nullptr;
   int* d_fac_last = nullptr;
   double fac_c = -1.0, fac_g = -1.0;
+  // single-precision preconditioner of an FP64 problem: float twiddles and factors
+  void* d_tw32 = nullptr;
+  void* d_fac32_rows = nullptr;
+  int* d_fac32_off = nullptr;
+  int* d_fac32_last = nullptr;
+  double fac32_c = -1.0, fac32_g = -1.0;
   void* d_vtab = nullptr;       // DG: per-mode 6x6 eigenbases of the coefficient coupling
   // resolved constants
   double lf = 0.0, c = 0.0;
@@ -337,6 +343,8 @@ inline int planes(const pdhg_problem& p) {
 // Either DG discretisation (coefficient planes, per-mode eigenbasis in the column solve).
 inline bool is_dg(const pdhg_problem& p) { return p.space == PDHG_DG_P2_LLF || p.space == PDHG_DG_P1_UPWIND; }
 inline bool is_full(const pdhg_problem& p) { return p.precond_kind == PDHG_PRECOND_FULL; }
+// FP64 state with the Gram preconditioner's spectral pass in single precision
+inline bool is_pre32(const pdhg_problem& p) { return p.precond_kind == PDHG_PRECOND_GRAM_F32; }
 
 WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   WsLayout L{};
@@ -535,7 +543,7 @@ int upload_factors_dg(pdhg_handle* h, double c) {
 }
 
 template <typename T>
-int upload_twiddles(pdhg_handle* h) {
+int upload_twiddles(pdhg_handle* h, void** dst) {
   const int n = h->prob.nx;
   std::vector<C2<T>> tw(n);
   const long double PI = 3.141592653589793238462643383279502884L;
@@ -543,14 +551,39 @@ int upload_twiddles(pdhg_handle* h) {
     const long double a = -2.0L * PI * i / n;
     tw[i] = C2<T>{(T)cosl(a), (T)sinl(a)};
   }
-  HIP_TRY(hipMalloc(&h->d_tw, n * sizeof(C2<T>)));
-  HIP_TRY(hipMemcpy(h->d_tw, tw.data(), n * sizeof(C2<T>), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(dst, n * sizeof(C2<T>)));
+  HIP_TRY(hipMemcpy(*dst, tw.data(), n * sizeof(C2<T>), hipMemcpyHostToDevice));
   return PDHG_OK;
 }
 
 template <typename T>
 FacTab<T> factab(const pdhg_handle* h) {
   return FacTab<T>{(const FacRow<T>*)h->d_fac_rows, h->d_fac_off, h->d_fac_last};
+}
+
+FacTab<float> factab32(const pdhg_handle* h) {
+  return FacTab<float>{(const FacRow<float>*)h->d_fac32_rows, h->d_fac32_off, h->d_fac32_last};
+}
+
+// Float factor tables of an FP64 problem with the single-precision preconditioner.
+int upload_factors32(pdhg_handle* h, double c, double ghat) {
+  std::vector<FacRow<float>> rows;
+  std::vector<int> off, last;
+  build_factor_rows<float>(h->prob, c, ghat, rows, off, last);
+  if (h->d_fac32_rows) hipFree(h->d_fac32_rows);
+  if (h->d_fac32_off) hipFree(h->d_fac32_off);
+  if (h->d_fac32_last) hipFree(h->d_fac32_last);
+  h->d_fac32_rows = nullptr;
+  h->d_fac32_off = h->d_fac32_last = nullptr;
+  HIP_TRY(hipMalloc(&h->d_fac32_rows, rows.size() * sizeof(FacRow<float>)));
+  HIP_TRY(hipMalloc((void**)&h->d_fac32_off, off.size() * sizeof(int)));
+  HIP_TRY(hipMalloc((void**)&h->d_fac32_last, last.size() * sizeof(int)));
+  HIP_TRY(hipMemcpy(h->d_fac32_rows, rows.data(), rows.size() * sizeof(FacRow<float>), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_fac32_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_fac32_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
+  h->fac32_c = c;
+  h->fac32_g = ghat;
+  return PDHG_OK;
 }
 
 int ensure_workspace(pdhg_handle* h, void*& ws) {
@@ -616,6 +649,10 @@ int resolve_constants_p(pdhg_handle* h, const T* u0, double* part, hipStream_t s
     }
   } else if (!h->d_fac_rows || h->fac_c != c || h->fac_g != p.precond_gamma_hat) {
     int rc = upload_factors<T>(h, c, p.precond_gamma_hat);
+    if (rc) return rc;
+  }
+  if (is_pre32(p) && (!h->d_fac32_rows || h->fac32_c != c || h->fac32_g != p.precond_gamma_hat)) {
+    int rc = upload_factors32(h, c, p.precond_gamma_hat);
     if (rc) return rc;
   }
   return PDHG_OK;
@@ -736,7 +773,10 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   if (p.nt > 8192) return PDHG_EUNSUPPORTED;   // column solve: <= 8 wavefronts of 64 x 16 levels per column
   // DG: nx cells >= 16 (8 spectrum columns per column block), nt <= 512 (8 levels per lane), no viscosity
   if (is_dg(p) && (p.nx < 16 || p.nt > 512 || p.gamma != 0.0)) return PDHG_EUNSUPPORTED;
-  if (p.precond_kind != PDHG_PRECOND_GRAM && p.precond_kind != PDHG_PRECOND_FULL) return PDHG_EINVAL;
+  if (p.precond_kind != PDHG_PRECOND_GRAM && p.precond_kind != PDHG_PRECOND_FULL && !is_pre32(p))
+    return PDHG_EINVAL;
+  // single-precision preconditioner: FP64 finite-difference problems
+  if (is_pre32(p) && (p.dtype != PDHG_F64 || is_dg(p))) return PDHG_EUNSUPPORTED;
   // full symbol: finite differences, one wavefront per mode in the column solve (nt <= 1024)
   if (is_full(p) && (is_dg(p) || p.nt > 1024)) return PDHG_EUNSUPPORTED;
   pdhg_handle* h = new (std::nothrow) pdhg_handle();
@@ -748,7 +788,8 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   int rc = PDHG_OK;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) rc = set_hip_error(h, e, "hipGetDevice");
-  if (!rc) rc = (p.dtype == PDHG_F64) ? upload_twiddles<double>(h) : upload_twiddles<float>(h);
+  if (!rc) rc = (p.dtype == PDHG_F64) ? upload_twiddles<double>(h, &h->d_tw) : upload_twiddles<float>(h, &h->d_tw);
+  if (!rc && is_pre32(p)) rc = upload_twiddles<float>(h, &h->d_tw32);
   if (!rc && (e = hipHostMalloc((void**)&h->h_ctrl, 2 * sizeof(Ctrl), hipHostMallocDefault)) != hipSuccess)
     rc = set_hip_error(h, e, "hipHostMalloc");
   if (!rc && (e = hipHostMalloc((void**)&h->h_scal, 64 * sizeof(double), hipHostMallocDefault)) != hipSuccess)
@@ -781,6 +822,10 @@ void pdhg_destroy(pdhg_handle* h) {
   if (h->d_fac_rows) hipFree(h->d_fac_rows);
   if (h->d_fac_off) hipFree(h->d_fac_off);
   if (h->d_fac_last) hipFree(h->d_fac_last);
+  if (h->d_tw32) hipFree(h->d_tw32);
+  if (h->d_fac32_rows) hipFree(h->d_fac32_rows);
+  if (h->d_fac32_off) hipFree(h->d_fac32_off);
+  if (h->d_fac32_last) hipFree(h->d_fac32_last);
   if (h->d_vtab) hipFree(h->d_vtab);
   if (h->own_ws) hipFree(h->own_ws);
   if (h->h_ctrl) hipHostFree(h->h_ctrl);
@@ -839,6 +884,16 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
   Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
   T* uin = odd ? u : u_alt;
   T* uout = odd ? u_alt : u;
+  if (is_pre32(p)) {   // the spectrum, its FFTs and the column solve in float
+    float* spec32 = (float*)wsp(ws, L.spec0);
+    HIP_TRY((launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tau_phi, ctrl, st)));
+    HIP_TRY((launch_primal_res<T, float>(s, uin, uout, phibar, phi, tau_u, spec32, h->lqb, h->d_tw32, part, ctrl,
+                                         st)));
+    const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
+    HIP_TRY(launch_colsolve_wave<float>(spec32, factab32(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, ctrl,
+                                        part, (p.nt + 1) / 2, wscale, hist, st));
+    return PDHG_OK;
+  }
   HIP_TRY(launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
   HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, st));
   HIP_TRY(colsolve_any<T>(h, spec, ctrl, part, (p.nt + 1) / 2, hist, st));
@@ -953,6 +1008,8 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   key.tau_u = tau_u; key.tau_phi = tau_phi; key.lf = h->lf; key.c = h->c;
   // fused passes need at least one full wavefront per row (nx >= 64); DG has its own body
   if (prm->variant == 2 && p.nx < 64 && !dg) return PDHG_EUNSUPPORTED;
+  // the single-precision preconditioner runs in the fused passes only
+  if (is_pre32(p) && (prm->variant == 1 || p.nx < 64)) return PDHG_EUNSUPPORTED;
   if (dg && prm->variant != 0 && prm->variant != 4) return PDHG_EUNSUPPORTED;
   key.variant = dg ? 4 : ((prm->variant == 1 || p.nx < 64) ? 1 : 2);
   key.chunk = chunk;
@@ -1028,6 +1085,7 @@ template <typename T>
 int solve_refined_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_params* prm,
                        const pdhg_refine_params* rp, pdhg_stats* stats, int64_t* level_iters, hipStream_t st) {
   const pdhg_problem& P = h->prob;
+  if (is_pre32(P)) return PDHG_EUNSUPPORTED;   // Algorithm 1 only
   std::vector<int> nts;   // coarse levels
   int n = rp->nt_start;
   while (n < P.nt) {
@@ -1228,6 +1286,7 @@ template <typename T>
 int onestep_impl(pdhg_handle* h, const T* u0, T* u, T* phi, const pdhg_params* prm, pdhg_stats* stats,
                  int64_t* step_iters, double* step_res, hipStream_t st) {
   const pdhg_problem& P = h->prob;
+  if (is_pre32(P)) return PDHG_EUNSUPPORTED;   // Algorithm 1 only
   if (P.space == PDHG_DG_P1_UPWIND) return onestep_dg1_impl<T>(h, u0, u, phi, prm, stats, step_iters, step_res, st);
   if (is_dg(P) || P.nx < 64) return PDHG_EUNSUPPORTED;
   const int nx = P.nx, nt = P.nt;
@@ -1496,8 +1555,21 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
   if (is_dg(p) && !(kernel <= 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
   if (is_dg(p) && (kernel == 7 || kernel == 0) && p.nx < 64) return PDHG_EUNSUPPORTED;
   if (p.space == PDHG_DG_P1_UPWIND && kernel == 0) return PDHG_EUNSUPPORTED;   // fused residual + FFT: P2 only
+  float* spec32 = (float*)spec;
   auto launch = [&]() -> hipError_t {
     if (is_dg(p)) return launch_dg();
+    if (is_pre32(p) && h->last.variant == 2) {   // the fused passes as the solve ran them
+      switch (kernel) {
+        case 0:
+          return launch_primal_res<T, float>(s, u, u_alt, phibar, phi, tu, spec32, h->lqb, h->d_tw32, prp, ctrl_t,
+                                             st);
+        case 7: return launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tp, nullptr, st);
+        case 1:
+          return launch_colsolve_wave<float>(spec32, factab32(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb,
+                                             nullptr, nullptr, 0, 0.0, nullptr, st);
+        default: break;
+      }
+    }
     switch (kernel) {
       case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
