@@ -247,7 +247,7 @@ __device__ __forceinline__ void stockham_stage(const C2<T>* src, C2<T>* dst, int
 // alt of N points the stages alternate between buf and alt (one barrier per
 // stage instead of two); the returned pointer (buf or alt) holds the result.
 template <bool INV, int EPT, typename T>
-__device__ C2<T>* fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int tid, int W,
+__device__ __forceinline__ C2<T>* fft_lds(C2<T>* buf, int N, const C2<T>* __restrict__ twl, int tid, int W,
                           C2<T>* alt = nullptr) {
   __syncthreads();
   C2<T>* src = buf;
