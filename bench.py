@@ -59,7 +59,7 @@ COUNTER_SOURCES = ("paper_2207_07234_amd/csrc/pdhg_fused.hip", "paper_2207_07234
 COUNTERS = {
     # (dtype, variant, kernel id): per-dispatch KiB of the kernel and of the copy kernel
     ("f64", 2, 0): {"fetch_kib": 12982.5, "write_kib": 16388.0, "copy_fetch_kib": 4104.5, "copy_write_kib": 8192.0,
-                    "sha": "2c79f5018169fe9f0e7d121120f254bce0ca0a99eb694b340147a57be875a1b1"},
+                    "sha": "ee435cdadb74e2ad618d8d7d03789b62433eecbba4fdce5fe9c6016ab290e39b"},
 }
 
 KERNELS_UNFUSED = {
