@@ -146,7 +146,9 @@ typedef struct {
 typedef struct {
   int64_t iters;            /* n*, the index of the returned iterate                      */
   double res_primal;        /* ||A(u^{n*})||   (space-time L2 norm sqrt(h_t h_x sum .^2)) */
-  double res_dual;          /* ||J(u^{n*})^T phi^{n*}||                                    */
+  double res_dual;          /* ||J(u^{n*})^T phi^{n*}||; NaN after divergence in the fused   */
+                            /* loop body, which evaluates it only where the stopping test  */
+                            /* or the last iterate needs it (||A(u)|| <= eps or n = max_iter) */
   double tau_u, tau_phi;    /* step sizes used                                            */
   double nu_max;            /* power-iteration estimate (0 if steps were given)           */
   double lf_speed, precond_c; /* constants used                                           */

@@ -115,13 +115,16 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
     const Consts<T> C(P.s);
     const C2<T>* tw = static_cast<const C2<T>*>(P.tw);
     double rp, rd;
+    const bool want_rd = rd_needed(ctrls + td.x);
     __syncthreads();
     if (!batch_needs_e8<TB>() || batch_ept(nx, TB) == 4)
       primal_res_pair<T, 4>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off, (T)P.tau_u,
-                            spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf, twl, edge, rp, rd);
+                            spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf, twl, edge, rp, rd,
+                            static_cast<C2<T>*>(nullptr), nullptr, want_rd);
     else if constexpr (batch_needs_e8<TB>())
       primal_res_pair<T, 8>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off, (T)P.tau_u,
-                            spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf, twl, edge, rp, rd);
+                            spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf, twl, edge, rp, rd,
+                            static_cast<C2<T>*>(nullptr), nullptr, want_rd);
     const double srp = subgroup_sum(rp, red, sg * nw, nw);
     const double srd = subgroup_sum(rd, red, sg * nw, nw);
     if (tid == 0 && pair < P.npairs) {
@@ -282,7 +285,7 @@ kb_init(const BatchProb* __restrict__ probs, const T* __restrict__ u0, T* __rest
     c->max_iter = max_iter;
     c->n_star = 0;
     c->status = 0;
-    c->pad = 0;
+    c->rd_lazy = 1;
     c->eps = eps;
     c->div_factor = div_factor;
     c->rp_prev = __builtin_nan("");

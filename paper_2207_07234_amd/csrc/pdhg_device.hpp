@@ -502,18 +502,30 @@ struct Ctrl {
   long long max_iter;
   long long n_star;    // returned iterate
   int status;          // 0 running, 1 converged, 2 diverged, 3 max_iter reached
-  int pad;
+  int rd_lazy;         // 1: the fused row pass evaluates Rd only where rd_needed says so
   double eps, div_factor;
   double rp_prev;      // ||A(u^{n_done})||
   double best;         // min over checked iterates of max(Rp, Rd)
   double rp_star, rd_star;
 };
 
+// Whether loop body n = n_done + 1 must evaluate Rd(n-1) = ||J(u^{n-1})^T phi^{n-1}||.
+// The stopping test needs it only where Rp(n-1) <= eps (both entries must be
+// below eps), and the stats report it for the last iterate (n-1 = max_iter);
+// divergence is judged on Rp alone.  Without rd_lazy it is always evaluated
+// (the residual history records every Rd).
+__device__ __forceinline__ bool rd_needed(const Ctrl* c) {
+  return !c->rd_lazy || c->rp_prev <= c->eps || c->n_done >= c->max_iter;
+}
+
 // End of loop body n = n_done + 1: Rp(n) and Rd(n-1) from the partial sums;
-// decide whether iterate n-1 is converged, diverged or the last one.
+// decide whether iterate n-1 is converged, diverged or the last one.  Where
+// Rd(n-1) was not evaluated (rd_needed false) srd is 0 and Rd reads as NaN.
 __device__ inline void finalize_body(Ctrl* c, double srp, double srd, double wscale, double* hist) {
+  const bool have_rd = rd_needed(c);
   const long long n = c->n_done + 1;
-  const double rp = sqrt(wscale * srp), rd = sqrt(wscale * srd);
+  const double rp = sqrt(wscale * srp);
+  const double rd = have_rd ? sqrt(wscale * srd) : __builtin_nan("");
   const long long it = n - 1;
   if (hist) {
     hist[2 * n] = rp;
@@ -522,14 +534,14 @@ __device__ inline void finalize_body(Ctrl* c, double srp, double srd, double wsc
   }
   int st = 0;
   if (it >= 1) {
-    const double m = fmax(c->rp_prev, rd);
-    if (!(m == m) || isinf(m)) st = 2;
-    else if (m <= c->eps) st = 1;
-    else if (m > c->div_factor * c->best) st = 2;
-    if (m < c->best) c->best = m;
+    const double p = c->rp_prev;
+    if (!(p == p) || isinf(p)) st = 2;
+    else if (p <= c->eps && rd <= c->eps) st = 1;
+    else if (p > c->div_factor * c->best) st = 2;
+    if (p < c->best) c->best = p;
     if (st == 0 && it >= c->max_iter) st = 3;
   }
-  if (st == 0 && !(rp == rp && rd == rd && !isinf(rp) && !isinf(rd))) st = 2;
+  if (st == 0 && !(rp == rp && !isinf(rp) && (!have_rd || (rd == rd && !isinf(rd))))) st = 2;
   if (st != 0) {
     c->status = st;
     c->n_star = it;

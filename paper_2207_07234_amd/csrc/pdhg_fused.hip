@@ -77,9 +77,10 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   constexpr int kMaxWaves = row_threads_max<T, E>() / 64;
   __shared__ double wsum[2 * kMaxWaves];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const bool want_rd = rd_needed(ctrl);
   double rp, rd;
   primal_res_pair<T, E, S>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
-                        edge, rp, rd, alt, wsum);
+                           edge, rp, rd, alt, wsum, want_rd);
   if (tid == 0) {
     const int nw = W >> 6;
     double srp = 0.0, srd = 0.0;

@@ -40,7 +40,10 @@ hipError_t launch_maxabs_dflux(const T* x, size_t n, double a2, double b, double
 template <typename T>
 hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st);
 
-hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st);
+// rd_lazy = 1: the fused row pass evaluates the dual residual only where the
+// stopping test or the stats need it (rd_needed).
+hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st,
+                            int rd_lazy = 0);
 hipError_t launch_finalize(Ctrl* c, const double* part_rp, int n_rp, const double* part_rd, int n_rd,
                            double wscale, double* hist, hipStream_t st);
 

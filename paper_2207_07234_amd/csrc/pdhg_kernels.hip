@@ -258,13 +258,13 @@ __global__ void k_normalize(T* __restrict__ x, size_t n, const double* nrm2) {
 }
 
 // ------------------------------------------------------------------ control
-__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor) {
+__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, int rd_lazy) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->n_done = 0;
     c->max_iter = max_iter;
     c->n_star = 0;
     c->status = 0;
-    c->pad = 0;
+    c->rd_lazy = rd_lazy;
     c->eps = eps;
     c->div_factor = div_factor;
     c->rp_prev = __builtin_nan("");
@@ -423,8 +423,9 @@ hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor);
+hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st,
+                            int rd_lazy) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor, rd_lazy);
   return hipGetLastError();
 }
 

@@ -151,7 +151,8 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
                                                 const T* __restrict__ phi, T tau_u, S* __restrict__ spec, int lqb,
                                                 const C2<S>* __restrict__ tw, int a, int tid, int W, int gtid,
                                                 int TB, C2<S>* buf, C2<S>* twl, T* edge, double& rp_out,
-                                                double& rd_out, C2<S>* alt = nullptr, double* wsum = nullptr) {
+                                                double& rd_out, C2<S>* alt = nullptr, double* wsum = nullptr,
+                                                bool want_rd = true) {
   const int nx = C.nx, nt = C.nt;
   const int lane = tid & 63, wv = tid >> 6, nw = W >> 6;
   const int seg0 = wv * 64 * E;
@@ -181,11 +182,13 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
     load_row_wave<T, E>(phibar, a - 2 + j, nt, nx, seg0, lane, PB[j], pv, nv);
     if (j < 4) { PBp[j] = pv; PBn[j] = nv; }
   }
+  if (want_rd) {   // phi is read only for the dual residual
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    T pv, nv;
-    load_row_wave<T, E>(phi, a + j, nt, nx, seg0, lane, PH[j], pv, nv);
-    if (j < 2) { PHp[j] = pv; PHn[j] = nv; }
+    for (int j = 0; j < 4; ++j) {
+      T pv, nv;
+      load_row_wave<T, E>(phi, a + j, nt, nx, seg0, lane, PH[j], pv, nv);
+      if (j < 2) { PHp[j] = pv; PHn[j] = nv; }
+    }
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -211,9 +214,11 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
       T* uw = u_out + (size_t)m * nx + seg0 + lane;
 #pragma unroll
       for (int e = 0; e < E; ++e) uw[64 * e] = U[i][e];
-      dual_op_regs<T, E>(C, m, PH[i - 2], PHp[i - 2], PHn[i - 2], PH[i - 1], PH[i], U0[i], g);
+      if (want_rd) {
+        dual_op_regs<T, E>(C, m, PH[i - 2], PHp[i - 2], PHn[i - 2], PH[i - 1], PH[i], U0[i], g);
 #pragma unroll
-      for (int e = 0; e < E; ++e) rd += (double)g[e] * (double)g[e];
+        for (int e = 0; e < E; ++e) rd += (double)g[e] * (double)g[e];
+      }
     }
   }
   // segment-edge values of the two levels whose flux differences are taken

@@ -999,7 +999,9 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
   HIP_TRY(launch_fill<T>(spec, n, T(0), st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
-  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st));
+  // fused loop body without a residual history: Rd only where the stopping test needs it
+  const int rd_lazy = (!dg && prm->variant != 1 && p.nx >= 64 && !prm->history) ? 1 : 0;
+  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st, rd_lazy));
 
   int chunk = prm->check_every > 0 ? prm->check_every : 64;
   chunk += chunk & 1;   // even: u ping-pong returns to its start buffer
@@ -1537,7 +1539,8 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
   const size_t n = (size_t)p.nt * p.nx * planes(p);
   const T tu = (T)h->last.tau_u, tp = (T)h->last.tau_phi;
   Ctrl* ctrl_t = (Ctrl*)wsp(ws, L.ctrl_t);
-  if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, st));
+  // B as in the steady state of a solve (Rp above eps: no dual residual)
+  if (kernel == 0) HIP_TRY(launch_ctrl_init(ctrl_t, 1ll << 60, 0.0, 1e300, st, 1));
   const int nr = planes(p) * p.nt;
   auto launch_dg = [&]() -> hipError_t {
     switch (kernel) {

@@ -254,6 +254,33 @@ def test_adjoint_gradient_matches_oracle(gpu_lib, dtype, time):
 
 
 # ------------------------------------------------------------------ failure handling
+@pytest.mark.parametrize("time", ["be", "bdf2"])
+def test_lazy_dual_residual_gives_the_same_solve(gpu_lib, time):
+    """Without a residual history the fused body evaluates ||J(u)^T phi|| only where ||A(u)|| <= eps or
+    at max_iter; with a history, every iteration.  Iterates, n* and the reported norms agree bitwise."""
+    nx, nt = 128, 32
+    u0 = syn.fourier_u0(1, nx)
+    _, gprob = _pair(gpu_lib, nx=nx, nt=nt, t_final=0.5, alpha=0.5, beta=0.0, gamma=0.0, time=time,
+                     space="fd_lf", dtype=torch.float64, u0=u0)
+    s = gpu_lib.Solver(gprob)
+    x0 = _dev(u0, torch.float64)
+    a = s.solve(x0, eps=1e-8, max_iter=20000, check_every=64)
+    b = s.solve(x0, eps=1e-8, max_iter=20000, check_every=64, history=True)
+    _say(f"lazy {time}: n* {a.stats['iters']} / {b.stats['iters']}")
+    assert a.status == 0 and b.status == 0
+    assert a.stats["iters"] == b.stats["iters"]
+    assert torch.equal(a.u, b.u) and torch.equal(a.phi, b.phi)
+    assert (a.stats["res_primal"], a.stats["res_dual"]) == (b.stats["res_primal"], b.stats["res_dual"])
+    h = b.history.cpu().numpy()
+    assert np.all(np.isfinite(h[1:]))
+    # stopped by max_iter: the last iterate's dual residual is evaluated
+    c = s.solve(x0, eps=1e-12, max_iter=53)
+    d = s.solve(x0, eps=1e-12, max_iter=53, history=True)
+    assert c.status == 1 and c.stats["iters"] == 53
+    assert np.isfinite(c.stats["res_dual"]) and c.stats["res_dual"] == d.stats["res_dual"]
+    assert torch.equal(c.u, d.u) and torch.equal(c.phi, d.phi)
+
+
 def test_large_steps_are_detected_as_divergence(gpu_lib):
     pk = gpu_lib
     u0 = syn.sine_u0(64)
