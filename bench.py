@@ -96,11 +96,14 @@ def counter_traffic(dtype: str, variant: int, kid: int, copy_bytes: float):
     return fetch + write
 
 
-def cpu_baseline(sample_iters: int):
-    """FP64 oracle Algorithm 1 on the same workload, timed over `sample_iters` iterations."""
+def cpu_baseline(sample_iters: int, u_gpu=None):
+    """FP64 oracle Algorithm 1 on the same workload, timed over `sample_iters` iterations.  With the
+    GPU solution u_gpu (to residual 1e-8) also the oracle's sequential Newton march of the same BDF2
+    scheme: its wall time and the max-norm difference to u_gpu (returned second, else None)."""
     import numpy as np
 
     import synthetic as syn
+    from oracle import newton as onewton
     from oracle import pdhg as opdhg
     from oracle.problem import Problem as OProblem, default_constants
     u0 = syn.fourier_u0(SEED, NX)
@@ -110,7 +113,7 @@ def cpu_baseline(sample_iters: int):
     opdhg.run(oprob, u0, 0.6, 0.6, eps=0.0, max_iter=sample_iters)
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
-    return {
+    base = {
         "value": NX * NT * sample_iters / wall,
         "unit": "DOF-iterations/s",
         "cores": max(1, int(round(cpu / wall))),
@@ -118,6 +121,15 @@ def cpu_baseline(sample_iters: int):
         "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1) on the same "
                   f"{NX}x{NT} BDF2 LF Burgers problem; {wall:.1f} s wall, host has {os.cpu_count()} CPUs",
     }
+    if u_gpu is None:
+        return base, None
+    t0 = time.perf_counter()
+    nw = onewton.march(oprob, u0)
+    march_s = time.perf_counter() - t0
+    err = {"max_abs_u_minus_newton_march": float(np.max(np.abs(u_gpu - nw))),
+           "max_abs_u": float(np.max(np.abs(nw))), "newton_march_seconds": march_s}
+    log(f"oracle Newton march: {march_s:.2f} s; max |u_gpu - u_newton| = {err['max_abs_u_minus_newton_march']:.3e}")
+    return base, err
 
 
 BATCH_COUNT, BATCH_ITERS, BATCH_SEED = 256, 300, 0
@@ -682,6 +694,7 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     dof = NX * NT
     value = dof * sum(iters) / wall
+    u_final = u.double().cpu().numpy() if eps > 0 else None   # converged solution, for the oracle check
 
     # per-kernel device time (HIP events on the solve's stream), buffers of the last solve
     kern = {}
@@ -734,7 +747,8 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
+        out["cpu_baseline"], err = cpu_baseline(args.cpu_iters, u_final)
+        out["config"]["error_vs_oracle"] = err
     print(json.dumps(out), flush=True)
 
 
