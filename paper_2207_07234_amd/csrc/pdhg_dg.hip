@@ -237,12 +237,13 @@ k_dg_primal(Scheme s, const T* __restrict__ u_in, T* __restrict__ u_out, const T
   const Consts<T> C(s);
   const int nx = s.nx;
   const size_t idx = (size_t)blockIdx.x * kDgThreads + threadIdx.x;
+  const bool want_rd = !ctrl || rd_needed(ctrl);   // the dual residual only where it can decide
   double acc = 0.0;
   if (idx < (size_t)s.nt * nx) {
     const int m = (int)(idx / nx) + 1, j = (int)(idx % nx);
-    T gb[3], g[3];
+    T gb[3], g[3] = {T(0), T(0), T(0)};
     dg_jt_point(C, u_in, phibar, m, j, gb);
-    dg_jt_point(C, u_in, phi, m, j, g);
+    if (want_rd) dg_jt_point(C, u_in, phi, m, j, g);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const size_t o = (size_t)m * 3 * nx + (size_t)k * nx + j;

@@ -145,11 +145,12 @@ k_primal(Scheme s, const T* __restrict__ u_in, T* __restrict__ u_out, const T* _
   __shared__ double red[kEwThreads / 64];
   const Consts<T> C(s);
   const size_t idx = (size_t)blockIdx.x * kEwThreads + threadIdx.x;
+  const bool want_rd = !ctrl || rd_needed(ctrl);   // the dual residual only where it can decide
   double acc = 0.0;
   if (idx < (size_t)s.nt * s.nx) {
     const int m = (int)(idx / s.nx) + 1, k = (int)(idx % s.nx);
     const T gbar = jt_point(C, u_in, phibar, m, k);
-    const T g = jt_point(C, u_in, phi, m, k);
+    const T g = want_rd ? jt_point(C, u_in, phi, m, k) : T(0);
     const size_t o = (size_t)m * s.nx + k;
     u_out[o] = u_in[o] - tau_u * gbar;
     acc = (double)g * (double)g;

@@ -999,8 +999,8 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
   HIP_TRY(launch_fill<T>(spec, n, T(0), st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
-  // fused loop body without a residual history: Rd only where the stopping test needs it
-  const int rd_lazy = (!dg && prm->variant != 1 && p.nx >= 64 && !prm->history) ? 1 : 0;
+  // without a residual history: Rd only where the stopping test needs it
+  const int rd_lazy = prm->history ? 0 : 1;
   HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st, rd_lazy));
 
   int chunk = prm->check_every > 0 ? prm->check_every : 64;
