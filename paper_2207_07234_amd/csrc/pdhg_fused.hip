@@ -9,11 +9,13 @@
 //                      touch, the dual residual ||J(u^{n-1})^T phi^{n-1}|| of the owned
 //                      levels, the implicit residual A(u^n) of the two rows, its
 //                      forward FFT (halfcomplex spectrum, column-block layout), and
-//                      per-block partial sums of ||A(u^n)||^2 and the dual residual
-//   C  k_colsolve_wave per Fourier mode: banded Cholesky solve along t
-//                      (the preconditioner K_d^{-1} of Section 2.2); its first wave
-//                      reduces B's partial sums and takes the convergence decision
-//                      (Section 3.3 stopping rule)
+//                      per-block partial sums of ||A(u^n)||^2 and of the dual
+//                      residual (the latter only where the stopping test needs it)
+//   C  k_colsolve_*    per spectrum column: banded Cholesky solve along t (the
+//                      preconditioner K_d^{-1} of Section 2.2; k_colsolve_half for
+//                      N_t <= 512, k_colsolve_wave up to 1024, k_colsolve_long up
+//                      to 8192); its first wave reduces B's partial sums and takes
+//                      the convergence decision (Section 3.3 stopping rule)
 // The pass bodies live in pdhg_passes.hpp (shared with the batched kernels).
 // Halo levels of u^n needed by the time stencil of A are recomputed by each
 // block from the same inputs (bitwise identical to the owner's values); u is
