@@ -227,6 +227,28 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def advection_cfl4(pk):
+    """Linear advection u_t + u_x = 0, 64 x 32, T = 2 (CFL 4), BE upwind, u0 = sin(2 pi x), FP64, sigma = tau =
+    0.7, to residual 1e-10: the small latency-bound case (one graph chunk of a few microseconds per
+    iteration).  The GPU tests pin its solution to the closed-form BE amplification at 1e-10."""
+    import numpy as np
+    import torch
+    import synthetic as syn
+    s = pk.Solver(pk.Problem(nx=64, nt=32, t_final=2.0, alpha=0.0, beta=1.0, time="be", space="fd_upwind",
+                             dtype=torch.float64))
+    u0 = torch.tensor(syn.sine_u0(64), dtype=torch.float64, device="cuda")
+    s.solve(u0, tau_u=0.7, tau_phi=0.7, eps=1e-10, max_iter=5000, check_every=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.solve(u0, tau_u=0.7, tau_phi=0.7, eps=1e-10, max_iter=5000, check_every=64)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = r.stats["iters"]
+    log(f"advection 64x32 CFL 4 to 1e-10: {n} iterations, {wall * 1e3:.2f} ms ({wall / n * 1e6:.2f} us/iteration)")
+    return {"iterations": n, "seconds": wall, "us_per_iteration": wall / n * 1e6, "status": r.status,
+            "variant": r.stats["variant"], "u_T_max": float(np.max(np.abs(r.u[-1].cpu().numpy())))}
+
+
 def large_single_sweep(pk):
     """Per-kernel device time of the fused passes on single problems large enough to fill the GPU many
     times over (N_t = 2048: 1024 row-pair blocks, four per CU; N_t = 8192, the column solve's limit, with
@@ -711,7 +733,7 @@ def main():
     log(f"plain copy of {dof} elements: {copy_ms*1e3:.1f} us, {copy_bytes / (copy_ms * 1e-3) / 1e9:.0f} GB/s")
     traffic = counter_traffic(args.dtype, stats["variant"], dom, copy_bytes)
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": traffic, "kernel": name,
+            "traffic": traffic, "traffic_GBs": traffic / (ms * 1e-3) / 1e9 if traffic else None, "kernel": name,
             "bytes_per_launch": words * esz * dof, "ms_per_launch": ms,
             "copy_GBs": copy_bytes / (copy_ms * 1e-3) / 1e9}
 
@@ -719,6 +741,7 @@ def main():
     if eps > 0 and not args.no_variants:
         variants = variant_comparison(pk, solver, prob, u0, tau, (iters[-1], ms_per_step / 1e3))
         variants["traffic_table3"] = traffic_table3(pk)
+        variants["advection_cfl4_64x32"] = advection_cfl4(pk)
         variants["large_single"] = large_single_sweep(pk)
 
     out = {
