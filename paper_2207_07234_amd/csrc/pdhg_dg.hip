@@ -304,6 +304,12 @@ k_dg_maxabs_trace(const T* __restrict__ u0, int nx, double a2, double b, double*
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// The three FFTs of k_dg_residual_fft alternate between two LDS arrays (one
+// barrier per stage instead of two) where a third N-point array fits in 96 KiB:
+// up to nx = 4096 in FP32 and 2048 in FP64.  Kernel and launcher decide alike.
+template <typename T>
+__host__ __device__ constexpr bool dg_fft_pingpong(int nx) { return 3 * (size_t)nx * sizeof(C2<T>) <= 98304; }
+
 // Residual of levels l = 2w and 2w + 1 (3 planes each) and the forward FFT of
 // those 6 coefficient rows of the 3 nt-row spectrum, as the three complex
 // FFTs of row pairs (6w, 6w+1), (6w+2, 6w+3), (6w+4, 6w+5).  W = nx / E
@@ -319,6 +325,7 @@ k_dg_residual_fft(Scheme s, const T* __restrict__ u, T* __restrict__ spec, int l
   const int nx = s.nx, nt = s.nt, nr = 3 * nt, W = blockDim.x, tid = threadIdx.x;
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   C2<T>* twl = buf + lds_fft_points(nx);
+  C2<T>* alt = dg_fft_pingpong<T>(nx) ? twl + lds_fft_points(nx) : nullptr;
   const int w = xcd_block(blockIdx.x, gridDim.x);
   const size_t L3 = (size_t)3 * nx;
   C2<T> twv[E];
@@ -367,8 +374,8 @@ k_dg_residual_fft(Scheme s, const T* __restrict__ u, T* __restrict__ spec, int l
       const int qa = 2 * i, qb = 2 * i + 1;
       buf[lpad(tid + e * W)] = {R[qa / 3][qa % 3][e], R[qb / 3][qb % 3][e]};
     }
-    fft_lds<false, E>(buf, nx, twl, tid, W);
-    if (ra < nr) store_halfcomplex_pair(buf, nx, spec, nr, lqb, ra, ra + 1 < nr, tid, W);
+    const C2<T>* res = fft_lds<false, E>(buf, nx, twl, tid, W, alt);
+    if (ra < nr) store_halfcomplex_pair(res, nx, spec, nr, lqb, ra, ra + 1 < nr, tid, W);
   }
   const double srp = block_sum_waves(rp, red);
   if (tid == 0) part[blockIdx.x] = srp;
@@ -541,7 +548,7 @@ template <typename T, int E>
 static hipError_t launch_dg_residual_fft_e(const Scheme& s, const T* u, T* spec, int lqb, const void* tw,
                                            double* part, const Ctrl* ctrl, hipStream_t st, int* nblocks) {
   const int W = s.nx / E;
-  const size_t lds = sizeof(C2<T>) * 2 * (size_t)lds_fft_points(s.nx);
+  const size_t lds = sizeof(C2<T>) * (dg_fft_pingpong<T>(s.nx) ? 3 : 2) * (size_t)lds_fft_points(s.nx);
   hipError_t e = allow_lds(k_dg_residual_fft<T, E>, lds);
   if (e != hipSuccess) return e;
   const int g = (s.nt + 1) / 2;
