@@ -96,6 +96,18 @@ def counter_traffic(dtype: str, variant: int, kid: int, copy_bytes: float):
     return fetch + write
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or 'unknown CPU'."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(sample_iters: int, u_gpu=None):
     """FP64 oracle Algorithm 1 on the same workload, timed over `sample_iters` iterations.  With the
     GPU solution u_gpu (to residual 1e-8) also the oracle's sequential Newton march of the same BDF2
@@ -119,7 +131,8 @@ def cpu_baseline(sample_iters: int, u_gpu=None):
         "cores": max(1, int(round(cpu / wall))),
         "kind": "oracle",
         "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1) on the same "
-                  f"{NX}x{NT} BDF2 LF Burgers problem; {wall:.1f} s wall, host has {os.cpu_count()} CPUs",
+                  f"{NX}x{NT} BDF2 LF Burgers problem; {wall:.1f} s wall, host has {os.cpu_count()} CPUs "
+                  f"({cpu_model()})",
     }
     if u_gpu is None:
         return base, None
@@ -498,7 +511,7 @@ def dg_cpu_baseline(sample_iters: int):
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
             "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1, DG P2) on the "
                       f"workload's {DG_NX} cells and first {DG_CPU_NT} levels (h_t = 3 h_x); {wall:.1f} s wall, "
-                      f"host has {os.cpu_count()} CPUs"}
+                      f"host has {os.cpu_count()} CPUs ({cpu_model()})"}
 
 
 def run_dg(args):
