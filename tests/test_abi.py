@@ -150,3 +150,40 @@ def test_batch_rejects_the_full_symbol():
     h = C.c_void_p()
     assert lib.pdhg_batch_setup(arr, 1, C.byref(h)) == B.PDHG_EUNSUPPORTED
     assert not h.value
+
+
+@pytest.mark.parametrize("dtype,space,nt,code", [("PDHG_F32", "PDHG_FD_LF", 16, "PDHG_EUNSUPPORTED"),
+                                                 ("PDHG_F64", "PDHG_DG_P2_LLF", 16, "PDHG_EUNSUPPORTED"),
+                                                 ("PDHG_F64", "PDHG_DG_P1_UPWIND", 16, "PDHG_EUNSUPPORTED")])
+def test_single_precision_preconditioner_limits(dtype, space, nt, code):
+    """PDHG_PRECOND_GRAM_F32: FP64 finite-difference problems only; rejected before the device is touched."""
+    B, lib = _lib()
+    p = B.pdhg_problem()
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 64, nt, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype, p.precond_kind = B.PDHG_BE, getattr(B, space), getattr(B, dtype), \
+        B.PDHG_PRECOND_GRAM_F32
+    h = C.c_void_p()
+    assert lib.pdhg_setup(C.byref(p), C.byref(h)) == getattr(B, code)
+    assert not h.value
+
+
+def test_time_axis_limit():
+    """N_t above 8192 (8 wavefronts of 64 lanes x 16 levels per spectrum column) is unsupported."""
+    B, lib = _lib()
+    p = B.pdhg_problem()
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 64, 8193, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype = B.PDHG_BE, B.PDHG_FD_LF, B.PDHG_F64
+    h = C.c_void_p()
+    assert lib.pdhg_setup(C.byref(p), C.byref(h)) == B.PDHG_EUNSUPPORTED
+    assert not h.value
+
+
+def test_batch_rejects_the_single_precision_preconditioner():
+    B, lib = _lib()
+    arr = (B.pdhg_problem * 1)()
+    p = arr[0]
+    p.nx, p.nt, p.length, p.t_final, p.alpha, p.beta = 256, 16, 1.0, 0.5, 0.5, 0.0
+    p.time, p.space, p.dtype, p.precond_kind = B.PDHG_BE, B.PDHG_FD_LF, B.PDHG_F64, B.PDHG_PRECOND_GRAM_F32
+    h = C.c_void_p()
+    assert lib.pdhg_batch_setup(arr, 1, C.byref(h)) == B.PDHG_EUNSUPPORTED
+    assert not h.value
