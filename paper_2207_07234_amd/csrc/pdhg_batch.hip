@@ -156,8 +156,26 @@ kb_colsolve(const BatchProb* __restrict__ probs, Ctrl* ctrls, const int2* __rest
     if (td.y == 0 && threadIdx.x < 64)
       finalize_wave(ctrls + td.x, part + P.part_off, P.npairs, rd_base, P.wscale, nullptr);
     const FacTab<T> fac{static_cast<const FacRow<T>*>(P.fac_rows), P.fac_off, P.fac_last};
-    const int nt = P.s.nt, nx = P.s.nx, q0 = td.y * kColCols;
+    const int nt = P.s.nt, nx = P.s.nx;
     T* sp = spec + P.f_off;
+    if (nt <= 256) {   // tiles of 16 columns, 16 lanes per column, LPL = ceil(nt / 16) <= 16
+      const int q0 = td.y * 16, lq = (nt + 15) / 16;
+      if (P.s.time == kTimeBDF2) {
+        if (lq <= 1) colsolve_group_half<T, 2, 1, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else if (lq <= 2) colsolve_group_half<T, 2, 2, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else if (lq <= 4) colsolve_group_half<T, 2, 4, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else if (lq <= 8) colsolve_group_half<T, 2, 8, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else colsolve_group_half<T, 2, 16, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+      } else {
+        if (lq <= 1) colsolve_group_half<T, 1, 1, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else if (lq <= 2) colsolve_group_half<T, 1, 2, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else if (lq <= 4) colsolve_group_half<T, 1, 4, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else if (lq <= 8) colsolve_group_half<T, 1, 8, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+        else colsolve_group_half<T, 1, 16, 16, 16>(sp, fac, nt, nx, P.lqb, q0, tile);
+      }
+      continue;
+    }
+    const int q0 = td.y * kColCols;
     // nt <= 512 (checked at set-up): 32 lanes per column, LPL = ceil(nt / 32) <= 16
     const int lpl = (nt + 31) / 32;
     if (P.s.time == kTimeBDF2) {
@@ -347,7 +365,9 @@ template <typename T>
 size_t batch_row_lds(int max_nx) { return row_lds_bytes<T, batch_row_threads<T>()>(max_nx); }
 
 template <typename T>
-size_t batch_col_lds() { return sizeof(T) * (size_t)kColCols * 16 * 33; }
+size_t batch_col_lds() {   // the larger of the 8-column (32 lanes) and 16-column (16 lanes) tiles
+  return sizeof(T) * std::max((size_t)kColCols * 16 * 33, (size_t)16 * 16 * 17);
+}
 
 template <typename T>
 hipError_t batch_occupancy(int which, int max_nx, int* blocks_per_cu) {

@@ -181,7 +181,7 @@ int setup_impl(pdhg_batch* b) {
     q.pairs_per_tile = TB / W;
     q.rtiles = (q.npairs + q.pairs_per_tile - 1) / q.pairs_per_tile;
     rt += q.rtiles;
-    q.ncolg = p.nx / 8;
+    q.ncolg = p.nx / (p.nt <= 256 ? 16 : 8);   // column tiles: 16 columns of 16 lanes up to N_t = 256
     cg += q.ncolg;
     b->max_nx = std::max(b->max_nx, p.nx);
   }

@@ -125,6 +125,20 @@ k_colsolve_half(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ct
                                              xcd_block(blockIdx.x, gridDim.x) * kColsHalf, tile);
 }
 
+// C for N_t <= 256: kColsQuarter columns per block, four per wave (16 lanes each).
+constexpr int kColsQuarter = 8;
+template <typename T, int BW, int LPL>
+__global__ void __launch_bounds__(16 * kColsQuarter)
+k_colsolve_quarter(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                   int nparts, double wscale, double* hist) {
+  if (ctrl && ctrl->status != 0) return;
+  if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
+  extern __shared__ char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  colsolve_group_half<T, BW, LPL, kColsQuarter, 16>(spec, fac, nt, nx, lqb,
+                                                     xcd_block(blockIdx.x, gridDim.x) * kColsQuarter, tile);
+}
+
 // C for 1024 < N_t <= 8192: WPC waves per column, 8 / WPC columns per block.
 template <typename T, int BW, int WPC>
 __global__ void __launch_bounds__(512)
@@ -359,6 +373,18 @@ static hipError_t launch_colsolve_half_l(T* spec, const FacTab<T>& fac, int nt, 
 }
 
 template <typename T, int BW, int LPL>
+static hipError_t launch_colsolve_quarter_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+                                            const double* part, int nparts, double wscale, double* hist,
+                                            hipStream_t st) {
+  const size_t lds = sizeof(T) * (size_t)kColsQuarter * LPL * 17;
+  hipError_t e = allow_lds(k_colsolve_quarter<T, BW, LPL>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_colsolve_quarter<T, BW, LPL>), dim3(nx / kColsQuarter), dim3(16 * kColsQuarter), lds, st,
+                     spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist);
+  return hipGetLastError();
+}
+
+template <typename T, int BW, int LPL>
 static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                          const double* part, int nparts, double wscale, double* hist,
                                          hipStream_t st) {
@@ -384,12 +410,31 @@ static hipError_t launch_colsolve_long_l(T* spec, const FacTab<T>& fac, int nt, 
 
 // C: nt <= 8192, nx >= 8.  With part != NULL the
 // first wave of block 0 also reduces the iteration's residual partial sums and
-// takes the stopping decision (ctrl must then be non-NULL).  N_t <= 512: two
-// 32-lane columns per wave; up to 1024: one wavefront per column; beyond:
-// 2, 4 or 8 wavefronts per column.
+// takes the stopping decision (ctrl must then be non-NULL).  N_t <= 256: four
+// 16-lane columns per wave; up to 512: two 32-lane columns per wave; up to
+// 1024: one wavefront per column; beyond: 2, 4 or 8 wavefronts per column.
 template <typename T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st) {
+  if (nt <= 256) {
+    const int lq = (nt + 15) / 16;
+#define PDHG_CQ(B, L) \
+  return launch_colsolve_quarter_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+    if (bw == 2) {
+      if (lq <= 1) PDHG_CQ(2, 1);
+      if (lq <= 2) PDHG_CQ(2, 2);
+      if (lq <= 4) PDHG_CQ(2, 4);
+      if (lq <= 8) PDHG_CQ(2, 8);
+      PDHG_CQ(2, 16);
+    } else {
+      if (lq <= 1) PDHG_CQ(1, 1);
+      if (lq <= 2) PDHG_CQ(1, 2);
+      if (lq <= 4) PDHG_CQ(1, 4);
+      if (lq <= 8) PDHG_CQ(1, 8);
+      PDHG_CQ(1, 16);
+    }
+#undef PDHG_CQ
+  }
   if (nt <= 512) {
     const int lh = (nt + 31) / 32;
 #define PDHG_CH(B, L) \

@@ -418,6 +418,29 @@ __device__ __forceinline__ void scan_incoming(T* H, T* P, int lane, T& in2, T& i
   }
 }
 
+// The same for four independent 16-lane columns per wavefront (one DPP row
+// each): only the row steps; the first lane of each column (forward) or its
+// last lane (backward) enters with zero.
+template <typename T, bool FWD>
+__device__ __forceinline__ void scan_incoming_quarter(T* H, T* P, int lane, T& in2, T& in1) {
+  scan_step_row<T, FWD, 1>(H, P);
+  scan_step_row<T, FWD, 2>(H, P);
+  scan_step_row<T, FWD, 4>(H, P);
+  scan_step_row<T, FWD, 8>(H, P);
+  const bool edge = FWD ? ((lane & 15) == 0) : ((lane & 15) == 15);
+  if (FWD) {
+    in2 = from_lane_below(P[0], T(0));
+    in1 = from_lane_below(P[1], T(0));
+  } else {
+    in2 = from_lane_above(P[0], T(0));
+    in1 = from_lane_above(P[1], T(0));
+  }
+  if (edge) {
+    in2 = T(0);
+    in1 = T(0);
+  }
+}
+
 // The same over a column shared by WPC consecutive waves of the block (wave j
 // of the column holds lanes 64 j .. 64 j + 63 of it): each wave's inclusive
 // scan, then the wave totals (the map of its last lane forward, of its first
@@ -538,7 +561,8 @@ __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, c
     T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
     T zm2, zm1;
     if (CW == 64) scan_incoming<T, true>(H, P, lane, zm2, zm1);
-    else scan_incoming_half<T, true>(H, P, lane, zm2, zm1);
+    else if (CW == 32) scan_incoming_half<T, true>(H, P, lane, zm2, zm1);
+    else scan_incoming_quarter<T, true>(H, P, lane, zm2, zm1);
 #pragma unroll
     for (int i = 0; i < LPL; ++i) {
       if (l0 + i < nt) {
@@ -566,7 +590,8 @@ __device__ __forceinline__ void tri_solve_wave(T (&z)[NC][LPL], const T* invd, c
     T H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
     T ym2, ym1;
     if (CW == 64) scan_incoming<T, false>(H, P, lane, ym2, ym1);
-    else scan_incoming_half<T, false>(H, P, lane, ym2, ym1);
+    else if (CW == 32) scan_incoming_half<T, false>(H, P, lane, ym2, ym1);
+    else scan_incoming_quarter<T, false>(H, P, lane, ym2, ym1);
 #pragma unroll
     for (int ii = 0; ii < LPL; ++ii) {
       const int i = LPL - 1 - ii;
@@ -731,22 +756,23 @@ __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTa
 }
 
 // The same for N_t <= 512 on NCOL columns q0..q0+NCOL-1 (q0 a multiple of
-// NCOL) by NCOL/2 waves of the calling block, two columns per wave and 32
-// lanes per column (LPL <= 16 levels per lane): a wave's scans run over 32
-// lanes, and a SIMD holds one wave with two columns instead of two waves with
-// one each, which halves the scan work per column.  tile: NCOL * LPL * 33
-// elements of LDS.
+// NCOL) by the calling block, CW = 32 lanes per column (two columns per wave,
+// N_t <= 512) or 16 (four per wave, N_t <= 256), LPL <= 16 levels per lane: a
+// wave's scans run over CW lanes, and a SIMD holds one wave with 64 / CW
+// columns instead of as many waves with one each, which cuts the scan work
+// per column.  tile: NCOL * LPL * (CW + 1) elements of LDS.
 constexpr int kColHalfThreads = 256;
-template <typename T, int BW, int LPL, int NCOL = kColCols>
+template <typename T, int BW, int LPL, int NCOL = kColCols, int CW = 32>
 __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx,
                                                     int lqb, int q0, T* tile) {
-  constexpr int kThreads = 32 * NCOL;
+  constexpr int kThreads = CW * NCOL;
+  constexpr int TS = CW + 1;   // tile row stride
   const int QB = 1 << lqb;
   T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
   const int tid = threadIdx.x;
-  constexpr int kPer = LPL;   // tile elements per thread (32 LPL NCOL / kThreads)
+  constexpr int kPer = LPL;   // tile elements per thread (CW LPL NCOL / kThreads)
   const int wv = tid >> 6, lane = tid & 63;
-  const int col = 2 * wv + (lane >> 5), q = lane & 31;
+  const int col = wv * (64 / CW) + lane / CW, q = lane % CW;
   const int kmode = spec_mode(q0 + col, nx);
   const int l0 = q * LPL;
   T invd[LPL], e1[LPL + 1], e2[LPL + 2];
@@ -762,21 +788,21 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
   for (int r = 0; r < kPer; ++r) {
     const int idx = tid + r * kThreads;
     const int l = idx / NCOL, c = idx % NCOL;
-    tile[(c * LPL + l % LPL) * 33 + l / LPL] = stage[r];
+    tile[(c * LPL + l % LPL) * TS + l / LPL] = stage[r];
   }
   __syncthreads();
   T z[1][LPL];
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) z[0][i] = tile[(col * LPL + i) * 33 + q];
-  cholesky_solve_wave<T, BW, LPL, 1, 32>(z, invd, e1, e2, lane, l0, nt);
+  for (int i = 0; i < LPL; ++i) z[0][i] = tile[(col * LPL + i) * TS + q];
+  cholesky_solve_wave<T, BW, LPL, 1, CW>(z, invd, e1, e2, lane, l0, nt);
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) tile[(col * LPL + i) * 33 + q] = z[0][i];
+  for (int i = 0; i < LPL; ++i) tile[(col * LPL + i) * TS + q] = z[0][i];
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int idx = tid + r * kThreads;
     const int l = idx / NCOL, c = idx % NCOL;
-    stage[r] = tile[(c * LPL + l % LPL) * 33 + l / LPL];
+    stage[r] = tile[(c * LPL + l % LPL) * TS + l / LPL];
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
