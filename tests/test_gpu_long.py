@@ -1,6 +1,7 @@
-"""GPU parity for long time axes (1024 < N_t <= 8192), where one spectrum column
-spans several wavefronts of the column solve (2, 4 or 8 waves, 16 levels per
-lane, wave totals exchanged through LDS).  The HIP path through the C ABI against
+"""GPU parity for long time axes: 512 < N_t <= 1024 (one wavefront per spectrum
+column) and 1024 < N_t <= 8192, where one column spans several wavefronts of the
+column solve (2, 4 or 8 waves, 16 levels per lane, wave totals exchanged
+through LDS).  The HIP path through the C ABI against
 the FP64 CPU oracle: K_d^{-1} r at 1e-10 (FP64) and 1e-5 (FP32), and Algorithm 1
 trajectories (fused and unfused loop bodies) at 1e-10.  N_t values include
 ragged tails (not a multiple of 1024, of 64 or of 16).
@@ -36,6 +37,7 @@ def _err(gpu, ref, name=""):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("nx,nt,time,c,ghat", [
+    (16, 600, "bdf2", 0.8, 0.0), (64, 900, "bdf2", 1.0, 0.0), (32, 1024, "be", 0.6, 0.0),
     (16, 1025, "be", 1.0, 0.0), (8, 2048, "bdf2", 0.7, 0.0), (32, 1999, "bdf2", 0.9, 1e-3),
     (16, 3000, "be", 0.5, 0.0), (64, 4096, "bdf2", 1.0, 0.0), (8, 5003, "bdf2", 0.3, 0.0),
     (16, 8192, "be", 1.0, 0.0), (8, 8192, "bdf2", 0.95, 0.0)])
