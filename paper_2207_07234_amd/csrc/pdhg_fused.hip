@@ -46,7 +46,7 @@ __host__ __device__ constexpr bool fft_pingpong(int nx) { return 3 * (size_t)nx 
 template <typename T, int EPT, typename S>
 __global__ void __launch_bounds__(kRowThreadsMax)
 k_dual_fft(const S* __restrict__ spec, int nt, int lqb, int nx, const C2<S>* __restrict__ tw, T* __restrict__ phi,
-           T* __restrict__ phibar, T tau, const Ctrl* ctrl) {
+           T* __restrict__ phibar, T tau, const Ctrl* ctrl, const T* __restrict__ s0) {
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
   C2<S>* buf = reinterpret_cast<C2<S>*>(smem);
@@ -54,7 +54,7 @@ k_dual_fft(const S* __restrict__ spec, int nt, int lqb, int nx, const C2<S>* __r
   const int tid = threadIdx.x, W = blockDim.x;
   const int a = 2 * xcd_block(blockIdx.x, gridDim.x);
   C2<S>* alt = fft_pingpong<S>(nx) ? twl + lds_fft_points(nx) : nullptr;
-  dual_fft_pair<T, EPT, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl, alt);
+  dual_fft_pair<T, EPT, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl, alt, s0);
 }
 
 // B: one block per pair of implicit rows, W = 64 nw threads, E = nx / W.  The
@@ -100,57 +100,57 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
 // C: 8 waves per block, one spectrum column each.  With part != NULL the
 // first wave of block 0 first reduces the iteration's partial sums and takes
 // the stopping decision.
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, typename A>
 __global__ void __launch_bounds__(64 * kFdColWaves)
-k_colsolve_wave(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
-                int nparts, double wscale, double* hist) {
+k_colsolve_wave(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                int nparts, double wscale, double* hist, A* s0) {
   if (ctrl && ctrl->status != 0) return;
   if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
   extern __shared__ char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  colsolve_group<T, BW, LPL>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile);
+  colsolve_group<T, BW, LPL, A>(spec, fac, nt, nx, lqb, xcd_block(blockIdx.x, gridDim.x) * kColCols, tile, s0);
 }
 
 // C for N_t <= 512: kColsHalf columns per block, two per wave (32 lanes each).
 constexpr int kColsHalf = 4;
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, typename A>
 __global__ void __launch_bounds__(32 * kColsHalf)
-k_colsolve_half(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
-                int nparts, double wscale, double* hist) {
+k_colsolve_half(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                int nparts, double wscale, double* hist, A* s0) {
   if (ctrl && ctrl->status != 0) return;
   if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
   extern __shared__ char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  colsolve_group_half<T, BW, LPL, kColsHalf>(spec, fac, nt, nx, lqb,
-                                             xcd_block(blockIdx.x, gridDim.x) * kColsHalf, tile);
+  colsolve_group_half<T, BW, LPL, kColsHalf, 32, A>(spec, fac, nt, nx, lqb,
+                                                    xcd_block(blockIdx.x, gridDim.x) * kColsHalf, tile, s0);
 }
 
 // C for N_t <= 256: kColsQuarter columns per block, four per wave (16 lanes each).
 constexpr int kColsQuarter = 8;
-template <typename T, int BW, int LPL>
+template <typename T, int BW, int LPL, typename A>
 __global__ void __launch_bounds__(16 * kColsQuarter)
-k_colsolve_quarter(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
-                   int nparts, double wscale, double* hist) {
+k_colsolve_quarter(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                   int nparts, double wscale, double* hist, A* s0) {
   if (ctrl && ctrl->status != 0) return;
   if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
   extern __shared__ char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  colsolve_group_half<T, BW, LPL, kColsQuarter, 16>(spec, fac, nt, nx, lqb,
-                                                     xcd_block(blockIdx.x, gridDim.x) * kColsQuarter, tile);
+  colsolve_group_half<T, BW, LPL, kColsQuarter, 16, A>(spec, fac, nt, nx, lqb,
+                                                       xcd_block(blockIdx.x, gridDim.x) * kColsQuarter, tile, s0);
 }
 
 // C for 1024 < N_t <= 8192: WPC waves per column, 8 / WPC columns per block.
-template <typename T, int BW, int WPC>
+template <typename T, int BW, int WPC, typename A>
 __global__ void __launch_bounds__(512)
-k_colsolve_long(T* __restrict__ spec, FacTab<T> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
-                int nparts, double wscale, double* hist) {
+k_colsolve_long(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
+                int nparts, double wscale, double* hist, A* s0) {
   if (ctrl && ctrl->status != 0) return;
   if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
   extern __shared__ char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  T* xch = tile + 8 * kColLongLpl * 65;
-  colsolve_group_long<T, BW, kColLongLpl, WPC>(spec, fac, nt, nx, lqb,
-                                                xcd_block(blockIdx.x, gridDim.x) * (8 / WPC), tile, xch);
+  A* xch = reinterpret_cast<A*>(tile + 8 * kColLongLpl * 65);
+  colsolve_group_long<T, BW, kColLongLpl, WPC, A>(spec, fac, nt, nx, lqb,
+                                                   xcd_block(blockIdx.x, gridDim.x) * (8 / WPC), tile, xch, s0);
 }
 
 // C (full-symbol preconditioner): per Fourier mode k, K_k = L_k L_k^* with
@@ -303,27 +303,27 @@ hipError_t launch_colsolve_full(T* spec, const FullSym& F, const void* tw, int n
 
 template <typename T, int EPT, typename S>
 static hipError_t launch_dual_fft_e(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
-                                    const Ctrl* ctrl, hipStream_t st) {
+                                    const Ctrl* ctrl, hipStream_t st, const T* s0) {
   const int W = nx / EPT;
   const size_t lds = sizeof(C2<S>) * (fft_pingpong<S>(nx) ? 3 : 2) * (size_t)lds_fft_points(nx);
   hipError_t e = allow_lds(k_dual_fft<T, EPT, S>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dual_fft<T, EPT, S>), dim3((nt + 1) / 2), dim3(W), lds, st, spec, nt, lqb, nx,
-                     (const C2<S>*)tw, phi, phibar, tau, ctrl);
+                     (const C2<S>*)tw, phi, phibar, tau, ctrl, s0);
   return hipGetLastError();
 }
 
 // A: nx >= 64.
 template <typename T, typename S>
 hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
-                           const Ctrl* ctrl, hipStream_t st) {
+                           const Ctrl* ctrl, hipStream_t st, const T* s0) {
   // EPT = nx / W with W = min(512, nx / 2) threads for nx >= 128 (8 waves at nx = 2048)
   const int W = nx >= 1024 ? 512 : (nx >= 128 ? nx / 2 : nx);
   switch (nx / W) {
-    case 1: return launch_dual_fft_e<T, 1, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
-    case 2: return launch_dual_fft_e<T, 2, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
-    case 4: return launch_dual_fft_e<T, 4, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
-    case 8: return launch_dual_fft_e<T, 8, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st);
+    case 1: return launch_dual_fft_e<T, 1, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st, s0);
+    case 2: return launch_dual_fft_e<T, 2, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st, s0);
+    case 4: return launch_dual_fft_e<T, 4, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st, s0);
+    case 8: return launch_dual_fft_e<T, 8, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, ctrl, st, s0);
     default: return hipErrorInvalidValue;
   }
 }
@@ -360,51 +360,51 @@ hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* 
   }
 }
 
-template <typename T, int BW, int LPL>
-static hipError_t launch_colsolve_half_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+template <typename T, int BW, int LPL, typename A>
+static hipError_t launch_colsolve_half_l(T* spec, const FacTab<A>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                          const double* part, int nparts, double wscale, double* hist,
-                                         hipStream_t st) {
+                                         hipStream_t st, A* s0) {
   const size_t lds = sizeof(T) * (size_t)kColsHalf * LPL * 33;
-  hipError_t e = allow_lds(k_colsolve_half<T, BW, LPL>, lds);
+  hipError_t e = allow_lds(k_colsolve_half<T, BW, LPL, A>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_colsolve_half<T, BW, LPL>), dim3(nx / kColsHalf), dim3(32 * kColsHalf), lds, st, spec,
-                     fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist);
+  hipLaunchKernelGGL((k_colsolve_half<T, BW, LPL, A>), dim3(nx / kColsHalf), dim3(32 * kColsHalf), lds, st, spec,
+                     fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, s0);
   return hipGetLastError();
 }
 
-template <typename T, int BW, int LPL>
-static hipError_t launch_colsolve_quarter_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+template <typename T, int BW, int LPL, typename A>
+static hipError_t launch_colsolve_quarter_l(T* spec, const FacTab<A>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                             const double* part, int nparts, double wscale, double* hist,
-                                            hipStream_t st) {
+                                            hipStream_t st, A* s0) {
   const size_t lds = sizeof(T) * (size_t)kColsQuarter * LPL * 17;
-  hipError_t e = allow_lds(k_colsolve_quarter<T, BW, LPL>, lds);
+  hipError_t e = allow_lds(k_colsolve_quarter<T, BW, LPL, A>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_colsolve_quarter<T, BW, LPL>), dim3(nx / kColsQuarter), dim3(16 * kColsQuarter), lds, st,
-                     spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist);
+  hipLaunchKernelGGL((k_colsolve_quarter<T, BW, LPL, A>), dim3(nx / kColsQuarter), dim3(16 * kColsQuarter), lds, st,
+                     spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, s0);
   return hipGetLastError();
 }
 
-template <typename T, int BW, int LPL>
-static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+template <typename T, int BW, int LPL, typename A>
+static hipError_t launch_colsolve_wave_l(T* spec, const FacTab<A>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                          const double* part, int nparts, double wscale, double* hist,
-                                         hipStream_t st) {
+                                         hipStream_t st, A* s0) {
   const size_t lds = sizeof(T) * (size_t)kColCols * LPL * 65;
-  hipError_t e = allow_lds(k_colsolve_wave<T, BW, LPL>, lds);
+  hipError_t e = allow_lds(k_colsolve_wave<T, BW, LPL, A>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_colsolve_wave<T, BW, LPL>), dim3(nx / kColCols), dim3(64 * kFdColWaves), lds, st, spec, fac,
-                     nt, nx, lqb, ctrl, part, nparts, wscale, hist);
+  hipLaunchKernelGGL((k_colsolve_wave<T, BW, LPL, A>), dim3(nx / kColCols), dim3(64 * kFdColWaves), lds, st, spec, fac,
+                     nt, nx, lqb, ctrl, part, nparts, wscale, hist, s0);
   return hipGetLastError();
 }
 
-template <typename T, int BW, int WPC>
-static hipError_t launch_colsolve_long_l(T* spec, const FacTab<T>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
+template <typename T, int BW, int WPC, typename A>
+static hipError_t launch_colsolve_long_l(T* spec, const FacTab<A>& fac, int nt, int nx, int lqb, Ctrl* ctrl,
                                          const double* part, int nparts, double wscale, double* hist,
-                                         hipStream_t st) {
-  const size_t lds = sizeof(T) * ((size_t)8 * kColLongLpl * 65 + 48);
-  hipError_t e = allow_lds(k_colsolve_long<T, BW, WPC>, lds);
+                                         hipStream_t st, A* s0) {
+  const size_t lds = sizeof(T) * (size_t)8 * kColLongLpl * 65 + sizeof(A) * 48;
+  hipError_t e = allow_lds(k_colsolve_long<T, BW, WPC, A>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_colsolve_long<T, BW, WPC>), dim3(nx / (8 / WPC)), dim3(512), lds, st, spec, fac, nt, nx,
-                     lqb, ctrl, part, nparts, wscale, hist);
+  hipLaunchKernelGGL((k_colsolve_long<T, BW, WPC, A>), dim3(nx / (8 / WPC)), dim3(512), lds, st, spec, fac, nt, nx,
+                     lqb, ctrl, part, nparts, wscale, hist, s0);
   return hipGetLastError();
 }
 
@@ -413,13 +413,13 @@ static hipError_t launch_colsolve_long_l(T* spec, const FacTab<T>& fac, int nt, 
 // takes the stopping decision (ctrl must then be non-NULL).  N_t <= 256: four
 // 16-lane columns per wave; up to 512: two 32-lane columns per wave; up to
 // 1024: one wavefront per column; beyond: 2, 4 or 8 wavefronts per column.
-template <typename T>
-hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
-                                const double* part, int nparts, double wscale, double* hist, hipStream_t st) {
+template <typename T, typename A>
+hipError_t launch_colsolve_wave(T* spec, const FacTab<A>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                const double* part, int nparts, double wscale, double* hist, hipStream_t st, A* s0) {
   if (nt <= 256) {
     const int lq = (nt + 15) / 16;
 #define PDHG_CQ(B, L) \
-  return launch_colsolve_quarter_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+  return launch_colsolve_quarter_l<T, B, L, A>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st, s0)
     if (bw == 2) {
       if (lq <= 1) PDHG_CQ(2, 1);
       if (lq <= 2) PDHG_CQ(2, 2);
@@ -438,7 +438,7 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
   if (nt <= 512) {
     const int lh = (nt + 31) / 32;
 #define PDHG_CH(B, L) \
-  return launch_colsolve_half_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+  return launch_colsolve_half_l<T, B, L, A>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st, s0)
     if (bw == 2) {
       if (lh <= 1) PDHG_CH(2, 1);
       if (lh <= 2) PDHG_CH(2, 2);
@@ -456,7 +456,7 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
   }
   const int lpl = (nt + 63) / 64;
 #define PDHG_CW(B, L) \
-  return launch_colsolve_wave_l<T, B, L>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+  return launch_colsolve_wave_l<T, B, L, A>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st, s0)
   if (bw == 2) {
     if (lpl <= 1) PDHG_CW(2, 1);
     if (lpl <= 2) PDHG_CW(2, 2);
@@ -472,7 +472,7 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
   }
 #undef PDHG_CW
 #define PDHG_CL(B, W) \
-  return launch_colsolve_long_l<T, B, W>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st)
+  return launch_colsolve_long_l<T, B, W, A>(spec, fac, nt, nx, lqb, ctrl, part, nparts, wscale, hist, st, s0)
   const int wpc = (nt + 64 * kColLongLpl - 1) / (64 * kColLongLpl);
   if (bw == 2) {
     if (wpc <= 2) PDHG_CL(2, 2);
@@ -488,11 +488,11 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, i
 }
 
 template hipError_t launch_dual_fft<float, float>(const float*, int, int, int, const void*, float*, float*, float,
-                                                  const Ctrl*, hipStream_t);
+                                                  const Ctrl*, hipStream_t, const float*);
 template hipError_t launch_dual_fft<double, double>(const double*, int, int, int, const void*, double*, double*,
-                                                    double, const Ctrl*, hipStream_t);
+                                                    double, const Ctrl*, hipStream_t, const double*);
 template hipError_t launch_dual_fft<double, float>(const float*, int, int, int, const void*, double*, double*,
-                                                   double, const Ctrl*, hipStream_t);
+                                                   double, const Ctrl*, hipStream_t, const double*);
 template hipError_t launch_primal_res<float, float>(const Scheme&, const float*, float*, const float*, const float*,
                                                     float, float*, int, const void*, double*, const Ctrl*,
                                                     hipStream_t);
@@ -502,13 +502,15 @@ template hipError_t launch_primal_res<double, double>(const Scheme&, const doubl
 template hipError_t launch_primal_res<double, float>(const Scheme&, const double*, double*, const double*,
                                                      const double*, double, float*, int, const void*, double*,
                                                      const Ctrl*, hipStream_t);
-template hipError_t launch_colsolve_wave<float>(float*, const FacTab<float>&, int, int, int, int, Ctrl*,
-                                                const double*, int, double, double*, hipStream_t);
+template hipError_t launch_colsolve_wave<float, float>(float*, const FacTab<float>&, int, int, int, int, Ctrl*,
+                                                       const double*, int, double, double*, hipStream_t, float*);
+template hipError_t launch_colsolve_wave<float, double>(float*, const FacTab<double>&, int, int, int, int, Ctrl*,
+                                                        const double*, int, double, double*, hipStream_t, double*);
 template hipError_t launch_colsolve_full<float>(float*, const FullSym&, const void*, int, int, int, Ctrl*,
                                                 const double*, int, double, double*, hipStream_t);
 template hipError_t launch_colsolve_full<double>(double*, const FullSym&, const void*, int, int, int, Ctrl*,
                                                  const double*, int, double, double*, hipStream_t);
-template hipError_t launch_colsolve_wave<double>(double*, const FacTab<double>&, int, int, int, int, Ctrl*,
-                                                 const double*, int, double, double*, hipStream_t);
+template hipError_t launch_colsolve_wave<double, double>(double*, const FacTab<double>&, int, int, int, int, Ctrl*,
+                                                         const double*, int, double, double*, hipStream_t, double*);
 
 }  // namespace pdhg

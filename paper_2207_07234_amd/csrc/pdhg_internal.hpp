@@ -56,16 +56,22 @@ hipError_t launch_adjoint_march(const Scheme& s, const T* u, const T* g, T* mu, 
 
 namespace pdhg {
 // S: type of the spectrum, the FFT and the twiddle table tw (T, or float with
-// an FP64 state and the single-precision preconditioner).
+// an FP64 state and the single-precision preconditioner).  s0 (optional, nt
+// values of type T): mode 0 of each spectrum row, taken from there instead of
+// the spectrum.
 template <typename T, typename S = T>
 hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
-                           const Ctrl* ctrl, hipStream_t st);
+                           const Ctrl* ctrl, hipStream_t st, const T* s0 = nullptr);
 template <typename T, typename S = T>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
                              S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st);
-template <typename T>
-hipError_t launch_colsolve_wave(T* spec, const FacTab<T>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
-                                const double* part, int nparts, double wscale, double* hist, hipStream_t st);
+// T: type of the spectrum; A: type of the factor rows and of the recurrences
+// (double for a float spectrum under an FP64 state).  s0 (optional, nt values
+// of type A): receives the mode-0 column of the solution.
+template <typename T, typename A = T>
+hipError_t launch_colsolve_wave(T* spec, const FacTab<A>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                const double* part, int nparts, double wscale, double* hist, hipStream_t st,
+                                A* s0 = nullptr);
 // Full-symbol preconditioner: g_k = (wr + vr)(1 - cos theta_k) + i ci sin theta_k per Fourier mode.
 struct FullSym {
   double inv_ht;   // 1 / h_t

@@ -30,7 +30,8 @@ template <typename T, int EPT, typename S = T>
 __device__ __forceinline__ void dual_fft_pair(const S* __restrict__ spec, int nt, int lqb, int nx,
                                               const C2<S>* __restrict__ tw, T* __restrict__ phi,
                                               T* __restrict__ phibar, T tau, int a, int tid, int W, int gtid, int TB,
-                                              C2<S>* buf, C2<S>* twl, C2<S>* alt = nullptr) {
+                                              C2<S>* buf, C2<S>* twl, C2<S>* alt = nullptr,
+                                              const T* __restrict__ s0 = nullptr) {
   const int b = a + 1;
   const bool act = a < nt, hasb = b < nt;
   const int half = nx >> 1;
@@ -60,8 +61,10 @@ __device__ __forceinline__ void dual_fft_pair(const S* __restrict__ spec, int nt
     if (act && k <= half) {
       if (k == 0 || k == half) {
         const int q = (k == 0) ? 0 : 1;
-        sar[e] = spec[spec_index(a, q, nt, lqb)];
-        if (hasb) sbr[e] = spec[spec_index(b, q, nt, lqb)];
+        if (k == half || !s0) {
+          sar[e] = spec[spec_index(a, q, nt, lqb)];
+          if (hasb) sbr[e] = spec[spec_index(b, q, nt, lqb)];
+        }
       } else {
         sar[e] = spec[spec_index(a, 2 * k, nt, lqb)];
         sai[e] = spec[spec_index(a, 2 * k + 1, nt, lqb)];
@@ -88,18 +91,21 @@ __device__ __forceinline__ void dual_fft_pair(const S* __restrict__ spec, int nt
   }
   const C2<S>* res = fft_lds<true, EPT>(buf, nx, twl, tid, W, alt);
   const S sc = S(1) / S(nx);
+  // with s0: the row means (mode 0) come from s0 in T, not from the float FFT
+  const T inv_nx = T(1) / T(nx);
+  const T ma = (s0 && act) ? s0[a] * inv_nx : T(0), mb = (s0 && hasb) ? s0[b] * inv_nx : T(0);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int x = tid + e * W;
     const C2<S> z = res[lpad(x)];
     if (act) {
-      const T ta = tau * T(z.x * sc);
+      const T ta = tau * (T(z.x * sc) + ma);
       const T p = fa[e] + ta;
       pa[x] = p;
       qa[x] = p + ta;
     }
     if (hasb) {
-      const T tb = tau * T(z.y * sc);
+      const T tb = tau * (T(z.y * sc) + mb);
       const T q = fb[e] + tb;
       pb[x] = q;
       qb[x] = q + tb;
@@ -702,12 +708,24 @@ __device__ __forceinline__ void finalize_wave(Ctrl* ctrl, const double* __restri
   if (lane == 0) finalize_body(ctrl, a, b, wscale, hist);
 }
 
+// Mode 0 of a float spectrum under an FP64 state: the row means of s = K_d^{-1} r
+// are kept in the arithmetic type A (s0[l], l < nt) besides the float
+// spectrum.  Mode 0 of K_d is the bare time Gram B_t B_t^T, whose solution is
+// large and smooth in t, and the primal step takes its time difference: float
+// rounding of it would be amplified by up to N_t there.
+template <typename A, int LPL>
+__device__ __forceinline__ void store_mode0(const A (&z)[LPL], A* __restrict__ s0, int l0, int nt) {
+#pragma unroll
+  for (int i = 0; i < LPL; ++i)
+    if (l0 + i < nt) s0[l0 + i] = z[i];
+}
+
 // Column solve of spectrum columns q0..q0+7 (q0 a multiple of 8) by the 8
 // waves of the calling block, one column each.  tile: kColCols * LPL * 65
 // elements of LDS.
-template <typename T, int BW, int LPL>
-__device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx, int lqb,
-                                               int q0, T* tile) {
+template <typename T, int BW, int LPL, typename A = T>
+__device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTab<A>& fac, int nt, int nx, int lqb,
+                                               int q0, T* tile, A* __restrict__ s0 = nullptr) {
   const int QB = 1 << lqb;
   T* base = spec + (size_t)(q0 >> lqb) * nt * QB + (q0 & (QB - 1));
   const int tid = threadIdx.x;
@@ -717,8 +735,8 @@ __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTa
   const int kmode = spec_mode(q0 + wv, nx);
   const int l0 = lane * LPL;
   // factor rows of this wave's mode first, so their latency overlaps the tile loads
-  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
-  load_factor_rows<T, LPL>(fac, kmode, l0, invd, e1, e2);
+  A invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<A, LPL>(fac, kmode, l0, invd, e1, e2);
   // all tile loads in flight before the first LDS write
   T stage[kPer];
 #pragma unroll
@@ -734,12 +752,13 @@ __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTa
     tile[(c * LPL + l % LPL) * 65 + l / LPL] = stage[r];
   }
   __syncthreads();
-  T z[1][LPL];
+  A z[1][LPL];
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) z[0][i] = tile[(wv * LPL + i) * 65 + lane];
-  cholesky_solve_wave<T, BW, LPL, 1>(z, invd, e1, e2, lane, l0, nt);
+  for (int i = 0; i < LPL; ++i) z[0][i] = A(tile[(wv * LPL + i) * 65 + lane]);
+  cholesky_solve_wave<A, BW, LPL, 1>(z, invd, e1, e2, lane, l0, nt);
+  if (s0 && q0 + wv == 0) store_mode0<A, LPL>(z[0], s0, l0, nt);
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) tile[(wv * LPL + i) * 65 + lane] = z[0][i];
+  for (int i = 0; i < LPL; ++i) tile[(wv * LPL + i) * 65 + lane] = T(z[0][i]);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
@@ -762,9 +781,9 @@ __device__ __forceinline__ void colsolve_group(T* __restrict__ spec, const FacTa
 // columns instead of as many waves with one each, which cuts the scan work
 // per column.  tile: NCOL * LPL * (CW + 1) elements of LDS.
 constexpr int kColHalfThreads = 256;
-template <typename T, int BW, int LPL, int NCOL = kColCols, int CW = 32>
-__device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx,
-                                                    int lqb, int q0, T* tile) {
+template <typename T, int BW, int LPL, int NCOL = kColCols, int CW = 32, typename A = T>
+__device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const FacTab<A>& fac, int nt, int nx,
+                                                    int lqb, int q0, T* tile, A* __restrict__ s0 = nullptr) {
   constexpr int kThreads = CW * NCOL;
   constexpr int TS = CW + 1;   // tile row stride
   const int QB = 1 << lqb;
@@ -775,8 +794,8 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
   const int col = wv * (64 / CW) + lane / CW, q = lane % CW;
   const int kmode = spec_mode(q0 + col, nx);
   const int l0 = q * LPL;
-  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
-  load_factor_rows<T, LPL>(fac, kmode, l0, invd, e1, e2);
+  A invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<A, LPL>(fac, kmode, l0, invd, e1, e2);
   T stage[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
@@ -791,12 +810,13 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
     tile[(c * LPL + l % LPL) * TS + l / LPL] = stage[r];
   }
   __syncthreads();
-  T z[1][LPL];
+  A z[1][LPL];
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) z[0][i] = tile[(col * LPL + i) * TS + q];
-  cholesky_solve_wave<T, BW, LPL, 1, CW>(z, invd, e1, e2, lane, l0, nt);
+  for (int i = 0; i < LPL; ++i) z[0][i] = A(tile[(col * LPL + i) * TS + q]);
+  cholesky_solve_wave<A, BW, LPL, 1, CW>(z, invd, e1, e2, lane, l0, nt);
+  if (s0 && q0 + col == 0) store_mode0<A, LPL>(z[0], s0, l0, nt);
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) tile[(col * LPL + i) * TS + q] = z[0][i];
+  for (int i = 0; i < LPL; ++i) tile[(col * LPL + i) * TS + q] = T(z[0][i]);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
@@ -816,9 +836,9 @@ __device__ __forceinline__ void colsolve_group_half(T* __restrict__ spec, const 
 // of 8 / WPC) by the block's 8 waves, WPC consecutive waves per column and
 // LPL levels per lane.  Wave v of the block holds levels 64 LPL (v % WPC) ..
 // of column v / WPC.  tile: 8 * LPL * 65 elements of LDS, xch: 48 more.
-template <typename T, int BW, int LPL, int WPC>
-__device__ __forceinline__ void colsolve_group_long(T* __restrict__ spec, const FacTab<T>& fac, int nt, int nx,
-                                                    int lqb, int q0, T* tile, T* xch) {
+template <typename T, int BW, int LPL, int WPC, typename A = T>
+__device__ __forceinline__ void colsolve_group_long(T* __restrict__ spec, const FacTab<A>& fac, int nt, int nx,
+                                                    int lqb, int q0, T* tile, A* xch, A* __restrict__ s0 = nullptr) {
   constexpr int kWaves = 8;
   constexpr int kThreads = 64 * kWaves;
   constexpr int NCB = kWaves / WPC;   // columns per block
@@ -830,8 +850,8 @@ __device__ __forceinline__ void colsolve_group_long(T* __restrict__ spec, const 
   const int col = wv / WPC;
   const int kmode = spec_mode(q0 + col, nx);
   const int l0 = ((wv % WPC) * 64 + lane) * LPL;
-  T invd[LPL], e1[LPL + 1], e2[LPL + 2];
-  load_factor_rows<T, LPL>(fac, kmode, l0, invd, e1, e2);
+  A invd[LPL], e1[LPL + 1], e2[LPL + 2];
+  load_factor_rows<A, LPL>(fac, kmode, l0, invd, e1, e2);
   T stage[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
@@ -847,12 +867,13 @@ __device__ __forceinline__ void colsolve_group_long(T* __restrict__ spec, const 
     tile[((c * WPC + (g >> 6)) * LPL + l % LPL) * 65 + (g & 63)] = stage[r];
   }
   __syncthreads();
-  T z[LPL];
+  A z[LPL];
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) z[i] = tile[(wv * LPL + i) * 65 + lane];
-  cholesky_solve_multi<T, BW, LPL, WPC>(z, invd, e1, e2, lane, wv, l0, nt, xch);
+  for (int i = 0; i < LPL; ++i) z[i] = A(tile[(wv * LPL + i) * 65 + lane]);
+  cholesky_solve_multi<A, BW, LPL, WPC>(z, invd, e1, e2, lane, wv, l0, nt, xch);
+  if (s0 && q0 + col == 0) store_mode0<A, LPL>(z, s0, l0, nt);
 #pragma unroll
-  for (int i = 0; i < LPL; ++i) tile[(wv * LPL + i) * 65 + lane] = z[i];
+  for (int i = 0; i < LPL; ++i) tile[(wv * LPL + i) * 65 + lane] = T(z[i]);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {

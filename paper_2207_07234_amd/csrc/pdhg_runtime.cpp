@@ -251,7 +251,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
-  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, total;
+  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, total;
   int max_parts;
 };
 
@@ -283,10 +283,6 @@ struct pdhg_handle {
   double fac_c = -1.0, fac_g = -1.0;
   // single-precision preconditioner of an FP64 problem: float twiddles and factors
   void* d_tw32 = nullptr;
-  void* d_fac32_rows = nullptr;
-  int* d_fac32_off = nullptr;
-  int* d_fac32_last = nullptr;
-  double fac32_c = -1.0, fac32_g = -1.0;
   void* d_vtab = nullptr;       // DG: per-mode 6x6 eigenbases of the coefficient coupling
   // resolved constants
   double lf = 0.0, c = 0.0;
@@ -365,6 +361,7 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.scal = o; o += align_up(sizeof(double) * 64);
   L.ctrl = o; o += align_up(sizeof(Ctrl));
   L.ctrl_t = o; o += align_up(sizeof(Ctrl));     // control block used only by kernel timing
+  L.s0 = o; o += align_up(sizeof(double) * nt);    // FP64 mode 0 of a float spectrum
   L.total = o;
   return L;
 }
@@ -561,31 +558,6 @@ FacTab<T> factab(const pdhg_handle* h) {
   return FacTab<T>{(const FacRow<T>*)h->d_fac_rows, h->d_fac_off, h->d_fac_last};
 }
 
-FacTab<float> factab32(const pdhg_handle* h) {
-  return FacTab<float>{(const FacRow<float>*)h->d_fac32_rows, h->d_fac32_off, h->d_fac32_last};
-}
-
-// Float factor tables of an FP64 problem with the single-precision preconditioner.
-int upload_factors32(pdhg_handle* h, double c, double ghat) {
-  std::vector<FacRow<float>> rows;
-  std::vector<int> off, last;
-  build_factor_rows<float>(h->prob, c, ghat, rows, off, last);
-  if (h->d_fac32_rows) hipFree(h->d_fac32_rows);
-  if (h->d_fac32_off) hipFree(h->d_fac32_off);
-  if (h->d_fac32_last) hipFree(h->d_fac32_last);
-  h->d_fac32_rows = nullptr;
-  h->d_fac32_off = h->d_fac32_last = nullptr;
-  HIP_TRY(hipMalloc(&h->d_fac32_rows, rows.size() * sizeof(FacRow<float>)));
-  HIP_TRY(hipMalloc((void**)&h->d_fac32_off, off.size() * sizeof(int)));
-  HIP_TRY(hipMalloc((void**)&h->d_fac32_last, last.size() * sizeof(int)));
-  HIP_TRY(hipMemcpy(h->d_fac32_rows, rows.data(), rows.size() * sizeof(FacRow<float>), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(h->d_fac32_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(h->d_fac32_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
-  h->fac32_c = c;
-  h->fac32_g = ghat;
-  return PDHG_OK;
-}
-
 int ensure_workspace(pdhg_handle* h, void*& ws) {
   if (ws) return PDHG_OK;
   const WsLayout L = layout_for(h->prob, h->esz);
@@ -649,10 +621,6 @@ int resolve_constants_p(pdhg_handle* h, const T* u0, double* part, hipStream_t s
     }
   } else if (!h->d_fac_rows || h->fac_c != c || h->fac_g != p.precond_gamma_hat) {
     int rc = upload_factors<T>(h, c, p.precond_gamma_hat);
-    if (rc) return rc;
-  }
-  if (is_pre32(p) && (!h->d_fac32_rows || h->fac32_c != c || h->fac32_g != p.precond_gamma_hat)) {
-    int rc = upload_factors32(h, c, p.precond_gamma_hat);
     if (rc) return rc;
   }
   return PDHG_OK;
@@ -823,9 +791,6 @@ void pdhg_destroy(pdhg_handle* h) {
   if (h->d_fac_off) hipFree(h->d_fac_off);
   if (h->d_fac_last) hipFree(h->d_fac_last);
   if (h->d_tw32) hipFree(h->d_tw32);
-  if (h->d_fac32_rows) hipFree(h->d_fac32_rows);
-  if (h->d_fac32_off) hipFree(h->d_fac32_off);
-  if (h->d_fac32_last) hipFree(h->d_fac32_last);
   if (h->d_vtab) hipFree(h->d_vtab);
   if (h->own_ws) hipFree(h->own_ws);
   if (h->h_ctrl) hipHostFree(h->h_ctrl);
@@ -886,12 +851,14 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
   T* uout = odd ? u_alt : u;
   if (is_pre32(p)) {   // the spectrum, its FFTs and the column solve in float
     float* spec32 = (float*)wsp(ws, L.spec0);
-    HIP_TRY((launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tau_phi, ctrl, st)));
+    T* s0 = (T*)wsp(ws, L.s0);   // mode 0 of the spectrum in FP64
+    HIP_TRY((launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tau_phi, ctrl, st, s0)));
     HIP_TRY((launch_primal_res<T, float>(s, uin, uout, phibar, phi, tau_u, spec32, h->lqb, h->d_tw32, part, ctrl,
                                          st)));
     const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
-    HIP_TRY(launch_colsolve_wave<float>(spec32, factab32(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb, ctrl,
-                                        part, (p.nt + 1) / 2, wscale, hist, st));
+    HIP_TRY((launch_colsolve_wave<float, double>(spec32, factab<double>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
+                                                 h->lqb, ctrl, part, (p.nt + 1) / 2, wscale, hist, st,
+                                                 (double*)s0)));
     return PDHG_OK;
   }
   HIP_TRY(launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
@@ -998,6 +965,7 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   }
   HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
   HIP_TRY(launch_fill<T>(spec, n, T(0), st));
+  if (is_pre32(p)) HIP_TRY(launch_fill<T>((T*)wsp(ws, L.s0), (size_t)p.nt, T(0), st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
   // without a residual history: Rd only where the stopping test needs it
   const int rd_lazy = prm->history ? 0 : 1;
@@ -1566,10 +1534,13 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
         case 0:
           return launch_primal_res<T, float>(s, u, u_alt, phibar, phi, tu, spec32, h->lqb, h->d_tw32, prp, ctrl_t,
                                              st);
-        case 7: return launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tp, nullptr, st);
+        case 7:
+          return launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tp, nullptr, st,
+                                           (const T*)wsp(ws, L.s0));
         case 1:
-          return launch_colsolve_wave<float>(spec32, factab32(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx, h->lqb,
-                                             nullptr, nullptr, 0, 0.0, nullptr, st);
+          return launch_colsolve_wave<float, double>(spec32, factab<double>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt,
+                                                      p.nx, h->lqb, nullptr, nullptr, 0, 0.0, nullptr, st,
+                                                      (double*)wsp(ws, L.s0));
         default: break;
       }
     }

@@ -131,31 +131,18 @@ def test_mixed_unsupported_combinations(gpu_lib):
         small.solve(_dev(syn.fourier_u0(0, 32)), max_iter=4)
 
 
-EPS32 = float(np.finfo(np.float32).eps)
-
-
-def _trajectory_bound(oprob, tau, n_iter, phi_ref):
-    """Rounding bound for the iterates of the float spectral pass.  Each iteration rounds s = K^-1 r
-    relative to its size, so phibar = phi + 2 tau s carries an error of a few eps32 times
-    |2 tau s| <= 2 max|phi|.  The primal step multiplies it by tau times the row sum of |J^T|, at
-    most 4/h_t + (2 lf + 2 max|f'|)/(2 h_x), and the errors add up over the iterations.  A factor
-    4 covers the FFTs and the banded solve.  This is the form of the FP32 trajectory bound."""
-    row = 4.0 / oprob.ht + 2.0 * max(oprob.lf_speed, 1.0) / oprob.hx + 4.0 * oprob.gamma / oprob.hx ** 2
-    return 4.0 * n_iter * EPS32 * tau * row * 2.0 * float(np.max(np.abs(phi_ref))) + 1e-5
-
-
 @pytest.mark.parametrize("nt,time", [(900, "bdf2"), (1500, "be")])
 def test_mixed_long_time_axis(gpu_lib, nt, time):
     """The float column solve for 512 < N_t <= 1024 (one wavefront per column) and beyond (several
-    wavefronts per column): 10 iterations within the derived rounding bound of the FP64 oracle.  Small
-    h_t makes the row sum of |J^T| large, so the flat 1e-5 bar does not apply here."""
+    wavefronts per column): 10 iterations within the FP32 bar of the FP64 oracle.  The recurrences
+    run in FP64 on the float spectrum and mode 0 of s stays FP64 end to end: its rounding to float
+    would be amplified up to N_t times by the time difference of the primal step (the CPU emulation
+    in test_float_spectral_emulation.py shows both effects)."""
     cfg = dict(nx=64, nt=nt, t_final=nt / 256, alpha=0.5, beta=0.0, gamma=0.0, time=time, space="fd_lf")
     u0 = syn.fourier_u0(4, cfg["nx"])
     oprob, gprob = _pair(gpu_lib, u0, **cfg)
     ref = opdhg.run(oprob, u0, 0.6, 0.6, eps=0.0, max_iter=10)
     res = gpu_lib.Solver(gprob).solve(_dev(u0), tau_u=0.6, tau_phi=0.6, eps=0.0, max_iter=10, check_every=2)
     assert res.stats["iters"] == 10
-    tol = _trajectory_bound(oprob, 0.6, 10, ref.phi)
-    _say(f"  bound {tol:.3e}")
-    assert _err(res.u, ref.u, "u") < tol
-    assert _err(res.phi, ref.phi, "phi") < tol
+    assert _err(res.u, ref.u, "u") < 1e-5
+    assert _err(res.phi, ref.phi, "phi") < 1e-5

@@ -45,7 +45,7 @@ def _heat(nx, nt):
                    precond_c=0.0, precond_gamma_hat=0.6, gamma_fn=syn.heat_gamma_at)
 
 
-@pytest.mark.parametrize("case", [0, 1, 2, 3])
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4])
 def test_table1_heat_iteration_counts(case):
     """Iterations to eps = 1e-6 and 1e-10 within +15 % of Table 1, and grid independent."""
     t1 = _table1()
