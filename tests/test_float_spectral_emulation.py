@@ -34,6 +34,8 @@ from oracle import pdhg as opdhg
 from oracle import precond as opre
 from oracle.problem import Problem, default_constants
 
+from fp32_emulation import segmented_solve
+
 F32 = np.float32
 
 
@@ -45,62 +47,20 @@ def _factor(prob):
 
 
 def _bands(L):
-    """(1/L_ll, L_{l,l-1}, L_{l,l-2}) for l = 0..N_t-1, zero outside the matrix; two rows of padding."""
+    """(1/L_ll, L_{l,l-1}, L_{l,l-2}) of one mode, shaped for segmented_solve (one column)."""
     nt = L.shape[0]
-    invd = 1.0 / np.diag(L)
-    e1 = np.zeros(nt + 2)
-    e2 = np.zeros(nt + 2)
-    e1[1:nt] = np.diagonal(L, -1)
+    invd = (1.0 / np.diag(L))[:, None]
+    e1 = np.zeros((nt + 2, 1))
+    e2 = np.zeros((nt + 2, 1))
+    e1[1:nt, 0] = np.diagonal(L, -1)
     if nt > 2:
-        e2[2:nt] = np.diagonal(L, -2)
+        e2[2:nt, 0] = np.diagonal(L, -2)
     return invd, e1, e2
 
 
 def _segmented_solve(bands, b, nlanes=64, dt=F32):
-    """Forward then backward substitution in dt, with the time axis cut into per-lane segments:
-    each segment's affine map (its particular solution from a zero state and its responses to the
-    two incoming values) is formed in dt, the maps are composed along the lanes in dt, and each
-    segment is re-run from its incoming state.  b: (nt, m) columns of one mode, of type dt."""
-    invd, e1, e2 = (x.astype(dt) for x in bands)
-    nt = b.shape[0]
-    lpl = -(-nt // nlanes)
-
-    def sweep(rhs, fwd):
-        out = np.zeros_like(rhs)
-        segs = [range(j * lpl, min(nt, (j + 1) * lpl)) for j in range(-(-nt // lpl))]
-        if not fwd:
-            segs = [list(reversed(s)) for s in reversed(segs)]
-
-        def coef(l):
-            if fwd:
-                return e1[l], e2[l]
-            return e1[l + 1], e2[l + 2]
-
-        s2 = np.zeros(rhs.shape[1], dt)
-        s1 = np.zeros(rhs.shape[1], dt)
-        for seg in segs:
-            # segment map from a zero state (particular p, responses a, b to the two incoming values)
-            p2 = np.zeros_like(s2)
-            p1 = np.zeros_like(s2)
-            a2, a1, b2, b1 = dt(1), dt(0), dt(0), dt(1)
-            for l in seg:
-                c1, c2 = coef(l)
-                pz = invd[l] * (rhs[l] - c1 * p1 - c2 * p2)
-                az = invd[l] * (-(c1 * a1) - c2 * a2)
-                bz = invd[l] * (-(c1 * b1) - c2 * b2)
-                p2, p1, a2, a1, b2, b1 = p1, pz, a1, az, b1, bz
-            # re-run from the incoming state
-            zm2, zm1 = s2, s1
-            for l in seg:
-                c1, c2 = coef(l)
-                zz = invd[l] * (rhs[l] - c1 * zm1 - c2 * zm2)
-                out[l] = zz
-                zm2, zm1 = zm1, zz
-            # incoming state of the next segment from the composed map
-            s2, s1 = a2 * s2 + b2 * s1 + p2, a1 * s2 + b1 * s1 + p1
-        return out
-
-    return sweep(sweep(b, True), False)
+    """Columns b (nt, m) of one mode through the segmented recurrence in type dt."""
+    return segmented_solve(*bands, b, nlanes, dt)
 
 
 def _segmented_solve32(bands, b):
