@@ -242,6 +242,24 @@ int pdhg_solve_onestep(pdhg_handle* h, const void* u0, void* u, void* phi, const
 int pdhg_residual(pdhg_handle* h, const void* u, const void* phi, void* Au, void* JTphi,
                   double* res, pdhg_stream_t stream);
 
+/* pdhg_residual without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, outputs and constants as
+ * pdhg_residual; A(u) and J(u)^T phi are bitwise those of pdhg_residual, and
+ * the two norms agree to rounding (they are reduced on the device instead of
+ * on the host).  Instead of the handle's workspace, the per-block partial sums
+ * live in a static device array of 4 MiB that each GPU the library runs on
+ * holds until the process ends; nt * nx must not exceed 67,092,480 points
+ * (PDHG_EINVAL otherwise, with the reason in pdhg_last_error).  Every call on
+ * one GPU shares that array: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must be serialised by the
+ * caller.  No hipMalloc, hipFree or other allocating call is made; the
+ * constants, when no solve ran yet, are resolved from u[0] without building
+ * the preconditioner's factor tables.  Synchronous on `stream` when res is
+ * non-NULL. */
+int pdhg_residual_static(pdhg_handle* h, const void* u, const void* phi, void* Au, void* JTphi,
+                         double* res, pdhg_stream_t stream);
+
 /* Preconditioner: s = K_d^{-1} r for r, s of shape [nt][nx] (may alias).
  * K_d = (B_t B_t^T) (x) I + I (x) (c^2 L_x + ghat^2 L_x^2), solved by FFT in x and
  * banded Cholesky in t (Sections 2.2, 3.3).  c = precond_c (must be resolved:

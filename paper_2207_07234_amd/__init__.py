@@ -231,6 +231,21 @@ class Solver:
             raise PdhgError(f"pdhg_residual failed: {self._status(rc)}")
         return au, jt, (res[0], res[1])
 
+    def residual_static(self, u, phi=None, Au=None, JTphi=None):
+        """pdhg_residual_static: the residual without any allocation inside the library (the caller
+        passes the outputs Au, JTphi or None for either)."""
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u, (nt + 1,) + lv, "u")
+        for t, name in ((phi, "phi"), (Au, "Au"), (JTphi, "JTphi")):
+            if t is not None:
+                self._check(t, (nt,) + lv, name)
+        res = (C.c_double * 2)()
+        rc = self.lib.pdhg_residual_static(self._h, _ptr(u), _ptr(phi), _ptr(Au), _ptr(JTphi), res,
+                                           _stream_ptr(self.device))
+        if rc != B.PDHG_OK:
+            raise PdhgError(f"pdhg_residual_static failed: {self._status(rc)}")
+        return Au, JTphi, (res[0], res[1])
+
     def precond(self, r, out=None):
         """s = K_d^{-1} r."""
         nt, lv = self.prob.nt, self.prob.level_shape

@@ -64,7 +64,7 @@ class pdhg_batch_params(C.Structure):
 
 
 EXPORTED = (
-    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_solve_refined", "pdhg_solve_onestep", "pdhg_residual", "pdhg_precond",
+    "pdhg_setup", "pdhg_workspace_bytes", "pdhg_solve", "pdhg_solve_refined", "pdhg_solve_onestep", "pdhg_residual", "pdhg_residual_static", "pdhg_precond",
     "pdhg_adjoint", "pdhg_time_kernel", "pdhg_destroy", "pdhg_status_string", "pdhg_last_error",
     "pdhg_batch_setup", "pdhg_batch_sizes", "pdhg_batch_offsets", "pdhg_batch_solve", "pdhg_batch_solve_onestep", "pdhg_batch_tune",
     "pdhg_batch_time_kernel", "pdhg_batch_destroy", "pdhg_batch_last_error",
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pdhg_solve_onestep.restype = C.c_int
     lib.pdhg_residual.argtypes = [H, vp, vp, vp, vp, C.POINTER(C.c_double), vp]
     lib.pdhg_residual.restype = C.c_int
+    lib.pdhg_residual_static.argtypes = [H, vp, vp, vp, vp, C.POINTER(C.c_double), vp]
+    lib.pdhg_residual_static.restype = C.c_int
     lib.pdhg_precond.argtypes = [H, vp, vp, vp]
     lib.pdhg_precond.restype = C.c_int
     lib.pdhg_adjoint.argtypes = [H, C.c_int32, vp, vp, vp, vp, vp, vp]

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -293,6 +294,7 @@ struct pdhg_handle {
   // host staging
   Ctrl* h_ctrl = nullptr;       // pinned, 2 slots
   double* h_scal = nullptr;     // pinned, 64 doubles
+  double* scratch_dev = nullptr;   // this device's address of the static scratch array (pdhg_residual_static)
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
   // graph cache
@@ -712,6 +714,105 @@ int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int it
 }  // namespace
 
 // =================================================================== C ABI
+// ------------------------------------------------------------------ static scratch
+// Device memory of the allocation-free entry point pdhg_residual_static: a
+// file-scope array that every GPU the library runs on holds until the process
+// ends.  Layout (doubles): [0, 64) partial maxima for the default constants,
+// then kStaticParts partial sums of ||A(u)||^2, kStaticParts of ||J^T phi||^2,
+// and the two reduced sums.  In host code `scratch` is only a stand-in for the
+// symbol: its device address is taken once per device with hipGetSymbolAddress
+// (with that device current) and kept in the handle.
+constexpr int kStaticParts = 262080;   // one partial sum per 256 points: nt * nx <= 67,092,480
+constexpr size_t kStaticScratchDoubles = 524288;   // 4 MiB
+static_assert(64 + 2 * (size_t)kStaticParts + 2 <= kStaticScratchDoubles, "static scratch layout");
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Address of `scratch` on the current device `device` (looked up once per device).
+int static_scratch_address(pdhg_handle* h, int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return PDHG_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return set_hip_error(h, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = static_cast<double*>(ptr);
+  }
+  h->scratch_dev = g_scratch_dev[device];
+  return PDHG_OK;
+}
+
+// out[0] = sum a[0..na), out[1] = sum b[0..nb): one block of 256 threads, each
+// adding its strided share in index order, then a fixed-order tree in LDS.
+__global__ void __launch_bounds__(256) k_static_sums(const double* __restrict__ a, int na,
+                                                     const double* __restrict__ b, int nb, double* out) {
+  __shared__ double ra[256], rb[256];
+  const int t = threadIdx.x;
+  double sa = 0.0, sb = 0.0;
+  for (int i = t; i < na; i += 256) sa += a[i];
+  for (int i = t; i < nb; i += 256) sb += b[i];
+  ra[t] = sa;
+  rb[t] = sb;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      ra[t] += ra[t + w];
+      rb[t] += rb[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = ra[0];
+    out[1] = rb[0];
+  }
+}
+
+// pdhg_residual without allocation: the partial sums live in the static
+// scratch, the constants are resolved without building factor tables, and
+// the norms are reduced on the device.
+template <typename T>
+int residual_static_impl(pdhg_handle* h, const T* u, const T* phi, T* Au, T* JTphi, double* res, hipStream_t st) {
+  const pdhg_problem& p = h->prob;
+  const size_t nparts = ((size_t)p.nt * p.nx + 255) / 256;
+  if (nparts > (size_t)kStaticParts) {
+    // h->err has capacity reserved at set-up: this assignment does not allocate
+    h->err.assign("pdhg_residual_static: nt * nx exceeds the static scratch (at most 67092480 points)");
+    return PDHG_EINVAL;
+  }
+  double* part_c = h->scratch_dev;
+  double* prp = part_c + 64;
+  double* prd = prp + kStaticParts;
+  double* sums = prd + kStaticParts;
+  if (!h->consts_valid) {
+    const int rc = resolve_constants_p<T>(h, u, part_c, st, false);
+    if (rc) return rc;
+  }
+  const Scheme s = scheme_of(h);
+  int nb1 = 0, nb2 = 0;
+  if (is_dg(p)) {
+    HIP_TRY(dgx_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
+    if (phi) HIP_TRY(dgx_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  } else {
+    HIP_TRY(launch_residual<T>(s, u, Au, prp, nullptr, st, &nb1));
+    if (phi) HIP_TRY(launch_apply_jt<T>(s, u, phi, JTphi, prd, st, &nb2));
+  }
+  if ((size_t)nb1 != nparts || (phi && (size_t)nb2 != nparts)) return PDHG_EUNSUPPORTED;
+  if (res) {
+    hipLaunchKernelGGL(k_static_sums, dim3(1), dim3(256), 0, st, prp, nb1, prd, nb2, sums);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h->h_scal, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    res[0] = std::sqrt(s.ht * s.hx * h->h_scal[0]);
+    res[1] = phi ? std::sqrt(s.ht * s.hx * h->h_scal[1]) : 0.0;
+  }
+  return PDHG_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* pdhg_status_string(int status) {
@@ -753,9 +854,11 @@ int pdhg_setup(const pdhg_problem* prob, pdhg_handle** out) {
   h->esz = (p.dtype == PDHG_F64) ? 8 : 4;
   h->lqb = 0;
   while ((1 << (h->lqb + 1)) <= std::min(16, p.nx)) ++h->lqb;
+  h->err.reserve(256);   // messages set by the allocation-free entry point fit without reallocation
   int rc = PDHG_OK;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) rc = set_hip_error(h, e, "hipGetDevice");
+  if (!rc) rc = static_scratch_address(h, h->device);
   if (!rc) rc = (p.dtype == PDHG_F64) ? upload_twiddles<double>(h, &h->d_tw) : upload_twiddles<float>(h, &h->d_tw);
   if (!rc && is_pre32(p)) rc = upload_twiddles<float>(h, &h->d_tw32);
   if (!rc && (e = hipHostMalloc((void**)&h->h_ctrl, 2 * sizeof(Ctrl), hipHostMallocDefault)) != hipSuccess)
@@ -1587,6 +1690,18 @@ int pdhg_residual(pdhg_handle* h, const void* u, const void* phi, void* Au, void
   if (h->prob.dtype == PDHG_F64)
     return residual_impl<double>(h, (const double*)u, (const double*)phi, (double*)Au, (double*)JTphi, res, st);
   return residual_impl<float>(h, (const float*)u, (const float*)phi, (float*)Au, (float*)JTphi, res, st);
+}
+
+int pdhg_residual_static(pdhg_handle* h, const void* u, const void* phi, void* Au, void* JTphi, double* res,
+                         pdhg_stream_t stream) {
+  if (!h || !u) return PDHG_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return set_hip_error(h, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->prob.dtype == PDHG_F64)
+    return residual_static_impl<double>(h, (const double*)u, (const double*)phi, (double*)Au, (double*)JTphi, res,
+                                        st);
+  return residual_static_impl<float>(h, (const float*)u, (const float*)phi, (float*)Au, (float*)JTphi, res, st);
 }
 
 int pdhg_precond(pdhg_handle* h, const void* r, void* s, pdhg_stream_t stream) {
