@@ -45,7 +45,10 @@ typedef struct ihipStream_t* pdhg_stream_t;   /* a hipStream_t; NULL = default s
 typedef enum {
   PDHG_OK = 0,
   PDHG_NOT_CONVERGED = 1,   /* max_iter reached; u, phi hold iterate max_iter            */
-  PDHG_DIVERGED = 2,        /* non-finite or exploding residual; u, phi hold the last iterate */
+  PDHG_DIVERGED = 2,        /* non-finite or exploding residual; u, phi hold the last good
+                               checkpoint (pdhg_solve) or the last iterate (the other solvers) */
+  PDHG_STALLED = 3,         /* stall_iters iterations without a new best ||A(u)|| (rounding
+                               floor); u, phi hold the last iterate (pdhg_solve only)      */
   PDHG_EINVAL = -1,         /* invalid argument (sizes, enums, null pointers)            */
   PDHG_EHIP = -2,           /* a HIP runtime call failed                                 */
   PDHG_EUNSUPPORTED = -3,   /* valid but not implemented combination                     */
@@ -137,10 +140,17 @@ typedef struct {
   int32_t variant;          /* 0 = auto (2; DG: 4), 1 = unfused reference kernels (7 per
                                iteration), 2 = fused passes (3 kernels per iteration),
                                4 = the DG loop body (5 kernels per iteration)            */
-  int32_t reserved;
+  int32_t backoff;          /* after a divergence, restart from the last good checkpoint with
+                               tau_u and tau_phi times 0.7, at most this many times (0: none) */
   double* history;          /* nullable DEVICE buffer [max_iter+2][2] of doubles: entry n holds
                                (||A(u^n)||, ||J(u^n)^T phi^n||) for n = 0..n*; entry 0 is
                                (NaN, ||J(u^0)^T phi^0||); entries past n* may be written */
+  double eps_rel;           /* > 0: the tolerance is max(eps, eps_rel ||u0|| / h_t) with
+                               ||u0|| = sqrt(h_x sum u0^2), the scale-free form for single
+                               precision, whose residual floor grows like 1/h_t          */
+  int32_t stall_iters;      /* > 0: stop with PDHG_STALLED when ||A(u)|| has not improved on its
+                               best for this many iterations (the rounding floor)         */
+  int32_t reserved;
 } pdhg_params;
 
 typedef struct {
@@ -176,6 +186,14 @@ size_t pdhg_workspace_bytes(const pdhg_handle* h);
  * of pdhg_workspace_bytes() bytes, or NULL to let the handle allocate its own
  * (kept until pdhg_destroy).  stats: host struct, filled on return.
  * Synchronises the stream (it polls the device-side convergence flag).
+ * Divergence (a non-finite residual, or ||A(u)|| above diverge_factor times the
+ * best so far) returns PDHG_DIVERGED with u, phi = the last good checkpoint:
+ * the iterate M = k check_every - 1 (k >= 1), or the start (M = 0), latest
+ * before the diverging one; stats then report M and that state's residuals.
+ * With params->backoff > 0 the solve instead restarts from that checkpoint
+ * with both step sizes times 0.7 (warm start: phibar = phi), up to backoff
+ * times; stats.iters counts every iteration run up to the returned iterate,
+ * and stats.tau_u, tau_phi are the steps of the last run.
  * Returns PDHG_OK, PDHG_NOT_CONVERGED, PDHG_DIVERGED or an error. */
 int pdhg_solve(pdhg_handle* h, const void* u0, void* u, void* phi, void* workspace,
                const pdhg_params* params, pdhg_stats* stats, pdhg_stream_t stream);

@@ -140,7 +140,8 @@ class Solver:
     # ----------------------------------------------------------------- API
     def solve(self, u0, tau_u: float = 0.0, tau_phi: float = 0.0, eps: float = 1e-8, max_iter: int = 10000,
               check_every: int = 64, u=None, phi=None, warm_start: bool = False, workspace=None,
-              history: bool = False, diverge_factor: float = 0.0, variant: int = 0) -> SolveResult:
+              history: bool = False, diverge_factor: float = 0.0, variant: int = 0,
+              backoff: int = 0, eps_rel: float = 0.0, stall_iters: int = 0) -> SolveResult:
         import torch
         nt, lv = self.prob.nt, self.prob.level_shape
         self._check(u0, lv, "u0")
@@ -151,7 +152,8 @@ class Solver:
         p = B.pdhg_params()
         p.tau_u, p.tau_phi, p.eps = float(tau_u), float(tau_phi), float(eps)
         p.max_iter, p.check_every, p.warm_start = int(max_iter), int(check_every), int(bool(warm_start))
-        p.diverge_factor, p.variant = float(diverge_factor), int(variant)
+        p.diverge_factor, p.variant, p.backoff = float(diverge_factor), int(variant), int(backoff)
+        p.eps_rel, p.stall_iters = float(eps_rel), int(stall_iters)
         p.history = hist.data_ptr() if hist is not None else None
         st = B.pdhg_stats()
         rc = self.lib.pdhg_solve(self._h, _ptr(u0), _ptr(u), _ptr(phi), _ptr(workspace), C.byref(p),
@@ -456,7 +458,8 @@ class BatchSolver:
             pass
 
 
-def differentiable_solve(u0, solver, **solve_kwargs):
-    """u (all levels) as a differentiable function of u0 (implicit adjoint backward)."""
+def differentiable_solve(u0, solver, allow_unconverged: bool = False, **solve_kwargs):
+    """u (all levels) as a differentiable function of u0 (implicit adjoint backward).  Raises when the
+    solve ends at max_iter, unless allow_unconverged (then it warns)."""
     from .autograd import solve
-    return solve(u0, solver, **solve_kwargs)
+    return solve(u0, solver, allow_unconverged=allow_unconverged, **solve_kwargs)

@@ -12,7 +12,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdhg.so")
 
-PDHG_OK, PDHG_NOT_CONVERGED, PDHG_DIVERGED = 0, 1, 2
+PDHG_OK, PDHG_NOT_CONVERGED, PDHG_DIVERGED, PDHG_STALLED = 0, 1, 2, 3
 PDHG_EINVAL, PDHG_EHIP, PDHG_EUNSUPPORTED, PDHG_EWORKSPACE = -1, -2, -3, -4
 PDHG_F32, PDHG_F64 = 0, 1
 PDHG_BE, PDHG_BDF2 = 0, 1
@@ -35,8 +35,8 @@ class pdhg_params(C.Structure):
     _fields_ = [
         ("tau_u", C.c_double), ("tau_phi", C.c_double), ("eps", C.c_double),
         ("max_iter", C.c_int64), ("check_every", C.c_int32), ("warm_start", C.c_int32),
-        ("diverge_factor", C.c_double), ("variant", C.c_int32), ("reserved", C.c_int32),
-        ("history", C.c_void_p),
+        ("diverge_factor", C.c_double), ("variant", C.c_int32), ("backoff", C.c_int32),
+        ("history", C.c_void_p), ("eps_rel", C.c_double), ("stall_iters", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

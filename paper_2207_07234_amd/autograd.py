@@ -14,6 +14,8 @@ derivative of the returned PDHG iterate up to the solve tolerance.
 """
 from __future__ import annotations
 
+import warnings
+
 import torch
 
 
@@ -21,10 +23,18 @@ class PDHGSolve(torch.autograd.Function):
     """u = PDHGSolve.apply(u0, solver, solve_kwargs) with u of shape (nt+1, nx)."""
 
     @staticmethod
-    def forward(ctx, u0, solver, solve_kwargs):
+    def forward(ctx, u0, solver, solve_kwargs, allow_unconverged=False):
         res = solver.solve(u0.detach().contiguous(), **(solve_kwargs or {}))
         if res.status < 0 or res.status == 2:
             raise RuntimeError(f"PDHG solve failed (status {res.status}): {res.stats}")
+        if res.status == 1:
+            # the implicit-function adjoint is the derivative of the solution of A(u) = 0; an iterate
+            # stopped by max_iter is not that solution
+            msg = (f"PDHG solve stopped at max_iter={res.stats['iters']} with ||A(u)|| = "
+                   f"{res.stats['res_primal']:.3e} above eps; the adjoint gradient assumes A(u) = 0")
+            if not allow_unconverged:
+                raise RuntimeError(msg + " (pass allow_unconverged=True to accept it)")
+            warnings.warn(msg, RuntimeWarning, stacklevel=2)
         ctx.solver = solver
         ctx.stats = res.stats
         ctx.save_for_backward(res.u)
@@ -34,9 +44,11 @@ class PDHGSolve(torch.autograd.Function):
     def backward(ctx, g_u):
         (u,) = ctx.saved_tensors
         grad = ctx.solver.adjoint_solve(u, g_u.contiguous())
-        return grad, None, None
+        return grad, None, None, None
 
 
-def solve(u0, solver, **solve_kwargs):
-    """Differentiable solve; see PDHGSolve."""
-    return PDHGSolve.apply(u0, solver, solve_kwargs)
+def solve(u0, solver, allow_unconverged: bool = False, **solve_kwargs):
+    """Differentiable solve; see PDHGSolve.  A solve that ends at max_iter raises unless
+    allow_unconverged (then it warns); one that stalls at the rounding floor (PDHG_STALLED, the
+    single-precision stop rule) is accepted."""
+    return PDHGSolve.apply(u0, solver, solve_kwargs, allow_unconverged)

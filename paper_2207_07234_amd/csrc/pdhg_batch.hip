@@ -310,7 +310,31 @@ kb_init(const BatchProb* __restrict__ probs, const T* __restrict__ u0, T* __rest
     c->best = __builtin_inf();
     c->rp_star = __builtin_nan("");
     c->rd_star = __builtin_nan("");
+    c->best_at = 0;
+    c->stall = 0;
+    c->ck_iter = -1;
   }
+}
+
+// Last-good checkpoint of every problem still running (the single-problem
+// k_checkpoint per problem slice): u_alt holds u^{N-1} and phi holds phi^{N-1}
+// after a chunk ending with body N; a problem that has stopped keeps its
+// previous checkpoint.  Grid: x strides over the slices, y = problem.
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_checkpoint(const BatchProb* __restrict__ probs, Ctrl* ctrls, const T* __restrict__ u_alt,
+              const T* __restrict__ phi, T* __restrict__ ck_u, T* __restrict__ ck_phi) {
+  const int p = blockIdx.y;
+  Ctrl* c = ctrls + p;
+  if (c->status != 0) return;
+  const BatchProb& P = probs[p];
+  const size_t nx = (size_t)P.s.nx, nu = (size_t)(P.s.nt + 1) * nx, nf = (size_t)P.s.nt * nx;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride)
+    ck_u[P.u_off + i] = u_alt[P.u_off + i];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride)
+    ck_phi[P.f_off + i] = phi[P.f_off + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->ck_iter = c->n_done > 0 ? c->n_done - 1 : 0;
 }
 
 // After the loop: the returned iterate n* of problem p sits in u_alt when n*
@@ -443,6 +467,14 @@ hipError_t launch_batch_init(const BatchLaunch& L, const T* u0, T* u, T* u_alt, 
 }
 
 template <typename T>
+hipError_t launch_batch_checkpoint(const BatchLaunch& L, const T* u_alt, const T* phi, T* ck_u, T* ck_phi,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(kb_checkpoint<T>, dim3(64, L.nprob), dim3(256), 0, st, L.probs, L.ctrls, u_alt, phi, ck_u,
+                     ck_phi);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_batch_finish(const BatchLaunch& L, T* u, const T* u_alt, double* drift, hipStream_t st) {
   hipLaunchKernelGGL(kb_finish<T>, dim3(L.nprob), dim3(256), 0, st, L.probs, L.ctrls, u, u_alt, drift);
   return hipGetLastError();
@@ -461,7 +493,8 @@ hipError_t launch_batch_finish(const BatchLaunch& L, T* u, const T* u_alt, doubl
   template hipError_t launch_batch_maxabs_dflux<T>(const BatchLaunch&, const T*, double*, hipStream_t);       \
   template hipError_t launch_batch_init<T>(const BatchLaunch&, const T*, T*, T*, T*, T*, int, long long, double, \
                                            double, hipStream_t);                                               \
-  template hipError_t launch_batch_finish<T>(const BatchLaunch&, T*, const T*, double*, hipStream_t);
+  template hipError_t launch_batch_finish<T>(const BatchLaunch&, T*, const T*, double*, hipStream_t);         \
+  template hipError_t launch_batch_checkpoint<T>(const BatchLaunch&, const T*, const T*, T*, T*, hipStream_t);
 
 PDHG_BATCH_INSTANTIATE(float)
 PDHG_BATCH_INSTANTIATE(double)

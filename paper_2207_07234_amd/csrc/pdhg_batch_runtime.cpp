@@ -96,7 +96,7 @@ int bset_hip_error(pdhg_batch* b, hipError_t e, const char* what) {
 bool is_pow2_b(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 struct BatchWs {
-  size_t u_alt, phibar, spec, total;
+  size_t u_alt, phibar, spec, ck_u, ck_phi, total;
 };
 
 BatchWs batch_ws(const pdhg_batch* b) {
@@ -105,6 +105,8 @@ BatchWs batch_ws(const pdhg_batch* b) {
   L.u_alt = o; o += align_b((size_t)b->u_elems * b->esz);
   L.phibar = o; o += align_b((size_t)b->f_elems * b->esz);
   L.spec = o; o += align_b((size_t)b->f_elems * b->esz);
+  L.ck_u = o; o += align_b((size_t)b->u_elems * b->esz);     // last-good checkpoints of the packed (u, phi)
+  L.ck_phi = o; o += align_b((size_t)b->f_elems * b->esz);
   L.total = o;
   return L;
 }
@@ -412,6 +414,40 @@ int build_batch_graph(pdhg_batch* b, int chunk, T* u, T* phi, void* ws) {
   return PDHG_OK;
 }
 
+// Copy problem i's slices of a checkpoint into u and phi and recompute its residual norms and
+// mass drift there (scratch: a spectrum-sized workspace region, free after the loop).
+template <typename T>
+int restore_checkpoint(pdhg_batch* b, int i, const T* cku, const T* ckphi, T* u, T* phi, double* scratch,
+                       hipStream_t st, double* rp, double* rd, double* drift) {
+  const pdhg_problem& q = b->probs[i];
+  const size_t nlev = (size_t)(q.nt + 1) * q.nx, nf = (size_t)q.nt * q.nx;
+  T* ui = u + b->u_off[i];
+  T* pi = phi + b->f_off[i];
+  BHIP_TRY(launch_copy<T>(ui, cku + b->u_off[i], nlev, st));
+  BHIP_TRY(launch_copy<T>(pi, ckphi + b->f_off[i], nf, st));
+  const Scheme& s = b->table[i].s;
+  const size_t np = (nf + 255) / 256;
+  double* prp = scratch;
+  double* prd = scratch + np;
+  double* lev = scratch + 2 * np;
+  int nb1 = 0, nb2 = 0;
+  BHIP_TRY(launch_residual<T>(s, ui, (T*)nullptr, prp, nullptr, st, &nb1));
+  BHIP_TRY(launch_apply_jt<T>(s, ui, pi, (T*)nullptr, prd, st, &nb2));
+  BHIP_TRY(launch_level_sums<T>(ui, q.nx, (size_t)q.nx, q.nt + 1, lev, st));
+  std::vector<double> h(2 * np + q.nt + 1);
+  BHIP_TRY(hipMemcpyAsync(h.data(), scratch, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+  double sa = 0.0, sb = 0.0;
+  for (int k = 0; k < nb1; ++k) sa += h[k];
+  for (int k = 0; k < nb2; ++k) sb += h[np + k];
+  *rp = std::sqrt(s.ht * s.hx * sa);
+  *rd = std::sqrt(s.ht * s.hx * sb);
+  double d = 0.0;
+  for (int l = 1; l <= q.nt; ++l) d = std::max(d, std::fabs(h[2 * np + l] - h[2 * np]) * s.hx);
+  *drift = d;
+  return PDHG_OK;
+}
+
 template <typename T>
 int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const pdhg_batch_params* prm,
                      pdhg_stats* stats, hipStream_t st) {
@@ -433,8 +469,12 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
   b->last_u = u;
   b->last_phi = phi;
   b->last_ws = ws;
+  // last-good checkpoints of every running problem, refreshed on the device after each chunk
+  T* ck_u = (T*)bws(ws, W.ck_u);
+  T* ck_phi = (T*)bws(ws, W.ck_phi);
   auto t0 = std::chrono::steady_clock::now();
   if (prm->max_iter > 0) {
+    BHIP_TRY(launch_batch_checkpoint<T>(L, u_alt, phi, ck_u, ck_phi, st));   // iterate 0
     rc = build_batch_graph<T>(b, chunk, u, phi, ws);
     if (rc) return rc;
     const long long bodies = prm->max_iter + 1;
@@ -444,6 +484,7 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
     while (!stop && launched < bodies) {
       BHIP_TRY(hipGraphLaunch(b->gexec, st));
       launched += chunk;
+      BHIP_TRY(launch_batch_checkpoint<T>(L, u_alt, phi, ck_u, ck_phi, st));
       int* slot = b->h_counts + 4 * (idx & 1);
       BHIP_TRY(hipMemcpyAsync(slot, b->d_counts, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
       BHIP_TRY(hipEventRecord(b->ev[idx & 1], st));
@@ -465,24 +506,30 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
     const Ctrl& c = b->h_ctrls[i];
     int status;
     long long nstar = c.n_star;
+    double rp = c.rp_star, rd = c.rd_star, drift = b->h_scal[i];
     if (prm->max_iter <= 0) { nstar = 0; status = PDHG_NOT_CONVERGED; }
     else if (c.status == 1) status = PDHG_OK;
     else if (c.status == 2) status = PDHG_DIVERGED;
     else status = PDHG_NOT_CONVERGED;
+    if (status == PDHG_DIVERGED) {   // back to the last good checkpoint
+      rc = restore_checkpoint<T>(b, i, ck_u, ck_phi, u, phi, (double*)bws(ws, W.spec), st, &rp, &rd, &drift);
+      if (rc) return rc;
+      nstar = c.ck_iter > 0 ? c.ck_iter : 0;
+    }
     if (status == PDHG_DIVERGED) worst = PDHG_DIVERGED;
     else if (status == PDHG_NOT_CONVERGED && worst == PDHG_OK) worst = PDHG_NOT_CONVERGED;
     if (stats) {
       pdhg_stats& s = stats[i];
       s.iters = nstar;
-      s.res_primal = c.rp_star;
-      s.res_dual = c.rd_star;
+      s.res_primal = rp;
+      s.res_dual = rd;
       s.tau_u = tau_u[i];
       s.tau_phi = tau_phi[i];
       s.nu_max = nu[i];
       s.lf_speed = b->lf[i];
       s.precond_c = b->c[i];
       s.seconds = secs;
-      s.mass_drift = b->h_scal[i];
+      s.mass_drift = drift;
       s.status = status;
       s.variant = 3;
     }

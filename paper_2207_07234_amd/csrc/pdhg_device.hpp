@@ -501,12 +501,15 @@ struct Ctrl {
   long long n_done;    // loop bodies completed
   long long max_iter;
   long long n_star;    // returned iterate
-  int status;          // 0 running, 1 converged, 2 diverged, 3 max_iter reached
+  int status;          // 0 running, 1 converged, 2 diverged, 3 max_iter reached, 4 stalled
   int rd_lazy;         // 1: the fused row pass evaluates Rd only where rd_needed says so
   double eps, div_factor;
   double rp_prev;      // ||A(u^{n_done})||
-  double best;         // min over checked iterates of max(Rp, Rd)
+  double best;         // min over checked iterates of ||A(u)||
   double rp_star, rd_star;
+  long long best_at;   // iterate at which best was reached
+  long long stall;     // > 0: stop (status 4) when best is that many iterates old
+  long long ck_iter;   // iterate held by the last-good checkpoint (-1: none)
 };
 
 // Whether loop body n = n_done + 1 must evaluate Rd(n-1) = ||J(u^{n-1})^T phi^{n-1}||.
@@ -538,7 +541,11 @@ __device__ inline void finalize_body(Ctrl* c, double srp, double srd, double wsc
     if (!(p == p) || isinf(p)) st = 2;
     else if (p <= c->eps && rd <= c->eps) st = 1;
     else if (p > c->div_factor * c->best) st = 2;
-    if (p < c->best) c->best = p;
+    if (p < c->best) {
+      c->best = p;
+      c->best_at = it;
+    }
+    if (st == 0 && c->stall > 0 && it - c->best_at >= c->stall) st = 4;   // rounding floor reached
     if (st == 0 && it >= c->max_iter) st = 3;
   }
   if (st == 0 && !(rp == rp && !isinf(rp) && (!have_rd || (rd == rd && !isinf(rd))))) st = 2;

@@ -42,8 +42,12 @@ hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st);
 
 // rd_lazy = 1: the fused row pass evaluates the dual residual only where the
 // stopping test or the stats need it (rd_needed).
+// Copy (su, sp) to (du, dp) and record ctrl->ck_iter = max(n_done - 1, 0), unless the solve has stopped.
+template <typename T>
+hipError_t launch_checkpoint(Ctrl* ctrl, const T* su, const T* sp, T* du, T* dp, size_t nu, size_t np,
+                             hipStream_t st);
 hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st,
-                            int rd_lazy = 0);
+                            int rd_lazy = 0, long long stall = 0);
 hipError_t launch_finalize(Ctrl* c, const double* part_rp, int n_rp, const double* part_rd, int n_rd,
                            double wscale, double* hist, hipStream_t st);
 
@@ -212,6 +216,9 @@ hipError_t launch_batch_maxabs_dflux(const BatchLaunch& L, const T* u0, double* 
 template <typename T>
 hipError_t launch_batch_init(const BatchLaunch& L, const T* u0, T* u, T* u_alt, T* phi, T* spec, int warm,
                              long long max_iter, double eps, double div_factor, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_checkpoint(const BatchLaunch& L, const T* u_alt, const T* phi, T* ck_u, T* ck_phi,
+                                   hipStream_t st);
 template <typename T>
 hipError_t launch_batch_finish(const BatchLaunch& L, T* u, const T* u_alt, double* drift, hipStream_t st);
 

@@ -259,7 +259,8 @@ __global__ void k_normalize(T* __restrict__ x, size_t n, const double* nrm2) {
 }
 
 // ------------------------------------------------------------------ control
-__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, int rd_lazy) {
+__global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, int rd_lazy,
+                            long long stall) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->n_done = 0;
     c->max_iter = max_iter;
@@ -272,7 +273,26 @@ __global__ void k_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_
     c->best = __builtin_inf();
     c->rp_star = __builtin_nan("");
     c->rd_star = __builtin_nan("");
+    c->best_at = 0;
+    c->stall = stall;
+    c->ck_iter = -1;
   }
+}
+
+// Last-good checkpoint of a solve: while the solve is running, after a chunk of
+// loop bodies ending with body N, u_alt holds u^{N-1} and phi holds phi^{N-1}
+// (each body first takes the dual step of the previous iterate), an iterate
+// that has passed the stopping and divergence tests.  Copied with its index; a
+// solve that has stopped keeps its previous checkpoint.  Before the first body
+// u_alt = u and phi are the start, iterate 0.
+template <typename T>
+__global__ void k_checkpoint(Ctrl* ctrl, const T* __restrict__ su, const T* __restrict__ sp, T* __restrict__ du,
+                             T* __restrict__ dp, size_t nu, size_t np) {
+  if (ctrl->status != 0) return;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) du[i] = su[i];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) dp[i] = sp[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->ck_iter = ctrl->n_done > 0 ? ctrl->n_done - 1 : 0;
 }
 
 __global__ void __launch_bounds__(kEwThreads)
@@ -405,6 +425,14 @@ hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t st) {
 }
 
 template <typename T>
+hipError_t launch_checkpoint(Ctrl* ctrl, const T* su, const T* sp, T* du, T* dp, size_t nu, size_t np,
+                             hipStream_t st) {
+  const unsigned g0 = grid_for(nu, kEwThreads), g = g0 < 2048u ? g0 : 2048u;
+  hipLaunchKernelGGL(k_checkpoint<T>, dim3(g), dim3(kEwThreads), 0, st, ctrl, su, sp, du, dp, nu, np);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_dot(const T* x, const T* y, size_t n, double* part, double* out, hipStream_t st) {
   const int g = 256;
   hipLaunchKernelGGL(k_partial_dot<T>, dim3(g), dim3(kEwThreads), 0, st, x, y, n, part);
@@ -425,8 +453,8 @@ hipError_t launch_normalize(T* x, size_t n, const double* nrm2, hipStream_t st) 
 }
 
 hipError_t launch_ctrl_init(Ctrl* c, long long max_iter, double eps, double div_factor, hipStream_t st,
-                            int rd_lazy) {
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor, rd_lazy);
+                            int rd_lazy, long long stall) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, eps, div_factor, rd_lazy, stall);
   return hipGetLastError();
 }
 
@@ -462,6 +490,7 @@ template hipError_t launch_refine_time<double>(const double*, const double*, int
   template hipError_t launch_broadcast_levels<T>(T*, const T*, int, int, hipStream_t);                        \
   template hipError_t launch_copy<T>(T*, const T*, size_t, hipStream_t);                                      \
   template hipError_t launch_dot<T>(const T*, const T*, size_t, double*, double*, hipStream_t);               \
+  template hipError_t launch_checkpoint<T>(Ctrl*, const T*, const T*, T*, T*, size_t, size_t, hipStream_t);  \
   template hipError_t launch_maxabs_dflux<T>(const T*, size_t, double, double, double*, hipStream_t);         \
   template hipError_t launch_normalize<T>(T*, size_t, const double*, hipStream_t);
 

@@ -252,7 +252,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
-  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, total;
+  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, ck_u, ck_phi, total;
   int max_parts;
 };
 
@@ -364,6 +364,8 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.ctrl = o; o += align_up(sizeof(Ctrl));
   L.ctrl_t = o; o += align_up(sizeof(Ctrl));     // control block used only by kernel timing
   L.s0 = o; o += align_up(sizeof(double) * nt);    // FP64 mode 0 of a float spectrum
+  L.ck_u = o; o += ufield;                         // last-good checkpoint (u, phi) of the solve loop
+  L.ck_phi = o; o += field;
   L.total = o;
   return L;
 }
@@ -820,6 +822,7 @@ const char* pdhg_status_string(int status) {
     case PDHG_OK: return "converged";
     case PDHG_NOT_CONVERGED: return "max_iter reached";
     case PDHG_DIVERGED: return "diverged";
+    case PDHG_STALLED: return "stalled at the rounding floor";
     case PDHG_EINVAL: return "invalid argument";
     case PDHG_EHIP: return "HIP error";
     case PDHG_EUNSUPPORTED: return "unsupported";
@@ -1035,6 +1038,33 @@ int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T t
   return PDHG_OK;
 }
 
+// ||A(u)|| and ||J(u)^T phi|| of a state (the partial sums in the workspace, added on the host).
+template <typename T>
+int state_norms(pdhg_handle* h, const T* u, const T* phi, void* ws, hipStream_t st, double* rp, double* rd) {
+  const WsLayout L = layout_for(h->prob, h->esz);
+  const Scheme s = scheme_of(h);
+  double* prp = (double*)wsp(ws, L.part_rp);
+  double* prd = (double*)wsp(ws, L.part_rd);
+  int nb1 = 0, nb2 = 0;
+  if (is_dg(h->prob)) {
+    HIP_TRY(dgx_residual<T>(s, u, (T*)nullptr, prp, nullptr, st, &nb1));
+    HIP_TRY(dgx_apply_jt<T>(s, u, phi, (T*)nullptr, prd, st, &nb2));
+  } else {
+    HIP_TRY(launch_residual<T>(s, u, (T*)nullptr, prp, nullptr, st, &nb1));
+    HIP_TRY(launch_apply_jt<T>(s, u, phi, (T*)nullptr, prd, st, &nb2));
+  }
+  std::vector<double> a(nb1), b(nb2);
+  HIP_TRY(hipMemcpyAsync(a.data(), prp, nb1 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(b.data(), prd, nb2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double sa = 0.0, sb = 0.0;
+  for (double x : a) sa += x;
+  for (double x : b) sb += x;
+  *rp = std::sqrt(s.ht * s.hx * sa);
+  *rd = std::sqrt(s.ht * s.hx * sb);
+  return PDHG_OK;
+}
+
 template <typename T>
 int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_params* prm, pdhg_stats* stats,
                hipStream_t st) {
@@ -1066,58 +1096,106 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
     if (!(nu > 0.0) || !std::isfinite(nu)) return PDHG_EINVAL;
     tau_u = tau_phi = std::sqrt(0.95 / nu);
   }
-  HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
-  HIP_TRY(launch_fill<T>(spec, n, T(0), st));
-  if (is_pre32(p)) HIP_TRY(launch_fill<T>((T*)wsp(ws, L.s0), (size_t)p.nt, T(0), st));
   const double div = prm->diverge_factor > 0 ? prm->diverge_factor : 1e6;
   // without a residual history: Rd only where the stopping test needs it
   const int rd_lazy = prm->history ? 0 : 1;
-  HIP_TRY(launch_ctrl_init(ctrl, (long long)prm->max_iter, prm->eps, div, st, rd_lazy));
-
+  if (prm->stall_iters < 0) return PDHG_EINVAL;
+  // scale-free tolerance: both residuals <= eps_rel ||u0|| / h_t, ||u0|| = sqrt(h_x sum u0^2)
+  double eps = prm->eps;
+  if (prm->eps_rel > 0.0) {
+    double* scal = (double*)wsp(ws, L.scal);
+    HIP_TRY(launch_dot<T>(u0, nullptr, (size_t)row, (double*)wsp(ws, L.part_rp), scal, st));
+    HIP_TRY(hipMemcpyAsync(h->h_scal, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double hx = p.length / p.nx, ht = p.t_final / p.nt;
+    eps = std::max(eps, prm->eps_rel * std::sqrt(hx * h->h_scal[0]) / ht);
+  }
   int chunk = prm->check_every > 0 ? prm->check_every : 64;
   chunk += chunk & 1;   // even: u ping-pong returns to its start buffer
   GraphKey key;
   key.u = u; key.phi = phi; key.ws = ws; key.hist = prm->history;
-  key.tau_u = tau_u; key.tau_phi = tau_phi; key.lf = h->lf; key.c = h->c;
+  key.lf = h->lf; key.c = h->c;
   // fused passes need at least one full wavefront per row (nx >= 64); DG has its own body
   if (prm->variant == 2 && p.nx < 64 && !dg) return PDHG_EUNSUPPORTED;
   // the single-precision preconditioner runs in the fused passes only
   if (is_pre32(p) && (prm->variant == 1 || p.nx < 64)) return PDHG_EUNSUPPORTED;
   if (dg && prm->variant != 0 && prm->variant != 4) return PDHG_EUNSUPPORTED;
+  if (prm->backoff < 0) return PDHG_EINVAL;
   key.variant = dg ? 4 : ((prm->variant == 1 || p.nx < 64) ? 1 : 2);
   key.chunk = chunk;
-  h->last = key;
-  const long long bodies = prm->max_iter + 1;
+  // Last-good checkpoint (u, phi, iterate index): refreshed on the device after every chunk while the
+  // solve runs (launch_checkpoint), so that it always holds an iterate that passed the tests.
+  T* ck_u = (T*)wsp(ws, L.ck_u);
+  T* ck_phi = (T*)wsp(ws, L.ck_phi);
+  long long done = 0;   // iterations completed before the current run (step-size back-offs)
+  int backoffs = 0;
+  double rp_ck = 0.0, rd_ck = 0.0;
+  bool restored = false;
+  Ctrl c{};
+  long long nstar = 0;
+  int status = PDHG_NOT_CONVERGED;
   auto t0 = std::chrono::steady_clock::now();
-  if (prm->max_iter > 0) {
-    rc = build_graph<T>(h, key, u, phi, ws, (T)tau_u, (T)tau_phi, prm->history);
-    if (rc) return rc;
-    long long launched = 0;
-    int idx = 0;
-    bool stop = false;
-    while (!stop && launched < bodies) {
-      HIP_TRY(hipGraphLaunch(h->gexec, st));
-      launched += chunk;
-      HIP_TRY(hipMemcpyAsync(&h->h_ctrl[idx & 1], ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipEventRecord(h->ev[idx & 1], st));
-      if (idx >= 1) {
-        HIP_TRY(hipEventSynchronize(h->ev[(idx - 1) & 1]));
-        if (h->h_ctrl[(idx - 1) & 1].status != 0) stop = true;
+  for (;;) {
+    HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
+    HIP_TRY(launch_fill<T>(spec, n, T(0), st));
+    if (is_pre32(p)) HIP_TRY(launch_fill<T>((T*)wsp(ws, L.s0), (size_t)p.nt, T(0), st));
+    const long long budget = prm->max_iter - done;
+    HIP_TRY(launch_ctrl_init(ctrl, budget, eps, div, st, rd_lazy, prm->stall_iters));
+    key.tau_u = tau_u;
+    key.tau_phi = tau_phi;
+    h->last = key;
+    if (budget > 0) {
+      HIP_TRY(launch_checkpoint<T>(ctrl, u_alt, phi, ck_u, ck_phi, nlev, n, st));   // iterate 0
+      rc = build_graph<T>(h, key, u, phi, ws, (T)tau_u, (T)tau_phi, prm->history);
+      if (rc) return rc;
+      const long long bodies = budget + 1;
+      long long launched = 0;
+      int idx = 0;
+      bool stop = false;
+      while (!stop && launched < bodies) {
+        HIP_TRY(hipGraphLaunch(h->gexec, st));
+        launched += chunk;
+        HIP_TRY(launch_checkpoint<T>(ctrl, u_alt, phi, ck_u, ck_phi, nlev, n, st));
+        HIP_TRY(hipMemcpyAsync(&h->h_ctrl[idx & 1], ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(h->ev[idx & 1], st));
+        if (idx >= 1) {
+          HIP_TRY(hipEventSynchronize(h->ev[(idx - 1) & 1]));
+          if (h->h_ctrl[(idx - 1) & 1].status != 0) stop = true;
+        }
+        ++idx;
       }
-      ++idx;
     }
+    HIP_TRY(hipMemcpyAsync(&h->h_ctrl[0], ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    c = h->h_ctrl[0];
+    nstar = c.n_star;
+    if (budget <= 0) { nstar = 0; status = PDHG_NOT_CONVERGED; }
+    else if (c.status == 1) status = PDHG_OK;
+    else if (c.status == 2) status = PDHG_DIVERGED;
+    else if (c.status == 4) status = PDHG_STALLED;
+    else status = PDHG_NOT_CONVERGED;
+    if (status != PDHG_DIVERGED) {
+      if (nstar & 1) HIP_TRY(launch_copy<T>(u, u_alt, nlev, st));
+      nstar += done;
+      break;
+    }
+    // diverged: back to the last good checkpoint
+    HIP_TRY(launch_copy<T>(u, ck_u, nlev, st));
+    HIP_TRY(launch_copy<T>(phi, ck_phi, n, st));
+    done += c.ck_iter > 0 ? c.ck_iter : 0;
+    if (backoffs < prm->backoff && done < prm->max_iter) {   // smaller steps from the checkpoint
+      ++backoffs;
+      tau_u *= 0.7;
+      tau_phi *= 0.7;
+      continue;
+    }
+    nstar = done;
+    restored = true;
+    rc = state_norms<T>(h, u, phi, ws, st, &rp_ck, &rd_ck);
+    if (rc) return rc;
+    break;
   }
-  HIP_TRY(hipMemcpyAsync(&h->h_ctrl[0], ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
   auto t1 = std::chrono::steady_clock::now();
-  const Ctrl c = h->h_ctrl[0];
-  long long nstar = c.n_star;
-  int status;
-  if (prm->max_iter <= 0) { nstar = 0; status = PDHG_NOT_CONVERGED; }
-  else if (c.status == 1) status = PDHG_OK;
-  else if (c.status == 2) status = PDHG_DIVERGED;
-  else status = PDHG_NOT_CONVERGED;
-  if (nstar & 1) HIP_TRY(launch_copy<T>(u, u_alt, nlev, st));
   double drift = 0.0;
   {
     double* lev = (double*)wsp(ws, L.part_rp);   // nt+1 <= max_parts
@@ -1133,8 +1211,8 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   if (stats) {
     stats->mass_drift = drift;
     stats->iters = nstar;
-    stats->res_primal = c.rp_star;
-    stats->res_dual = c.rd_star;
+    stats->res_primal = restored ? rp_ck : c.rp_star;
+    stats->res_dual = restored ? rd_ck : c.rd_star;
     stats->tau_u = tau_u;
     stats->tau_phi = tau_phi;
     stats->nu_max = nu;
