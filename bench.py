@@ -16,6 +16,17 @@ bounded sample of iterations of the same workload.
     python bench.py --workload dg [--dg-iters N] [--dtype f32|f64]
     python bench.py --workload adjoint [--dtype f32|f64]
 
+The default run also measures the other workloads, under config.variants:
+the DG P2 workload (4096 cells x 512 levels, FP32 to its rounding floor and
+FP64 to 1e-8), the 256-problem batch (FP32 throughput batched against one solve
+per problem; FP64 time to residual 1e-8 over all problems with Algorithms 1
+and 3, batched against one solve per problem), the differentiable solve
+(viscous Burgers, forward + adjoint, FP32 and FP64), the FP32 run of the
+headline workload and single problems too large for the 256 MB MALL.  The
+cpu_baseline leg then runs the FP64 oracle: its timing on all host cores and in
+a one-thread process, and the Newton march / adjoint gradient of each workload,
+against which the FP64 error of every GPU result is reported.
+
 The single workload also reports the paper's three variants side by side
 (Section 4, comparison of the variants): Algorithm 1, mesh refinement in time
 (Algorithm 2, levels N_t = 1, 2, ..., 512) and the one-time-step solver
@@ -108,10 +119,49 @@ def cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(sample_iters: int, u_gpu=None):
-    """FP64 oracle Algorithm 1 on the same workload, timed over `sample_iters` iterations.  With the
-    GPU solution u_gpu (to residual 1e-8) also the oracle's sequential Newton march of the same BDF2
-    scheme: its wall time and the max-norm difference to u_gpu (returned second, else None)."""
+def host_cores() -> int:
+    """CPU cores this process may run on (the affinity mask), else os.cpu_count()."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+_ORACLE_SAMPLE = """
+import sys, time
+sys.path.insert(0, {root!r})
+import synthetic as syn
+from oracle import pdhg as opdhg
+from oracle.problem import Problem as OProblem, default_constants
+u0 = syn.fourier_u0({seed}, {nx})
+op = default_constants(OProblem(nx={nx}, nt={nt}, t_final={tf}, alpha=0.5, beta=0.0, space="fd_lf", time="bdf2"), u0)
+t0 = time.perf_counter()
+opdhg.run(op, u0, 0.6, 0.6, eps=0.0, max_iter={iters})
+print(time.perf_counter() - t0)
+"""
+
+
+def oracle_single_thread(sample_iters: int) -> float:
+    """Wall seconds of the same oracle sample in a fresh CPU-only process limited to one thread (the BLAS
+    and FFT thread counts are fixed before numpy is imported)."""
+    import subprocess
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS",
+              "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    env["HIP_VISIBLE_DEVICES"] = ""
+    code = _ORACLE_SAMPLE.format(root=ROOT, seed=SEED, nx=NX, nt=NT, tf=T_FINAL, iters=sample_iters)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600,
+                         check=True)
+    return float(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(sample_iters: int, u_gpu=None, gpu_iters=None):
+    """FP64 oracle Algorithm 1 on the same workload, timed over `sample_iters` iterations on every host core
+    and again in a one-thread process.  With the GPU's iteration count to 1e-8, the oracle's time to
+    residual 1e-8 is extrapolated as that count times its seconds per iteration.  With the GPU solution
+    u_gpu (to residual 1e-8) also the oracle's sequential Newton march of the same BDF2 scheme: its wall
+    time and the max-norm difference to u_gpu (returned second, else None)."""
     import numpy as np
 
     import synthetic as syn
@@ -125,24 +175,36 @@ def cpu_baseline(sample_iters: int, u_gpu=None):
     opdhg.run(oprob, u0, 0.6, 0.6, eps=0.0, max_iter=sample_iters)
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
+    cores = host_cores()
+    try:
+        wall1 = oracle_single_thread(sample_iters)
+    except Exception as exc:   # the one-thread leg is informative only
+        log(f"one-thread oracle leg failed: {exc}")
+        wall1 = None
     base = {
         "value": NX * NT * sample_iters / wall,
         "unit": "DOF-iterations/s",
-        "cores": max(1, int(round(cpu / wall))),
+        "cores": cores,
         "kind": "oracle",
+        "nproc": os.cpu_count(),
+        "concurrency": cpu / wall,
+        "single_thread_value": NX * NT * sample_iters / wall1 if wall1 else None,
+        "seconds_per_iteration": wall / sample_iters,
+        "time_to_residual_1e-8_extrapolated_s": wall / sample_iters * gpu_iters if gpu_iters else None,
         "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1) on the same "
-                  f"{NX}x{NT} BDF2 LF Burgers problem; {wall:.1f} s wall, host has {os.cpu_count()} CPUs "
-                  f"({cpu_model()})",
+                  f"{NX}x{NT} BDF2 LF Burgers problem; {wall:.1f} s wall on {cores} cores (process CPU time / wall "
+                  f"= {cpu / wall:.1f}), " + (f"{wall1:.1f} s in a one-thread process; " if wall1 else "") +
+                  f"{cpu_model()}",
     }
     if u_gpu is None:
-        return base, None
+        return base, None, None
     t0 = time.perf_counter()
     nw = onewton.march(oprob, u0)
     march_s = time.perf_counter() - t0
     err = {"max_abs_u_minus_newton_march": float(np.max(np.abs(u_gpu - nw))),
            "max_abs_u": float(np.max(np.abs(nw))), "newton_march_seconds": march_s}
     log(f"oracle Newton march: {march_s:.2f} s; max |u_gpu - u_newton| = {err['max_abs_u_minus_newton_march']:.3e}")
-    return base, err
+    return base, err, nw
 
 
 BATCH_COUNT, BATCH_ITERS, BATCH_SEED = 256, 300, 0
@@ -240,19 +302,22 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def fp32_run(pk):
-    """The same Burgers workload in FP32 (the precision floor is far above 1e-8, so a fixed 5000
-    iterations): DOF-iterations/s and the fused passes' event times at 4 bytes per word."""
+def fp32_run(pk, checks):
+    """The same Burgers workload in FP32.  Its rounding floor lies far above 1e-8, so the solve stops on
+    the single-precision rule: 500 iterations without a new best ||A(u)|| (the floor).  Reported:
+    DOF-iterations/s, the status and the fused passes' event times at 4 bytes per word; the returned u
+    goes to the oracle check (FP64 error against the Newton march)."""
     import torch
     import synthetic as syn
     s = pk.Solver(pk.Problem(nx=NX, nt=NT, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf",
                              dtype=torch.float32))
     u0 = torch.tensor(syn.fourier_u0(SEED, NX), dtype=torch.float32, device="cuda")
-    first = s.solve(u0, eps=0.0, max_iter=5000, check_every=128)
+    kw = dict(eps=EPS, max_iter=100000, check_every=128, stall_iters=500)
+    first = s.solve(u0, **kw)
     tau = first.stats["tau_u"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = s.solve(u0, tau_u=tau, tau_phi=tau, eps=0.0, max_iter=5000, check_every=128)
+    r = s.solve(u0, tau_u=tau, tau_phi=tau, **kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n = r.stats["iters"]
@@ -260,10 +325,13 @@ def fp32_run(pk):
     for kid, (name, words) in KERNELS_FUSED.items():
         ms = s.time_kernel(kid, reps=50)
         kern[name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": words * 4 * NX * NT / (ms * 1e-3) / 1e9}
-    log(f"FP32 run: {n} iterations, {wall:.3f} s, {NX * NT * n / wall:.3e} DOF-it/s, Rp {r.stats['res_primal']:.2e}")
-    return {"iterations": n, "seconds": wall, "dof_iterations_per_s": NX * NT * n / wall,
+    checks["burgers_f32"] = r.u.double().cpu().numpy()
+    log(f"FP32 run: status {r.status}, {n} iterations, {wall:.3f} s, {NX * NT * n / wall:.3e} DOF-it/s, "
+        f"Rp {r.stats['res_primal']:.2e}")
+    return {"status": r.status, "stop_rule": "500 iterations without a new best ||A(u)|| (eps 1e-8 unreachable)",
+            "iterations": n, "seconds": wall, "dof_iterations_per_s": NX * NT * n / wall,
             "us_per_iteration": wall / n * 1e6, "res_primal": r.stats["res_primal"],
-            "res_dual": r.stats["res_dual"], "kernels": kern}
+            "res_dual": r.stats["res_dual"], "kernels": kern, "fp64_error": None}
 
 
 def advection_cfl4(pk):
@@ -358,7 +426,7 @@ def traffic_table3(pk):
     return out
 
 
-def variant_comparison(pk, solver, prob, u0, tau, vanilla):
+def variant_comparison(pk, solver, prob, u0, tau, vanilla, checks):
     """Algorithms 1, 2 and 3 on the single workload (FP64, 1e-8); `vanilla` = (iterations, seconds)."""
     import torch
     out = {"algorithm_1": {"iterations": vanilla[0], "world_time": vanilla[0],
@@ -372,6 +440,7 @@ def variant_comparison(pk, solver, prob, u0, tau, vanilla):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lv = r.stats["level_iters"]
+    checks["mesh_refinement"] = r.u.double().cpu().numpy()
     nts = [1 << k for k in range(len(lv))]
     out["mesh_refinement"] = {"iterations": lv, "world_time": sum(lv),
                               "work_N": sum(n * (m + 1) for n, m in zip(lv, nts)), "seconds": wall,
@@ -386,6 +455,7 @@ def variant_comparison(pk, solver, prob, u0, tau, vanilla):
     wall = time.perf_counter() - t0
     _, _, res = solver.residual(r.u, r.phi, want_fields=False)
     n = r.stats["iters"]
+    checks["one_step"] = r.u.double().cpu().numpy()
     out["one_step"] = {"iterations": n, "world_time": n, "work_N": 2 * n, "seconds": wall, "status": r.status,
                        "space_time_residual": list(res), "steps": NT,
                        "us_per_iteration": r.stats["seconds"] / n * 1e6}
@@ -403,6 +473,7 @@ def variant_comparison(pk, solver, prob, u0, tau, vanilla):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n = r.stats["iters"]
+    checks["algorithm_1_full_symbol"] = r.u.double().cpu().numpy()
     cms = fs.time_kernel(1, reps=50)
     out["algorithm_1_full_symbol"] = {"iterations": n, "world_time": n, "work_N": n * (NT + 1), "seconds": wall,
                                       "status": r.status, "precond_c": r.stats["precond_c"],
@@ -417,6 +488,7 @@ def variant_comparison(pk, solver, prob, u0, tau, vanilla):
     wall = time.perf_counter() - t0
     _, _, res = fs.residual(r.u, r.phi, want_fields=False)
     n = r.stats["iters"]
+    checks["one_step_full_symbol"] = r.u.double().cpu().numpy()
     out["one_step_full_symbol"] = {"iterations": n, "world_time": n, "work_N": 2 * n, "seconds": wall,
                                    "status": r.status, "space_time_residual": list(res),
                                    "us_per_iteration": r.stats["seconds"] / n * 1e6}
@@ -434,6 +506,7 @@ def variant_comparison(pk, solver, prob, u0, tau, vanilla):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         n = r.stats["iters"]
+        checks["algorithm_1_gram_f32"] = r.u.double().cpu().numpy()
         kus = {name: ms.time_kernel(kid, reps=50) * 1e3 for kid, (name, _) in KERNELS_FUSED.items()}
         out["algorithm_1_gram_f32"] = {"iterations": n, "world_time": n, "work_N": n * (NT + 1), "seconds": wall,
                                        "status": r.status, "res_primal": r.stats["res_primal"],
@@ -534,7 +607,7 @@ def dg_cpu_baseline(sample_iters: int):
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     return {"value": 3 * DG_NX * DG_CPU_NT * sample_iters / wall, "unit": "DOF-iterations/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "cores": host_cores(), "concurrency": cpu / wall, "kind": "oracle",
             "sample": f"{sample_iters} iterations of the FP64 NumPy/SciPy oracle (Algorithm 1, DG P2) on the "
                       f"workload's {DG_NX} cells and first {DG_CPU_NT} levels (h_t = 3 h_x); {wall:.1f} s wall, "
                       f"host has {os.cpu_count()} CPUs ({cpu_model()})"}
@@ -611,8 +684,8 @@ def run_dg(args):
 def run_adjoint(args):
     """Differentiable workload: viscous Burgers (gamma = 1e-3), 2048 x 512, T = 0.5, backward Euler,
     Lax-Friedrichs flux with centred diffusion, loss h_x ||u^{N_t} - target||^2 with the target from
-    seed + 1.  The forward solve (FP32: a fixed budget of 15000 iterations, which reaches its rounding
-    floor; FP64: residual 1e-8), then the adjoint march for d loss / d u0, timed with HIP events."""
+    seed + 1.  The forward solve (FP32: to its rounding floor, 1000 iterations without a new best
+    ||A(u)||; FP64: residual 1e-8), then the adjoint march for d loss / d u0, timed with HIP events."""
     import torch
 
     import paper_2207_07234_amd as pk
@@ -627,13 +700,15 @@ def run_adjoint(args):
     solver = pk.Solver(prob)
     u0 = torch.tensor(syn.fourier_u0(SEED, nx), dtype=dtype, device=dev)
     tgt = torch.tensor(syn.fourier_u0(SEED + 1, nx), dtype=dtype, device=dev)
-    eps, max_iter = (1e-8, 200000) if esz == 8 else (0.0, 15000)
-    first = solver.solve(u0, eps=eps, max_iter=max_iter, check_every=128)
+    eps, max_iter = 1e-8, 200000
+    stall = 1000 if esz == 4 else 0   # FP32: to its rounding floor
+    first = solver.solve(u0, eps=eps, max_iter=max_iter, check_every=128, stall_iters=stall)
     tau = first.stats["tau_u"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = solver.solve(u0, tau_u=tau, tau_phi=tau, eps=eps, max_iter=max_iter, check_every=128)
+        r = solver.solve(u0, tau_u=tau, tau_phi=tau, eps=eps, max_iter=max_iter, check_every=128,
+                         stall_iters=stall)
     torch.cuda.synchronize()
     fwd = (time.perf_counter() - t0) / args.steps
     n = r.stats["iters"]
@@ -672,6 +747,300 @@ def run_adjoint(args):
                      "bytes_per_launch": adj_bytes, "ms_per_launch": adj_ms},
     }
     print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ the other workloads (variants)
+def dg_summary(pk, checks):
+    """DG P2 workload (Burgers, Legendre P2 with local Lax-Friedrichs, 4096 cells x 512 levels, h_t = 3 h_x,
+    backward Euler).  FP32 to its rounding floor (500 iterations without a new best ||A(u)||) and FP64 to
+    residual 1e-8: time to residual, DOF-iterations/s and the passes' event times against the roofline."""
+    import torch
+    import synthetic as syn
+    T = 3.0 * DG_NT / DG_NX
+    dof = 3 * DG_NX * DG_NT
+    out = {"workload": f"Burgers, DG P2 Legendre, local Lax-Friedrichs, backward Euler, {DG_NX} cells x {DG_NT} "
+                       f"levels, h_t = 3 h_x (T = {T})", "dof": dof}
+    for dt, key in ((torch.float32, "f32"), (torch.float64, "f64")):
+        esz = 4 if dt == torch.float32 else 8
+        s = pk.Solver(pk.Problem(nx=DG_NX, nt=DG_NT, t_final=T, alpha=0.5, beta=0.0, time="be", space="dg_p2_llf",
+                                 dtype=dt))
+        u0 = torch.tensor(syn.fourier_u0_legendre(SEED, DG_NX), dtype=dt, device="cuda")
+        kw = dict(eps=EPS, max_iter=100000, check_every=128, stall_iters=500 if esz == 4 else 0)
+        first = s.solve(u0, **kw)
+        tau = first.stats["tau_u"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve(u0, tau_u=tau, tau_phi=tau, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n = r.stats["iters"]
+        kern = {}
+        for kid, (name, words) in DG_KERNELS.items():
+            ms = s.time_kernel(kid, reps=30)
+            gbs = words * esz * dof / (ms * 1e-3) / 1e9
+            kern[name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        dom = max(kern, key=lambda k: kern[k]["us_per_launch"])
+        checks["dg_" + key] = r.u.double().cpu().numpy()
+        out[key] = {"status": r.status, "iterations": n, "seconds": wall, "dof_iterations_per_s": dof * n / wall,
+                    "us_per_iteration": wall / n * 1e6, "res_primal": r.stats["res_primal"],
+                    "res_dual": r.stats["res_dual"], "tau": tau, "kernels": kern, "dominant": dom,
+                    "dominant_frac": kern[dom]["frac"], "fp64_error": None,
+                    "stop": "residual 1e-8" if esz == 8 else "500 iterations without a new best ||A(u)||"}
+        log(f"DG P2 {key}: status {r.status}, {n} iterations, {wall:.3f} s, {dof * n / wall:.3e} DOF-it/s; "
+            f"dominant {dom} {kern[dom]['us_per_launch']:.1f} us ({kern[dom]['frac']:.2f} of peak)")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def batch_summary(pk, checks, sample=6):
+    """The 256-problem batch (Burgers, BDF2, LF, T = 0.5, nx in {256..4096}, nt in {64..512}):
+    * FP32 throughput at a fixed budget of BATCH_ITERS iterations, batched against one solve per problem;
+    * FP64 time to residual 1e-8 over all 256 problems with Algorithm 1 (a diverging problem stops at
+      detection and returns its last good checkpoint; counts reported), batched against one solve per
+      problem;
+    * FP64 time to step residual 1e-8 over all 256 problems with Algorithm 3 (one-step), batched (one
+      launch) against one solve per problem.
+    Converged problems of a sample go to the oracle check."""
+    import torch
+    dev = torch.device("cuda", 0)
+    out = {}
+    # ---- FP32 throughput
+    probs, u0s = batch_problems(pk, torch.float32)
+    bs = pk.BatchSolver(probs)
+    u0 = bs.pack_u0(u0s)
+    first = bs.solve(u0, eps=0.0, max_iter=2, check_every=2)
+    taus = [st["tau_u"] for st in first.stats]
+    grids = bs.tune(u0, tau_u=taus, tau_phi=taus)
+    bs.solve(u0, tau_u=taus, tau_phi=taus, eps=0.0, max_iter=BATCH_ITERS, check_every=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = bs.solve(u0, tau_u=taus, tau_phi=taus, eps=0.0, max_iter=BATCH_ITERS, check_every=50)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    dofit_b = sum(p.nx * p.nt * st["iters"] for p, st in zip(probs, r.stats))
+    dof = sum(p.nx * p.nt for p in probs)
+    kern = {}
+    for kid, (name, words) in BATCH_WORDS.items():
+        ms = bs.time_kernel(kid, reps=10)
+        gbs = words * 4 * dof / (ms * 1e-3) / 1e9
+        kern[name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    dom = max(kern, key=lambda k: kern[k]["us_per_launch"])
+    singles = [pk.Solver(p) for p in probs]
+    u0d = [torch.tensor(x, dtype=torch.float32, device=dev) for x in u0s]
+    for i, s in enumerate(singles):
+        s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], eps=0.0, max_iter=2, check_every=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dofit_s = 0
+    for i, s in enumerate(singles):
+        rr = s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], eps=0.0, max_iter=BATCH_ITERS, check_every=50)
+        dofit_s += probs[i].nx * probs[i].nt * rr.stats["iters"]
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    out["f32_fixed_budget"] = {
+        "iterations": BATCH_ITERS, "problems": len(probs), "dof": dof, "grids": grids,
+        "batched_s": wall_b, "batched_dof_iterations_per_s": dofit_b / wall_b,
+        "one_solve_per_problem_s": wall_s, "one_solve_per_problem_dof_iterations_per_s": dofit_s / wall_s,
+        "diverged": sum(st["status"] == 2 for st in r.stats), "kernels": kern, "dominant": dom,
+        "dominant_frac": kern[dom]["frac"]}
+    log(f"batch FP32, {BATCH_ITERS} iterations: batched {wall_b * 1e3:.1f} ms ({dofit_b / wall_b:.3e} DOF-it/s), "
+        f"one solve per problem {wall_s * 1e3:.1f} ms; dominant {dom} {kern[dom]['frac']:.2f} of peak")
+    del singles, u0d, bs
+    torch.cuda.empty_cache()
+    # ---- FP64 time to residual, Algorithm 1 and Algorithm 3, all problems
+    probs, u0s = batch_problems(pk, torch.float64)
+    bs = pk.BatchSolver(probs)
+    u0 = bs.pack_u0(u0s)
+    first = bs.solve(u0, eps=0.0, max_iter=2, check_every=2)
+    taus = [st["tau_u"] for st in first.stats]
+    bs.tune(u0, tau_u=taus, tau_phi=taus)
+    kw = dict(eps=EPS, max_iter=40000, check_every=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = bs.solve(u0, tau_u=taus, tau_phi=taus, **kw)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    singles = [pk.Solver(p) for p in probs]
+    u0d = [torch.tensor(x, dtype=torch.float64, device=dev) for x in u0s]
+    for i, s in enumerate(singles):
+        s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], eps=0.0, max_iter=2, check_every=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single_stats = []
+    for i, s in enumerate(singles):
+        rr = s.solve(u0d[i], tau_u=taus[i], tau_phi=taus[i], **kw)
+        single_stats.append((rr.stats["status"], rr.stats["iters"]))
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    conv = [i for i, st in enumerate(r.stats) if st["status"] == 0]
+    pick = conv[:: max(1, len(conv) // sample)][:sample]
+    checks["batch_alg1"] = {i: (probs[i].nx, probs[i].nt, u0s[i], r.views_u[i].double().cpu().numpy())
+                            for i in pick}
+    out["f64_algorithm_1_to_1e-8"] = {
+        "problems": len(probs), "converged": len(conv), "diverged": sum(st["status"] == 2 for st in r.stats),
+        "max_iter_reached": sum(st["status"] == 1 for st in r.stats),
+        "batched_s": wall_b, "one_solve_per_problem_s": wall_s, "speedup": wall_s / wall_b,
+        "same_status_and_n_star_as_single": all((st["status"], st["iters"]) == ss
+                                                for st, ss in zip(r.stats, single_stats)),
+        "differing_from_single": [(i, probs[i].nx, probs[i].nt, (st["status"], st["iters"]), ss)
+                                  for i, (st, ss) in enumerate(zip(r.stats, single_stats))
+                                  if (st["status"], st["iters"]) != ss][:12],
+        "max_n_star": max(st["iters"] for st in r.stats),
+        "converged_dof_iterations": sum(probs[i].nx * probs[i].nt * r.stats[i]["iters"] for i in conv),
+        "fp64_error": None}
+    log(f"batch FP64 Algorithm 1 to 1e-8: batched {wall_b:.2f} s, one solve per problem {wall_s:.2f} s; "
+        f"{len(conv)} converged, {out['f64_algorithm_1_to_1e-8']['diverged']} diverged")
+    # Algorithm 3
+    bs.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = bs.solve_onestep(u0, eps=EPS, max_iter=20000)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    for i, s in enumerate(singles):
+        s.solve_onestep(u0d[i], eps=EPS, max_iter=2)   # step sizes (power iteration) outside the timing
+    taus1 = [st["tau_u"] for st in r.stats]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok_single = 0
+    for i, s in enumerate(singles):
+        rr = s.solve_onestep(u0d[i], tau_u=taus1[i], tau_phi=taus1[i], eps=EPS, max_iter=20000)
+        ok_single += rr.status == 0
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    conv = [i for i, st in enumerate(r.stats) if st["status"] == 0]
+    pick = list(range(0, len(probs), max(1, len(probs) // sample)))[:sample]
+    checks["batch_alg3"] = {i: (probs[i].nx, probs[i].nt, u0s[i], r.views_u[i].double().cpu().numpy())
+                            for i in pick}
+    slice_its = sum(p.nx * st["iters"] for p, st in zip(probs, r.stats))
+    out["f64_algorithm_3_to_1e-8"] = {
+        "problems": len(probs), "converged": len(conv), "converged_single": ok_single,
+        "diverged": sum(st["status"] == 2 for st in r.stats), "batched_s": wall_b,
+        "one_solve_per_problem_s": wall_s, "speedup": wall_s / wall_b,
+        "slice_dof_iterations_per_s": slice_its / wall_b, "fp64_error": None}
+    log(f"batch FP64 Algorithm 3 to step residual 1e-8: batched {wall_b:.3f} s, one solve per problem "
+        f"{wall_s:.3f} s; {len(conv)} converged")
+    return out
+
+
+def adjoint_summary(pk, checks):
+    """Differentiable workload: viscous Burgers (gamma = 1e-3), 2048 x 512, T = 0.5, BE, LF + centred
+    diffusion, loss h_x ||u^{N_t} - target||^2 (target from seed + 1).  Forward in FP32 (to its rounding
+    floor: 1000 iterations without a new best) and FP64 (residual 1e-8), then the adjoint march for
+    d loss / d u0; the gradients go to the oracle check."""
+    import torch
+    import synthetic as syn
+    out = {"workload": f"viscous Burgers (gamma 1e-3), FD LF + centred diffusion, BE, {NX}x{NT}, T={T_FINAL}, "
+                       f"loss h_x |u(T) - target|^2, seeds {SEED}/{SEED + 1}"}
+    for dt, key in ((torch.float32, "f32"), (torch.float64, "f64")):
+        esz = 4 if dt == torch.float32 else 8
+        s = pk.Solver(pk.Problem(nx=NX, nt=NT, t_final=T_FINAL, alpha=0.5, beta=0.0, gamma=1e-3, time="be",
+                                 space="fd_lf", dtype=dt, precond_gamma_hat=1e-3))
+        u0 = torch.tensor(syn.fourier_u0(SEED, NX), dtype=dt, device="cuda")
+        tgt = torch.tensor(syn.fourier_u0(SEED + 1, NX), dtype=dt, device="cuda")
+        kw = dict(eps=EPS, max_iter=200000, check_every=128, stall_iters=1000 if esz == 4 else 0)
+        first = s.solve(u0, **kw)
+        tau = first.stats["tau_u"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve(u0, tau_u=tau, tau_phi=tau, **kw)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - t0
+        g = torch.zeros((NT + 1, NX), dtype=dt, device="cuda")
+        g[-1] = (2.0 / NX) * (r.u[-1] - tgt)
+        grad = s.adjoint_solve(r.u, g)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            grad = s.adjoint_solve(r.u, g)
+        e1.record()
+        torch.cuda.synchronize()
+        adj_ms = e0.elapsed_time(e1) / 10
+        adj_bytes = (2 * (NT + 1) * NX + NX) * esz
+        n = r.stats["iters"]
+        checks["adjoint_" + key] = grad.double().cpu().numpy()
+        out[key] = {"forward_status": r.status, "forward_iterations": n, "forward_s": fwd,
+                    "dof_iterations_per_s": NX * NT * n / fwd, "res_primal": r.stats["res_primal"],
+                    "adjoint_ms": adj_ms, "adjoint_GBs": adj_bytes / (adj_ms * 1e-3) / 1e9,
+                    "differentiable_solve_s": fwd + adj_ms * 1e-3, "gradient_fp64_rel_error": None}
+        log(f"differentiable {key}: forward status {r.status}, {n} iterations, {fwd:.3f} s; adjoint {adj_ms:.2f} ms")
+        s.close()
+    return out
+
+
+def onestep_us_sweep(pk):
+    """Algorithm 3 microseconds per iteration against N_x (FP64, BDF2 Burgers, 8 steps of a fixed 200
+    iterations each, h_t = 2 h_x): the one-workgroup march is latency-bound."""
+    import torch
+    import synthetic as syn
+    out = {}
+    for nx in (256, 512, 2048, 4096):
+        s = pk.Solver(pk.Problem(nx=nx, nt=8, t_final=16.0 / nx, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf",
+                                 dtype=torch.float64))
+        u0 = torch.tensor(syn.fourier_u0(SEED, nx), dtype=torch.float64, device="cuda")
+        s.solve_onestep(u0, tau_u=0.5, tau_phi=0.5, eps=0.0, max_iter=200)
+        r = s.solve_onestep(u0, tau_u=0.5, tau_phi=0.5, eps=0.0, max_iter=200)
+        out[str(nx)] = r.stats["seconds"] / r.stats["iters"] * 1e6
+        s.close()
+    log("one-step us per iteration (FP64): " + ", ".join(f"{k}: {v:.1f}" for k, v in out.items()))
+    return out
+
+
+def oracle_checks(checks, variants, headline_nw):
+    """The cpu_baseline leg's oracle references: the Newton march of each workload's implicit scheme and
+    the adjoint gradient, and the max-norm FP64 error of every GPU result against them."""
+    import numpy as np
+
+    import synthetic as syn
+    from oracle import adjoint as oadj
+    from oracle import dg as odg
+    from oracle import newton as onewton
+    from oracle.problem import Problem as OProblem, default_constants
+
+    def err(a, ref):
+        return float(np.max(np.abs(a - ref)))
+
+    if headline_nw is not None:
+        for key, target in (("burgers_f32", ("fp32_stop_rule",)), ("mesh_refinement", ("mesh_refinement",)),
+                            ("one_step", ("one_step",)), ("algorithm_1_full_symbol", ("algorithm_1_full_symbol",)),
+                            ("one_step_full_symbol", ("one_step_full_symbol",)),
+                            ("algorithm_1_gram_f32", ("algorithm_1_gram_f32",))):
+            if key in checks and target[0] in variants:
+                variants[target[0]]["fp64_error"] = err(checks[key], headline_nw)
+    if "dg_f64" in checks and "dg_p2" in variants:
+        t0 = time.perf_counter()
+        u0 = odg.p2_project(lambda x: syn.fourier_u0_at(SEED, x), DG_NX)
+        op = default_constants(OProblem(nx=DG_NX, nt=DG_NT, t_final=3.0 * DG_NT / DG_NX, alpha=0.5, beta=0.0,
+                                        space="dg_p2_llf", time="be"), u0)
+        nw = onewton.march(op, u0)
+        for key in ("f32", "f64"):
+            variants["dg_p2"][key]["fp64_error"] = err(checks["dg_" + key], nw)
+        log(f"oracle DG Newton march {time.perf_counter() - t0:.1f} s: errors "
+            f"{variants['dg_p2']['f32']['fp64_error']:.2e} (FP32), {variants['dg_p2']['f64']['fp64_error']:.2e} (FP64)")
+    if "batch_256" in variants:
+        for ck, vk in (("batch_alg1", "f64_algorithm_1_to_1e-8"), ("batch_alg3", "f64_algorithm_3_to_1e-8")):
+            worst = 0.0
+            for i, (nx, nt, u0, u) in checks.get(ck, {}).items():
+                op = default_constants(OProblem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, space="fd_lf",
+                                                time="bdf2"), u0)
+                worst = max(worst, err(u, onewton.march(op, u0)))
+            variants["batch_256"][vk]["fp64_error"] = worst
+            variants["batch_256"][vk]["fp64_error_sample"] = sorted(checks.get(ck, {}))
+    if "adjoint_f64" in checks and "differentiable" in variants:
+        t0 = time.perf_counter()
+        u0, tgt = syn.fourier_u0(SEED, NX), syn.fourier_u0(SEED + 1, NX)
+        op = default_constants(OProblem(nx=NX, nt=NT, t_final=T_FINAL, alpha=0.5, beta=0.0, gamma=1e-3,
+                                        space="fd_lf", time="be"), u0)
+        nw = onewton.march(op, u0)
+        gref = oadj.gradient_u0(op, nw, oadj.terminal_loss_grad(op, nw, tgt))
+        for key in ("f32", "f64"):
+            variants["differentiable"][key]["gradient_fp64_rel_error"] = \
+                err(checks["adjoint_" + key], gref) / float(np.max(np.abs(gref)))
+        log(f"oracle adjoint gradient {time.perf_counter() - t0:.1f} s")
+
 
 
 def main():
@@ -777,12 +1146,17 @@ def main():
             "copy_GBs": copy_bytes / (copy_ms * 1e-3) / 1e9}
 
     variants = None
+    checks = {}   # GPU results for the oracle check of the cpu_baseline leg
     if eps > 0 and not args.no_variants:
-        variants = variant_comparison(pk, solver, prob, u0, tau, (iters[-1], ms_per_step / 1e3))
+        variants = variant_comparison(pk, solver, prob, u0, tau, (iters[-1], ms_per_step / 1e3), checks)
         variants["traffic_table3"] = traffic_table3(pk)
         variants["advection_cfl4_64x32"] = advection_cfl4(pk)
-        variants["fp32_5000_iterations"] = fp32_run(pk)
+        variants["fp32_stop_rule"] = fp32_run(pk, checks)
         variants["large_single"] = large_single_sweep(pk)
+        variants["one_step_us_per_iteration_f64"] = onestep_us_sweep(pk)
+        variants["dg_p2"] = dg_summary(pk, checks)
+        variants["batch_256"] = batch_summary(pk, checks)
+        variants["differentiable"] = adjoint_summary(pk, checks)
 
     out = {
         "metric": METRIC,
@@ -810,8 +1184,10 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], err = cpu_baseline(args.cpu_iters, u_final)
+        out["cpu_baseline"], err, nw = cpu_baseline(args.cpu_iters, u_final, gpu_iters=iters[-1] if eps > 0 else None)
         out["config"]["error_vs_oracle"] = err
+        if variants is not None:
+            oracle_checks(checks, variants, nw)
     print(json.dumps(out), flush=True)
 
 
