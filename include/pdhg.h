@@ -150,7 +150,16 @@ typedef struct {
                                precision, whose residual floor grows like 1/h_t          */
   int32_t stall_iters;      /* > 0: stop with PDHG_STALLED when ||A(u)|| has not improved on its
                                best for this many iterations (the rounding floor)         */
-  int32_t reserved;
+  int32_t init_multiplier;  /* 1: the multiplier form of Algorithm 1 (Section 3.3): u^0 is an
+                               unknown and lambda imposes u^0 = u0 through the term
+                               h_x sum_j lambda_j (u^0_j - u0_j) of the Lagrangian; standard
+                               primal-dual steps u^0 <- u^0 - tau_u0 (h_t J_0^T phibar + lambdabar),
+                               lambda <- lambda + tau_lam (u^0 - u0) with extrapolation, where
+                               h_t J_0^T phibar = -phibar^0 (+ phibar^1 / 2 for BDF2); u[0] then
+                               returns the iterated u^0.  Fused finite-difference passes only
+                               (PDHG_EUNSUPPORTED otherwise, and with backoff > 0).       */
+  double tau_u0;            /* u^0 step of the multiplier form; <= 0: tau_u / 2            */
+  double tau_lam;           /* lambda step of the multiplier form; <= 0: 0.99              */
 } pdhg_params;
 
 typedef struct {

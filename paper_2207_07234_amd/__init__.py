@@ -141,7 +141,8 @@ class Solver:
     def solve(self, u0, tau_u: float = 0.0, tau_phi: float = 0.0, eps: float = 1e-8, max_iter: int = 10000,
               check_every: int = 64, u=None, phi=None, warm_start: bool = False, workspace=None,
               history: bool = False, diverge_factor: float = 0.0, variant: int = 0,
-              backoff: int = 0, eps_rel: float = 0.0, stall_iters: int = 0) -> SolveResult:
+              backoff: int = 0, eps_rel: float = 0.0, stall_iters: int = 0, init_multiplier: bool = False,
+              tau_u0: float = 0.0, tau_lam: float = 0.0) -> SolveResult:
         import torch
         nt, lv = self.prob.nt, self.prob.level_shape
         self._check(u0, lv, "u0")
@@ -154,6 +155,7 @@ class Solver:
         p.max_iter, p.check_every, p.warm_start = int(max_iter), int(check_every), int(bool(warm_start))
         p.diverge_factor, p.variant, p.backoff = float(diverge_factor), int(variant), int(backoff)
         p.eps_rel, p.stall_iters = float(eps_rel), int(stall_iters)
+        p.init_multiplier, p.tau_u0, p.tau_lam = int(bool(init_multiplier)), float(tau_u0), float(tau_lam)
         p.history = hist.data_ptr() if hist is not None else None
         st = B.pdhg_stats()
         rc = self.lib.pdhg_solve(self._h, _ptr(u0), _ptr(u), _ptr(phi), _ptr(workspace), C.byref(p),

@@ -36,7 +36,8 @@ class pdhg_params(C.Structure):
         ("tau_u", C.c_double), ("tau_phi", C.c_double), ("eps", C.c_double),
         ("max_iter", C.c_int64), ("check_every", C.c_int32), ("warm_start", C.c_int32),
         ("diverge_factor", C.c_double), ("variant", C.c_int32), ("backoff", C.c_int32),
-        ("history", C.c_void_p), ("eps_rel", C.c_double), ("stall_iters", C.c_int32), ("reserved", C.c_int32),
+        ("history", C.c_void_p), ("eps_rel", C.c_double), ("stall_iters", C.c_int32),
+        ("init_multiplier", C.c_int32), ("tau_u0", C.c_double), ("tau_lam", C.c_double),
     ]
 
 

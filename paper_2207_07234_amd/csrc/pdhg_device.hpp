@@ -496,6 +496,20 @@ struct FacTab {
   const int* last;
 };
 
+// Multiplier form of Algorithm 1 (Section 3.3): the initial level u^0 is an
+// unknown, and lambda (nx values) imposes u^0 = u0.  u0 == nullptr: u^0 is held
+// fixed.  The pass that holds rows 0 and 1 updates u^0 and lambda (no other
+// pair reads u^0): u^0 <- u^0 - tau_u0 (h_t J_0^T phibar + lambdabar) with
+// h_t J_0^T phibar = c1(0) phibar^0 + c2(1) phibar^1, then
+// lambda <- lambda + tau_lam (u^0 - u0), lambdabar = 2 lambda_new - lambda_old.
+template <typename T>
+struct LamArgs {
+  const T* u0;
+  T* lam;
+  T* lambar;
+  T tau_u0, tau_lam;
+};
+
 // Device-side control block of one solve.
 struct Ctrl {
   long long n_done;    // loop bodies completed

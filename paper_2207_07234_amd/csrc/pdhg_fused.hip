@@ -66,7 +66,7 @@ template <typename T, int E, typename S>
 __global__ void __launch_bounds__((row_threads_max<T, E>()))
 k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
              const T* __restrict__ phi, T tau_u, S* __restrict__ spec, int lqb, const C2<S>* __restrict__ tw,
-             double* __restrict__ part, const Ctrl* ctrl) {
+             double* __restrict__ part, const Ctrl* ctrl, LamArgs<T> lam) {
   if (ctrl->status != 0) return;
   extern __shared__ char smem[];
   const Consts<T> C(sch);
@@ -82,7 +82,7 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   const bool want_rd = rd_needed(ctrl);
   double rp, rd;
   primal_res_pair<T, E, S>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
-                           edge, rp, rd, alt, wsum, want_rd);
+                           edge, rp, rd, alt, wsum, want_rd, &lam);
   if (tid == 0) {
     const int nw = W >> 6;
     double srp = 0.0, srd = 0.0;
@@ -331,14 +331,14 @@ hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* t
 template <typename T, int E, typename S>
 static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi,
                                       T tau_u, S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl,
-                                      hipStream_t st) {
+                                      hipStream_t st, const LamArgs<T>& lam) {
   const int W = s.nx / E;
   const size_t lds = sizeof(C2<S>) * (fft_pingpong<S>(s.nx) ? 3 : 2) * (size_t)lds_fft_points(s.nx) +
                      sizeof(T) * 4 * (W / 64);
   hipError_t e = allow_lds(k_primal_res<T, E, S>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_primal_res<T, E, S>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out, phibar, phi,
-                     tau_u, spec, lqb, (const C2<S>*)tw, part, ctrl);
+                     tau_u, spec, lqb, (const C2<S>*)tw, part, ctrl, lam);
   return hipGetLastError();
 }
 
@@ -347,15 +347,17 @@ static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, 
 // W >= 64 (nx >= 64).
 template <typename T, typename S>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
-                             S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st) {
+                             S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st,
+                             const LamArgs<T>* lam) {
+  const LamArgs<T> la = lam ? *lam : LamArgs<T>{nullptr, nullptr, nullptr, T(0), T(0)};
   int W;
   if (sizeof(T) == 4) W = clampi(s.nx / 4, 64, 1024);
   else W = s.nx <= 2048 ? clampi(s.nx / 2, 64, 1024) : 512;
   switch (s.nx / W) {
-    case 1: return launch_primal_res_e<T, 1, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
-    case 2: return launch_primal_res_e<T, 2, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
-    case 4: return launch_primal_res_e<T, 4, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
-    case 8: return launch_primal_res_e<T, 8, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st);
+    case 1: return launch_primal_res_e<T, 1, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
+    case 2: return launch_primal_res_e<T, 2, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
+    case 4: return launch_primal_res_e<T, 4, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
+    case 8: return launch_primal_res_e<T, 8, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
     default: return hipErrorInvalidValue;
   }
 }
@@ -495,13 +497,13 @@ template hipError_t launch_dual_fft<double, float>(const float*, int, int, int, 
                                                    double, const Ctrl*, hipStream_t, const double*);
 template hipError_t launch_primal_res<float, float>(const Scheme&, const float*, float*, const float*, const float*,
                                                     float, float*, int, const void*, double*, const Ctrl*,
-                                                    hipStream_t);
+                                                    hipStream_t, const LamArgs<float>*);
 template hipError_t launch_primal_res<double, double>(const Scheme&, const double*, double*, const double*,
                                                       const double*, double, double*, int, const void*, double*,
-                                                      const Ctrl*, hipStream_t);
+                                                      const Ctrl*, hipStream_t, const LamArgs<double>*);
 template hipError_t launch_primal_res<double, float>(const Scheme&, const double*, double*, const double*,
                                                      const double*, double, float*, int, const void*, double*,
-                                                     const Ctrl*, hipStream_t);
+                                                     const Ctrl*, hipStream_t, const LamArgs<double>*);
 template hipError_t launch_colsolve_wave<float, float>(float*, const FacTab<float>&, int, int, int, int, Ctrl*,
                                                        const double*, int, double, double*, hipStream_t, float*);
 template hipError_t launch_colsolve_wave<float, double>(float*, const FacTab<double>&, int, int, int, int, Ctrl*,

@@ -68,7 +68,8 @@ hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* t
                            const Ctrl* ctrl, hipStream_t st, const T* s0 = nullptr);
 template <typename T, typename S = T>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
-                             S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st);
+                             S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st,
+                             const LamArgs<T>* lam = nullptr);
 // T: type of the spectrum; A: type of the factor rows and of the recurrences
 // (double for a float spectrum under an FP64 state).  s0 (optional, nt values
 // of type A): receives the mode-0 column of the solution.

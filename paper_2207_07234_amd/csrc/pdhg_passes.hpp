@@ -158,7 +158,7 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
                                                 const C2<S>* __restrict__ tw, int a, int tid, int W, int gtid,
                                                 int TB, C2<S>* buf, C2<S>* twl, T* edge, double& rp_out,
                                                 double& rd_out, C2<S>* alt = nullptr, double* wsum = nullptr,
-                                                bool want_rd = true) {
+                                                bool want_rd = true, const LamArgs<T>* lam = nullptr) {
   const int nx = C.nx, nt = C.nt;
   const int lane = tid & 63, wv = tid >> 6, nw = W >> 6;
   const int seg0 = wv * 64 * E;
@@ -208,8 +208,22 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
     const int m = a - 1 + i;
     if (m < 0 || m > nt || (!bdf2 && i == 0)) continue;
     if (m == 0) {
+      if (lam && lam->u0) {   // multiplier form: u^0 and lambda step (this pair holds rows 0 and 1)
+        const T c1 = C.c1(0), c2 = C.c2(1);
 #pragma unroll
-      for (int e = 0; e < E; ++e) U[i][e] = U0[i][e];
+        for (int e = 0; e < E; ++e) {
+          const int x = seg0 + lane + 64 * e;
+          const T lb = lam->lambar[x], lo = lam->lam[x];
+          U[i][e] = U0[i][e] - lam->tau_u0 * (c1 * PB[i + 1][e] + c2 * PB[i + 2][e] + lb);
+          const T dl = lam->tau_lam * (U[i][e] - lam->u0[x]);
+          lam->lam[x] = lo + dl;
+          lam->lambar[x] = lo + T(2) * dl;
+          u_out[x] = U[i][e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) U[i][e] = U0[i][e];
+      }
       continue;
     }
     T g[E];

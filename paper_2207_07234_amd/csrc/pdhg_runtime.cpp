@@ -252,7 +252,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
-  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, ck_u, ck_phi, total;
+  size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, ck_u, ck_phi, lam, lambar,
+      total;
   int max_parts;
 };
 
@@ -263,9 +264,12 @@ struct GraphKey {
   const void* hist = nullptr;
   double tau_u = 0, tau_phi = 0, lf = 0, c = 0;
   int variant = 0, chunk = 0;
+  const void* lam_u0 = nullptr;   // multiplier form: the initial data (nullptr: u^0 fixed)
+  double tau_u0 = 0, tau_lam = 0;
   bool operator==(const GraphKey& o) const {
     return u == o.u && phi == o.phi && ws == o.ws && hist == o.hist && tau_u == o.tau_u &&
-           tau_phi == o.tau_phi && lf == o.lf && c == o.c && variant == o.variant && chunk == o.chunk;
+           tau_phi == o.tau_phi && lf == o.lf && c == o.c && variant == o.variant && chunk == o.chunk &&
+           lam_u0 == o.lam_u0 && tau_u0 == o.tau_u0 && tau_lam == o.tau_lam;
   }
 };
 
@@ -366,6 +370,8 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.s0 = o; o += align_up(sizeof(double) * nt);    // FP64 mode 0 of a float spectrum
   L.ck_u = o; o += ufield;                         // last-good checkpoint (u, phi) of the solve loop
   L.ck_phi = o; o += field;
+  L.lam = o; o += align_up(nx * esz);              // multiplier of u^0 = u0 and its extrapolation
+  L.lambar = o; o += align_up(nx * esz);
   L.total = o;
   return L;
 }
@@ -955,12 +961,14 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
   Ctrl* ctrl = (Ctrl*)wsp(ws, L.ctrl);
   T* uin = odd ? u : u_alt;
   T* uout = odd ? u_alt : u;
+  const GraphKey& K = h->last;   // the loop being captured
+  LamArgs<T> lam{(const T*)K.lam_u0, (T*)wsp(ws, L.lam), (T*)wsp(ws, L.lambar), (T)K.tau_u0, (T)K.tau_lam};
   if (is_pre32(p)) {   // the spectrum, its FFTs and the column solve in float
     float* spec32 = (float*)wsp(ws, L.spec0);
     T* s0 = (T*)wsp(ws, L.s0);   // mode 0 of the spectrum in FP64
     HIP_TRY((launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tau_phi, ctrl, st, s0)));
     HIP_TRY((launch_primal_res<T, float>(s, uin, uout, phibar, phi, tau_u, spec32, h->lqb, h->d_tw32, part, ctrl,
-                                         st)));
+                                         st, &lam)));
     const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
     HIP_TRY((launch_colsolve_wave<float, double>(spec32, factab<double>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
                                                  h->lqb, ctrl, part, (p.nt + 1) / 2, wscale, hist, st,
@@ -968,7 +976,7 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
     return PDHG_OK;
   }
   HIP_TRY(launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
-  HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, st));
+  HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, st, &lam));
   HIP_TRY(colsolve_any<T>(h, spec, ctrl, part, (p.nt + 1) / 2, hist, st));
   return PDHG_OK;
 }
@@ -1123,6 +1131,12 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   if (prm->backoff < 0) return PDHG_EINVAL;
   key.variant = dg ? 4 : ((prm->variant == 1 || p.nx < 64) ? 1 : 2);
   key.chunk = chunk;
+  if (prm->init_multiplier) {   // the multiplier form: fused finite-difference passes only, no back-off
+    if (key.variant != 2 || prm->backoff > 0 || is_full(p)) return PDHG_EUNSUPPORTED;
+    key.lam_u0 = u0;
+    key.tau_u0 = prm->tau_u0 > 0 ? prm->tau_u0 : 0.5 * tau_u;
+    key.tau_lam = prm->tau_lam > 0 ? prm->tau_lam : 0.99;
+  }
   // Last-good checkpoint (u, phi, iterate index): refreshed on the device after every chunk while the
   // solve runs (launch_checkpoint), so that it always holds an iterate that passed the tests.
   T* ck_u = (T*)wsp(ws, L.ck_u);
@@ -1139,6 +1153,10 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
     HIP_TRY(launch_copy<T>(u_alt, u, nlev, st));
     HIP_TRY(launch_fill<T>(spec, n, T(0), st));
     if (is_pre32(p)) HIP_TRY(launch_fill<T>((T*)wsp(ws, L.s0), (size_t)p.nt, T(0), st));
+    if (prm->init_multiplier) {   // lambda = lambdabar = 0; u^0 starts from u0 (the broadcast above)
+      HIP_TRY(launch_fill<T>((T*)wsp(ws, L.lam), (size_t)p.nx, T(0), st));
+      HIP_TRY(launch_fill<T>((T*)wsp(ws, L.lambar), (size_t)p.nx, T(0), st));
+    }
     const long long budget = prm->max_iter - done;
     HIP_TRY(launch_ctrl_init(ctrl, budget, eps, div, st, rd_lazy, prm->stall_iters));
     key.tau_u = tau_u;

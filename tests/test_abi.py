@@ -54,7 +54,7 @@ def test_binding_struct_sizes_match_header_layout():
     B, _ = _lib()
     # field order/size mirrors include/pdhg.h; natural alignment on x86-64
     assert C.sizeof(B.pdhg_problem) == 4 * 2 + 8 * 5 + 4 * 4 + 8 * 3
-    assert C.sizeof(B.pdhg_params) == 8 * 3 + 8 + 4 * 2 + 8 + 4 * 2 + 8 + 8 + 4 * 2
+    assert C.sizeof(B.pdhg_params) == 8 * 3 + 8 + 4 * 2 + 8 + 4 * 2 + 8 + 8 + 4 * 2 + 8 * 2
     assert C.sizeof(B.pdhg_stats) == 8 * 10 + 4 * 2
 
 
