@@ -41,19 +41,40 @@ constexpr int row_threads_max() { return E * (int)sizeof(T) <= 16 ? 1024 : 512; 
 template <typename T>
 __host__ __device__ constexpr bool fft_pingpong(int nx) { return 3 * (size_t)nx * sizeof(C2<T>) <= 98304; }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// Row-pair grids of at least two blocks per CU run their row passes for
+// occupancy: A without the third LDS array (two blocks share a CU's LDS), B
+// with the streaming body (a sliding window of rows in registers, no third LDS
+// array).  A grid of at most one block per CU keeps the one-block layouts,
+// whose load-everything-first order suits a block that has its CU to itself.
+// Either way the arithmetic, and so every iterate, is the same.
+static inline bool rows_for_occupancy(int nt) { return (nt + 1) / 2 >= 2 * device_cus(); }
+
 // A: one block per pair of dual rows, W = nx / EPT threads; S is the type of
 // the spectrum and of the FFT.
 template <typename T, int EPT, typename S>
 __global__ void __launch_bounds__(kRowThreadsMax)
 k_dual_fft(const S* __restrict__ spec, int nt, int lqb, int nx, const C2<S>* __restrict__ tw, T* __restrict__ phi,
-           T* __restrict__ phibar, T tau, const Ctrl* ctrl, const T* __restrict__ s0) {
+           T* __restrict__ phibar, T tau, const Ctrl* ctrl, const T* __restrict__ s0, int pp) {
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
   C2<S>* buf = reinterpret_cast<C2<S>*>(smem);
   C2<S>* twl = buf + lds_fft_points(nx);
   const int tid = threadIdx.x, W = blockDim.x;
   const int a = 2 * xcd_block(blockIdx.x, gridDim.x);
-  C2<S>* alt = fft_pingpong<S>(nx) ? twl + lds_fft_points(nx) : nullptr;
+  C2<S>* alt = pp ? twl + lds_fft_points(nx) : nullptr;
   dual_fft_pair<T, EPT, S>(spec, nt, lqb, nx, tw, phi, phibar, tau, a, tid, W, tid, W, buf, twl, alt, s0);
 }
 
@@ -62,8 +83,8 @@ k_dual_fft(const S* __restrict__ spec, int nt, int lqb, int nx, const C2<S>* __r
 // solve of the same iteration reduces them.  The per-wave sums are taken
 // before the FFT, whose barriers publish them, and added up by thread 0 in
 // wave order at the end (the order of block_sum_waves).
-template <typename T, int E, typename S>
-__global__ void __launch_bounds__((row_threads_max<T, E>()))
+template <typename T, int E, typename S, bool STREAM>
+__global__ void __launch_bounds__((STREAM ? 1024 : row_threads_max<T, E>()))
 k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, const T* __restrict__ phibar,
              const T* __restrict__ phi, T tau_u, S* __restrict__ spec, int lqb, const C2<S>* __restrict__ tw,
              double* __restrict__ part, const Ctrl* ctrl, LamArgs<T> lam) {
@@ -73,16 +94,16 @@ k_primal_res(Scheme sch, const T* __restrict__ u_in, T* __restrict__ u_out, cons
   const int nx = sch.nx, W = blockDim.x, tid = threadIdx.x;
   C2<S>* buf = reinterpret_cast<C2<S>*>(smem);
   C2<S>* twl = buf + lds_fft_points(nx);
-  const bool pp = fft_pingpong<S>(nx);
+  const bool pp = !STREAM && fft_pingpong<S>(nx);
   C2<S>* alt = pp ? twl + lds_fft_points(nx) : nullptr;
   T* edge = reinterpret_cast<T*>(twl + (pp ? 2 : 1) * lds_fft_points(nx));   // [2 rows][first, last][nw]
-  constexpr int kMaxWaves = row_threads_max<T, E>() / 64;
+  constexpr int kMaxWaves = (STREAM ? 1024 : row_threads_max<T, E>()) / 64;
   __shared__ double wsum[2 * kMaxWaves];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const bool want_rd = rd_needed(ctrl);
   double rp, rd;
-  primal_res_pair<T, E, S>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf, twl,
-                           edge, rp, rd, alt, wsum, want_rd, &lam);
+  primal_res_pair<T, E, S, STREAM>(C, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, 2 * blk, tid, W, tid, W, buf,
+                                   twl, edge, rp, rd, alt, wsum, want_rd, &lam);
   if (tid == 0) {
     const int nw = W >> 6;
     double srp = 0.0, srd = 0.0;
@@ -305,11 +326,12 @@ template <typename T, int EPT, typename S>
 static hipError_t launch_dual_fft_e(const S* spec, int nt, int lqb, int nx, const void* tw, T* phi, T* phibar, T tau,
                                     const Ctrl* ctrl, hipStream_t st, const T* s0) {
   const int W = nx / EPT;
-  const size_t lds = sizeof(C2<S>) * (fft_pingpong<S>(nx) ? 3 : 2) * (size_t)lds_fft_points(nx);
+  const int pp = fft_pingpong<S>(nx) && !rows_for_occupancy(nt);
+  const size_t lds = sizeof(C2<S>) * (pp ? 3 : 2) * (size_t)lds_fft_points(nx);
   hipError_t e = allow_lds(k_dual_fft<T, EPT, S>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dual_fft<T, EPT, S>), dim3((nt + 1) / 2), dim3(W), lds, st, spec, nt, lqb, nx,
-                     (const C2<S>*)tw, phi, phibar, tau, ctrl, s0);
+                     (const C2<S>*)tw, phi, phibar, tau, ctrl, s0, pp);
   return hipGetLastError();
 }
 
@@ -328,28 +350,41 @@ hipError_t launch_dual_fft(const S* spec, int nt, int lqb, int nx, const void* t
   }
 }
 
-template <typename T, int E, typename S>
+template <typename T, int E, typename S, bool STREAM = false>
 static hipError_t launch_primal_res_e(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi,
                                       T tau_u, S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl,
                                       hipStream_t st, const LamArgs<T>& lam) {
   const int W = s.nx / E;
-  const size_t lds = sizeof(C2<S>) * (fft_pingpong<S>(s.nx) ? 3 : 2) * (size_t)lds_fft_points(s.nx) +
-                     sizeof(T) * 4 * (W / 64);
-  hipError_t e = allow_lds(k_primal_res<T, E, S>, lds);
+  const bool pp = !STREAM && fft_pingpong<S>(s.nx);
+  const size_t lds = sizeof(C2<S>) * (pp ? 3 : 2) * (size_t)lds_fft_points(s.nx) + sizeof(T) * 4 * (W / 64);
+  hipError_t e = allow_lds(k_primal_res<T, E, S, STREAM>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_primal_res<T, E, S>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out, phibar, phi,
-                     tau_u, spec, lqb, (const C2<S>*)tw, part, ctrl, lam);
+  hipLaunchKernelGGL((k_primal_res<T, E, S, STREAM>), dim3((s.nt + 1) / 2), dim3(W), lds, st, s, u_in, u_out,
+                     phibar, phi, tau_u, spec, lqb, (const C2<S>*)tw, part, ctrl, lam);
   return hipGetLastError();
 }
 
 // B: E = 4 points per thread in FP32 (W = nx / 4 <= 1024 threads); in FP64
 // E = 2 up to nx = 2048 (W = nx / 2 <= 1024), E = 8 at nx = 4096 (W = 512);
-// W >= 64 (nx >= 64).
+// W >= 64 (nx >= 64).  Grids of two or more blocks per CU (rows_for_occupancy)
+// take the streaming body with E = 8 in FP32 (W = nx / 8) and E = 4 in FP64
+// (W = nx / 4), from nx = 512 and 256 on; FP64 at nx = 4096 always streams
+// (W = 1024): its load-first body would spill.
 template <typename T, typename S>
 hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* phibar, const T* phi, T tau_u,
                              S* spec, int lqb, const void* tw, double* part, const Ctrl* ctrl, hipStream_t st,
                              const LamArgs<T>* lam) {
   const LamArgs<T> la = lam ? *lam : LamArgs<T>{nullptr, nullptr, nullptr, T(0), T(0)};
+  const bool occ = rows_for_occupancy(s.nt);
+  if constexpr (sizeof(T) == 4) {
+    if (occ && s.nx >= 512)
+      return launch_primal_res_e<T, 8, S, true>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st,
+                                                la);
+  } else {
+    if ((occ && s.nx >= 256) || s.nx == 4096)
+      return launch_primal_res_e<T, 4, S, true>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st,
+                                                la);
+  }
   int W;
   if (sizeof(T) == 4) W = clampi(s.nx / 4, 64, 1024);
   else W = s.nx <= 2048 ? clampi(s.nx / 2, 64, 1024) : 512;
@@ -357,7 +392,6 @@ hipError_t launch_primal_res(const Scheme& s, const T* u_in, T* u_out, const T* 
     case 1: return launch_primal_res_e<T, 1, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
     case 2: return launch_primal_res_e<T, 2, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
     case 4: return launch_primal_res_e<T, 4, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
-    case 8: return launch_primal_res_e<T, 8, S>(s, u_in, u_out, phibar, phi, tau_u, spec, lqb, tw, part, ctrl, st, la);
     default: return hipErrorInvalidValue;
   }
 }

@@ -144,14 +144,19 @@ __device__ __forceinline__ void dual_op_regs(const Consts<T>& C, int m, const T*
 }
 
 // E = nx / W points per thread; wave v of the sub-group owns x in
-// [v 64E, (v+1) 64E), lane l element e at x = v 64E + l + 64 e.  Every global
-// row the pair needs is loaded up front: u^{n-1} on levels a-1..a+2, phibar on
-// rows a-2..a+3, phi on rows a..a+3.  Returns this thread's contributions to
+// [v 64E, (v+1) 64E), lane l element e at x = v 64E + l + 64 e.  The pair
+// reads u^{n-1} on levels a-1..a+2, phibar on rows a-2..a+3 and phi on rows
+// a..a+3.  STREAM = false: every row is loaded up front, so that all load
+// latencies overlap (a block that has its CU to itself).  STREAM = true: the
+// levels are stepped in order and each step loads the rows of the next one,
+// so that only a sliding window of rows is held in registers (fewer VGPRs, so
+// that several blocks share a CU and hide each other's latencies).  The
+// arithmetic is the same either way.  Returns this thread's contributions to
 // ||A(u^n)||^2 (rows a, a+1) and ||J(u^{n-1})^T phi^{n-1}||^2 (levels a+1, a+2).
 // edge: 4 (W / 64) values of LDS for this sub-group.  alt (optional): a second
 // N-point LDS array for the FFT.  wsum (optional, 2 W / 64 doubles of LDS): the
 // per-wave sums of the two contributions, stored before the FFT.
-template <typename T, int E, typename S = T>
+template <typename T, int E, typename S = T, bool STREAM = false>
 __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __restrict__ u_in,
                                                 T* __restrict__ u_out, const T* __restrict__ phibar,
                                                 const T* __restrict__ phi, T tau_u, S* __restrict__ spec, int lqb,
@@ -175,26 +180,36 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
   T U0[4][E], U[4][E];                 // u^{n-1} and u^n on levels a-1+i
   T PB[6][E], PBp[4], PBn[4];          // phibar rows a-2+j (edges for j = 0..3)
   T PH[4][E], PHp[2], PHn[2];          // phi rows a+j (edges for j = 0, 1)
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  auto load_u0 = [&](int i) __attribute__((always_inline)) {
     const int m = a - 1 + i;
     const bool ok = m >= 0 && m <= nt && (bdf2 || i > 0);
 #pragma unroll
     for (int e = 0; e < E; ++e) U0[i][e] = ok ? u_in[(size_t)m * nx + seg0 + lane + 64 * e] : T(0);
-  }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  };
+  auto load_pb = [&](int j) __attribute__((always_inline)) {
     T pv, nv;
     load_row_wave<T, E>(phibar, a - 2 + j, nt, nx, seg0, lane, PB[j], pv, nv);
     if (j < 4) { PBp[j] = pv; PBn[j] = nv; }
-  }
-  if (want_rd) {   // phi is read only for the dual residual
+  };
+  auto load_ph = [&](int j) __attribute__((always_inline)) {
+    T pv, nv;
+    load_row_wave<T, E>(phi, a + j, nt, nx, seg0, lane, PH[j], pv, nv);
+    if (j < 2) { PHp[j] = pv; PHn[j] = nv; }
+  };
+  if constexpr (!STREAM) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      T pv, nv;
-      load_row_wave<T, E>(phi, a + j, nt, nx, seg0, lane, PH[j], pv, nv);
-      if (j < 2) { PHp[j] = pv; PHn[j] = nv; }
+    for (int i = 0; i < 4; ++i) load_u0(i);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) load_pb(j);
+    if (want_rd) {   // phi is read only for the dual residual
+#pragma unroll
+      for (int j = 0; j < 4; ++j) load_ph(j);
     }
+  } else {
+    load_u0(0);
+    load_pb(0);
+    load_pb(1);
+    load_pb(2);
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -206,6 +221,10 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int m = a - 1 + i;
+    if constexpr (STREAM) {   // the rows of the next level
+      if (i + 3 <= 5) load_pb(i + 3);
+      if (i + 1 <= 3) load_u0(i + 1);
+    }
     if (m < 0 || m > nt || (!bdf2 && i == 0)) continue;
     if (m == 0) {
       if (lam && lam->u0) {   // multiplier form: u^0 and lambda step (this pair holds rows 0 and 1)
@@ -234,7 +253,27 @@ __device__ __forceinline__ void primal_res_pair(const Consts<T>& C, const T* __r
       T* uw = u_out + (size_t)m * nx + seg0 + lane;
 #pragma unroll
       for (int e = 0; e < E; ++e) uw[64 * e] = U[i][e];
-      if (want_rd) {
+      if (!STREAM && want_rd) {
+        dual_op_regs<T, E>(C, m, PH[i - 2], PHp[i - 2], PHn[i - 2], PH[i - 1], PH[i], U0[i], g);
+#pragma unroll
+        for (int e = 0; e < E; ++e) rd += (double)g[e] * (double)g[e];
+      }
+    }
+  }
+  if constexpr (STREAM) {
+    // the dual residual of the owned levels, from reloaded inputs (u^{n-1} is
+    // still intact in u_in); it is needed only near convergence, and holding
+    // its four phi rows through the primal step would widen the window
+    if (want_rd) {
+      load_u0(2);
+      load_u0(3);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) load_ph(j);
+#pragma unroll
+      for (int i = 2; i < 4; ++i) {
+        const int m = a - 1 + i;
+        if (m < 1 || m > nt) continue;
+        T g[E];
         dual_op_regs<T, E>(C, m, PH[i - 2], PHp[i - 2], PHn[i - 2], PH[i - 1], PH[i], U0[i], g);
 #pragma unroll
         for (int e = 0; e < E; ++e) rd += (double)g[e] * (double)g[e];
