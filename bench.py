@@ -70,8 +70,8 @@ COUNTER_SOURCES = ("paper_2207_07234_amd/csrc/pdhg_fused.hip", "paper_2207_07234
                    "paper_2207_07234_amd/csrc/pdhg_device.hpp")
 COUNTERS = {
     # (dtype, variant, kernel id): per-dispatch KiB of the kernel and of the copy kernel
-    ("f64", 2, 0): {"fetch_kib": 8774.0, "write_kib": 16388.0, "copy_fetch_kib": 4102.5, "copy_write_kib": 8192.0,
-                    "sha": "40e68dcb7efb27f2a7531a8c41df0ce47d08cce64b44720c0a9ac04fb6f3390b"},
+    ("f64", 2, 0): {"fetch_kib": 8779.5, "write_kib": 16388.0, "copy_fetch_kib": 4105.5, "copy_write_kib": 8192.0,
+                    "sha": "9f9fb0b05e5fd811b6d59f32bb7ab9343abd4d5b1d06cff8d4a78143ad4265d1"},
 }
 
 KERNELS_UNFUSED = {
@@ -356,6 +356,11 @@ def advection_cfl4(pk):
             "variant": r.stats["variant"], "u_T_max": float(np.max(np.abs(r.u[-1].cpu().numpy())))}
 
 
+# single problems too large for the MALL: (N_x, N_t, dtype)
+LARGE_SIZES = ((2048, 2048, "f64"), (4096, 2048, "f64"), (4096, 2048, "f32"), (2048, 8192, "f64"),
+               (4096, 8192, "f32"))
+
+
 def large_single_sweep(pk):
     """Per-kernel device time of the fused passes on single problems large enough to fill the GPU many
     times over (N_t = 2048: 1024 row-pair blocks, four per CU; N_t = 8192, the column solve's limit, with
@@ -364,8 +369,8 @@ def large_single_sweep(pk):
     import torch
     import synthetic as syn
     out = []
-    for nx, nt, dt in ((2048, 2048, torch.float64), (4096, 2048, torch.float64), (4096, 2048, torch.float32),
-                       (2048, 8192, torch.float64), (4096, 8192, torch.float32)):
+    for nx, nt, dts in LARGE_SIZES:
+        dt = torch.float64 if dts == "f64" else torch.float32
         esz = 8 if dt == torch.float64 else 4
         prob = pk.Problem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf", dtype=dt)
         s = pk.Solver(prob)
@@ -386,6 +391,55 @@ def large_single_sweep(pk):
         del s, u0
         torch.cuda.empty_cache()
     return out
+
+
+def run_kernels(args):
+    """Profiling driver: the fused passes only, event-timed (--kernel-reps launches each) on the single
+    problems of the large sweep, and the three batched passes on the 256-problem batch (FP32, every
+    problem running).  Each configuration is set up by a 2-iteration solve and also times the plain copy
+    kernel of its size, whose counter readings calibrate the HBM counters of a profiler run."""
+    import torch
+
+    import paper_2207_07234_amd as pk
+    import synthetic as syn
+    torch.cuda.set_device(torch.device("cuda", 0))
+    reps = args.kernel_reps
+    out = {"single": [], "batch": None}
+    for nx, nt, dt in LARGE_SIZES:
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        esz = 8 if dt == "f64" else 4
+        prob = pk.Problem(nx=nx, nt=nt, t_final=T_FINAL, alpha=0.5, beta=0.0, time="bdf2", space="fd_lf", dtype=tdt)
+        s = pk.Solver(prob)
+        s.solve(torch.tensor(syn.fourier_u0(SEED, nx), dtype=tdt, device="cuda"), tau_u=0.5, tau_phi=0.5, eps=0.0,
+                max_iter=2, check_every=2)
+        rec = {"nx": nx, "nt": nt, "dtype": dt, "kernels": {}}
+        for kid, (name, words) in KERNELS_FUSED.items():
+            ms = s.time_kernel(kid, reps=reps)
+            gbs = words * esz * nx * nt / (ms * 1e-3) / 1e9
+            rec["kernels"][name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            log(f"{nx}x{nt} {dt}: {name}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f})")
+        ms = s.time_kernel(COPY_KERNEL, reps=reps)
+        rec["copy_us"] = ms * 1e3
+        out["single"].append(rec)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    probs, u0s = batch_problems(pk, torch.float32)
+    bs = pk.BatchSolver(probs)
+    u0 = bs.pack_u0(u0s)
+    taus = [0.5] * len(probs)   # fixed steps: no power iterations (the pass timings do not depend on them)
+    grids = bs.tune(u0, tau_u=taus, tau_phi=taus)
+    bs.solve(u0, tau_u=taus, tau_phi=taus, eps=0.0, max_iter=2, check_every=2)
+    dof = sum(p.nx * p.nt for p in probs)
+    rec = {"problems": len(probs), "dof": dof, "grids": grids, "kernels": {}}
+    for kid, (name, words) in BATCH_WORDS.items():
+        ms = bs.time_kernel(kid, reps=reps)
+        gbs = words * 4 * dof / (ms * 1e-3) / 1e9
+        rec["kernels"][name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        log(f"batch f32 ({len(probs)} problems, {dof} DOF): {name}: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s "
+            f"({gbs / HBM_PEAK_GBS:.2f})")
+    out["batch"] = rec
+    print(json.dumps(out), flush=True)
 
 
 def traffic_table3(pk):
@@ -1056,7 +1110,10 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None,
                     help="compute type (default f64 for the single workload, f32 for the batch)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto (fused), 1 unfused, 2 fused")
-    ap.add_argument("--workload", choices=["burgers", "batch", "dg", "adjoint"], default="burgers")
+    ap.add_argument("--workload", choices=["burgers", "batch", "dg", "adjoint", "kernels"], default="burgers",
+                    help="kernels: event-time the passes of the large single problems and of the 256-problem "
+                         "batch only (profiler driver)")
+    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--dg-iters", type=int, default=DG_ITERS)
     ap.add_argument("--dg-cpu-iters", type=int, default=2)
     ap.add_argument("--dg-eps", type=float, default=0.0,
@@ -1069,6 +1126,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is design-only",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "kernels":
+        run_kernels(args)
+        return
     if args.workload == "batch":
         run_batch(args)
         return
