@@ -10,24 +10,40 @@ with dA/du0 nonzero only in row 0 (-1/h_t I, backward Euler start) and, for
 BDF2, row 1 (+1/(2 h_t) I).  The solve J^T mu = g is the discrete dual
 (backward-in-time) equation of Section 3.1 with a source term; here it is a
 plain sparse direct solve, not a march.
+
+For the DG schemes (Section 3.2: the P2 Legendre scheme with the local
+Lax-Friedrichs flux, and the paper's P1 nodal upwind scheme) the unknowns of a
+level are the cell coefficients (or nodal values), arrays (p, N_x), and J is
+their exact Jacobian; the time coefficients act per coefficient, so the same
+formula gives dl/du0 with respect to the initial coefficients.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from . import fd
+from . import dg, dg1, fd
 from .problem import Problem, time_coeffs
 
 
+def _jacobian(prob: Problem, u: np.ndarray):
+    if prob.space == "dg_p2_llf":
+        return dg.p2_jacobian(prob, u)
+    if prob.space == "dg_p1_upwind":
+        return dg1.p1_jacobian(prob, u)
+    return fd.jacobian(prob, u)
+
+
 def adjoint_solve(prob: Problem, u: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """mu with J(u)^T mu = g[1:] (rows l = 0..N_t-1); g has shape (N_t+1, N_x)."""
-    J = fd.jacobian(prob, u).T.tocsc()
-    return spla.spsolve(J, np.asarray(g[1:], dtype=np.float64).ravel()).reshape(prob.nt, prob.nx)
+    """mu with J(u)^T mu = g[1:] (rows l = 0..N_t-1); g has the shape of u, (N_t+1, N_x) or
+    (N_t+1, p, N_x) for DG."""
+    J = _jacobian(prob, u).T.tocsc()
+    shape = (prob.nt,) + tuple(np.shape(u)[1:])
+    return spla.spsolve(J, np.asarray(g[1:], dtype=np.float64).ravel()).reshape(shape)
 
 
 def gradient_u0(prob: Problem, u: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """dl/du0 given g = dl/du for every level (shape (N_t+1, N_x))."""
+    """dl/du0 given g = dl/du for every level (the shape of u)."""
     mu = adjoint_solve(prob, u, g)
     grad = np.array(g[0], dtype=np.float64)
     for row in (0, 1):
