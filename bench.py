@@ -835,13 +835,24 @@ def dg_summary(pk, checks):
             kern[name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
         dom = max(kern, key=lambda k: kern[k]["us_per_launch"])
         checks["dg_" + key] = r.u.double().cpu().numpy()
+        # the implicit adjoint at this solution (terminal loss |u^{N_t}|^2 h_x): one block-tridiagonal
+        # cyclic reduction per level, in one workgroup
+        g = torch.zeros_like(r.u)
+        g[-1] = 2.0 * (1.0 / DG_NX) * r.u[-1]
+        s.adjoint_solve(r.u, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.adjoint_solve(r.u, g)
+        torch.cuda.synchronize()
+        adj_ms = (time.perf_counter() - t0) * 1e3
         out[key] = {"status": r.status, "iterations": n, "seconds": wall, "dof_iterations_per_s": dof * n / wall,
                     "us_per_iteration": wall / n * 1e6, "res_primal": r.stats["res_primal"],
                     "res_dual": r.stats["res_dual"], "tau": tau, "kernels": kern, "dominant": dom,
-                    "dominant_frac": kern[dom]["frac"], "fp64_error": None,
+                    "dominant_frac": kern[dom]["frac"], "fp64_error": None, "adjoint_ms": adj_ms,
                     "stop": "residual 1e-8" if esz == 8 else "500 iterations without a new best ||A(u)||"}
         log(f"DG P2 {key}: status {r.status}, {n} iterations, {wall:.3f} s, {dof * n / wall:.3e} DOF-it/s; "
-            f"dominant {dom} {kern[dom]['us_per_launch']:.1f} us ({kern[dom]['frac']:.2f} of peak)")
+            f"dominant {dom} {kern[dom]['us_per_launch']:.1f} us ({kern[dom]['frac']:.2f} of peak); "
+            f"adjoint march {adj_ms:.1f} ms")
         s.close()
         del s
         torch.cuda.empty_cache()

@@ -295,13 +295,19 @@ int pdhg_precond(pdhg_handle* h, const void* r, void* s, pdhg_stream_t stream);
 
 /* Dual-equation operator and the implicit adjoint (Section 3.1).
  *  mode PDHG_ADJ_APPLY: out[nt][nx] = J(u)^T in, in = phi [nt][nx].
- *  mode PDHG_ADJ_SOLVE (finite differences; PDHG_EUNSUPPORTED for DG):
+ *  mode PDHG_ADJ_SOLVE:
  *     in = dL/du [nt+1][nx] (all levels, level 0 included);
- *     solves J(u)^T mu = dL/du[1:] by a backward march in time (one periodic
- *     tridiagonal solve per level) and writes out[nx] = dL/du0 =
- *     dL/du^0 - (dA/du0)^T mu.  mu [nt][nx] receives the multiplier if non-NULL.
- *     u must be the converged implicit solution for this to be the gradient of
- *     the solution map.  workspace as for pdhg_solve (NULL allowed). */
+ *     solves J(u)^T mu = dL/du[1:] by a backward march in time and writes
+ *     out[nx] = dL/du0 = dL/du^0 - (dA/du0)^T mu.  mu [nt][nx] receives the
+ *     multiplier if non-NULL.  Finite differences: one periodic tridiagonal
+ *     solve per level (cyclic reduction in one workgroup).  DG (P2 and P1; every
+ *     [nx] above is [planes][nx], and the gradient is with respect to the
+ *     initial coefficients or nodal values): one periodic block-tridiagonal
+ *     solve per level (3x3 or 2x2 blocks of the exact Jacobian, block cyclic
+ *     reduction in one workgroup over a block-row array in the workspace).
+ *     Arithmetic in double for both storage types.  u must be the converged
+ *     implicit solution for this to be the gradient of the solution map.
+ *     workspace as for pdhg_solve (NULL allowed). */
 typedef enum { PDHG_ADJ_APPLY = 0, PDHG_ADJ_SOLVE = 1 } pdhg_adjoint_mode;
 int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, void* out,
                  void* mu, void* workspace, pdhg_stream_t stream);

@@ -274,11 +274,11 @@ class Solver:
 
     def adjoint_solve(self, u, g, want_mu: bool = False):
         """dL/du0 from dL/du (all levels) through the implicit scheme at its solution u."""
-        nx, nt = self.prob.nx, self.prob.nt
-        self._check(u, (nt + 1, nx), "u")
-        self._check(g, (nt + 1, nx), "g")
-        out = self._empty(nx)
-        mu = self._empty(nt, nx) if want_mu else None
+        nt, lv = self.prob.nt, self.prob.level_shape
+        self._check(u, (nt + 1,) + lv, "u")
+        self._check(g, (nt + 1,) + lv, "g")
+        out = self._empty(*lv)
+        mu = self._empty(nt, *lv) if want_mu else None
         rc = self.lib.pdhg_adjoint(self._h, B.PDHG_ADJ_SOLVE, _ptr(u), _ptr(g), _ptr(out), _ptr(mu), None,
                                    _stream_ptr(self.device))
         if rc != B.PDHG_OK:

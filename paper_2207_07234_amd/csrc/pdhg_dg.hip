@@ -26,6 +26,7 @@
 // rotates back by V.
 #include "pdhg_internal.hpp"
 #include "pdhg_passes.hpp"
+#include "pdhg_dg1.hpp"
 
 namespace pdhg {
 
@@ -612,6 +613,340 @@ hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int 
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------ implicit adjoint (DG)
+// The backward march of the dual equation with a source term (Section 3.1), as
+// for finite differences: for m = N_t .. 1,
+//   (c0(m-1)/h_t I + dF(u^m)^T) mu^{m-1} = g^m - c1(m)/h_t mu^m - c2(m+1)/h_t mu^{m+1},
+// then dl/du0 = g^0 - c1(0)/h_t mu^0 - c2(1)/h_t mu^1, per coefficient.  Per
+// level the system is periodic block tridiagonal over the cells, NP x NP
+// blocks: row j reads  A_j mu_{j-1} + B_j mu_j + C_j mu_{j+1} = d_j  with
+//   A_j = U_{j-1}^T, B_j = (c0/h_t I + D_j)^T, C_j = L_{j+1}^T,
+// D_j, L_j, U_j the blocks of dF coupling cell j to cells j, j-1, j+1.
+//   P2 (LLF; s_k = -(2k+1)/h_x, P_m at the Gauss nodes):
+//     D_j[k][m] = s_k (Vol_km - da_{j+1/2} + (-1)^{k+m} db_{j-1/2}),
+//     Vol_1m = sum_q w_q f'(u_q) P_m(xi_q), Vol_2m = sum_q w_q f'(u_q) 3 xi_q P_m(xi_q), Vol_0m = 0,
+//     U_j[k][m] = -s_k db_{j+1/2} (-1)^m,  L_j[k][m] = s_k (-1)^k da_{j-1/2};
+//   P1 (nodal upwind, trace t(v) = -v_1/2 + 3 v_2/2, M^{-1} = [7 1; 1 7] / (4 h_x)):
+//     D_j = -M^{-1} [dr1/dv; dr2/dv], dr1/dv_m = -S_m + da_j t_m / 2, dr2/dv_m = S_m - 3 da_j t_m / 2,
+//     L_j = -M^{-1} [3 da_{j-1} t / 2; -da_{j-1} t / 2], U_j = 0,
+//   with the generalised LLF derivatives of the residual kernels (a's branch on ties).
+// The system is solved by block cyclic reduction, in place: at stride s the
+// rows i = -1 mod 2s eliminate their neighbours i -+ s (rows = s - 1 mod 2s,
+// which keep their coefficients for the back substitution); the last row is
+// coupled to itself only (periodic), (A + B + C) x = d; then back substitution
+// from stride N_x/2 down to 1.  One workgroup; the block rows live in a
+// workspace array (L2-resident: 240 bytes per cell for P2), the multipliers of
+// three consecutive levels in another.  Arithmetic in double for both storage
+// types, as for finite differences.
+constexpr int kDgAdjThreads = 512;
+
+template <int NP>
+struct AdjRow {
+  static constexpr int kA = 0, kB = NP * NP, kC = 2 * NP * NP, kD = 3 * NP * NP, kLen = 3 * NP * NP + NP;
+};
+
+template <int NP>
+__device__ __forceinline__ void mat_inv(const double* M, double* R) {
+  if (NP == 2) {
+    const double id = 1.0 / (M[0] * M[3] - M[1] * M[2]);
+    R[0] = M[3] * id;
+    R[1] = -M[1] * id;
+    R[2] = -M[2] * id;
+    R[3] = M[0] * id;
+  } else {
+    const double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[5] * M[6] - M[3] * M[8], c02 = M[3] * M[7] - M[4] * M[6];
+    const double id = 1.0 / (M[0] * c00 + M[1] * c01 + M[2] * c02);
+    R[0] = c00 * id;
+    R[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+    R[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+    R[3] = c01 * id;
+    R[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+    R[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+    R[6] = c02 * id;
+    R[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+    R[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+  }
+}
+
+// R = X Y (NP x NP, row-major)
+template <int NP>
+__device__ __forceinline__ void mat_mul(const double* X, const double* Y, double* R) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) a += X[i * NP + k] * Y[k * NP + j];
+      R[i * NP + j] = a;
+    }
+}
+
+// Block row j of level m (transposed system) from u^m and the right-hand side.
+template <typename T, int NP>
+__device__ __forceinline__ void adj_build_row(const Consts<double>& C, const T* __restrict__ um, int nx, int j,
+                                              double d0, const double* rhs, double* row) {
+  typedef AdjRow<NP> R;
+  double Dm[NP * NP], Lm[NP * NP], Um[NP * NP];   // D_j, L_{j+1}, U_{j-1} as blocks of dF
+  const double h1 = C.inv_hx;
+  if constexpr (NP == 3) {
+    double v[3], vl[3], vr[3];
+    const int jl = (j - 1 + nx) & (nx - 1), jr = (j + 1) & (nx - 1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[k] = (double)um[k * nx + j];
+      vl[k] = (double)um[k * nx + jl];
+      vr[k] = (double)um[k * nx + jr];
+    }
+    const double a = v[0] + v[1] + v[2], b = v[0] - v[1] + v[2];
+    const double a_left = vl[0] + vl[1] + vl[2], b_right = vr[0] - vr[1] + vr[2];
+    double da_r, db_r, da_l, db_l;
+    llf_partials(C, a, b_right, da_r, db_r);   // interface j+1/2
+    llf_partials(C, a_left, b, da_l, db_l);    // interface j-1/2
+    double vol1[3] = {0.0, 0.0, 0.0}, vol2[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double x = DgCell<double>::xq(q), p2 = DgCell<double>::p2q(q);
+      const double wf = DgCell<double>::wq(q) * C.dflux(v[0] + v[1] * x + v[2] * p2);
+      const double P[3] = {1.0, x, p2};
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        vol1[m] += wf * P[m];
+        vol2[m] += wf * 3.0 * x * P[m];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double sk = -(2.0 * k + 1.0) * h1, pk = (k & 1) ? -1.0 : 1.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double pm = (m & 1) ? -1.0 : 1.0;
+        const double vol = k == 0 ? 0.0 : (k == 1 ? vol1[m] : vol2[m]);
+        Dm[k * 3 + m] = sk * (vol - da_r + pk * pm * db_l);
+        Um[k * 3 + m] = -sk * db_l * pm;   // U_{j-1}: db at interface j-1/2
+        Lm[k * 3 + m] = sk * pk * da_r;    // L_{j+1}: da at interface j+1/2
+      }
+    }
+  } else {
+    double v[2];
+    v[0] = (double)um[j];
+    v[1] = (double)um[nx + j];
+    const double g1 = P1Cell<double>::g1(), g2 = P1Cell<double>::g2();
+    const double d0q = C.dflux(g1 * v[0] + g2 * v[1]), d1q = C.dflux(g2 * v[0] + g1 * v[1]);
+    const double da = C.dflux(P1Cell<double>::trace(v));
+    const double S[2] = {d0q * g1 + d1q * g2, d0q * g2 + d1q * g1};
+    const double t[2] = {-0.5, 1.5};
+    const double q4 = 0.25 * h1;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double r1 = -S[m] + 0.5 * da * t[m], r2 = S[m] - 1.5 * da * t[m];
+      Dm[m] = -q4 * (7.0 * r1 + r2);
+      Dm[2 + m] = -q4 * (r1 + 7.0 * r2);
+      // L_{j+1} couples cell j+1 to cell j through cell j's trace
+      const double l1 = 1.5 * da * t[m], l2 = -0.5 * da * t[m];
+      Lm[m] = -q4 * (7.0 * l1 + l2);
+      Lm[2 + m] = -q4 * (l1 + 7.0 * l2);
+      Um[m] = 0.0;
+      Um[2 + m] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      // transposed blocks: row m, column k
+      row[R::kA + m * NP + k] = Um[k * NP + m];
+      row[R::kB + m * NP + k] = Dm[k * NP + m] + (k == m ? d0 : 0.0);
+      row[R::kC + m * NP + k] = Lm[k * NP + m];
+    }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) row[R::kD + k] = rhs[k];
+}
+
+template <typename T, int NP>
+__global__ void __launch_bounds__(kDgAdjThreads)
+k_dg_adjoint_march(Scheme s, const T* __restrict__ u, const T* __restrict__ g, T* __restrict__ mu_out,
+                   T* __restrict__ grad, double* __restrict__ rows, double* __restrict__ ring) {
+  typedef AdjRow<NP> R;
+  const Consts<double> C(s);
+  const int nx = s.nx, nt = s.nt, tid = threadIdx.x;
+  const size_t lev = (size_t)NP * nx;
+  // ring slot of level l: (l mod 3); mu^{nt} and mu^{nt+1} are zero
+  for (int i = tid; i < NP * nx; i += kDgAdjThreads) {
+    ring[((size_t)(nt % 3)) * lev + i] = 0.0;
+    ring[((size_t)((nt + 1) % 3)) * lev + i] = 0.0;
+  }
+  __syncthreads();
+  for (int m = nt; m >= 1; --m) {
+    const T* um = u + (size_t)m * lev;
+    const T* gm = g + (size_t)m * lev;
+    const double* mu1 = ring + (size_t)(m % 3) * lev;
+    const double* mu2 = ring + (size_t)((m + 1) % 3) * lev;
+    double* x = ring + (size_t)((m - 1) % 3) * lev;
+    const double d0 = C.c0(m - 1) * C.inv_ht, k1 = C.c1(m) * C.inv_ht, k2 = C.c2(m + 1) * C.inv_ht;
+    for (int j = tid; j < nx; j += kDgAdjThreads) {
+      double rhs[NP], row[R::kLen];
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+        rhs[k] = (double)gm[k * nx + j] - k1 * mu1[k * nx + j] - k2 * mu2[k * nx + j];
+      adj_build_row<T, NP>(C, um, nx, j, d0, rhs, row);
+      double* dst = rows + (size_t)j * R::kLen;
+#pragma unroll
+      for (int e = 0; e < R::kLen; ++e) dst[e] = row[e];
+    }
+    __syncthreads();
+    // forward reduction
+    for (int st = 1; st < nx; st <<= 1) {
+      const int n_act = nx / (2 * st);
+      for (int q = tid; q < n_act; q += kDgAdjThreads) {
+        const int i = 2 * st * q + 2 * st - 1;
+        const int il = (i - st) & (nx - 1), ir = (i + st) & (nx - 1);
+        double* ri = rows + (size_t)i * R::kLen;
+        const double* rl = rows + (size_t)il * R::kLen;
+        const double* rr = rows + (size_t)ir * R::kLen;
+        double Ai[NP * NP], Bi[NP * NP], Ci[NP * NP], Di[NP], inv[NP * NP], al[NP * NP], be[NP * NP], t[NP * NP];
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) {
+          Ai[e] = ri[R::kA + e];
+          Bi[e] = ri[R::kB + e];
+          Ci[e] = ri[R::kC + e];
+        }
+#pragma unroll
+        for (int e = 0; e < NP; ++e) Di[e] = ri[R::kD + e];
+        // alpha = -A_i B_il^{-1}, beta = -C_i B_ir^{-1}
+        double Bl[NP * NP], Br[NP * NP];
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) {
+          Bl[e] = rl[R::kB + e];
+          Br[e] = rr[R::kB + e];
+        }
+        mat_inv<NP>(Bl, inv);
+        mat_mul<NP>(Ai, inv, al);
+        mat_inv<NP>(Br, inv);
+        mat_mul<NP>(Ci, inv, be);
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) {
+          al[e] = -al[e];
+          be[e] = -be[e];
+        }
+        double X[NP * NP];
+        // B_i += alpha C_il + beta A_ir
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) X[e] = rl[R::kC + e];
+        mat_mul<NP>(al, X, t);
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) Bi[e] += t[e];
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) X[e] = rr[R::kA + e];
+        mat_mul<NP>(be, X, t);
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) Bi[e] += t[e];
+        // A_i = alpha A_il, C_i = beta C_ir
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) X[e] = rl[R::kA + e];
+        mat_mul<NP>(al, X, Ai);
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) X[e] = rr[R::kC + e];
+        mat_mul<NP>(be, X, Ci);
+        // d_i += alpha d_il + beta d_ir
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          double acc = Di[a];
+#pragma unroll
+          for (int k = 0; k < NP; ++k) acc += al[a * NP + k] * rl[R::kD + k] + be[a * NP + k] * rr[R::kD + k];
+          Di[a] = acc;
+        }
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) {
+          ri[R::kA + e] = Ai[e];
+          ri[R::kB + e] = Bi[e];
+          ri[R::kC + e] = Ci[e];
+        }
+#pragma unroll
+        for (int e = 0; e < NP; ++e) ri[R::kD + e] = Di[e];
+      }
+      __syncthreads();
+    }
+    // the last row couples to itself only: (A + B + C) x = d
+    if (tid == 0) {
+      const int i = nx - 1;
+      const double* ri = rows + (size_t)i * R::kLen;
+      double Mx[NP * NP], inv[NP * NP];
+#pragma unroll
+      for (int e = 0; e < NP * NP; ++e) Mx[e] = ri[R::kA + e] + ri[R::kB + e] + ri[R::kC + e];
+      mat_inv<NP>(Mx, inv);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc += inv[a * NP + k] * ri[R::kD + k];
+        x[a * nx + i] = acc;
+      }
+    }
+    __syncthreads();
+    // back substitution: rows s - 1 mod 2s from the solved rows at distance s
+    for (int st = nx >> 1; st >= 1; st >>= 1) {
+      const int n_act = nx / (2 * st);
+      for (int q = tid; q < n_act; q += kDgAdjThreads) {
+        const int i = 2 * st * q + st - 1;
+        const int il = (i - st) & (nx - 1), ir = (i + st) & (nx - 1);
+        const double* ri = rows + (size_t)i * R::kLen;
+        double r[NP], Bi[NP * NP], inv[NP * NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          double acc = ri[R::kD + a];
+#pragma unroll
+          for (int k = 0; k < NP; ++k)
+            acc -= ri[R::kA + a * NP + k] * x[k * nx + il] + ri[R::kC + a * NP + k] * x[k * nx + ir];
+          r[a] = acc;
+        }
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) Bi[e] = ri[R::kB + e];
+        mat_inv<NP>(Bi, inv);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) acc += inv[a * NP + k] * r[k];
+          x[a * nx + i] = acc;
+        }
+      }
+      __syncthreads();
+    }
+    if (mu_out) {
+      T* mo = mu_out + (size_t)(m - 1) * lev;
+      for (int i = tid; i < NP * nx; i += kDgAdjThreads) mo[i] = (T)x[i];
+    }
+    __syncthreads();
+  }
+  // dl/du0 = g^0 - c1(0)/h_t mu^0 - c2(1)/h_t mu^1
+  const double k1 = C.c1(0) * C.inv_ht, k2 = (nt >= 2) ? C.c2(1) * C.inv_ht : 0.0;
+  const double* mu0 = ring;                           // slot 0 mod 3
+  const double* mu1 = ring + (size_t)(1 % 3) * lev;   // slot 1
+  for (int i = tid; i < NP * nx; i += kDgAdjThreads)
+    grad[i] = (T)((double)g[i] - k1 * mu0[i] - (nt >= 2 ? k2 * mu1[i] : 0.0));
+}
+
+// Workspace of the DG adjoint march: block rows and three levels of multipliers (doubles).
+size_t dg_adjoint_scratch_doubles(int nx, int np) {
+  const int len = 3 * np * np + np;
+  return (size_t)nx * len + 3 * (size_t)np * nx;
+}
+
+template <typename T>
+hipError_t launch_dg_adjoint_march(const Scheme& s, const T* u, const T* g, T* mu, T* grad, double* scratch,
+                                   hipStream_t st) {
+  const int np = s.space == kSpaceDgP1 ? 2 : 3;
+  const size_t len = (size_t)(3 * np * np + np);
+  double* rows = scratch;
+  double* ring = scratch + (size_t)s.nx * len;
+  if (np == 3)
+    hipLaunchKernelGGL((k_dg_adjoint_march<T, 3>), dim3(1), dim3(kDgAdjThreads), 0, st, s, u, g, mu, grad, rows, ring);
+  else
+    hipLaunchKernelGGL((k_dg_adjoint_march<T, 2>), dim3(1), dim3(kDgAdjThreads), 0, st, s, u, g, mu, grad, rows, ring);
+  return hipGetLastError();
+}
+
 #define PDHG_DG_INSTANTIATE(T)                                                                                   \
   template hipError_t launch_dg_residual<T>(const Scheme&, const T*, T*, double*, const Ctrl*, hipStream_t, int*); \
   template hipError_t launch_dg_apply_jt<T>(const Scheme&, const T*, const T*, T*, double*, hipStream_t, int*);    \
@@ -622,7 +957,8 @@ hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int 
   template hipError_t launch_dg_residual_fft<T>(const Scheme&, const T*, T*, int, const void*, double*,           \
                                                 const Ctrl*, hipStream_t, int*);                                 \
   template hipError_t launch_dg_colsolve<T>(T*, const FacTab<T>&, const T*, int, int, int, int, const Ctrl*,      \
-                                            hipStream_t, int);
+                                            hipStream_t, int);                                                   \
+  template hipError_t launch_dg_adjoint_march<T>(const Scheme&, const T*, const T*, T*, T*, double*, hipStream_t);
 
 PDHG_DG_INSTANTIATE(float)
 PDHG_DG_INSTANTIATE(double)

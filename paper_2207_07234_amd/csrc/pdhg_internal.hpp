@@ -260,6 +260,13 @@ template <typename T>
 hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
                               const Ctrl* ctrl, hipStream_t st, int np);
 
+// Implicit adjoint march of the DG schemes (pdhg_dg.hip): P2 or P1 by s.space; scratch of
+// dg_adjoint_scratch_doubles(nx, planes) doubles of device memory.
+size_t dg_adjoint_scratch_doubles(int nx, int np);
+template <typename T>
+hipError_t launch_dg_adjoint_march(const Scheme& s, const T* u, const T* g, T* mu, T* grad, double* scratch,
+                                   hipStream_t st);
+
 // DG P1 nodal upwind space discretisation (pdhg_dg1.hip).
 template <typename T>
 hipError_t launch_dg1_residual(const Scheme& s, const T* u, T* r, double* part, const Ctrl* ctrl, hipStream_t st,

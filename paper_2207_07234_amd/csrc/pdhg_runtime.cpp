@@ -253,7 +253,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
   size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, ck_u, ck_phi, lam, lambar,
-      total;
+      adj, total;
   int max_parts;
 };
 
@@ -372,6 +372,8 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.ck_phi = o; o += field;
   L.lam = o; o += align_up(nx * esz);              // multiplier of u^0 = u0 and its extrapolation
   L.lambar = o; o += align_up(nx * esz);
+  L.adj = o;                                       // DG adjoint march: block rows and three levels of multipliers
+  if (is_dg(p)) o += align_up(sizeof(double) * dg_adjoint_scratch_doubles(p.nx, planes(p)));
   L.total = o;
   return L;
 }
@@ -1682,7 +1684,11 @@ int adjoint_impl(pdhg_handle* h, int mode, const T* u, const T* in, T* out, T* m
     return PDHG_OK;
   }
   if (mode != PDHG_ADJ_SOLVE) return PDHG_EINVAL;
-  if (dg) return PDHG_EUNSUPPORTED;   // the backward march is implemented for finite differences
+  if (dg) {
+    const WsLayout L = layout_for(h->prob, h->esz);
+    HIP_TRY(launch_dg_adjoint_march<T>(s, u, in, mu, out, (double*)wsp(ws, L.adj), st));
+    return PDHG_OK;
+  }
   HIP_TRY(launch_adjoint_march<T>(s, u, in, mu, out, st));
   return PDHG_OK;
 }
