@@ -833,7 +833,7 @@ def dg_summary(pk, checks):
             ms = s.time_kernel(kid, reps=30)
             gbs = words * esz * dof / (ms * 1e-3) / 1e9
             kern[name] = {"us_per_launch": ms * 1e3, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
-        dom = max(kern, key=lambda k: kern[k]["us_per_launch"])
+        dom = max(kern, key=lambda k: kern[k]["us_per_launch"])   # of the loop body's passes
         checks["dg_" + key] = r.u.double().cpu().numpy()
         # the implicit adjoint at this solution (terminal loss |u^{N_t}|^2 h_x): one block-tridiagonal
         # cyclic reduction per level, in one workgroup
@@ -845,6 +845,12 @@ def dg_summary(pk, checks):
         s.adjoint_solve(r.u, g)
         torch.cuda.synchronize()
         adj_ms = (time.perf_counter() - t0) * 1e3
+        if esz == 4:   # the residual with its per-cell products on the matrix cores, beside the VALU residual
+            r_valu = s.time_kernel(5, reps=30)
+            r_mfma = s.time_kernel(9, reps=30)
+            kern["residual (unfused), VALU"] = {"us_per_launch": r_valu * 1e3}
+            kern["residual (unfused), per-cell products on MFMA"] = {"us_per_launch": r_mfma * 1e3}
+            log(f"DG P2 f32 unfused residual: VALU {r_valu * 1e3:.1f} us, MFMA products {r_mfma * 1e3:.1f} us")
         out[key] = {"status": r.status, "iterations": n, "seconds": wall, "dof_iterations_per_s": dof * n / wall,
                     "us_per_iteration": wall / n * 1e6, "res_primal": r.stats["res_primal"],
                     "res_dual": r.stats["res_dual"], "tau": tau, "kernels": kern, "dominant": dom,

@@ -139,7 +139,11 @@ typedef struct {
                                <= 0: 1e6                                                 */
   int32_t variant;          /* 0 = auto (2; DG: 4), 1 = unfused reference kernels (7 per
                                iteration), 2 = fused passes (3 kernels per iteration),
-                               4 = the DG loop body (5 kernels per iteration)            */
+                               4 = the DG loop body (5 kernels per iteration),
+                               6 = the DG P2 body (FP32, nx >= 64) whose residual runs its
+                               per-cell Gauss-node and volume products on the matrix cores
+                               (v_mfma_f32_16x16x4f32), then the row FFT: a measured
+                               alternative to 4 (PDHG_EUNSUPPORTED for other problems)  */
   int32_t backoff;          /* after a divergence, restart from the last good checkpoint with
                                tau_u and tau_phi times 0.7, at most this many times (0: none) */
   double* history;          /* nullable DEVICE buffer [max_iter+2][2] of doubles: entry n holds
@@ -321,7 +325,8 @@ int pdhg_adjoint(pdhg_handle* h, int32_t mode, const void* u, const void* in, vo
  * (DG: 0 = residual of two levels + forward FFT of their six coefficient rows,
  * 1 = column solve in the per-mode eigenbasis, 4 = primal step with the
  * dual residual, 5 = residual, 6 = forward row FFT of the 3 nt coefficient
- * rows, 7 = inverse FFT + dual step, 8 = copy; others PDHG_EUNSUPPORTED)
+ * rows, 7 = inverse FFT + dual step, 8 = copy, 9 = residual with its per-cell
+ * products on the matrix cores (P2, FP32); others PDHG_EUNSUPPORTED)
  * of N_t*N_x elements (one read and one write per element; the reference point
  * for bandwidth and for scaling hardware byte counters).
  * Used for roofline measurements.  Returns PDHG_EINVAL without a previous solve. */

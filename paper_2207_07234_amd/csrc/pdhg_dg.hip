@@ -178,6 +178,119 @@ k_dg_residual(Scheme s, const T* __restrict__ u, T* __restrict__ r, double* part
   }
 }
 
+// The same residual with the per-cell products on the matrix cores (FP32,
+// v_mfma_f32_16x16x4f32; a measured alternative, loop-body variant 6).  A
+// wavefront takes 64 cells of one level, as four groups of 16.  Per group two
+// 16x16x4 products:
+//   (1) E v: rows q = 0..2 evaluate u_h at the Gauss nodes (P_m(xi_q)), row 3
+//       the right trace (1, 1, 1), row 4 the left trace (1, -1, 1); K = the
+//       three coefficients (fourth zero); N = the 16 cells of the group;
+//   (2) W f(u_q): rows k = 1, 2 hold w_q P_k'(xi_q) (P_1' = 1, P_2' = 3 xi);
+//       K = the three nodes; the volume terms V_1, V_2 of the 16 cells.
+// Operand layouts of the 16x16x4 f32 product: lane i + 16 k supplies A[i][k],
+// lane j + 16 k supplies B[k][j]; lane j + 16 g receives D[4 g + r][j] in its
+// r-th result.  The products' results are then moved (lane permutes) so that
+// lane L works on cell j0 + L: LLF fluxes, time difference, norm, one cell
+// per lane as in the VALU kernel.
+typedef float pdhg_fx4 __attribute__((ext_vector_type(4)));
+constexpr int kDgMfmaThreads = 256;
+
+__global__ void __launch_bounds__(kDgMfmaThreads)
+k_dg_residual_mfma(Scheme s, const float* __restrict__ u, float* __restrict__ r, double* part, const Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  __shared__ double red[kDgMfmaThreads / 64];
+  const Consts<float> C(s);
+  const int nx = s.nx, nt = s.nt;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, kk = lane >> 4;
+  const size_t first = ((size_t)blockIdx.x * (kDgMfmaThreads / 64) + wv) * 64;   // flattened l nx + j
+  double acc = 0.0;
+  if (first < (size_t)nt * nx) {   // uniform per wavefront: 64 | nx
+    const int l = (int)(first / nx), j0 = (int)(first % nx);
+    const size_t L3 = (size_t)3 * nx;
+    const float* up1 = u + (size_t)(l + 1) * L3;
+    float ea = 0.f, wa = 0.f;
+    if (kk < 3) {
+      if (col < 3) ea = kk == 0 ? 1.f : (kk == 1 ? DgCell<float>::xq(col) : DgCell<float>::p2q(col));
+      else if (col == 3) ea = 1.f;
+      else if (col == 4) ea = (kk & 1) ? -1.f : 1.f;
+      if (col == 1 || col == 2) wa = DgCell<float>::wq(kk) * (col == 1 ? 1.f : 3.f * DgCell<float>::xq(kk));
+    }
+    const pdhg_fx4 zero = {0.f, 0.f, 0.f, 0.f};
+    // per group g: right trace a, left trace b, V_1, V_2 of cell j0 + 16 g + col, held by lane col
+    float ag[4], bg[4], v1g[4], v2g[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float bv = kk < 3 ? up1[(size_t)kk * nx + j0 + 16 * g + col] : 0.f;
+      const pdhg_fx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(ea, bv, zero, 0, 0, 0);
+      const float f0 = C.flux(d[0]), f1 = C.flux(d[1]), f2 = C.flux(d[2]);
+      const float g0 = __shfl(f0, col), g1 = __shfl(f1, col), g2 = __shfl(f2, col);
+      const float bf = kk == 0 ? g0 : (kk == 1 ? g1 : (kk == 2 ? g2 : 0.f));
+      const pdhg_fx4 V = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, bf, zero, 0, 0, 0);
+      ag[g] = d[3];
+      bg[g] = __shfl(d[0], col + 16);   // row 4 of the first product
+      v1g[g] = V[1];
+      v2g[g] = V[2];
+    }
+    // lane L = 16 kk + col takes cell j0 + L: its values sit in group kk of lane col
+    float aj = 0.f, bj = 0.f, V1 = 0.f, V2 = 0.f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float ta = __shfl(ag[g], col), tb = __shfl(bg[g], col);
+      const float t1 = __shfl(v1g[g], col), t2 = __shfl(v2g[g], col);
+      if (kk == g) {
+        aj = ta;
+        bj = tb;
+        V1 = t1;
+        V2 = t2;
+      }
+    }
+    const int j = j0 + lane;
+    float am = __shfl(aj, (lane + 63) & 63);   // right trace of cell j - 1
+    float bp = __shfl(bj, (lane + 1) & 63);    // left trace of cell j + 1
+    if (lane == 0) {
+      float vm[3];
+      load_cell(up1, nx, (j - 1) & (nx - 1), vm);
+      am = vm[0] + vm[1] + vm[2];
+    }
+    if (lane == 63) {
+      float vp[3];
+      load_cell(up1, nx, (j + 1) & (nx - 1), vp);
+      bp = vp[0] - vp[1] + vp[2];
+    }
+    const float fr = llf(C, aj, bp), fl = llf(C, am, bj);
+    const float h1 = C.inv_hx;
+    float F[3];
+    F[0] = -h1 * (0.f - fr + fl);
+    F[1] = -3.f * h1 * (V1 - fr - fl);
+    F[2] = -5.f * h1 * (V2 - fr + fl);
+    const float c0 = C.c0(l), c1 = C.c1(l), c2 = C.c2(l);
+    const bool use2 = l >= 1 && C.time == kTimeBDF2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float t = c0 * up1[(size_t)k * nx + j] + c1 * u[(size_t)l * L3 + (size_t)k * nx + j];
+      if (use2) t += c2 * u[(size_t)(l - 1) * L3 + (size_t)k * nx + j];
+      const float val = t * C.inv_ht + F[k];
+      if (r) r[(size_t)l * L3 + (size_t)k * nx + j] = val;
+      acc += (double)val * (double)val;
+    }
+  }
+  if (part) {
+    const double sum = block_sum<kDgMfmaThreads>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
+  }
+}
+
+hipError_t launch_dg_residual_mfma(const Scheme& s, const float* u, float* r, double* part, const Ctrl* ctrl,
+                                   hipStream_t st, int* nblocks) {
+  if (s.nx < 64 || s.space != kSpaceDgP2) return hipErrorInvalidValue;
+  const size_t waves = (size_t)s.nt * s.nx / 64;
+  const unsigned g = (unsigned)((waves + kDgMfmaThreads / 64 - 1) / (kDgMfmaThreads / 64));
+  if (nblocks) *nblocks = (int)g;
+  hipLaunchKernelGGL(k_dg_residual_mfma, dim3(g), dim3(kDgMfmaThreads), 0, st, s, u, r, part, ctrl);
+  return hipGetLastError();
+}
+
 // (J(u)^T psi) at unknown level m (1..nt), cell j, all three coefficients.
 template <typename T>
 __device__ __forceinline__ void dg_jt_point(const Consts<T>& C, const T* __restrict__ u, const T* __restrict__ psi,

@@ -260,6 +260,10 @@ template <typename T>
 hipError_t launch_dg_colsolve(T* spec, const FacTab<T>& fac, const T* vtab, int bw, int nt, int nx, int lqb,
                               const Ctrl* ctrl, hipStream_t st, int np);
 
+// DG P2 residual with its per-cell products on the matrix cores (FP32; nx >= 64).
+hipError_t launch_dg_residual_mfma(const Scheme& s, const float* u, float* r, double* part, const Ctrl* ctrl,
+                                   hipStream_t st, int* nblocks);
+
 // Implicit adjoint march of the DG schemes (pdhg_dg.hip): P2 or P1 by s.space; scratch of
 // dg_adjoint_scratch_doubles(nx, planes) doubles of device memory.
 size_t dg_adjoint_scratch_doubles(int nx, int np);

@@ -988,7 +988,7 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
 // the per-mode eigenbasis, norms and stopping decision.
 template <typename T>
 int enqueue_body_dg(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T tau_phi, double* hist,
-                    hipStream_t st) {
+                    hipStream_t st, bool mfma = false) {
   const pdhg_problem& p = h->prob;
   const WsLayout L = layout_for(p, h->esz);
   const Scheme s = scheme_of(h);
@@ -1011,7 +1011,14 @@ int enqueue_body_dg(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u, T
     HIP_TRY(launch_dual<T>(phi, phibar, srow, (size_t)nr * p.nx, tau_phi, ctrl, st));
   }
   HIP_TRY(dgx_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
-  if (p2 && p.nx >= 64) {   // P2: residual of two levels + forward FFT of their six coefficient rows, fused
+  if (mfma) {   // variant 6: the residual with its per-cell products on the matrix cores, then the row FFT
+    if constexpr (sizeof(T) == 4) {
+      HIP_TRY(launch_dg_residual_mfma(s, (const float*)uout, (float*)srow, prp, ctrl, st, &nb_rp));
+    } else {
+      return PDHG_EUNSUPPORTED;
+    }
+    HIP_TRY(launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, ctrl, st));
+  } else if (p2 && p.nx >= 64) {   // P2: residual of two levels + forward FFT of their six coefficient rows, fused
     HIP_TRY(launch_dg_residual_fft<T>(s, uout, spec, h->lqb, h->d_tw, prp, ctrl, st, &nb_rp));
   } else {
     HIP_TRY(dgx_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
@@ -1031,8 +1038,8 @@ int build_graph(pdhg_handle* h, const GraphKey& key, T* u, T* phi, void* ws, T t
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = PDHG_OK;
   for (int b = 0; b < key.chunk && rc == PDHG_OK; ++b) {
-    if (key.variant == 4)
-      rc = enqueue_body_dg<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
+    if (key.variant == 4 || key.variant == 6)
+      rc = enqueue_body_dg<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream, key.variant == 6);
     else if (key.variant == 1)
       rc = enqueue_body_unfused<T>(h, (b % 2) == 0, u, phi, ws, tau_u, tau_phi, hist, h->cap_stream);
     else
@@ -1129,9 +1136,12 @@ int solve_impl(pdhg_handle* h, const T* u0, T* u, T* phi, void* ws, const pdhg_p
   if (prm->variant == 2 && p.nx < 64 && !dg) return PDHG_EUNSUPPORTED;
   // the single-precision preconditioner runs in the fused passes only
   if (is_pre32(p) && (prm->variant == 1 || p.nx < 64)) return PDHG_EUNSUPPORTED;
-  if (dg && prm->variant != 0 && prm->variant != 4) return PDHG_EUNSUPPORTED;
+  if (dg && prm->variant != 0 && prm->variant != 4 && prm->variant != 6) return PDHG_EUNSUPPORTED;
+  // variant 6: the DG P2 body with the residual's per-cell products on the matrix cores (FP32)
+  if (prm->variant == 6 && !(p.space == PDHG_DG_P2_LLF && p.dtype == PDHG_F32 && p.nx >= 64))
+    return PDHG_EUNSUPPORTED;
   if (prm->backoff < 0) return PDHG_EINVAL;
-  key.variant = dg ? 4 : ((prm->variant == 1 || p.nx < 64) ? 1 : 2);
+  key.variant = dg ? (prm->variant == 6 ? 6 : 4) : ((prm->variant == 1 || p.nx < 64) ? 1 : 2);
   key.chunk = chunk;
   if (prm->init_multiplier) {   // the multiplier form: fused finite-difference passes only, no back-off
     if (key.variant != 2 || prm->backoff > 0 || is_full(p)) return PDHG_EUNSUPPORTED;
@@ -1725,10 +1735,15 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
       case 6: return launch_rows_fwd<T>(srow, nr, spec, nr, h->lqb, p.nx, h->d_tw, nullptr, st);
       case 7: return launch_dual_fft<T>(spec, nr, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
       case 8: return launch_copy<T>(srow, phibar, n, st);
+      case 9:
+        if constexpr (sizeof(T) == 4) return launch_dg_residual_mfma(s, (const float*)u_alt, (float*)srow, prp,
+                                                                     nullptr, st, nullptr);
+        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   };
-  if (is_dg(p) && !(kernel <= 1 || (kernel >= 4 && kernel <= 8))) return PDHG_EUNSUPPORTED;
+  if (is_dg(p) && kernel == 9 && !(p.space == PDHG_DG_P2_LLF && p.dtype == PDHG_F32)) return PDHG_EUNSUPPORTED;
+  if (is_dg(p) && !(kernel <= 1 || (kernel >= 4 && kernel <= 9))) return PDHG_EUNSUPPORTED;
   if (is_dg(p) && (kernel == 7 || kernel == 0) && p.nx < 64) return PDHG_EUNSUPPORTED;
   if (p.space == PDHG_DG_P1_UPWIND && kernel == 0) return PDHG_EUNSUPPORTED;   // fused residual + FFT: P2 only
   float* spec32 = (float*)spec;
@@ -1762,7 +1777,7 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
       default: return hipErrorInvalidValue;
     }
   };
-  if (kernel < 0 || kernel > 8) return PDHG_EUNSUPPORTED;
+  if (kernel < 0 || kernel > (is_dg(p) ? 9 : 8)) return PDHG_EUNSUPPORTED;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
