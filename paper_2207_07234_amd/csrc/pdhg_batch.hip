@@ -25,6 +25,9 @@ namespace pdhg {
 // EPT = 4 points per thread when nx <= 4 TB, else 8 (nx = 8 TB).
 constexpr int kBatchMaxNx = 4096;
 __host__ __device__ constexpr int batch_ept(int nx, int TB) { return nx <= 4 * TB ? 4 : 8; }
+// The primal pass runs the streaming body in FP32 (see batch_row_threads).
+template <typename T>
+constexpr bool batch_stream() { return sizeof(T) == 4; }
 // Whether blocks of TB threads ever need the EPT = 8 bodies.
 template <int TB>
 constexpr bool batch_needs_e8() { return 4 * TB < kBatchMaxNx; }
@@ -90,7 +93,7 @@ kb_dual_fft(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls,
 // Partial sums: part[P.part_off + pair] (residual) and part[rd_base + P.part_off
 // + pair] (dual residual), one per row pair.
 template <typename T, int TB>
-__global__ void __launch_bounds__(TB)
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(batch_stream<T>() ? 4 : 1)))
 kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls, const int2* __restrict__ tiles,
               const int* __restrict__ counts, int max_nx, const T* __restrict__ u_in, T* __restrict__ u_out,
               const T* __restrict__ phibar, const T* __restrict__ phi, T* __restrict__ spec,
@@ -117,14 +120,15 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
     double rp, rd;
     const bool want_rd = rd_needed(ctrls + td.x);
     __syncthreads();
+    constexpr bool kStream = batch_stream<T>();
     if (!batch_needs_e8<TB>() || batch_ept(nx, TB) == 4)
-      primal_res_pair<T, 4>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off, (T)P.tau_u,
-                            spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf, twl, edge, rp, rd,
-                            static_cast<C2<T>*>(nullptr), nullptr, want_rd);
+      primal_res_pair<T, 4, T, kStream>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off,
+                                        (T)P.tau_u, spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf,
+                                        twl, edge, rp, rd, static_cast<C2<T>*>(nullptr), nullptr, want_rd);
     else if constexpr (batch_needs_e8<TB>())
-      primal_res_pair<T, 8>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off, (T)P.tau_u,
-                            spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf, twl, edge, rp, rd,
-                            static_cast<C2<T>*>(nullptr), nullptr, want_rd);
+      primal_res_pair<T, 8, T, kStream>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off,
+                                        (T)P.tau_u, spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf,
+                                        twl, edge, rp, rd, static_cast<C2<T>*>(nullptr), nullptr, want_rd);
     const double srp = subgroup_sum(rp, red, sg * nw, nw);
     const double srd = subgroup_sum(rd, red, sg * nw, nw);
     if (tid == 0 && pair < P.npairs) {
@@ -373,10 +377,13 @@ static size_t row_lds_bytes(int max_nx) {
   return sizeof(C2<T>) * batch_row_lds_points(max_nx, 256, TB) + sizeof(T) * 4 * (TB / 64);
 }
 
-// Threads per row block: 1024 in FP32 (EPT = 4 for every nx <= 4096), 512 in
-// FP64 (register budget; nx = 4096 then takes EPT = 8).
+// Threads per row block: 512 (EPT = 4 up to nx = 2048, 8 at nx = 4096).  In
+// FP32 the primal pass runs the streaming body (a sliding window of rows in
+// registers, at most 122 VGPRs), so that two of its persistent blocks share a
+// CU and hide each other's loads; in FP64 the load-first body (register budget).
 template <typename T>
-constexpr int batch_row_threads() { return sizeof(T) == 4 ? 1024 : 512; }
+constexpr int batch_row_threads() { return 512; }
+
 
 template <typename T>
 int batch_row_block_threads() { return batch_row_threads<T>(); }
