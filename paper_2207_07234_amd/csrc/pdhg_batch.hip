@@ -78,7 +78,7 @@ kb_dual_fft(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls,
     C2<T>* twl;
     row_tile_geometry<T, TB>(nx, W, sg, tid, buf, twl, smem, max_nx);
     const int a = 2 * (td.y + sg);
-    const C2<T>* tw = static_cast<const C2<T>*>(P.tw);
+    const C2<T>* tw = as_global(static_cast<const C2<T>*>(P.tw));
     __syncthreads();   // LDS of the previous tile is free
     if (!batch_needs_e8<TB>() || batch_ept(nx, TB) == 4)
       dual_fft_pair<T, 4>(spec + P.f_off, nt, P.lqb, nx, tw, phi + P.f_off, phibar + P.f_off, (T)P.tau_phi, a, tid,
@@ -116,7 +116,7 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
     T* edge = edge_all + sg * 4 * nw;
     const int pair = td.y + sg;
     const Consts<T> C(P.s);
-    const C2<T>* tw = static_cast<const C2<T>*>(P.tw);
+    const C2<T>* tw = as_global(static_cast<const C2<T>*>(P.tw));
     double rp, rd;
     const bool want_rd = rd_needed(ctrls + td.x);
     __syncthreads();
@@ -159,7 +159,8 @@ kb_colsolve(const BatchProb* __restrict__ probs, Ctrl* ctrls, const int2* __rest
     const BatchProb& P = probs[td.x];
     if (td.y == 0 && threadIdx.x < 64)
       finalize_wave(ctrls + td.x, part + P.part_off, P.npairs, rd_base, P.wscale, nullptr);
-    const FacTab<T> fac{static_cast<const FacRow<T>*>(P.fac_rows), P.fac_off, P.fac_last};
+    const FacTab<T> fac{as_global(static_cast<const FacRow<T>*>(P.fac_rows)), as_global(P.fac_off),
+                        as_global(P.fac_last)};
     const int nt = P.s.nt, nx = P.s.nx;
     T* sp = spec + P.f_off;
     if (nt <= 256) {   // tiles of 16 columns, 16 lanes per column, LPL = ceil(nt / 16) <= 16

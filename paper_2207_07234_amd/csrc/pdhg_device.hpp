@@ -21,6 +21,18 @@ constexpr int kSpaceLF = 1;
 constexpr int kSpaceDgP2 = 2;
 constexpr int kSpaceDgP1 = 3;
 
+// A device pointer read from a table in memory (rather than passed as a kernel
+// argument) is generic to the compiler, and every access through it becomes a
+// flat instruction, which counts against both the vector-memory and the LDS
+// wait counters.  Re-typing it through an integer as a global pointer lets the
+// address-space inference turn its accesses into global loads and stores.
+// Only for pointers into device (HBM) allocations.
+template <typename P>
+__device__ __forceinline__ P* as_global(P* p) {
+  using G = __attribute__((address_space(1))) char*;
+  return (P*)(reinterpret_cast<G>(reinterpret_cast<uintptr_t>(p)));
+}
+
 // Host-filled description of one problem (all in double; kernels convert).
 struct Scheme {
   int nx, nt;

@@ -100,14 +100,30 @@ struct PairConsts {
   const T* pcr;
 };
 
+// This block's problem entry, with its pointers re-typed as global (they are
+// read from the problem table, so the compiler cannot infer their space).
+template <typename T>
+__device__ __forceinline__ OneStepProb<T> load_prob(const OneStepProb<T>* __restrict__ probs) {
+  OneStepProb<T> P = probs[blockIdx.x];
+  P.tw = as_global(P.tw);
+  P.sym = as_global(P.sym);
+  P.u0 = as_global(P.u0);
+  P.u = as_global(P.u);
+  P.phi = as_global(P.phi);
+  P.stat = as_global(P.stat);
+  P.flag = as_global(P.flag);
+  P.pcr = as_global(P.pcr);
+  return P;
+}
+
 // Symbol (or cyclic-reduction coefficients) of row r (0: c0 = 1, 1: c0 = 3/2).
 template <typename T, int KP>
 __device__ __forceinline__ void load_pair_symbol(PairConsts<T, KP>& pc, const OneStepProb<T>& P, int r, bool act,
                                                  int tid, int W, int M) {
   pc.pcr_k = P.pcr_k[r];
-  pc.pcr = P.pcr + 16 * r;
+  pc.pcr = as_global(P.pcr + 16 * r);
   if (pc.pcr_k > 0) return;
-  const T* symr = P.sym + (size_t)r * 2 * M;
+  const T* symr = as_global(P.sym + (size_t)r * 2 * M);
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
     const int k = tid + j * W;
@@ -423,7 +439,7 @@ __device__ __forceinline__ double onestep_power(const OneStepProb<T>& P, int W, 
 template <typename T>
 __global__ void __launch_bounds__(kOneStepThreadsMax)
 k_onestep_power(OneStepProb<T>* __restrict__ probs, int iters, double* __restrict__ nu) {
-  const OneStepProb<T> P = probs[blockIdx.x];
+  const OneStepProb<T> P = load_prob(probs);
   extern __shared__ char smem[];
   __shared__ T ends[3][2 * kOneStepWavesMax];
   __shared__ double red[2][kOneStepWavesMax];
@@ -465,7 +481,7 @@ template <typename T>
 __global__ void __launch_bounds__(kOneStepThreadsMax)
 k_onestep(const OneStepProb<T>* __restrict__ probs, int l_begin, int l_end, double eps, long long max_iter,
           double dfac) {
-  const OneStepProb<T> P = probs[blockIdx.x];
+  const OneStepProb<T> P = load_prob(probs);
   if (*P.flag != 0) return;   // this problem's march has stopped (diverged step)
   const int le = l_end < P.s.nt ? l_end : P.s.nt;
   if (l_begin >= le) return;
@@ -712,7 +728,7 @@ template <typename T>
 __global__ void __launch_bounds__(kOneStepThreadsMax)
 k_onestep_dg1(const OneStepProb<T>* __restrict__ probs, int l_begin, int l_end, double eps, long long max_iter,
               double dfac) {
-  const OneStepProb<T> P = probs[blockIdx.x];
+  const OneStepProb<T> P = load_prob(probs);
   if (*P.flag != 0) return;
   const int le = l_end < P.s.nt ? l_end : P.s.nt;
   if (l_begin >= le) return;
