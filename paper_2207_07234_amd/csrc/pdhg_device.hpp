@@ -508,6 +508,29 @@ struct FacTab {
   const int* last;
 };
 
+// Chunked column solve: chunks of kChunkLevels levels of kChunkCols spectrum
+// columns (one column block), kChunkCw lanes per column, kChunkLpl levels per lane.
+constexpr int kChunkLpl = 8;
+constexpr int kChunkCw = 32;
+constexpr int kChunkLevels = kChunkLpl * kChunkCw;
+constexpr int kChunkCols = 16;
+constexpr int kChunkThreads = kChunkCw * kChunkCols;
+constexpr int kChunkMinNt = 4097;   // N_t from which the fused solve uses the chunked column solve
+__host__ __device__ constexpr int chunk_count(int nt) { return (nt + kChunkLevels - 1) / kChunkLevels; }
+
+// Arguments of the chunked column solve of long time axes (N_t > 4096,
+// N_x >= 16).  Column blocks g < g64 (and every block where f32.rows is null)
+// run their recurrences in FP64 on f64, the others in float on f32; the maps
+// and the chunk states are FP64.
+struct ChunkArgs {
+  FacTab<double> f64;
+  FacTab<float> f32;
+  const double* cmap;   // [N_x/2 + 1][nchunk][12]: H, G, K of every mode and chunk
+  double* cwork;        // [2][nchunk][N_x][4]: pass-1 records (P, R), entering states (t, h)
+  int nchunk;
+  int g64;
+};
+
 // Multiplier form of Algorithm 1 (Section 3.3): the initial level u^0 is an
 // unknown, and lambda (nx values) imposes u^0 = u0.  u0 == nullptr: u^0 is held
 // fixed.  The pass that holds rows 0 and 1 updates u^0 and lambda (no other

@@ -14,8 +14,10 @@
 //   C  k_colsolve_*    per spectrum column: banded Cholesky solve along t (the
 //                      preconditioner K_d^{-1} of Section 2.2; k_colsolve_half for
 //                      N_t <= 512, k_colsolve_wave up to 1024, k_colsolve_long up
-//                      to 8192); its first wave reduces B's partial sums and takes
-//                      the convergence decision (Section 3.3 stopping rule)
+//                      to 4096 (N_x = 8: 8192), beyond that k_colchunk_pass1, the
+//                      carry pass and k_colchunk_pass2 on chunks of 256 levels); its
+//                      first wave reduces B's partial sums and takes the convergence
+//                      decision (Section 3.3 stopping rule)
 // The pass bodies live in pdhg_passes.hpp (shared with the batched kernels).
 // Halo levels of u^n needed by the time stencil of A are recomputed by each
 // block from the same inputs (bitwise identical to the owner's values); u is
@@ -172,6 +174,127 @@ k_colsolve_long(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb, Ct
   A* xch = reinterpret_cast<A*>(tile + 8 * kColLongLpl * 65);
   colsolve_group_long<T, BW, kColLongLpl, WPC, A>(spec, fac, nt, nx, lqb,
                                                    xcd_block(blockIdx.x, gridDim.x) * (8 / WPC), tile, xch, s0);
+}
+
+// C for N_t > 4096 and N_x >= 16, in chunks of kChunkLevels levels (the
+// chunked solve above): pass 1, the carry pass and pass 2, one block per
+// (column block, chunk) in the passes.  The first wave of block 0 of pass 1
+// reduces B's partial sums and takes the stopping decision; once a solve has
+// stopped every later launch returns at once.  A float spectrum's column
+// blocks below ca.g64 (the slowly decaying low modes) run in FP64.
+template <typename A>
+__device__ __forceinline__ const FacTab<A>& chunk_fac(const ChunkArgs& ca);
+template <>
+__device__ __forceinline__ const FacTab<double>& chunk_fac<double>(const ChunkArgs& ca) { return ca.f64; }
+template <>
+__device__ __forceinline__ const FacTab<float>& chunk_fac<float>(const ChunkArgs& ca) { return ca.f32; }
+
+// Grids over the tiles of column blocks g0 .. g0 + gridDim.x / nchunk - 1,
+// one tile per block, arithmetic type A (the launcher runs the FP64 and the
+// float column blocks of a float spectrum as separate grids, so that each has
+// its own register budget).
+template <typename T, int BW, typename A>
+__global__ void __launch_bounds__(kChunkThreads)
+k_colchunk_pass1(T* __restrict__ spec, ChunkArgs ca, int g0, int nt, int nx, Ctrl* ctrl, const double* part,
+                 int nparts, double wscale, double* hist) {
+  if (ctrl && ctrl->status != 0) return;
+  if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
+  extern __shared__ char smem[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  colchunk_item<T, BW, A, false>(spec, chunk_fac<A>(ca), ca, nt, nx, g0 + b / ca.nchunk, b % ca.nchunk,
+                                 reinterpret_cast<T*>(smem), nullptr);
+}
+
+template <typename T, int BW, typename A>
+__global__ void __launch_bounds__(kChunkThreads)
+k_colchunk_pass2(T* __restrict__ spec, ChunkArgs ca, int g0, int nt, int nx, Ctrl* ctrl, double* s0) {
+  if (ctrl && ctrl->status != 0) return;
+  extern __shared__ char smem[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  colchunk_item<T, BW, A, true>(spec, chunk_fac<A>(ca), ca, nt, nx, g0 + b / ca.nchunk, b % ca.nchunk,
+                                reinterpret_cast<T*>(smem), s0);
+}
+
+// Entering states of every chunk: one 32-lane group per column, lane c for
+// chunk c (nchunk <= 32).  The forward maps (H_c, P_c) are scanned up the
+// chunks from t_0 = 0, then the backward maps (G_c, K_c t_c + R_c) down them
+// from h_{nchunk-1} = 0; lanes past the last chunk hold the identity.  Writes
+// (t_c, h_c) to fac.cwork[1][c].
+constexpr int kChunkCarryThreads = 256;
+__global__ void __launch_bounds__(kChunkCarryThreads)
+k_colchunk_carry(ChunkArgs ca, int nx, Ctrl* ctrl) {
+  if (ctrl && ctrl->status != 0) return;
+  typedef double A;
+  const int nc = ca.nchunk;
+  const int lane = threadIdx.x & 63, c = lane & 31;
+  const int j = blockIdx.x * (kChunkCarryThreads / 32) + (threadIdx.x >> 5);
+  const bool act = c < nc && j < nx;
+  A H[4] = {A(1), A(0), A(0), A(1)}, P[2] = {A(0), A(0)};
+  A G[4] = {A(1), A(0), A(0), A(1)}, K[4] = {A(0), A(0), A(0), A(0)}, R[2] = {A(0), A(0)};
+  if (act) {
+    const A* m = ca.cmap + ((size_t)spec_mode(j, nx) * nc + c) * 12;
+    const A* w = ca.cwork + ((size_t)c * nx + j) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      H[k] = m[k];
+      G[k] = m[4 + k];
+      K[k] = m[8 + k];
+    }
+    P[0] = w[0]; P[1] = w[1];
+    R[0] = w[2]; R[1] = w[3];
+  }
+  A t2, t1, h2, h1;
+  scan_half_from<A, true>(H, P, lane, A(0), A(0), t2, t1);
+  A Q[2] = {K[0] * t2 + K[1] * t1 + R[0], K[2] * t2 + K[3] * t1 + R[1]};
+  scan_half_from<A, false>(G, Q, lane, A(0), A(0), h2, h1);
+  if (act) {
+    A* o = ca.cwork + ((size_t)(nc + c) * nx + j) * 4;
+    o[0] = t2; o[1] = t1; o[2] = h2; o[3] = h1;
+  }
+}
+
+// The maps of mode k and chunk c (one thread each) from the factor rows:
+// H (forward homogeneous responses at the chunk's last two levels to the
+// entering z_{s-2}, z_{s-1}), G (backward homogeneous responses at its first
+// two levels to the entering y_{e+1}, y_e) and K (the backward solve, from
+// zero, of the forward homogeneous responses, at the first two levels).  K is
+// accumulated in the forward sweep: y_i = <L_c^{-1} e_i, v> for the chunk's
+// diagonal block L_c of the factor.  out: [nmodes][nchunk][12] = H, G, K.
+template <typename A, int BW>
+__global__ void __launch_bounds__(256)
+k_colchunk_maps(FacTab<A> fac, int nt, int nmodes, A* __restrict__ out) {
+  const int nc = chunk_count(nt);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nmodes * nc) return;
+  const int k = idx / nc, c = idx % nc;
+  const FacRow<A>* rows = fac.rows + fac.off[k];
+  const int last = fac.last[k];
+  const int s = c * kChunkLevels, e = min(nt, s + kChunkLevels);
+  A a2 = 1, a1 = 0, b2 = 0, b1 = 1, u2 = 0, u1 = 0, v2 = 0, v1 = 0;
+  A k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+  for (int l = s; l < e; ++l) {
+    const FacRow<A> r = rows[min(l, last)];
+    const A f2 = BW == 2 ? r.e2 : A(0);
+    const A az = r.invd * (-(r.e1 * a1) - f2 * a2);
+    const A bz = r.invd * (-(r.e1 * b1) - f2 * b2);
+    const A uz = r.invd * ((l == s ? A(1) : A(0)) - r.e1 * u1 - f2 * u2);       // L_c^{-1} e_s
+    const A vz = r.invd * ((l == s + 1 ? A(1) : A(0)) - r.e1 * v1 - f2 * v2);   // L_c^{-1} e_{s+1}
+    a2 = a1; a1 = az; b2 = b1; b1 = bz; u2 = u1; u1 = uz; v2 = v1; v1 = vz;
+    k0 += vz * az; k1 += vz * bz; k2 += uz * az; k3 += uz * bz;
+  }
+  A* o = out + (size_t)idx * 12;
+  o[0] = a2; o[1] = b2; o[2] = a1; o[3] = b1;
+  a2 = 1; a1 = 0; b2 = 0; b1 = 1;
+  for (int l = e - 1; l >= s; --l) {
+    const A invd = rows[min(l, last)].invd;
+    const A f1 = rows[min(l + 1, last)].e1;
+    const A f2 = BW == 2 ? rows[min(l + 2, last)].e2 : A(0);
+    const A az = invd * (-(f1 * a1) - f2 * a2);
+    const A bz = invd * (-(f1 * b1) - f2 * b2);
+    a2 = a1; a1 = az; b2 = b1; b1 = bz;
+  }
+  o[4] = a2; o[5] = b2; o[6] = a1; o[7] = b1;
+  o[8] = k0; o[9] = k1; o[10] = k2; o[11] = k3;
 }
 
 // C (full-symbol preconditioner): per Fourier mode k, K_k = L_k L_k^* with
@@ -443,6 +566,72 @@ static hipError_t launch_colsolve_long_l(T* spec, const FacTab<A>& fac, int nt, 
                      lqb, ctrl, part, nparts, wscale, hist, s0);
   return hipGetLastError();
 }
+
+template <typename T, int BW>
+static hipError_t launch_colsolve_chunk_l(T* spec, const ChunkArgs& ca, int nt, int nx, Ctrl* ctrl,
+                                          const double* part, int nparts, double wscale, double* hist,
+                                          hipStream_t st, double* s0) {
+  const size_t lds = sizeof(T) * (size_t)kChunkCols * kChunkLpl * (kChunkCw + 1);
+  const int nblocks = nx / kChunkCols;
+  // column blocks [0, n64) in FP64, [n64, nblocks) in float (a float spectrum with float rows only)
+  const int n64 = (sizeof(T) == 4 && ca.f32.rows) ? (ca.g64 < nblocks ? ca.g64 : nblocks) : nblocks;
+  const int i64 = n64 * ca.nchunk, i32 = (nblocks - n64) * ca.nchunk;   // tiles of either grid
+  hipError_t e = allow_lds(k_colchunk_pass1<T, BW, double>, lds);
+  if (e == hipSuccess) e = allow_lds(k_colchunk_pass2<T, BW, double>, lds);
+  if (e != hipSuccess) return e;
+  // the grid holding block 0 reduces the partial sums
+  if (i64 > 0)
+    hipLaunchKernelGGL((k_colchunk_pass1<T, BW, double>), dim3(i64), dim3(kChunkThreads), lds, st, spec, ca, 0, nt,
+                       nx, ctrl, part, nparts, wscale, hist);
+  if constexpr (sizeof(T) == 4) {
+    if (i32 > 0) {
+      if ((e = allow_lds(k_colchunk_pass1<T, BW, float>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_colchunk_pass1<T, BW, float>), dim3(i32), dim3(kChunkThreads), lds, st, spec, ca, n64,
+                         nt, nx, ctrl, i64 > 0 ? nullptr : part, nparts, wscale, hist);
+    }
+  }
+  hipLaunchKernelGGL(k_colchunk_carry, dim3((nx + 7) / 8), dim3(kChunkCarryThreads), 0, st, ca, nx, ctrl);
+  if (i64 > 0)
+    hipLaunchKernelGGL((k_colchunk_pass2<T, BW, double>), dim3(i64), dim3(kChunkThreads), lds, st, spec, ca, 0, nt,
+                       nx, ctrl, s0);
+  if constexpr (sizeof(T) == 4) {
+    if (i32 > 0) {
+      if ((e = allow_lds(k_colchunk_pass2<T, BW, float>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_colchunk_pass2<T, BW, float>), dim3(i32), dim3(kChunkThreads), lds, st, spec, ca, n64,
+                         nt, nx, ctrl, s0);
+    }
+  }
+  return hipGetLastError();
+}
+
+// C in chunks: N_t >= kChunkMinNt, N_x >= 16 (column blocks of 16), at most 32
+// chunks.  ctrl, part, nparts, wscale, hist as for launch_colsolve_wave; s0
+// (nullable): receives the mode-0 column of the solution in FP64.
+template <typename T>
+hipError_t launch_colsolve_chunk(T* spec, const ChunkArgs& ca, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st,
+                                 double* s0) {
+  if (nt < kChunkMinNt || nx < kChunkCols || lqb != 4 || ca.nchunk != chunk_count(nt) || ca.nchunk > 32 ||
+      !ca.cmap || !ca.cwork || !ca.f64.rows)
+    return hipErrorInvalidValue;
+  if (bw == 2) return launch_colsolve_chunk_l<T, 2>(spec, ca, nt, nx, ctrl, part, nparts, wscale, hist, st, s0);
+  return launch_colsolve_chunk_l<T, 1>(spec, ca, nt, nx, ctrl, part, nparts, wscale, hist, st, s0);
+}
+template hipError_t launch_colsolve_chunk<float>(float*, const ChunkArgs&, int, int, int, int, Ctrl*, const double*,
+                                                 int, double, double*, hipStream_t, double*);
+template hipError_t launch_colsolve_chunk<double>(double*, const ChunkArgs&, int, int, int, int, Ctrl*,
+                                                  const double*, int, double, double*, hipStream_t, double*);
+
+template <typename A>
+hipError_t launch_colchunk_maps(const FacTab<A>& fac, int bw, int nt, int nmodes, A* out, hipStream_t st) {
+  const int n = nmodes * chunk_count(nt);
+  if (bw == 2)
+    hipLaunchKernelGGL((k_colchunk_maps<A, 2>), dim3((n + 255) / 256), dim3(256), 0, st, fac, nt, nmodes, out);
+  else
+    hipLaunchKernelGGL((k_colchunk_maps<A, 1>), dim3((n + 255) / 256), dim3(256), 0, st, fac, nt, nmodes, out);
+  return hipGetLastError();
+}
+template hipError_t launch_colchunk_maps<double>(const FacTab<double>&, int, int, int, double*, hipStream_t);
 
 // C: nt <= 8192, nx >= 8.  With part != NULL the
 // first wave of block 0 also reduces the iteration's residual partial sums and

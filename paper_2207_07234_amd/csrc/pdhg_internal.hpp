@@ -77,6 +77,16 @@ template <typename T, typename A = T>
 hipError_t launch_colsolve_wave(T* spec, const FacTab<A>& fac, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st,
                                 A* s0 = nullptr);
+// Maps of the chunked column solve (per mode and chunk, from the factor rows;
+// nmodes = N_x/2 + 1): out [nmodes][chunk_count(nt)][12].
+template <typename A>
+hipError_t launch_colchunk_maps(const FacTab<A>& fac, int bw, int nt, int nmodes, A* out, hipStream_t st);
+// The chunked column solve (N_t >= kChunkMinNt, N_x >= 16); s0 as for
+// launch_colsolve_wave, in FP64.
+template <typename T>
+hipError_t launch_colsolve_chunk(T* spec, const ChunkArgs& ca, int bw, int nt, int nx, int lqb, Ctrl* ctrl,
+                                 const double* part, int nparts, double wscale, double* hist, hipStream_t st,
+                                 double* s0 = nullptr);
 // Full-symbol preconditioner: g_k = (wr + vr)(1 - cos theta_k) + i ci sin theta_k per Fourier mode.
 struct FullSym {
   double inv_ht;   // 1 / h_t

@@ -17,6 +17,8 @@
 // >= nt is idle: it takes part in the barriers and stores nothing.
 #pragma once
 
+#include <type_traits>
+
 #include "pdhg_device.hpp"
 
 namespace pdhg {
@@ -940,6 +942,265 @@ __device__ __forceinline__ void colsolve_group_long(T* __restrict__ spec, const 
     const int idx = tid + r * kThreads;
     const int l = idx / NCB, c = idx % NCB;
     if (l < nt) base[(size_t)l * QB + c] = stage[r];
+  }
+}
+
+// ------------------------------------------------------------------ C, chunked (long time axes)
+// For N_t > 4096 the solve L L^T y = r of every spectrum column runs on chunks
+// of kChunkLevels levels.  Both substitutions are linear, so the state entering
+// chunk c of a column (forward: t_c = (z_{s-2}, z_{s-1}) at its first level s;
+// backward: h_c = (y_{e+1}, y_e) at its end e) is an affine function of the
+// neighbouring chunk's:
+//   t_{c+1} = H_c t_c + P_c
+//   h_{c-1} = G_c h_c + K_c t_c + R_c
+// H_c, G_c (the homogeneous responses over the chunk) and K_c (the backward
+// particular response to the forward homogeneous responses) depend only on the
+// factor rows: 12 values per mode and chunk, computed once with the factor
+// table (k_colchunk_maps).  P_c and R_c are the forward and backward states
+// leaving the chunk when it is solved from zero entering states.  Pass 1 solves
+// every chunk from zero and records P_c, R_c; the carry pass runs the two
+// recurrences per column; pass 2 solves every chunk again from its entering
+// states and stores y.  Every load and store of a block moves whole lines: a
+// block holds the kChunkCols columns of one column block of the spectrum.
+
+// Inclusive scan of segment maps over the 32-lane columns of a wavefront
+// (H, P in place), and the state entering this lane's segment when the
+// column's segment chain is entered with state (x2, x1).
+template <typename T, bool FWD>
+__device__ __forceinline__ void scan_half_from(T* H, T* P, int lane, T x2, T x1, T& in2, T& in1) {
+  scan_step_row<T, FWD, 1>(H, P);
+  scan_step_row<T, FWD, 2>(H, P);
+  scan_step_row<T, FWD, 4>(H, P);
+  scan_step_row<T, FWD, 8>(H, P);
+  scan_cross_half(H, P, lane, FWD);
+  T E[4], F[2];
+  if (FWD) {
+    E[0] = from_lane_below(H[0], T(1));
+    E[1] = from_lane_below(H[1], T(0));
+    E[2] = from_lane_below(H[2], T(0));
+    E[3] = from_lane_below(H[3], T(1));
+    F[0] = from_lane_below(P[0], T(0));
+    F[1] = from_lane_below(P[1], T(0));
+  } else {
+    E[0] = from_lane_above(H[0], T(1));
+    E[1] = from_lane_above(H[1], T(0));
+    E[2] = from_lane_above(H[2], T(0));
+    E[3] = from_lane_above(H[3], T(1));
+    F[0] = from_lane_above(P[0], T(0));
+    F[1] = from_lane_above(P[1], T(0));
+  }
+  if (FWD ? ((lane & 31) == 0) : ((lane & 31) == 31)) {   // the column's first segment: the identity
+    E[0] = T(1); E[1] = T(0); E[2] = T(0); E[3] = T(1);
+    F[0] = T(0); F[1] = T(0);
+  }
+  in2 = E[0] * x2 + E[1] * x1 + F[0];
+  in1 = E[2] * x2 + E[3] * x1 + F[1];
+}
+
+// One tile of the chunked solve: kChunkCols columns x kChunkLevels levels of
+// column block g from level ls, contiguous in the spectrum (QB = kChunkCols),
+// moved in 16-byte pieces; levels at or past nt read as zero and are not
+// stored.
+template <typename T>
+struct ChunkTile {
+  static constexpr int VW = 16 / (int)sizeof(T);
+  static constexpr int kVec = kChunkCols * kChunkLevels / (kChunkThreads * VW);
+  static constexpr int TS = kChunkCw + 1;
+  typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type V;
+  V v[kVec];
+  // unconditional loads (from the last level for levels past nt, then zeroed), so that no branch
+  // separates them and the waits for the loads issued around them stay exact
+  __device__ __forceinline__ void load(const T* __restrict__ spec, int nt, int g, int ls) {
+    const V* base = reinterpret_cast<const V*>(spec + (size_t)g * nt * kChunkCols);
+#pragma unroll
+    for (int r = 0; r < kVec; ++r) {
+      const int e = (threadIdx.x + r * kChunkThreads) * VW;
+      const int l = ls + e / kChunkCols;
+      v[r] = base[((size_t)(l < nt ? l : nt - 1) * kChunkCols + e % kChunkCols) / VW];
+    }
+#pragma unroll
+    for (int r = 0; r < kVec; ++r) {
+      const int e = (threadIdx.x + r * kChunkThreads) * VW;
+      if (ls + e / kChunkCols >= nt) v[r] = V{};
+    }
+  }
+  // LDS tile: element (level l, column c) at (c * kChunkLpl + l % kChunkLpl) * TS + l / kChunkLpl
+  __device__ __forceinline__ void to_lds(T* tile) const {
+#pragma unroll
+    for (int r = 0; r < kVec; ++r) {
+      const int e = (threadIdx.x + r * kChunkThreads) * VW;
+      const int l = e / kChunkCols, c0 = e % kChunkCols;
+      const T* x = reinterpret_cast<const T*>(&v[r]);
+#pragma unroll
+      for (int k = 0; k < VW; ++k) tile[((c0 + k) * kChunkLpl + l % kChunkLpl) * TS + l / kChunkLpl] = x[k];
+    }
+  }
+  static __device__ __forceinline__ void store_from_lds(const T* tile, T* __restrict__ spec, int nt, int g, int ls) {
+    V* base = reinterpret_cast<V*>(spec + ((size_t)g * nt + ls) * kChunkCols);
+#pragma unroll
+    for (int r = 0; r < kVec; ++r) {
+      const int e = (threadIdx.x + r * kChunkThreads) * VW;
+      const int l = e / kChunkCols, c0 = e % kChunkCols;
+      V w;
+      T* x = reinterpret_cast<T*>(&w);
+#pragma unroll
+      for (int k = 0; k < VW; ++k) x[k] = tile[((c0 + k) * kChunkLpl + l % kChunkLpl) * TS + l / kChunkLpl];
+      if (ls + l < nt) base[e / VW] = w;
+    }
+  }
+};
+
+// The solve of one tile held in LDS (column block g, chunk c) by a block of
+// kChunkThreads threads, arithmetic type A on the factor rows fac.
+// SOLVE = false: pass 1 (records P_c, R_c in ca.cwork[0][c]); true: pass 2
+// (reads the entering states from ca.cwork[1][c] and writes the solution back
+// into the tile).
+// A lane's share of a tile: column j of the tile, levels l0 .. l0 + kChunkLpl
+// - 1, its factor rows and (pass 2) the states entering the chunk.  lookup()
+// issues the loads of the mode's row offset and of the entering states,
+// load_rows() those of the rows: the tile's loads go in between, so that all
+// of them are in flight together (a wait for a load also waits for every
+// load issued before it).
+template <typename A>
+struct ChunkLane {
+  int col, q, j, l0, off, last;
+  A invd[kChunkLpl], e1[kChunkLpl + 1], e2[kChunkLpl + 2];
+  A x2 = A(0), x1 = A(0), w2 = A(0), w1 = A(0);   // entering states: forward, backward
+  __device__ __forceinline__ void lookup(const FacTab<A>& fac, const ChunkArgs& ca, int nx, int g, int c,
+                                         bool solve) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    col = wv * (64 / kChunkCw) + lane / kChunkCw;
+    q = lane % kChunkCw;
+    j = g * kChunkCols + col;
+    l0 = c * kChunkLevels + q * kChunkLpl;
+    const int k = spec_mode(j, nx);
+    off = fac.off[k];
+    last = fac.last[k];
+    if (solve) {
+      const double* cin = ca.cwork + ((size_t)(ca.nchunk + c) * nx + j) * 4;
+      x2 = A(cin[0]); x1 = A(cin[1]); w2 = A(cin[2]); w1 = A(cin[3]);
+    }
+  }
+  __device__ __forceinline__ void load_rows(const FacTab<A>& fac) {
+    const FacRow<A>* rows = fac.rows + off;
+#pragma unroll
+    for (int i = 0; i < kChunkLpl; ++i) {
+      const FacRow<A> fr = rows[min(l0 + i, last)];
+      invd[i] = fr.invd;
+      e1[i] = fr.e1;
+      e2[i] = fr.e2;
+    }
+    e1[kChunkLpl] = rows[min(l0 + kChunkLpl, last)].e1;
+    e2[kChunkLpl] = rows[min(l0 + kChunkLpl, last)].e2;
+    e2[kChunkLpl + 1] = rows[min(l0 + kChunkLpl + 1, last)].e2;
+  }
+};
+
+template <typename T, int BW, typename A, bool SOLVE>
+__device__ __forceinline__ void colchunk_tile(const ChunkLane<A>& ln, const ChunkArgs& ca, int nt, int nx, int c,
+                                              T* tile, double* __restrict__ s0) {
+  constexpr int LPL = kChunkLpl, CW = kChunkCw, TS = CW + 1;
+  const int lane = threadIdx.x & 63;
+  const int col = ln.col, q = ln.q, j = ln.j, l0 = ln.l0;
+  const A* invd = ln.invd;
+  const A* e1 = ln.e1;
+  const A* e2 = ln.e2;
+  const A x2 = ln.x2, x1 = ln.x1, w2 = ln.w2, w1 = ln.w1;
+  A z[LPL];
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) z[i] = A(tile[(col * LPL + i) * TS + q]);
+  // forward: z_l = invd_l (r_l - e1_l z_{l-1} - e2_l z_{l-2})
+  {
+    A p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      if (l0 + i < nt) {
+        const A pz = invd[i] * (z[i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : A(0)));
+        const A az = invd[i] * (-(e1[i] * a1) - (BW == 2 ? e2[i] * a2 : A(0)));
+        const A bz = invd[i] * (-(e1[i] * b1) - (BW == 2 ? e2[i] * b2 : A(0)));
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    A H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
+    A zm2, zm1;
+    scan_half_from<A, true>(H, P, lane, x2, x1, zm2, zm1);
+    if (!SOLVE && q == CW - 1) {   // state leaving the chunk (from zero)
+      double* rec = ca.cwork + ((size_t)c * nx + j) * 4;
+      rec[0] = double(P[0]);
+      rec[1] = double(P[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < LPL; ++i) {
+      if (l0 + i < nt) {
+        const A zz = invd[i] * (z[i] - e1[i] * zm1 - (BW == 2 ? e2[i] * zm2 : A(0)));
+        z[i] = zz;
+        zm2 = zm1; zm1 = zz;
+      }
+    }
+  }
+  // backward: y_l = invd_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2})
+  {
+    A p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+    for (int ii = 0; ii < LPL; ++ii) {
+      const int i = LPL - 1 - ii;
+      if (l0 + i < nt) {
+        const A f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : A(0);
+        const A pz = invd[i] * (z[i] - f1 * p1 - f2 * p2);
+        const A az = invd[i] * (-(f1 * a1) - f2 * a2);
+        const A bz = invd[i] * (-(f1 * b1) - f2 * b2);
+        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+      }
+    }
+    A H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
+    A ym2, ym1;
+    scan_half_from<A, false>(H, P, lane, w2, w1, ym2, ym1);
+    if (!SOLVE) {
+      if (q == 0) {   // state leaving the chunk backwards (forward values from zero)
+        double* rec = ca.cwork + ((size_t)c * nx + j) * 4;
+        rec[2] = double(P[0]);
+        rec[3] = double(P[1]);
+      }
+      return;
+    }
+#pragma unroll
+    for (int ii = 0; ii < LPL; ++ii) {
+      const int i = LPL - 1 - ii;
+      if (l0 + i < nt) {
+        const A f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : A(0);
+        const A yy = invd[i] * (z[i] - f1 * ym1 - f2 * ym2);
+        z[i] = yy;
+        ym2 = ym1; ym1 = yy;
+      }
+    }
+  }
+  if (s0 && j == 0) {
+#pragma unroll
+    for (int i = 0; i < LPL; ++i)
+      if (l0 + i < nt) s0[l0 + i] = double(z[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) tile[(col * LPL + i) * TS + q] = T(z[i]);
+}
+
+// One tile (column block g, chunk c) by the calling block: the lookup of the
+// mode's row offset and the entering states, the tile's loads and the factor
+// rows are issued in that order, so that their latencies overlap.
+// tile: kChunkCols * kChunkLpl * (kChunkCw + 1) elements of LDS.
+template <typename T, int BW, typename A, bool SOLVE>
+__device__ __forceinline__ void colchunk_item(T* __restrict__ spec, const FacTab<A>& fac, const ChunkArgs& ca,
+                                              int nt, int nx, int g, int c, T* tile, double* __restrict__ s0) {
+  ChunkLane<A> ln;
+  ln.lookup(fac, ca, nx, g, c, SOLVE);
+  ChunkTile<T> buf;
+  buf.load(spec, nt, g, c * kChunkLevels);
+  ln.load_rows(fac);
+  buf.to_lds(tile);
+  __syncthreads();
+  colchunk_tile<T, BW, A, SOLVE>(ln, ca, nt, nx, c, tile, s0);
+  if (SOLVE) {
+    __syncthreads();
+    ChunkTile<T>::store_from_lds(tile, spec, nt, g, c * kChunkLevels);
   }
 }
 

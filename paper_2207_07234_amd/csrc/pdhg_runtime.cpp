@@ -253,7 +253,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct WsLayout {
   size_t u_alt, phi_alt, spec0, spec1, srow, phibar, part_rp, part_rd, scal, ctrl, ctrl_t, s0, ck_u, ck_phi, lam, lambar,
-      adj, total;
+      adj, colchunk, total;
   int max_parts;
 };
 
@@ -286,6 +286,13 @@ struct pdhg_handle {
   int* d_fac_off = nullptr;
   int* d_fac_last = nullptr;
   double fac_c = -1.0, fac_g = -1.0;
+  // chunked column solve (always FP64 arithmetic): per-mode, per-chunk maps, and for FP32 problems an
+  // FP64 copy of the factor table
+  double* d_cmap = nullptr;
+  int chunk_g64 = 0;            // column blocks below it run in FP64 when the spectrum is float
+  void* d_f64_rows = nullptr;
+  int* d_f64_off = nullptr;
+  int* d_f64_last = nullptr;
   // single-precision preconditioner of an FP64 problem: float twiddles and factors
   void* d_tw32 = nullptr;
   void* d_vtab = nullptr;       // DG: per-mode 6x6 eigenbases of the coefficient coupling
@@ -347,6 +354,10 @@ inline bool is_dg(const pdhg_problem& p) { return p.space == PDHG_DG_P2_LLF || p
 inline bool is_full(const pdhg_problem& p) { return p.precond_kind == PDHG_PRECOND_FULL; }
 // FP64 state with the Gram preconditioner's spectral pass in single precision
 inline bool is_pre32(const pdhg_problem& p) { return p.precond_kind == PDHG_PRECOND_GRAM_F32; }
+// The Gram column solve of a finite-difference problem runs in chunks (N_t > 4096, N_x >= 16).
+inline bool uses_chunks(const pdhg_problem& p) {
+  return !is_dg(p) && !is_full(p) && p.nt >= kChunkMinNt && p.nx >= kChunkCols;
+}
 
 WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   WsLayout L{};
@@ -374,6 +385,8 @@ WsLayout layout_for(const pdhg_problem& p, size_t esz) {
   L.lambar = o; o += align_up(nx * esz);
   L.adj = o;                                       // DG adjoint march: block rows and three levels of multipliers
   if (is_dg(p)) o += align_up(sizeof(double) * dg_adjoint_scratch_doubles(p.nx, planes(p)));
+  L.colchunk = o;                                  // chunked column solve: pass-1 records and entering states
+  if (uses_chunks(p)) o += align_up(sizeof(double) * 8 * (size_t)chunk_count(p.nt) * p.nx);
   L.total = o;
   return L;
 }
@@ -407,6 +420,32 @@ FullSym full_sym_of(const pdhg_handle* h) {
   return F;
 }
 
+// Column blocks of the chunked solve whose recurrences run in FP64 when the
+// spectrum is float: block g holds modes 8g .. 8g+7 (block 0: mode 0), and a
+// mode whose shift s_k = c^2 mu_k + ghat^2 mu_k^2 is small against (1/h_t)^2
+// (s_k h_t^2 < 1e-2) decays slowly along t: its part of s is large and smooth
+// in t, and the primal step differences it in time, which amplifies float
+// rounding of its recurrences.  Returns the first block whose lowest mode is
+// past that bound (N_x / 16 if none is).
+int chunk_fp64_blocks(const pdhg_problem& p, double c, double ghat) {
+  const double PI = 3.141592653589793;
+  const double ht = p.t_final / p.nt, hx = p.length / p.nx;
+  const int nblocks = p.nx / kChunkCols;
+  for (int g = 1; g < nblocks; ++g) {
+    const double sn = std::sin(PI * (8 * g) / p.nx);
+    const double mu = 4.0 * sn * sn / (hx * hx);
+    if ((c * c * mu + ghat * ghat * mu * mu) * ht * ht >= 1e-2) return g;
+  }
+  return nblocks;
+}
+
+// FP64 factor rows of the chunked column solve: the factor table of an FP64
+// problem, the FP64 copy of an FP32 problem's.
+FacTab<double> chunk_rows(const pdhg_handle* h) {
+  if (h->d_f64_rows) return FacTab<double>{(const FacRow<double>*)h->d_f64_rows, h->d_f64_off, h->d_f64_last};
+  return FacTab<double>{(const FacRow<double>*)h->d_fac_rows, h->d_fac_off, h->d_fac_last};
+}
+
 template <typename T>
 int upload_factors(pdhg_handle* h, double c, double ghat) {
   std::vector<FacRow<T>> rows;
@@ -423,6 +462,32 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
   HIP_TRY(hipMemcpy(h->d_fac_rows, rows.data(), rows.size() * sizeof(FacRow<T>), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_fac_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_fac_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (h->d_cmap) hipFree(h->d_cmap);
+  if (h->d_f64_rows) hipFree(h->d_f64_rows);
+  if (h->d_f64_off) hipFree(h->d_f64_off);
+  if (h->d_f64_last) hipFree(h->d_f64_last);
+  h->d_cmap = nullptr;
+  h->d_f64_rows = nullptr;
+  h->d_f64_off = h->d_f64_last = nullptr;
+  if (uses_chunks(h->prob)) {   // the chunked column solve: FP64 rows and their maps
+    if (sizeof(T) != sizeof(double)) {
+      std::vector<FacRow<double>> r64;
+      std::vector<int> o64, l64;
+      build_factor_rows<double>(h->prob, c, ghat, r64, o64, l64);
+      HIP_TRY(hipMalloc(&h->d_f64_rows, r64.size() * sizeof(FacRow<double>)));
+      HIP_TRY(hipMalloc((void**)&h->d_f64_off, o64.size() * sizeof(int)));
+      HIP_TRY(hipMalloc((void**)&h->d_f64_last, l64.size() * sizeof(int)));
+      HIP_TRY(hipMemcpy(h->d_f64_rows, r64.data(), r64.size() * sizeof(FacRow<double>), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(h->d_f64_off, o64.data(), o64.size() * sizeof(int), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(h->d_f64_last, l64.data(), l64.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    const int nmodes = h->prob.nx / 2 + 1;
+    h->chunk_g64 = chunk_fp64_blocks(h->prob, c, ghat);
+    HIP_TRY(hipMalloc((void**)&h->d_cmap, sizeof(double) * 12 * (size_t)nmodes * chunk_count(h->prob.nt)));
+    HIP_TRY(launch_colchunk_maps<double>(chunk_rows(h), h->prob.time == PDHG_BDF2 ? 2 : 1, h->prob.nt, nmodes,
+                                         h->d_cmap, nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+  }
   h->fac_c = c;
   h->fac_g = ghat;
   return PDHG_OK;
@@ -585,6 +650,19 @@ int ensure_workspace(pdhg_handle* h, void*& ws) {
 
 inline char* wsp(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
+// Arguments of the chunked column solve with its work buffer in workspace ws: FP64 rows for every block,
+// and for a float state the float rows of the blocks at and above chunk_g64.
+ChunkArgs chunk_args(const pdhg_handle* h, void* ws) {
+  ChunkArgs a{};
+  a.f64 = chunk_rows(h);
+  if (h->prob.dtype == PDHG_F32) a.f32 = factab<float>(h);
+  a.cmap = h->d_cmap;
+  a.cwork = (double*)wsp(ws, layout_for(h->prob, h->esz).colchunk);
+  a.nchunk = chunk_count(h->prob.nt);
+  a.g64 = h->chunk_g64;
+  return a;
+}
+
 // max |f'(u0)| on the device, read back (synchronous).  part: >= 64 doubles of device scratch.
 template <typename T>
 int max_abs_dflux(pdhg_handle* h, const T* u0, double* part, hipStream_t st, double* out) {
@@ -648,20 +726,23 @@ int resolve_constants(pdhg_handle* h, const T* u0, void* ws, hipStream_t st) {
 // also reduces the iteration's residual partial sums (nparts per norm) and
 // takes the stopping decision, in the first wavefront of block 0.
 template <typename T>
-hipError_t colsolve_any(pdhg_handle* h, T* spec, Ctrl* ctrl, const double* part, int nparts, double* hist,
-                        hipStream_t st) {
+hipError_t colsolve_any(pdhg_handle* h, void* ws, T* spec, Ctrl* ctrl, const double* part, int nparts,
+                        double* hist, hipStream_t st) {
   const pdhg_problem& p = h->prob;
   const int bw = p.time == PDHG_BDF2 ? 2 : 1;
   const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
   if (is_full(p))   // nt <= 1024 (checked at set-up)
     return launch_colsolve_full<T>(spec, full_sym_of(h), h->d_tw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale,
                                    hist, st);
+  if (uses_chunks(p) && h->d_cmap)
+    return launch_colsolve_chunk<T>(spec, chunk_args(h, ws), bw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale,
+                                    hist, st);
   return launch_colsolve_wave<T>(spec, factab<T>(h), bw, p.nt, p.nx, h->lqb, ctrl, part, nparts, wscale, hist, st);
 }
 
 // s = K_d^{-1} r through the workspace spectrum buffer spec.
 template <typename T>
-int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
+int precond_apply(pdhg_handle* h, void* ws, const T* r, T* s, T* spec, hipStream_t st) {
   const pdhg_problem& p = h->prob;
   if (is_dg(p)) {   // planes x nt coefficient rows; per-mode eigenbasis in the column solve
     const int nr = planes(p) * p.nt;
@@ -672,7 +753,7 @@ int precond_apply(pdhg_handle* h, const T* r, T* s, T* spec, hipStream_t st) {
     return PDHG_OK;
   }
   HIP_TRY(launch_rows_fwd<T>(r, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, nullptr, st));
-  HIP_TRY(colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st));
+  HIP_TRY(colsolve_any<T>(h, ws, spec, nullptr, nullptr, 0, nullptr, st));
   HIP_TRY(launch_rows_inv<T>(spec, p.nt, h->lqb, s, p.nt, p.nx, h->d_tw, nullptr, st));
   return PDHG_OK;
 }
@@ -705,7 +786,7 @@ int power_iteration(pdhg_handle* h, const T* u, void* ws, hipStream_t st, int it
   for (int it = 0; it < iters; ++it) {
     if (dg) HIP_TRY(dgx_apply_j<T>(s, u, v, w, st));             // w = J v
     else HIP_TRY(launch_apply_j<T>(s, u, v, w, st));
-    int rc = precond_apply<T>(h, w, w, spec, st);                 // w = K_d^{-1} w
+    int rc = precond_apply<T>(h, ws, w, w, spec, st);                 // w = K_d^{-1} w
     if (rc) return rc;
     if (dg) HIP_TRY(dgx_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));         // t = J^T w
     else HIP_TRY(launch_apply_jt<T>(s, u, w, t, nullptr, st, nullptr));
@@ -904,6 +985,10 @@ void pdhg_destroy(pdhg_handle* h) {
   if (h->d_fac_rows) hipFree(h->d_fac_rows);
   if (h->d_fac_off) hipFree(h->d_fac_off);
   if (h->d_fac_last) hipFree(h->d_fac_last);
+  if (h->d_cmap) hipFree(h->d_cmap);
+  if (h->d_f64_rows) hipFree(h->d_f64_rows);
+  if (h->d_f64_off) hipFree(h->d_f64_off);
+  if (h->d_f64_last) hipFree(h->d_f64_last);
   if (h->d_tw32) hipFree(h->d_tw32);
   if (h->d_vtab) hipFree(h->d_vtab);
   if (h->own_ws) hipFree(h->own_ws);
@@ -943,7 +1028,7 @@ int enqueue_body_unfused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau
   HIP_TRY(launch_primal<T>(s, uin, uout, phibar, phi, tau_u, prd, ctrl, st, &nb_rd));
   HIP_TRY(launch_residual<T>(s, uout, srow, prp, ctrl, st, &nb_rp));
   HIP_TRY(launch_rows_fwd<T>(srow, p.nt, spec, p.nt, h->lqb, p.nx, h->d_tw, ctrl, st));
-  HIP_TRY(colsolve_any<T>(h, spec, ctrl, nullptr, 0, nullptr, st));
+  HIP_TRY(colsolve_any<T>(h, ws, spec, ctrl, nullptr, 0, nullptr, st));
   HIP_TRY(launch_finalize(ctrl, prp, nb_rp, prd, nb_rd, s.ht * s.hx, hist, st));
   return PDHG_OK;
 }
@@ -972,14 +1057,18 @@ int enqueue_body_fused(pdhg_handle* h, bool odd, T* u, T* phi, void* ws, T tau_u
     HIP_TRY((launch_primal_res<T, float>(s, uin, uout, phibar, phi, tau_u, spec32, h->lqb, h->d_tw32, part, ctrl,
                                          st, &lam)));
     const double wscale = (p.t_final / p.nt) * (p.length / p.nx);
-    HIP_TRY((launch_colsolve_wave<float, double>(spec32, factab<double>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
-                                                 h->lqb, ctrl, part, (p.nt + 1) / 2, wscale, hist, st,
-                                                 (double*)s0)));
+    const int bw = p.time == PDHG_BDF2 ? 2 : 1;
+    if (uses_chunks(p) && h->d_cmap)
+      HIP_TRY(launch_colsolve_chunk<float>(spec32, chunk_args(h, ws), bw, p.nt, p.nx, h->lqb, ctrl, part,
+                                           (p.nt + 1) / 2, wscale, hist, st, (double*)s0));
+    else
+      HIP_TRY((launch_colsolve_wave<float, double>(spec32, factab<double>(h), bw, p.nt, p.nx, h->lqb, ctrl, part,
+                                                   (p.nt + 1) / 2, wscale, hist, st, (double*)s0)));
     return PDHG_OK;
   }
   HIP_TRY(launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tau_phi, ctrl, st));
   HIP_TRY(launch_primal_res<T>(s, uin, uout, phibar, phi, tau_u, spec, h->lqb, h->d_tw, part, ctrl, st, &lam));
-  HIP_TRY(colsolve_any<T>(h, spec, ctrl, part, (p.nt + 1) / 2, hist, st));
+  HIP_TRY(colsolve_any<T>(h, ws, spec, ctrl, part, (p.nt + 1) / 2, hist, st));
   return PDHG_OK;
 }
 
@@ -1675,7 +1764,7 @@ int precond_impl(pdhg_handle* h, const T* r, T* s, hipStream_t st) {
     if (rc) return rc;
   }
   const WsLayout L = layout_for(h->prob, h->esz);
-  return precond_apply<T>(h, r, s, (T*)wsp(ws, L.spec0), st);
+  return precond_apply<T>(h, ws, r, s, (T*)wsp(ws, L.spec0), st);
 }
 
 template <typename T>
@@ -1758,6 +1847,10 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
           return launch_dual_fft<T, float>(spec32, p.nt, h->lqb, p.nx, h->d_tw32, phi, phibar, tp, nullptr, st,
                                            (const T*)wsp(ws, L.s0));
         case 1:
+          if (uses_chunks(p) && h->d_cmap)
+            return launch_colsolve_chunk<float>(spec32, chunk_args(h, ws), p.time == PDHG_BDF2 ? 2 : 1, p.nt, p.nx,
+                                                h->lqb, nullptr, nullptr, 0, 0.0, nullptr, st,
+                                                (double*)wsp(ws, L.s0));
           return launch_colsolve_wave<float, double>(spec32, factab<double>(h), p.time == PDHG_BDF2 ? 2 : 1, p.nt,
                                                       p.nx, h->lqb, nullptr, nullptr, 0, 0.0, nullptr, st,
                                                       (double*)wsp(ws, L.s0));
@@ -1767,7 +1860,7 @@ int time_kernel_impl(pdhg_handle* h, int kernel, int reps, double* ms, hipStream
     switch (kernel) {
       case 0: return launch_primal_res<T>(s, u, u_alt, phibar, phi, tu, spec, h->lqb, h->d_tw, prp, ctrl_t, st);
       case 7: return launch_dual_fft<T>(spec, p.nt, h->lqb, p.nx, h->d_tw, phi, phibar, tp, nullptr, st);
-      case 1: return colsolve_any<T>(h, spec, nullptr, nullptr, 0, nullptr, st);
+      case 1: return colsolve_any<T>(h, ws, spec, nullptr, nullptr, 0, nullptr, st);
       case 2: return launch_rows_inv<T>(spec, p.nt, h->lqb, srow, p.nt, p.nx, h->d_tw, nullptr, st);
       case 3: return launch_dual<T>(phi, phibar, srow, n, tp, nullptr, st);
       case 4: return launch_primal<T>(s, u, u_alt, phibar, phi, tu, prd, nullptr, st, nullptr);

@@ -16,6 +16,10 @@ emulations, which round where the GPU path rounds:
   GPU runs it: float FFTs along x, and the banded Cholesky recurrences along t
   in float, cut into per-lane segments whose affine maps are composed across
   the lanes (16 lanes per column up to N_t = 256, 32 up to 512, 64 beyond);
+  from N_t = 4097 on (N_x >= 16) the column solve runs in chunks of 256
+  levels: the slowly decaying low modes (``gpu_fp64_modes``) with FP64
+  recurrences rounded to float once, the others with float recurrences from
+  chunk states carried in FP64 (``chunked_solve``);
   for DG likewise: float FFTs over the cells, the per-mode eigenbasis rotation
   in float and one float segmented recurrence per eigen-branch.
 * ``segmented_solve``: that segmented recurrence on its own (any type), also
@@ -37,19 +41,27 @@ F32 = np.float32
 
 def cholesky_bands(prob):
     """Per mode k = 0..N_x/2: (1/L_ll, L_{l,l-1}, L_{l,l-2}) of the Cholesky factor of
-    B_t B_t^T + s_k I, as arrays (N_t, M) and (N_t + 2, M) (zero outside the matrix)."""
+    B_t B_t^T + s_k I, as arrays (N_t, M) and (N_t + 2, M) (zero outside the matrix); the factor
+    of the banded matrix in banded storage (LAPACK pbtrf)."""
+    import scipy.linalg as sla
     kt = opre.time_gram(prob)
     sh = opre.mode_shifts(prob)
     nt, m = prob.nt, prob.nx // 2 + 1
+    band = np.zeros((3, nt))   # lower banded storage: band[d, l] = K[l + d, l]
+    for d in range(3):
+        if d < nt:
+            band[d, :nt - d] = np.diagonal(kt, -d)
     invd = np.zeros((nt, m))
     e1 = np.zeros((nt + 2, m))
     e2 = np.zeros((nt + 2, m))
     for k in range(m):
-        L = np.linalg.cholesky(kt + sh[k] * np.eye(nt))
-        invd[:, k] = 1.0 / np.diag(L)
-        e1[1:nt, k] = np.diagonal(L, -1)
+        b = band.copy()
+        b[0] += sh[k]
+        lb = sla.cholesky_banded(b, lower=True)
+        invd[:, k] = 1.0 / lb[0]
+        e1[1:nt, k] = lb[1, :nt - 1]
         if nt > 2:
-            e2[2:nt, k] = np.diagonal(L, -2)
+            e2[2:nt, k] = lb[2, :nt - 2]
     return invd, e1, e2
 
 
@@ -100,14 +112,111 @@ def gpu_lanes_per_column(nt: int) -> int:
     return 16 if nt <= 256 else (32 if nt <= 512 else 64)
 
 
+CHUNK_LEVELS = 256
+
+
+def gpu_chunked_columns(nt: int, nx: int) -> bool:
+    """Whether the GPU's column solve runs in chunks."""
+    return nt >= 4097 and nx >= 16
+
+
+def gpu_fp64_modes(prob) -> int:
+    """Modes 0 .. k-1 whose chunked column solve the GPU runs in FP64 for a float spectrum: those of
+    the column blocks (8 modes each, block 0 with mode 0) before the first block whose lowest mode
+    has s_k h_t^2 >= 1e-2 (the shift against (1/h_t)^2: slower decay along t below it)."""
+    sh = opre.mode_shifts(prob)
+    ht = prob.t_final / prob.nt
+    for g in range(1, prob.nx // 16):
+        if sh[8 * g] * ht * ht >= 1e-2:
+            return 8 * g
+    return prob.nx // 2 + 1
+
+
+def chunked_solve(invd, e1, e2, b, dt):
+    """L L^T y = b along axis 0 for every column of b as the GPU's chunked column solve computes it
+    with recurrences in type dt: each chunk of CHUNK_LEVELS levels is solved from zero entering
+    states (forward state leaving it P, backward state leaving it R); the states entering every
+    chunk follow in FP64 from P, R and the chunk's maps (H, G: homogeneous responses over the
+    chunk; K: its backward solve of the forward homogeneous responses); each chunk is solved again
+    from its entering states, rounded to dt.  Forward, then backward within a chunk."""
+    nt, m = b.shape
+    nc = -(-nt // CHUNK_LEVELS)
+    f64 = np.float64
+    iv, f1, f2 = invd.astype(dt), e1.astype(dt), e2.astype(dt)
+    bb = b.astype(dt)
+
+    def solve(c, x2, x1, w2, w1):
+        s, e = c * CHUNK_LEVELS, min(nt, (c + 1) * CHUNK_LEVELS)
+        z = np.zeros((e - s, m), dt)
+        zm2, zm1 = x2.astype(dt), x1.astype(dt)
+        for l in range(s, e):
+            zz = iv[l] * (bb[l] - f1[l] * zm1 - f2[l] * zm2)
+            z[l - s] = zz
+            zm2, zm1 = zm1, zz
+        p = (zm2, zm1)
+        ym2, ym1 = w2.astype(dt), w1.astype(dt)
+        for l in range(e - 1, s - 1, -1):
+            yy = iv[l] * (z[l - s] - f1[l + 1] * ym1 - f2[l + 2] * ym2)
+            z[l - s] = yy
+            ym2, ym1 = ym1, yy
+        return z, p, (ym2, ym1)
+
+    zero = np.zeros(m, f64)
+    one = np.ones(m, f64)
+    rec = [solve(c, zero, zero, zero, zero)[1:] for c in range(nc)]
+    i8, g1, g2 = invd.astype(f64), e1.astype(f64), e2.astype(f64)
+    maps = []
+    for c in range(nc):
+        s, e = c * CHUNK_LEVELS, min(nt, (c + 1) * CHUNK_LEVELS)
+        a2, a1, b2, b1, u2, u1, v2, v1 = one, zero, zero, one, zero, zero, zero, zero
+        k = [zero, zero, zero, zero]
+        for l in range(s, e):
+            az = i8[l] * (-(g1[l] * a1) - g2[l] * a2)
+            bz = i8[l] * (-(g1[l] * b1) - g2[l] * b2)
+            uz = i8[l] * ((one if l == s else zero) - g1[l] * u1 - g2[l] * u2)
+            vz = i8[l] * ((one if l == s + 1 else zero) - g1[l] * v1 - g2[l] * v2)
+            a2, a1, b2, b1, u2, u1, v2, v1 = a1, az, b1, bz, u1, uz, v1, vz
+            k = [k[0] + vz * az, k[1] + vz * bz, k[2] + uz * az, k[3] + uz * bz]
+        hmap = (a2, b2, a1, b1)
+        a2, a1, b2, b1 = one, zero, zero, one
+        for l in range(e - 1, s - 1, -1):
+            az = i8[l] * (-(g1[l + 1] * a1) - g2[l + 2] * a2)
+            bz = i8[l] * (-(g1[l + 1] * b1) - g2[l + 2] * b2)
+            a2, a1, b2, b1 = a1, az, b1, bz
+        maps.append((hmap, (a2, b2, a1, b1), k))
+    t, h = [None] * nc, [None] * nc
+    t2 = t1 = zero
+    for c in range(nc):
+        t[c] = (t2, t1)
+        hm, p = maps[c][0], rec[c][0]
+        t2, t1 = (hm[0] * t2 + hm[1] * t1 + p[0].astype(f64), hm[2] * t2 + hm[3] * t1 + p[1].astype(f64))
+    h2 = h1 = zero
+    for c in range(nc - 1, -1, -1):
+        h[c] = (h2, h1)
+        gm, km, r = maps[c][1], maps[c][2], rec[c][1]
+        u2, u1 = t[c]
+        h2, h1 = (gm[0] * h2 + gm[1] * h1 + km[0] * u2 + km[1] * u1 + r[0].astype(f64),
+                  gm[2] * h2 + gm[3] * h1 + km[2] * u2 + km[3] * u1 + r[1].astype(f64))
+    return np.concatenate([solve(c, *t[c], *h[c])[0] for c in range(nc)])
+
+
 def kd_solve_fp32_fd(prob, bands, r32):
-    """K_d^{-1} r as the FP32 finite-difference path computes it (float FFTs, float segmented
-    recurrences, float spectrum)."""
+    """K_d^{-1} r as the FP32 finite-difference path computes it (float FFTs, float spectrum; float
+    segmented recurrences, or the chunked solve on long time axes)."""
     nx = prob.nx
     rh = np.fft.rfft(r32.astype(F32), axis=1).astype(np.complex64)
-    lanes = gpu_lanes_per_column(prob.nt)
-    re = segmented_solve(*bands, rh.real, lanes, F32)
-    im = segmented_solve(*bands, rh.imag, lanes, F32)
+    if gpu_chunked_columns(prob.nt, nx):
+        k64 = gpu_fp64_modes(prob)
+        lo = [x[:, :k64] for x in bands]
+        hi = [x[:, k64:] for x in bands]
+        re = np.concatenate([chunked_solve(*lo, rh.real[:, :k64], np.float64).astype(F32),
+                             chunked_solve(*hi, rh.real[:, k64:], F32)], axis=1)
+        im = np.concatenate([chunked_solve(*lo, rh.imag[:, :k64], np.float64).astype(F32),
+                             chunked_solve(*hi, rh.imag[:, k64:], F32)], axis=1)
+    else:
+        lanes = gpu_lanes_per_column(prob.nt)
+        re = segmented_solve(*bands, rh.real, lanes, F32)
+        im = segmented_solve(*bands, rh.imag, lanes, F32)
     sh = (re + 1j * im).astype(np.complex64)
     return np.fft.irfft(sh, n=nx, axis=1).astype(F32)
 

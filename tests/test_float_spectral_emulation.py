@@ -148,6 +148,26 @@ def test_emulation_without_rounding_is_the_oracle_solve():
     assert np.max(np.abs(s - ref)) < 1e-5 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("nt,time,ghat", [(1025, "be", 0.0), (1281, "bdf2", 0.0), (1999, "bdf2", 1e-3)])
+def test_chunked_solve_without_rounding_is_the_oracle_solve(nt, time, ghat):
+    """The chunked column solve of long time axes (chunks of 256 levels solved from zero, entering
+    states carried through the chunk maps H, G, K, every chunk solved again), in FP64, is the banded
+    solve of the oracle's K_d per mode: ragged last chunks (1025 = 4 x 256 + 1, 1281 = 5 x 256 + 1),
+    BE and BDF2, with and without the viscous term of the shift."""
+    from fp32_emulation import chunked_solve
+    prob = Problem(nx=32, nt=nt, t_final=nt / 256, time=time, precond_c=0.7, precond_gamma_hat=ghat)
+    factors = _factor(prob)
+    r = np.random.default_rng(nt).standard_normal((prob.nt, 3))
+    for k in (0, 1, 5, prob.nx // 2):
+        kt = opre.time_gram(prob) + opre.mode_shifts(prob)[k] * np.eye(prob.nt)
+        ab = np.zeros((3, prob.nt))
+        for d in range(3):
+            ab[2 - d, d:] = np.diagonal(kt, d)
+        ref = sla.solveh_banded(ab, r)
+        got = chunked_solve(*_bands(factors[k]), r, np.float64)
+        assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref)), k
+
+
 def test_segmented_float_recurrence_is_the_excess():
     """N_t = 900, BDF2: the segmented float recurrence loses several times more than the
     sequential one; with FP64 recurrences and FP64 mode 0 the iterates are inside 1e-5."""

@@ -131,10 +131,11 @@ def test_mixed_unsupported_combinations(gpu_lib):
         small.solve(_dev(syn.fourier_u0(0, 32)), max_iter=4)
 
 
-@pytest.mark.parametrize("nt,time", [(900, "bdf2"), (1500, "be")])
+@pytest.mark.parametrize("nt,time", [(900, "bdf2"), (1500, "be"), (4500, "bdf2")])
 def test_mixed_long_time_axis(gpu_lib, nt, time):
-    """The float column solve for 512 < N_t <= 1024 (one wavefront per column) and beyond (several
-    wavefronts per column): 10 iterations within the FP32 bar of the FP64 oracle.  The recurrences
+    """The float column solve for 512 < N_t <= 1024 (one wavefront per column), beyond (several
+    wavefronts per column) and beyond 4096 (the chunked solve: chunks of 256 levels, the entering
+    states carried through the chunk maps): 10 iterations within the FP32 bar of the FP64 oracle.  The recurrences
     run in FP64 on the float spectrum and mode 0 of s stays FP64 end to end: its rounding to float
     would be amplified up to N_t times by the time difference of the primal step (the CPU emulation
     in test_float_spectral_emulation.py shows both effects)."""
