@@ -522,10 +522,16 @@ __host__ __device__ constexpr int chunk_count(int nt) { return (nt + kChunkLevel
 // N_x >= 16).  Column blocks g < g64 (and every block where f32.rows is null)
 // run their recurrences in FP64 on f64, the others in float on f32; the maps
 // and the chunk states are FP64.
+// Past a mode's last distinct factor row every lane of a chunk sees the same
+// rows, so each lane's homogeneous segment map (kChunkLpl levels, the same
+// both ways) is one 2x2 matrix M per mode; the scans of such chunks use the
+// powers M^(2^s), s < kChunkPow.
+constexpr int kChunkPow = 4;
 struct ChunkArgs {
   FacTab<double> f64;
   FacTab<float> f32;
   const double* cmap;   // [N_x/2 + 1][nchunk][12]: H, G, K of every mode and chunk
+  const double* cpow;   // [N_x/2 + 1][kChunkPow][4]: M, M^2, M^4, M^8 of every mode (below)
   double* cwork;        // [2][nchunk][N_x][4]: pass-1 records (P, R), entering states (t, h)
   int nchunk;
   int g64;

@@ -206,7 +206,7 @@ k_colchunk_pass1(T* __restrict__ spec, ChunkArgs ca, int g0, int nt, int nx, Ctr
 }
 
 template <typename T, int BW, typename A>
-__global__ void __launch_bounds__(kChunkThreads)
+__global__ void __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_colchunk_pass2(T* __restrict__ spec, ChunkArgs ca, int g0, int nt, int nx, Ctrl* ctrl, double* s0) {
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
@@ -571,7 +571,8 @@ template <typename T, int BW>
 static hipError_t launch_colsolve_chunk_l(T* spec, const ChunkArgs& ca, int nt, int nx, Ctrl* ctrl,
                                           const double* part, int nparts, double wscale, double* hist,
                                           hipStream_t st, double* s0) {
-  const size_t lds = sizeof(T) * (size_t)kChunkCols * kChunkLpl * (kChunkCw + 1);
+  const size_t lds = sizeof(T) * (size_t)kChunkCols * kChunkLpl * (kChunkCw + 1) +
+                     sizeof(double) * kChunkCols * (kChunkPow + 1) * 4;   // the tile, the powers, the states
   const int nblocks = nx / kChunkCols;
   // column blocks [0, n64) in FP64, [n64, nblocks) in float (a float spectrum with float rows only)
   const int n64 = (sizeof(T) == 4 && ca.f32.rows) ? (ca.g64 < nblocks ? ca.g64 : nblocks) : nblocks;
@@ -612,7 +613,7 @@ hipError_t launch_colsolve_chunk(T* spec, const ChunkArgs& ca, int bw, int nt, i
                                  const double* part, int nparts, double wscale, double* hist, hipStream_t st,
                                  double* s0) {
   if (nt < kChunkMinNt || nx < kChunkCols || lqb != 4 || ca.nchunk != chunk_count(nt) || ca.nchunk > 32 ||
-      !ca.cmap || !ca.cwork || !ca.f64.rows)
+      !ca.cmap || !ca.cpow || !ca.cwork || !ca.f64.rows)
     return hipErrorInvalidValue;
   if (bw == 2) return launch_colsolve_chunk_l<T, 2>(spec, ca, nt, nx, ctrl, part, nparts, wscale, hist, st, s0);
   return launch_colsolve_chunk_l<T, 1>(spec, ca, nt, nx, ctrl, part, nparts, wscale, hist, st, s0);
@@ -621,6 +622,40 @@ template hipError_t launch_colsolve_chunk<float>(float*, const ChunkArgs&, int, 
                                                  int, double, double*, hipStream_t, double*);
 template hipError_t launch_colsolve_chunk<double>(double*, const ChunkArgs&, int, int, int, int, Ctrl*,
                                                   const double*, int, double, double*, hipStream_t, double*);
+
+// The segment map M of every mode past its last distinct factor row (one
+// thread per mode; kChunkLpl steps of the homogeneous recurrence on row
+// `last`, the layout of the scan's H) and its repeated squares.
+template <int BW>
+__global__ void __launch_bounds__(256)
+k_colchunk_powers(FacTab<double> fac, int nmodes, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nmodes) return;
+  const FacRow<double> r = fac.rows[fac.off[k] + fac.last[k]];
+  const double e2 = BW == 2 ? r.e2 : 0.0;
+  double a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+  for (int i = 0; i < kChunkLpl; ++i) {
+    const double az = r.invd * (-(r.e1 * a1) - e2 * a2);
+    const double bz = r.invd * (-(r.e1 * b1) - e2 * b2);
+    a2 = a1; a1 = az; b2 = b1; b1 = bz;
+  }
+  double m[4] = {a2, b2, a1, b1};
+  double* o = out + (size_t)k * kChunkPow * 4;
+  for (int s = 0; s < kChunkPow; ++s) {
+    for (int i = 0; i < 4; ++i) o[4 * s + i] = m[i];
+    const double s0 = m[0] * m[0] + m[1] * m[2], s1 = m[0] * m[1] + m[1] * m[3];
+    const double s2 = m[2] * m[0] + m[3] * m[2], s3 = m[2] * m[1] + m[3] * m[3];
+    m[0] = s0; m[1] = s1; m[2] = s2; m[3] = s3;
+  }
+}
+
+hipError_t launch_colchunk_powers(const FacTab<double>& fac, int bw, int nmodes, double* out, hipStream_t st) {
+  if (bw == 2)
+    hipLaunchKernelGGL(k_colchunk_powers<2>, dim3((nmodes + 255) / 256), dim3(256), 0, st, fac, nmodes, out);
+  else
+    hipLaunchKernelGGL(k_colchunk_powers<1>, dim3((nmodes + 255) / 256), dim3(256), 0, st, fac, nmodes, out);
+  return hipGetLastError();
+}
 
 template <typename A>
 hipError_t launch_colchunk_maps(const FacTab<A>& fac, int bw, int nt, int nmodes, A* out, hipStream_t st) {

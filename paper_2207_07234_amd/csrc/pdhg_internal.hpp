@@ -81,6 +81,9 @@ hipError_t launch_colsolve_wave(T* spec, const FacTab<A>& fac, int bw, int nt, i
 // nmodes = N_x/2 + 1): out [nmodes][chunk_count(nt)][12].
 template <typename A>
 hipError_t launch_colchunk_maps(const FacTab<A>& fac, int bw, int nt, int nmodes, A* out, hipStream_t st);
+// The constant-row segment map of every mode and its squares (ChunkArgs::cpow):
+// out [nmodes][kChunkPow][4].
+hipError_t launch_colchunk_powers(const FacTab<double>& fac, int bw, int nmodes, double* out, hipStream_t st);
 // The chunked column solve (N_t >= kChunkMinNt, N_x >= 16); s0 as for
 // launch_colsolve_wave, in FP64.
 template <typename T>

@@ -997,6 +997,84 @@ __device__ __forceinline__ void scan_half_from(T* H, T* P, int lane, T x2, T x1,
   in1 = E[2] * x2 + E[3] * x1 + F[1];
 }
 
+// Row-local inclusive scan of the particular parts P of lane maps that all
+// share the homogeneous part M (rows of 16 lanes, forward from the row's first
+// lane or backward from its last): at distance d = 2^s a lane that spans d
+// lanes takes in the lane d before (after) it, P += M^d P'.  pw: M^(2^s),
+// s = 0..3, 4 values each (the layout of the scan's H).
+// Entries of a block's LDS table at p + o, read where they are used: the
+// offset is hidden from the compiler so that it neither hoists the reads nor
+// keeps the values in registers across the scans.
+template <typename A>
+__device__ __forceinline__ const A* lds_at(const A* p, int o) {
+  asm volatile("" : "+v"(o));
+  return p + o;
+}
+
+template <typename A, bool FWD>
+__device__ __forceinline__ void pow_scan_row(A* P, const A* pw) {
+  auto step = [&](auto dd) __attribute__((always_inline)) {
+    constexpr int S = decltype(dd)::value;
+    constexpr int CTRL = FWD ? (0x110 + (1 << S)) : (0x100 + (1 << S));
+    const A* m = lds_at(pw, 4 * S);
+    const A q2 = dpp_move<CTRL>(P[0], A(0)), q1 = dpp_move<CTRL>(P[1], A(0));
+    P[0] += m[0] * q2 + m[1] * q1;
+    P[1] += m[2] * q2 + m[3] * q1;
+  };
+  step(std::integral_constant<int, 0>{});
+  step(std::integral_constant<int, 1>{});
+  step(std::integral_constant<int, 2>{});
+  step(std::integral_constant<int, 3>{});
+}
+
+// scan_half_from for a column (32 lanes) whose lane maps all have the
+// homogeneous part M: the row scan of P, then each second row (forward: lanes
+// 16..31; backward: lanes 0..15) adds M^s S, S the total of the row it
+// follows and s the lanes it spans, as a second row scan started from M S in
+// its first lane.  The entering state x is folded into the first lane's P
+// (M x), so no prefix powers are needed: the state entering lane q is the
+// inclusive P of the lane before it, x for the first lane.
+template <typename A, bool FWD>
+__device__ __forceinline__ void scan_half_const(A* P, const A* pw, int lane, A x2, A x1, bool fold, A& in2,
+                                                A& in1) {
+  const int q = lane & 31, r = lane & 15, row = lane >> 4;
+  const bool first = FWD ? q == 0 : q == 31;
+  if (fold && first) {
+    const A* m = lds_at(pw, 0);
+    P[0] += m[0] * x2 + m[1] * x1;
+    P[1] += m[2] * x2 + m[3] * x1;
+  }
+  pow_scan_row<A, FWD>(P, pw);
+  {
+    const int sa = FWD ? 15 : 16, sb = FWD ? 47 : 48;   // the first row's total, per column
+    const A a2 = read_lane(P[0], sa), a1 = read_lane(P[1], sa);
+    const A b2 = read_lane(P[0], sb), b1 = read_lane(P[1], sb);
+    const bool second = (row & 1) == (FWD ? 1 : 0);
+    const bool head = second && r == (FWD ? 0 : 15);
+    const A s2 = row < 2 ? a2 : b2, s1 = row < 2 ? a1 : b1;
+    A D[2] = {A(0), A(0)};
+    if (head) {
+      const A* m = lds_at(pw, 0);
+      D[0] = m[0] * s2 + m[1] * s1;
+      D[1] = m[2] * s2 + m[3] * s1;
+    }
+    pow_scan_row<A, FWD>(D, pw);
+    P[0] += D[0];
+    P[1] += D[1];
+  }
+  if (FWD) {
+    in2 = from_lane_below(P[0], A(0));
+    in1 = from_lane_below(P[1], A(0));
+  } else {
+    in2 = from_lane_above(P[0], A(0));
+    in1 = from_lane_above(P[1], A(0));
+  }
+  if (first) {
+    in2 = x2;
+    in1 = x1;
+  }
+}
+
 // One tile of the chunked solve: kChunkCols columns x kChunkLevels levels of
 // column block g from level ls, contiguous in the spectrum (QB = kChunkCols),
 // moved in 16-byte pieces; levels at or past nt read as zero and are not
@@ -1056,18 +1134,15 @@ struct ChunkTile {
 // (reads the entering states from ca.cwork[1][c] and writes the solution back
 // into the tile).
 // A lane's share of a tile: column j of the tile, levels l0 .. l0 + kChunkLpl
-// - 1, its factor rows and (pass 2) the states entering the chunk.  lookup()
-// issues the loads of the mode's row offset and of the entering states,
-// load_rows() those of the rows: the tile's loads go in between, so that all
-// of them are in flight together (a wait for a load also waits for every
-// load issued before it).
+// - 1, and its factor rows.  lookup() issues the loads of the mode's row
+// offset, load_rows() those of the rows: the tile's loads go in between, so
+// that all of them are in flight together (a wait for a load also waits for
+// every load issued before it).
 template <typename A>
 struct ChunkLane {
   int col, q, j, l0, off, last;
   A invd[kChunkLpl], e1[kChunkLpl + 1], e2[kChunkLpl + 2];
-  A x2 = A(0), x1 = A(0), w2 = A(0), w1 = A(0);   // entering states: forward, backward
-  __device__ __forceinline__ void lookup(const FacTab<A>& fac, const ChunkArgs& ca, int nx, int g, int c,
-                                         bool solve) {
+  __device__ __forceinline__ void lookup(const FacTab<A>& fac, int nx, int g, int c) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     col = wv * (64 / kChunkCw) + lane / kChunkCw;
     q = lane % kChunkCw;
@@ -1076,10 +1151,6 @@ struct ChunkLane {
     const int k = spec_mode(j, nx);
     off = fac.off[k];
     last = fac.last[k];
-    if (solve) {
-      const double* cin = ca.cwork + ((size_t)(ca.nchunk + c) * nx + j) * 4;
-      x2 = A(cin[0]); x1 = A(cin[1]); w2 = A(cin[2]); w1 = A(cin[3]);
-    }
   }
   __device__ __forceinline__ void load_rows(const FacTab<A>& fac) {
     const FacRow<A>* rows = fac.rows + off;
@@ -1098,32 +1169,51 @@ struct ChunkLane {
 
 template <typename T, int BW, typename A, bool SOLVE>
 __device__ __forceinline__ void colchunk_tile(const ChunkLane<A>& ln, const ChunkArgs& ca, int nt, int nx, int c,
-                                              T* tile, double* __restrict__ s0) {
+                                              T* tile, const A* pw, const A* st, double* __restrict__ s0) {
   constexpr int LPL = kChunkLpl, CW = kChunkCw, TS = CW + 1;
   const int lane = threadIdx.x & 63;
   const int col = ln.col, q = ln.q, j = ln.j, l0 = ln.l0;
   const A* invd = ln.invd;
   const A* e1 = ln.e1;
   const A* e2 = ln.e2;
-  const A x2 = ln.x2, x1 = ln.x1, w2 = ln.w2, w1 = ln.w1;
   A z[LPL];
 #pragma unroll
   for (int i = 0; i < LPL; ++i) z[i] = A(tile[(col * LPL + i) * TS + q]);
+  // a full chunk past the mode's last distinct factor row (the same for the whole column): every lane map
+  // has the homogeneous part M, whose powers come from the block's table
+  const bool cst = c * kChunkLevels >= ln.last && (c + 1) * kChunkLevels <= nt;
   // forward: z_l = invd_l (r_l - e1_l z_{l-1} - e2_l z_{l-2})
   {
-    A p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
-#pragma unroll
-    for (int i = 0; i < LPL; ++i) {
-      if (l0 + i < nt) {
-        const A pz = invd[i] * (z[i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : A(0)));
-        const A az = invd[i] * (-(e1[i] * a1) - (BW == 2 ? e2[i] * a2 : A(0)));
-        const A bz = invd[i] * (-(e1[i] * b1) - (BW == 2 ? e2[i] * b2 : A(0)));
-        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
-      }
+    A P[2], zm2, zm1, x2 = A(0), x1 = A(0);
+    if (SOLVE) {   // the state entering the chunk, read from the block's copy where it is needed
+      const A* x = lds_at(st, 0);
+      x2 = x[0];
+      x1 = x[1];
     }
-    A H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
-    A zm2, zm1;
-    scan_half_from<A, true>(H, P, lane, x2, x1, zm2, zm1);
+    if (cst) {
+      A p2 = 0, p1 = 0;
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        const A pz = invd[i] * (z[i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : A(0)));
+        p2 = p1; p1 = pz;
+      }
+      P[0] = p2; P[1] = p1;
+      scan_half_const<A, true>(P, pw, lane, x2, x1, SOLVE, zm2, zm1);
+    } else {
+      A p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        if (l0 + i < nt) {
+          const A pz = invd[i] * (z[i] - e1[i] * p1 - (BW == 2 ? e2[i] * p2 : A(0)));
+          const A az = invd[i] * (-(e1[i] * a1) - (BW == 2 ? e2[i] * a2 : A(0)));
+          const A bz = invd[i] * (-(e1[i] * b1) - (BW == 2 ? e2[i] * b2 : A(0)));
+          p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+        }
+      }
+      A H[4] = {a2, b2, a1, b1};
+      P[0] = p2; P[1] = p1;
+      scan_half_from<A, true>(H, P, lane, x2, x1, zm2, zm1);
+    }
     if (!SOLVE && q == CW - 1) {   // state leaving the chunk (from zero)
       double* rec = ca.cwork + ((size_t)c * nx + j) * 4;
       rec[0] = double(P[0]);
@@ -1140,21 +1230,40 @@ __device__ __forceinline__ void colchunk_tile(const ChunkLane<A>& ln, const Chun
   }
   // backward: y_l = invd_l (z_l - e1_{l+1} y_{l+1} - e2_{l+2} y_{l+2})
   {
-    A p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+    A P[2], ym2, ym1, w2 = A(0), w1 = A(0);
+    if (SOLVE) {
+      const A* w = lds_at(st, 2);
+      w2 = w[0];
+      w1 = w[1];
+    }
+    if (cst) {
+      A p2 = 0, p1 = 0;
 #pragma unroll
-    for (int ii = 0; ii < LPL; ++ii) {
-      const int i = LPL - 1 - ii;
-      if (l0 + i < nt) {
+      for (int ii = 0; ii < LPL; ++ii) {
+        const int i = LPL - 1 - ii;
         const A f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : A(0);
         const A pz = invd[i] * (z[i] - f1 * p1 - f2 * p2);
-        const A az = invd[i] * (-(f1 * a1) - f2 * a2);
-        const A bz = invd[i] * (-(f1 * b1) - f2 * b2);
-        p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+        p2 = p1; p1 = pz;
       }
+      P[0] = p2; P[1] = p1;
+      scan_half_const<A, false>(P, pw, lane, w2, w1, SOLVE, ym2, ym1);
+    } else {
+      A p2 = 0, p1 = 0, a2 = 1, a1 = 0, b2 = 0, b1 = 1;
+#pragma unroll
+      for (int ii = 0; ii < LPL; ++ii) {
+        const int i = LPL - 1 - ii;
+        if (l0 + i < nt) {
+          const A f1 = e1[i + 1], f2 = (BW == 2) ? e2[i + 2] : A(0);
+          const A pz = invd[i] * (z[i] - f1 * p1 - f2 * p2);
+          const A az = invd[i] * (-(f1 * a1) - f2 * a2);
+          const A bz = invd[i] * (-(f1 * b1) - f2 * b2);
+          p2 = p1; p1 = pz; a2 = a1; a1 = az; b2 = b1; b1 = bz;
+        }
+      }
+      A H[4] = {a2, b2, a1, b1};
+      P[0] = p2; P[1] = p1;
+      scan_half_from<A, false>(H, P, lane, w2, w1, ym2, ym1);
     }
-    A H[4] = {a2, b2, a1, b1}, P[2] = {p2, p1};
-    A ym2, ym1;
-    scan_half_from<A, false>(H, P, lane, w2, w1, ym2, ym1);
     if (!SOLVE) {
       if (q == 0) {   // state leaving the chunk backwards (forward values from zero)
         double* rec = ca.cwork + ((size_t)c * nx + j) * 4;
@@ -1191,13 +1300,27 @@ template <typename T, int BW, typename A, bool SOLVE>
 __device__ __forceinline__ void colchunk_item(T* __restrict__ spec, const FacTab<A>& fac, const ChunkArgs& ca,
                                               int nt, int nx, int g, int c, T* tile, double* __restrict__ s0) {
   ChunkLane<A> ln;
-  ln.lookup(fac, ca, nx, g, c, SOLVE);
+  ln.lookup(fac, nx, g, c);
   ChunkTile<T> buf;
   buf.load(spec, nt, g, c * kChunkLevels);
+  // the power table of the block's columns, after the tile in LDS: [kChunkCols][kChunkPow][4] (every thread
+  // loads, the first kChunkCols * kChunkPow * 4 store)
+  constexpr int NPW = kChunkCols * kChunkPow * 4;
+  static_assert(NPW <= kChunkThreads, "one power entry per thread");
+  A* pwl = reinterpret_cast<A*>(tile + kChunkCols * kChunkLpl * (kChunkCw + 1));
+  const int pe = threadIdx.x % NPW;
+  const double pv = ca.cpow[(size_t)spec_mode(g * kChunkCols + pe / (kChunkPow * 4), nx) * (kChunkPow * 4) +
+                            pe % (kChunkPow * 4)];
+  // pass 2: the states entering the chunk (t, h) of the block's columns, after the powers: [kChunkCols][4]
+  A* stl = pwl + NPW;
+  const double sv = SOLVE ? ca.cwork[((size_t)(ca.nchunk + c) * nx + g * kChunkCols) * 4 + threadIdx.x % (4 * kChunkCols)]
+                          : 0.0;
   ln.load_rows(fac);
   buf.to_lds(tile);
+  if (threadIdx.x < NPW) pwl[threadIdx.x] = A(pv);
+  if (SOLVE && threadIdx.x < 4 * kChunkCols) stl[threadIdx.x] = A(sv);
   __syncthreads();
-  colchunk_tile<T, BW, A, SOLVE>(ln, ca, nt, nx, c, tile, s0);
+  colchunk_tile<T, BW, A, SOLVE>(ln, ca, nt, nx, c, tile, pwl + ln.col * (kChunkPow * 4), stl + ln.col * 4, s0);
   if (SOLVE) {
     __syncthreads();
     ChunkTile<T>::store_from_lds(tile, spec, nt, g, c * kChunkLevels);

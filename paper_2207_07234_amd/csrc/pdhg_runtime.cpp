@@ -289,6 +289,7 @@ struct pdhg_handle {
   // chunked column solve (always FP64 arithmetic): per-mode, per-chunk maps, and for FP32 problems an
   // FP64 copy of the factor table
   double* d_cmap = nullptr;
+  double* d_cpow = nullptr;
   int chunk_g64 = 0;            // column blocks below it run in FP64 when the spectrum is float
   void* d_f64_rows = nullptr;
   int* d_f64_off = nullptr;
@@ -463,10 +464,12 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
   HIP_TRY(hipMemcpy(h->d_fac_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_fac_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
   if (h->d_cmap) hipFree(h->d_cmap);
+  if (h->d_cpow) hipFree(h->d_cpow);
   if (h->d_f64_rows) hipFree(h->d_f64_rows);
   if (h->d_f64_off) hipFree(h->d_f64_off);
   if (h->d_f64_last) hipFree(h->d_f64_last);
   h->d_cmap = nullptr;
+  h->d_cpow = nullptr;
   h->d_f64_rows = nullptr;
   h->d_f64_off = h->d_f64_last = nullptr;
   if (uses_chunks(h->prob)) {   // the chunked column solve: FP64 rows and their maps
@@ -486,6 +489,8 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
     HIP_TRY(hipMalloc((void**)&h->d_cmap, sizeof(double) * 12 * (size_t)nmodes * chunk_count(h->prob.nt)));
     HIP_TRY(launch_colchunk_maps<double>(chunk_rows(h), h->prob.time == PDHG_BDF2 ? 2 : 1, h->prob.nt, nmodes,
                                          h->d_cmap, nullptr));
+    HIP_TRY(hipMalloc((void**)&h->d_cpow, sizeof(double) * 4 * kChunkPow * (size_t)nmodes));
+    HIP_TRY(launch_colchunk_powers(chunk_rows(h), h->prob.time == PDHG_BDF2 ? 2 : 1, nmodes, h->d_cpow, nullptr));
     HIP_TRY(hipStreamSynchronize(nullptr));
   }
   h->fac_c = c;
@@ -657,6 +662,7 @@ ChunkArgs chunk_args(const pdhg_handle* h, void* ws) {
   a.f64 = chunk_rows(h);
   if (h->prob.dtype == PDHG_F32) a.f32 = factab<float>(h);
   a.cmap = h->d_cmap;
+  a.cpow = h->d_cpow;
   a.cwork = (double*)wsp(ws, layout_for(h->prob, h->esz).colchunk);
   a.nchunk = chunk_count(h->prob.nt);
   a.g64 = h->chunk_g64;
@@ -986,6 +992,7 @@ void pdhg_destroy(pdhg_handle* h) {
   if (h->d_fac_off) hipFree(h->d_fac_off);
   if (h->d_fac_last) hipFree(h->d_fac_last);
   if (h->d_cmap) hipFree(h->d_cmap);
+  if (h->d_cpow) hipFree(h->d_cpow);
   if (h->d_f64_rows) hipFree(h->d_f64_rows);
   if (h->d_f64_off) hipFree(h->d_f64_off);
   if (h->d_f64_last) hipFree(h->d_f64_last);
