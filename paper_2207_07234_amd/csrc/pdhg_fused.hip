@@ -163,8 +163,9 @@ k_colsolve_quarter(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb,
 }
 
 // C for 1024 < N_t <= 8192: WPC waves per column, 8 / WPC columns per block.
+// Float recurrences are held to 128 VGPRs, so that two blocks share a CU.
 template <typename T, int BW, int WPC, typename A>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(A) == 4 ? 4 : 1)))
 k_colsolve_long(T* __restrict__ spec, FacTab<A> fac, int nt, int nx, int lqb, Ctrl* ctrl, const double* part,
                 int nparts, double wscale, double* hist, A* s0) {
   if (ctrl && ctrl->status != 0) return;

@@ -997,11 +997,6 @@ __device__ __forceinline__ void scan_half_from(T* H, T* P, int lane, T x2, T x1,
   in1 = E[2] * x2 + E[3] * x1 + F[1];
 }
 
-// Row-local inclusive scan of the particular parts P of lane maps that all
-// share the homogeneous part M (rows of 16 lanes, forward from the row's first
-// lane or backward from its last): at distance d = 2^s a lane that spans d
-// lanes takes in the lane d before (after) it, P += M^d P'.  pw: M^(2^s),
-// s = 0..3, 4 values each (the layout of the scan's H).
 // Entries of a block's LDS table at p + o, read where they are used: the
 // offset is hidden from the compiler so that it neither hoists the reads nor
 // keeps the values in registers across the scans.
@@ -1011,6 +1006,11 @@ __device__ __forceinline__ const A* lds_at(const A* p, int o) {
   return p + o;
 }
 
+// Row-local inclusive scan of the particular parts P of lane maps that all
+// share the homogeneous part M (rows of 16 lanes, forward from the row's first
+// lane or backward from its last): at distance d = 2^s a lane that spans d
+// lanes takes in the lane d before (after) it, P += M^d P'.  pw: M^(2^s),
+// s = 0..3, 4 values each (the layout of the scan's H).
 template <typename A, bool FWD>
 __device__ __forceinline__ void pow_scan_row(A* P, const A* pw) {
   auto step = [&](auto dd) __attribute__((always_inline)) {

@@ -44,7 +44,8 @@ def _err(gpu, ref, name=""):
     (16, 1025, "be", 1.0, 0.0), (8, 2048, "bdf2", 0.7, 0.0), (32, 1999, "bdf2", 0.9, 1e-3),
     (16, 3000, "be", 0.5, 0.0), (64, 4096, "bdf2", 1.0, 0.0), (8, 5003, "bdf2", 0.3, 0.0),
     (16, 8192, "be", 1.0, 0.0), (8, 8192, "bdf2", 0.95, 0.0), (64, 4097, "bdf2", 1.0, 0.0),
-    (32, 4500, "bdf2", 0.9, 1e-3), (16, 6001, "be", 0.7, 0.0), (32, 4352, "bdf2", 1.0, 0.0)])
+    (32, 4500, "bdf2", 0.9, 1e-3), (16, 6001, "be", 0.7, 0.0), (32, 4352, "bdf2", 1.0, 0.0),
+    (256, 2048, "bdf2", 1.0, 0.0), (512, 3000, "be", 0.7, 0.0), (128, 4096, "bdf2", 0.9, 1e-3)])
 def test_precond_long_columns_match_oracle(gpu_lib, dtype, nx, nt, time, c, ghat):
     _say(f"precond long nx={nx} nt={nt} {time} c={c} ghat={ghat} {dtype}")
     pk = gpu_lib
