@@ -533,6 +533,13 @@ struct ChunkArgs {
   const double* cmap;   // [N_x/2 + 1][nchunk][12]: H, G, K of every mode and chunk
   const double* cpow;   // [N_x/2 + 1][kChunkPow][4]: M, M^2, M^4, M^8 of every mode (below)
   double* cwork;        // [2][nchunk][N_x][4]: pass-1 records (P, R), entering states (t, h)
+  // tiles (g nchunk + c) of the four grids of either pass, in this order: FP64 recurrences with general
+  // rows, FP64 with constant rows, float general, float constant (constant: for every column of the tile
+  // the chunk is full and lies past the last distinct row of the table it uses); tile[k] starts at
+  // tiles + toff[k] and holds ntile[k] entries
+  const int* tiles;
+  int toff[4];
+  int ntile[4];
   int nchunk;
   int g64;
 };

@@ -190,30 +190,32 @@ __device__ __forceinline__ const FacTab<double>& chunk_fac<double>(const ChunkAr
 template <>
 __device__ __forceinline__ const FacTab<float>& chunk_fac<float>(const ChunkArgs& ca) { return ca.f32; }
 
-// Grids over the tiles of column blocks g0 .. g0 + gridDim.x / nchunk - 1,
-// one tile per block, arithmetic type A (the launcher runs the FP64 and the
-// float column blocks of a float spectrum as separate grids, so that each has
-// its own register budget).
-template <typename T, int BW, typename A>
+// Grids over a list of tiles (g nchunk + c), one tile per block, arithmetic
+// type A; CST grids hold the tiles past every column's last distinct factor
+// row.  The launcher runs FP64 and float recurrences, general and constant
+// tiles as separate grids, so that each has its own register budget (a
+// constant tile needs one factor row per lane instead of kChunkLpl + 2).
+template <typename T, int BW, typename A, bool CST>
 __global__ void __launch_bounds__(kChunkThreads)
-k_colchunk_pass1(T* __restrict__ spec, ChunkArgs ca, int g0, int nt, int nx, Ctrl* ctrl, const double* part,
-                 int nparts, double wscale, double* hist) {
+k_colchunk_pass1(T* __restrict__ spec, ChunkArgs ca, const int* __restrict__ tiles, int nt, int nx, Ctrl* ctrl,
+                 const double* part, int nparts, double wscale, double* hist) {
   if (ctrl && ctrl->status != 0) return;
   if (part && blockIdx.x == 0 && threadIdx.x < 64) finalize_wave(ctrl, part, nparts, nparts, wscale, hist);
   extern __shared__ char smem[];
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  colchunk_item<T, BW, A, false>(spec, chunk_fac<A>(ca), ca, nt, nx, g0 + b / ca.nchunk, b % ca.nchunk,
-                                 reinterpret_cast<T*>(smem), nullptr);
+  const int tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  colchunk_item<T, BW, A, false, CST>(spec, chunk_fac<A>(ca), ca, nt, nx, tl / ca.nchunk, tl % ca.nchunk,
+                                      reinterpret_cast<T*>(smem), nullptr);
 }
 
-template <typename T, int BW, typename A>
-__global__ void __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(4)))
-k_colchunk_pass2(T* __restrict__ spec, ChunkArgs ca, int g0, int nt, int nx, Ctrl* ctrl, double* s0) {
+template <typename T, int BW, typename A, bool CST>
+__global__ void __launch_bounds__(kChunkThreads)
+k_colchunk_pass2(T* __restrict__ spec, ChunkArgs ca, const int* __restrict__ tiles, int nt, int nx, Ctrl* ctrl,
+                 double* s0) {
   if (ctrl && ctrl->status != 0) return;
   extern __shared__ char smem[];
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  colchunk_item<T, BW, A, true>(spec, chunk_fac<A>(ca), ca, nt, nx, g0 + b / ca.nchunk, b % ca.nchunk,
-                                reinterpret_cast<T*>(smem), s0);
+  const int tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  colchunk_item<T, BW, A, true, CST>(spec, chunk_fac<A>(ca), ca, nt, nx, tl / ca.nchunk, tl % ca.nchunk,
+                                     reinterpret_cast<T*>(smem), s0);
 }
 
 // Entering states of every chunk: one 32-lane group per column, lane c for
@@ -574,34 +576,40 @@ static hipError_t launch_colsolve_chunk_l(T* spec, const ChunkArgs& ca, int nt, 
                                           hipStream_t st, double* s0) {
   const size_t lds = sizeof(T) * (size_t)kChunkCols * kChunkLpl * (kChunkCw + 1) +
                      sizeof(double) * kChunkCols * (kChunkPow + 1) * 4;   // the tile, the powers, the states
-  const int nblocks = nx / kChunkCols;
-  // column blocks [0, n64) in FP64, [n64, nblocks) in float (a float spectrum with float rows only)
-  const int n64 = (sizeof(T) == 4 && ca.f32.rows) ? (ca.g64 < nblocks ? ca.g64 : nblocks) : nblocks;
-  const int i64 = n64 * ca.nchunk, i32 = (nblocks - n64) * ca.nchunk;   // tiles of either grid
-  hipError_t e = allow_lds(k_colchunk_pass1<T, BW, double>, lds);
-  if (e == hipSuccess) e = allow_lds(k_colchunk_pass2<T, BW, double>, lds);
-  if (e != hipSuccess) return e;
-  // the grid holding block 0 reduces the partial sums
-  if (i64 > 0)
-    hipLaunchKernelGGL((k_colchunk_pass1<T, BW, double>), dim3(i64), dim3(kChunkThreads), lds, st, spec, ca, 0, nt,
-                       nx, ctrl, part, nparts, wscale, hist);
+  // the four grids of a pass, in order: FP64 general, FP64 constant, float general, float constant (the float
+  // grids only for a float spectrum); the first grid launched reduces the partial sums
+  auto pass1 = [&](auto tg, auto cg, int k) -> hipError_t {
+    using A = decltype(tg);
+    constexpr bool CST = decltype(cg)::value;
+    if (ca.ntile[k] == 0) return hipSuccess;
+    hipError_t r = allow_lds(k_colchunk_pass1<T, BW, A, CST>, lds);
+    if (r != hipSuccess) return r;
+    hipLaunchKernelGGL((k_colchunk_pass1<T, BW, A, CST>), dim3(ca.ntile[k]), dim3(kChunkThreads), lds, st, spec, ca,
+                       ca.tiles + ca.toff[k], nt, nx, ctrl, part, nparts, wscale, hist);
+    part = nullptr;
+    return hipGetLastError();
+  };
+  auto pass2 = [&](auto tg, auto cg, int k) -> hipError_t {
+    using A = decltype(tg);
+    constexpr bool CST = decltype(cg)::value;
+    if (ca.ntile[k] == 0) return hipSuccess;
+    hipError_t r = allow_lds(k_colchunk_pass2<T, BW, A, CST>, lds);
+    if (r != hipSuccess) return r;
+    hipLaunchKernelGGL((k_colchunk_pass2<T, BW, A, CST>), dim3(ca.ntile[k]), dim3(kChunkThreads), lds, st, spec, ca,
+                       ca.tiles + ca.toff[k], nt, nx, ctrl, s0);
+    return hipGetLastError();
+  };
+  using F = std::false_type;
+  using Tr = std::true_type;
+  hipError_t e;
+  if ((e = pass1(0.0, F{}, 0)) != hipSuccess || (e = pass1(0.0, Tr{}, 1)) != hipSuccess) return e;
   if constexpr (sizeof(T) == 4) {
-    if (i32 > 0) {
-      if ((e = allow_lds(k_colchunk_pass1<T, BW, float>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_colchunk_pass1<T, BW, float>), dim3(i32), dim3(kChunkThreads), lds, st, spec, ca, n64,
-                         nt, nx, ctrl, i64 > 0 ? nullptr : part, nparts, wscale, hist);
-    }
+    if ((e = pass1(0.0f, F{}, 2)) != hipSuccess || (e = pass1(0.0f, Tr{}, 3)) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_colchunk_carry, dim3((nx + 7) / 8), dim3(kChunkCarryThreads), 0, st, ca, nx, ctrl);
-  if (i64 > 0)
-    hipLaunchKernelGGL((k_colchunk_pass2<T, BW, double>), dim3(i64), dim3(kChunkThreads), lds, st, spec, ca, 0, nt,
-                       nx, ctrl, s0);
+  if ((e = pass2(0.0, F{}, 0)) != hipSuccess || (e = pass2(0.0, Tr{}, 1)) != hipSuccess) return e;
   if constexpr (sizeof(T) == 4) {
-    if (i32 > 0) {
-      if ((e = allow_lds(k_colchunk_pass2<T, BW, float>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_colchunk_pass2<T, BW, float>), dim3(i32), dim3(kChunkThreads), lds, st, spec, ca, n64,
-                         nt, nx, ctrl, s0);
-    }
+    if ((e = pass2(0.0f, F{}, 2)) != hipSuccess || (e = pass2(0.0f, Tr{}, 3)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -614,7 +622,9 @@ hipError_t launch_colsolve_chunk(T* spec, const ChunkArgs& ca, int bw, int nt, i
                                  const double* part, int nparts, double wscale, double* hist, hipStream_t st,
                                  double* s0) {
   if (nt < kChunkMinNt || nx < kChunkCols || lqb != 4 || ca.nchunk != chunk_count(nt) || ca.nchunk > 32 ||
-      !ca.cmap || !ca.cpow || !ca.cwork || !ca.f64.rows)
+      !ca.cmap || !ca.cpow || !ca.cwork || !ca.f64.rows || !ca.tiles ||
+      ca.ntile[0] + ca.ntile[1] + ca.ntile[2] + ca.ntile[3] != (nx / kChunkCols) * ca.nchunk ||
+      (sizeof(T) == 8 && ca.ntile[2] + ca.ntile[3] != 0))
     return hipErrorInvalidValue;
   if (bw == 2) return launch_colsolve_chunk_l<T, 2>(spec, ca, nt, nx, ctrl, part, nparts, wscale, hist, st, s0);
   return launch_colsolve_chunk_l<T, 1>(spec, ca, nt, nx, ctrl, part, nparts, wscale, hist, st, s0);

@@ -1165,9 +1165,22 @@ struct ChunkLane {
     e2[kChunkLpl] = rows[min(l0 + kChunkLpl, last)].e2;
     e2[kChunkLpl + 1] = rows[min(l0 + kChunkLpl + 1, last)].e2;
   }
+  // a tile past the last distinct row: every level uses row `last`
+  __device__ __forceinline__ void load_row_last(const FacTab<A>& fac) {
+    const FacRow<A> fr = fac.rows[off + last];
+#pragma unroll
+    for (int i = 0; i < kChunkLpl; ++i) {
+      invd[i] = fr.invd;
+      e1[i] = fr.e1;
+      e2[i] = fr.e2;
+    }
+    e1[kChunkLpl] = fr.e1;
+    e2[kChunkLpl] = fr.e2;
+    e2[kChunkLpl + 1] = fr.e2;
+  }
 };
 
-template <typename T, int BW, typename A, bool SOLVE>
+template <typename T, int BW, typename A, bool SOLVE, bool CST>
 __device__ __forceinline__ void colchunk_tile(const ChunkLane<A>& ln, const ChunkArgs& ca, int nt, int nx, int c,
                                               T* tile, const A* pw, const A* st, double* __restrict__ s0) {
   constexpr int LPL = kChunkLpl, CW = kChunkCw, TS = CW + 1;
@@ -1179,9 +1192,9 @@ __device__ __forceinline__ void colchunk_tile(const ChunkLane<A>& ln, const Chun
   A z[LPL];
 #pragma unroll
   for (int i = 0; i < LPL; ++i) z[i] = A(tile[(col * LPL + i) * TS + q]);
-  // a full chunk past the mode's last distinct factor row (the same for the whole column): every lane map
+  // CST: a full chunk past the last distinct factor row of every column of the tile, so that every lane map
   // has the homogeneous part M, whose powers come from the block's table
-  const bool cst = c * kChunkLevels >= ln.last && (c + 1) * kChunkLevels <= nt;
+  constexpr bool cst = CST;
   // forward: z_l = invd_l (r_l - e1_l z_{l-1} - e2_l z_{l-2})
   {
     A P[2], zm2, zm1, x2 = A(0), x1 = A(0);
@@ -1296,7 +1309,10 @@ __device__ __forceinline__ void colchunk_tile(const ChunkLane<A>& ln, const Chun
 // mode's row offset and the entering states, the tile's loads and the factor
 // rows are issued in that order, so that their latencies overlap.
 // tile: kChunkCols * kChunkLpl * (kChunkCw + 1) elements of LDS.
-template <typename T, int BW, typename A, bool SOLVE>
+// One tile (column block g, chunk c) of either pass; CST: a tile whose every
+// column lies past its last distinct factor row (only row `last` is loaded,
+// and the scans use the powers of M).
+template <typename T, int BW, typename A, bool SOLVE, bool CST>
 __device__ __forceinline__ void colchunk_item(T* __restrict__ spec, const FacTab<A>& fac, const ChunkArgs& ca,
                                               int nt, int nx, int g, int c, T* tile, double* __restrict__ s0) {
   ChunkLane<A> ln;
@@ -1308,19 +1324,22 @@ __device__ __forceinline__ void colchunk_item(T* __restrict__ spec, const FacTab
   constexpr int NPW = kChunkCols * kChunkPow * 4;
   static_assert(NPW <= kChunkThreads, "one power entry per thread");
   A* pwl = reinterpret_cast<A*>(tile + kChunkCols * kChunkLpl * (kChunkCw + 1));
-  const int pe = threadIdx.x % NPW;
-  const double pv = ca.cpow[(size_t)spec_mode(g * kChunkCols + pe / (kChunkPow * 4), nx) * (kChunkPow * 4) +
-                            pe % (kChunkPow * 4)];
+  double pv = 0.0;
+  if (CST) {
+    const int pe = threadIdx.x % NPW;
+    pv = ca.cpow[(size_t)spec_mode(g * kChunkCols + pe / (kChunkPow * 4), nx) * (kChunkPow * 4) + pe % (kChunkPow * 4)];
+  }
   // pass 2: the states entering the chunk (t, h) of the block's columns, after the powers: [kChunkCols][4]
   A* stl = pwl + NPW;
   const double sv = SOLVE ? ca.cwork[((size_t)(ca.nchunk + c) * nx + g * kChunkCols) * 4 + threadIdx.x % (4 * kChunkCols)]
                           : 0.0;
-  ln.load_rows(fac);
+  if (CST) ln.load_row_last(fac);
+  else ln.load_rows(fac);
   buf.to_lds(tile);
-  if (threadIdx.x < NPW) pwl[threadIdx.x] = A(pv);
+  if (CST && threadIdx.x < NPW) pwl[threadIdx.x] = A(pv);
   if (SOLVE && threadIdx.x < 4 * kChunkCols) stl[threadIdx.x] = A(sv);
   __syncthreads();
-  colchunk_tile<T, BW, A, SOLVE>(ln, ca, nt, nx, c, tile, pwl + ln.col * (kChunkPow * 4), stl + ln.col * 4, s0);
+  colchunk_tile<T, BW, A, SOLVE, CST>(ln, ca, nt, nx, c, tile, pwl + ln.col * (kChunkPow * 4), stl + ln.col * 4, s0);
   if (SOLVE) {
     __syncthreads();
     ChunkTile<T>::store_from_lds(tile, spec, nt, g, c * kChunkLevels);

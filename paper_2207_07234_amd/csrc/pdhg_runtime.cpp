@@ -16,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "pdhg.h"
@@ -290,6 +291,8 @@ struct pdhg_handle {
   // FP64 copy of the factor table
   double* d_cmap = nullptr;
   double* d_cpow = nullptr;
+  int* d_ctiles = nullptr;      // the chunked solve's four tile lists (ChunkArgs::tiles)
+  int ctoff[4] = {0, 0, 0, 0}, cntile[4] = {0, 0, 0, 0};
   int chunk_g64 = 0;            // column blocks below it run in FP64 when the spectrum is float
   void* d_f64_rows = nullptr;
   int* d_f64_off = nullptr;
@@ -447,6 +450,36 @@ FacTab<double> chunk_rows(const pdhg_handle* h) {
   return FacTab<double>{(const FacRow<double>*)h->d_fac_rows, h->d_fac_off, h->d_fac_last};
 }
 
+// The chunked solve's tiles (g nchunk + c) in the order of its four grids: FP64 recurrences on blocks g < n64
+// (general, then constant), float on the others (likewise).  A tile is constant when its chunk is full and
+// lies past the last distinct row of every column's mode in the table of its grid (last64: the FP64 rows,
+// last32: the float rows of an FP32 problem, else empty).
+static void chunk_tile_lists(const pdhg_problem& p, int g64, const std::vector<int>& last64,
+                             const std::vector<int>& last32, std::vector<int>& tiles, int toff[4], int ntile[4]) {
+  const int nblocks = p.nx / kChunkCols, nch = chunk_count(p.nt);
+  const int n64 = last32.empty() ? nblocks : std::min(g64, nblocks);
+  std::vector<int> lists[4];
+  for (int g = 0; g < nblocks; ++g) {
+    const bool f64 = g < n64;
+    const std::vector<int>& lst = f64 ? last64 : last32;
+    int ml = 0;
+    for (int j = g * kChunkCols; j < (g + 1) * kChunkCols; ++j) {
+      const int k = j == 0 ? 0 : (j == 1 ? p.nx / 2 : j >> 1);
+      ml = std::max(ml, lst[k]);
+    }
+    for (int c = 0; c < nch; ++c) {
+      const bool cst = c * kChunkLevels >= ml && (c + 1) * kChunkLevels <= p.nt;
+      lists[(f64 ? 0 : 2) + (cst ? 1 : 0)].push_back(g * nch + c);
+    }
+  }
+  tiles.clear();
+  for (int k = 0; k < 4; ++k) {
+    toff[k] = (int)tiles.size();
+    ntile[k] = (int)lists[k].size();
+    tiles.insert(tiles.end(), lists[k].begin(), lists[k].end());
+  }
+}
+
 template <typename T>
 int upload_factors(pdhg_handle* h, double c, double ghat) {
   std::vector<FacRow<T>> rows;
@@ -465,17 +498,20 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
   HIP_TRY(hipMemcpy(h->d_fac_last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
   if (h->d_cmap) hipFree(h->d_cmap);
   if (h->d_cpow) hipFree(h->d_cpow);
+  if (h->d_ctiles) hipFree(h->d_ctiles);
   if (h->d_f64_rows) hipFree(h->d_f64_rows);
   if (h->d_f64_off) hipFree(h->d_f64_off);
   if (h->d_f64_last) hipFree(h->d_f64_last);
   h->d_cmap = nullptr;
   h->d_cpow = nullptr;
+  h->d_ctiles = nullptr;
   h->d_f64_rows = nullptr;
   h->d_f64_off = h->d_f64_last = nullptr;
   if (uses_chunks(h->prob)) {   // the chunked column solve: FP64 rows and their maps
+    std::vector<int> l64 = last;   // the FP64 rows' last distinct rows
     if (sizeof(T) != sizeof(double)) {
       std::vector<FacRow<double>> r64;
-      std::vector<int> o64, l64;
+      std::vector<int> o64;
       build_factor_rows<double>(h->prob, c, ghat, r64, o64, l64);
       HIP_TRY(hipMalloc(&h->d_f64_rows, r64.size() * sizeof(FacRow<double>)));
       HIP_TRY(hipMalloc((void**)&h->d_f64_off, o64.size() * sizeof(int)));
@@ -491,6 +527,11 @@ int upload_factors(pdhg_handle* h, double c, double ghat) {
                                          h->d_cmap, nullptr));
     HIP_TRY(hipMalloc((void**)&h->d_cpow, sizeof(double) * 4 * kChunkPow * (size_t)nmodes));
     HIP_TRY(launch_colchunk_powers(chunk_rows(h), h->prob.time == PDHG_BDF2 ? 2 : 1, nmodes, h->d_cpow, nullptr));
+    std::vector<int> tiles;
+    chunk_tile_lists(h->prob, h->chunk_g64, l64, sizeof(T) == sizeof(double) ? std::vector<int>() : last, tiles,
+                     h->ctoff, h->cntile);
+    HIP_TRY(hipMalloc((void**)&h->d_ctiles, sizeof(int) * tiles.size()));
+    HIP_TRY(hipMemcpy(h->d_ctiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipStreamSynchronize(nullptr));
   }
   h->fac_c = c;
@@ -663,6 +704,11 @@ ChunkArgs chunk_args(const pdhg_handle* h, void* ws) {
   if (h->prob.dtype == PDHG_F32) a.f32 = factab<float>(h);
   a.cmap = h->d_cmap;
   a.cpow = h->d_cpow;
+  a.tiles = h->d_ctiles;
+  for (int k = 0; k < 4; ++k) {
+    a.toff[k] = h->ctoff[k];
+    a.ntile[k] = h->cntile[k];
+  }
   a.cwork = (double*)wsp(ws, layout_for(h->prob, h->esz).colchunk);
   a.nchunk = chunk_count(h->prob.nt);
   a.g64 = h->chunk_g64;
@@ -993,6 +1039,7 @@ void pdhg_destroy(pdhg_handle* h) {
   if (h->d_fac_last) hipFree(h->d_fac_last);
   if (h->d_cmap) hipFree(h->d_cmap);
   if (h->d_cpow) hipFree(h->d_cpow);
+  if (h->d_ctiles) hipFree(h->d_ctiles);
   if (h->d_f64_rows) hipFree(h->d_f64_rows);
   if (h->d_f64_off) hipFree(h->d_f64_off);
   if (h->d_f64_last) hipFree(h->d_f64_last);
