@@ -10,6 +10,9 @@
 //                 sub-group of W = nx / EPT threads (every tile of a block has
 //                 the same shape, so all tiles cost the same TB EPT points)
 //     col tiles   (p, column group): 8 spectrum columns of problem p
+//   Row tiles list the problems of 4 points per thread first (counts[3] of
+//   them), then those of 8, so that the primal pass runs one grid for each,
+//   each with its own register budget.
 // * Persistent grids: blocks take contiguous ranges of row tiles (neighbouring
 //   pairs share halo rows; the range of XCD x is contiguous) and strided
 //   column tiles (ordered by decreasing N_t, so every block gets a mix of
@@ -24,6 +27,7 @@ namespace pdhg {
 // Row tile shape for rows of length nx in a block of TB threads:
 // EPT = 4 points per thread when nx <= 4 TB, else 8 (nx = 8 TB).
 constexpr int kBatchMaxNx = 4096;
+constexpr int kBatchRowThreads = 512;   // threads of a row-pass block, either type
 __host__ __device__ constexpr int batch_ept(int nx, int TB) { return nx <= 4 * TB ? 4 : 8; }
 // The primal pass runs the streaming body in FP32 (see batch_row_threads).
 template <typename T>
@@ -92,7 +96,9 @@ kb_dual_fft(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls,
 // ------------------------------------------------------------------ B
 // Partial sums: part[P.part_off + pair] (residual) and part[rd_base + P.part_off
 // + pair] (dual residual), one per row pair.
-template <typename T, int TB>
+// E: the points per thread of the tiles this grid takes (where problems of
+// both kinds can occur, tiles [0, counts[3]) have 4 and the rest 8).
+template <typename T, int TB, int E>
 __global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(batch_stream<T>() ? 4 : 1)))
 kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls, const int2* __restrict__ tiles,
               const int* __restrict__ counts, int max_nx, const T* __restrict__ u_in, T* __restrict__ u_out,
@@ -101,9 +107,11 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
   extern __shared__ char smem[];
   __shared__ double red[TB / 64];
   T* edge_all = reinterpret_cast<T*>(smem + sizeof(C2<T>) * batch_row_lds_points(max_nx, 256, TB));
+  const int base = (batch_needs_e8<TB>() && E == 8) ? counts[3] : 0;
+  const int n = batch_needs_e8<TB>() ? (E == 4 ? counts[3] : counts[0] - counts[3]) : counts[0];
   int t0, t1;
-  block_range(counts[0], xcd_block(blockIdx.x, gridDim.x), gridDim.x, t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  block_range(n, xcd_block(blockIdx.x, gridDim.x), gridDim.x, t0, t1);
+  for (int t = base + t0; t < base + t1; ++t) {
     const int2 td = tiles[t];
     if (ctrls[td.x].status != 0) continue;
     const BatchProb& P = probs[td.x];
@@ -121,14 +129,9 @@ kb_primal_res(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrl
     const bool want_rd = rd_needed(ctrls + td.x);
     __syncthreads();
     constexpr bool kStream = batch_stream<T>();
-    if (!batch_needs_e8<TB>() || batch_ept(nx, TB) == 4)
-      primal_res_pair<T, 4, T, kStream>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off,
-                                        (T)P.tau_u, spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf,
-                                        twl, edge, rp, rd, static_cast<C2<T>*>(nullptr), nullptr, want_rd);
-    else if constexpr (batch_needs_e8<TB>())
-      primal_res_pair<T, 8, T, kStream>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off,
-                                        (T)P.tau_u, spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf,
-                                        twl, edge, rp, rd, static_cast<C2<T>*>(nullptr), nullptr, want_rd);
+    primal_res_pair<T, E, T, kStream>(C, u_in + P.u_off, u_out + P.u_off, phibar + P.f_off, phi + P.f_off,
+                                      (T)P.tau_u, spec + P.f_off, P.lqb, tw, 2 * pair, tid, W, threadIdx.x, TB, buf,
+                                      twl, edge, rp, rd, static_cast<C2<T>*>(nullptr), nullptr, want_rd);
     const double srp = subgroup_sum(rp, red, sg * nw, nw);
     const double srd = subgroup_sum(rd, red, sg * nw, nw);
     if (tid == 0 && pair < P.npairs) {
@@ -201,8 +204,9 @@ kb_colsolve(const BatchProb* __restrict__ probs, Ctrl* ctrls, const int2* __rest
 
 // ------------------------------------------------------------------ work lists
 // One block of kCompactThreads threads.  Problems are visited in the order
-// given by `order` (row tiles) and `corder` (column tiles); converged problems
-// contribute no tiles.  counts = {row tiles, column tiles, active problems}.
+// given by `order` (row tiles; the problems of 4 points per thread first) and
+// `corder` (column tiles); converged problems contribute no tiles.  counts =
+// {row tiles, column tiles, active problems, row tiles of 4 points per thread}.
 constexpr int kCompactThreads = 1024;
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
@@ -226,7 +230,7 @@ kb_compact(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls, 
            const int* __restrict__ order, const int* __restrict__ corder, int2* __restrict__ row_tiles,
            int2* __restrict__ col_tiles, int* __restrict__ counts) {
   __shared__ int sh[kCompactThreads];
-  int rbase = 0, cbase = 0, nact = 0;
+  int rbase = 0, cbase = 0, nact = 0, r4base = 0;
   for (int c0 = 0; c0 < nprob; c0 += kCompactThreads) {
     const int i = c0 + threadIdx.x;
     // row tiles
@@ -238,6 +242,9 @@ kb_compact(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls, 
     const int S = act ? probs[p].pairs_per_tile : 1;
     for (int k = 0; k < rn; ++k) row_tiles[roff + k] = make_int2(p, k * S);
     rbase += rtot;
+    int r4tot;
+    block_exclusive_scan(act && batch_ept(probs[p].s.nx, kBatchRowThreads) == 4 ? rn : 0, sh, r4tot);
+    r4base += r4tot;
     // column tiles
     p = i < nprob ? corder[i] : -1;
     act = p >= 0 && ctrls[p].status == 0;
@@ -254,6 +261,7 @@ kb_compact(const BatchProb* __restrict__ probs, const Ctrl* __restrict__ ctrls, 
     counts[0] = rbase;
     counts[1] = cbase;
     counts[2] = nact;
+    counts[3] = r4base;
   }
 }
 
@@ -383,7 +391,7 @@ static size_t row_lds_bytes(int max_nx) {
 // registers, at most 122 VGPRs), so that two of its persistent blocks share a
 // CU and hide each other's loads; in FP64 the load-first body (register budget).
 template <typename T>
-constexpr int batch_row_threads() { return 512; }
+constexpr int batch_row_threads() { return kBatchRowThreads; }
 
 
 template <typename T>
@@ -412,8 +420,9 @@ hipError_t batch_occupancy(int which, int max_nx, int* blocks_per_cu) {
   }
   if (which == 1) {
     const size_t lds = batch_row_lds<T>(max_nx);
-    if ((e = allow_lds(kb_primal_res<T, TB>, lds)) != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kb_primal_res<T, TB>, TB, lds);
+    constexpr int E = batch_needs_e8<TB>() ? 8 : 4;   // the grid of the larger register budget
+    if ((e = allow_lds(kb_primal_res<T, TB, E>, lds)) != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kb_primal_res<T, TB, E>, TB, lds);
   }
   const size_t lds = batch_col_lds<T>();
   if ((e = allow_lds(kb_colsolve<T>, lds)) != hipSuccess) return e;
@@ -436,10 +445,15 @@ hipError_t launch_batch_primal_res(const BatchLaunch& L, int grid, const T* u_in
                                    const T* phi, T* spec, double* part, int rd_base, hipStream_t st) {
   constexpr int TB = batch_row_threads<T>();
   const size_t lds = batch_row_lds<T>(L.max_nx);
-  hipError_t e = allow_lds(kb_primal_res<T, TB>, lds);
+  hipError_t e = allow_lds(kb_primal_res<T, TB, 4>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_primal_res<T, TB>), dim3(grid), dim3(TB), lds, st, L.probs, L.ctrls, L.row_tiles, L.counts,
-                     L.max_nx, u_in, u_out, phibar, phi, spec, part, rd_base);
+  hipLaunchKernelGGL((kb_primal_res<T, TB, 4>), dim3(grid), dim3(TB), lds, st, L.probs, L.ctrls, L.row_tiles,
+                     L.counts, L.max_nx, u_in, u_out, phibar, phi, spec, part, rd_base);
+  if constexpr (batch_needs_e8<TB>()) {   // the tiles of 8 points per thread, after those of 4
+    if ((e = allow_lds(kb_primal_res<T, TB, 8>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((kb_primal_res<T, TB, 8>), dim3(grid), dim3(TB), lds, st, L.probs, L.ctrls, L.row_tiles,
+                       L.counts, L.max_nx, u_in, u_out, phibar, phi, spec, part, rd_base);
+  }
   return hipGetLastError();
 }
 

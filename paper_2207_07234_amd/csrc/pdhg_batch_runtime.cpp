@@ -201,9 +201,13 @@ int setup_impl(pdhg_batch* b) {
     }
     b->table[i].tw = b->d_tw[n];
   }
-  // tile orders: rows in problem order; columns by decreasing nt (stable)
+  // tile orders: rows in problem order, those of 4 points per thread before those of 8 (the primal pass runs
+  // a grid for each); columns by decreasing nt (stable)
   std::vector<int> order(P), corder(P);
   for (int i = 0; i < P; ++i) order[i] = corder[i] = i;
+  const int w4 = 4 * batch_row_block_threads<T>();   // widest row of 4 points per thread
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return (b->probs[x].nx > w4) < (b->probs[y].nx > w4); });
   std::stable_sort(corder.begin(), corder.end(),
                    [&](int x, int y) { return b->probs[x].nt > b->probs[y].nt; });
   BHIP_TRY(hipMalloc((void**)&b->d_probs, sizeof(BatchProb) * P));
