@@ -376,7 +376,7 @@ inline char* bws(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 // One iteration of every running problem: A, B, C.  `odd` selects the u
 // ping-pong direction (odd iterations read u and write u_alt).
 template <typename T>
-int enqueue_batch_body(pdhg_batch* b, bool odd, T* u, T* phi, void* ws, hipStream_t st) {
+int enqueue_batch_body(pdhg_batch* b, bool odd, T* u, T* phi, void* ws, const int* grid, hipStream_t st) {
   const BatchWs W = batch_ws(b);
   const BatchLaunch L = launch_of(b);
   T* u_alt = (T*)bws(ws, W.u_alt);
@@ -384,22 +384,23 @@ int enqueue_batch_body(pdhg_batch* b, bool odd, T* u, T* phi, void* ws, hipStrea
   T* spec = (T*)bws(ws, W.spec);
   T* uin = odd ? u : u_alt;
   T* uout = odd ? u_alt : u;
-  BHIP_TRY(launch_batch_dual_fft<T>(L, b->grid[0], spec, phi, phibar, st));
-  BHIP_TRY(launch_batch_primal_res<T>(L, b->grid[1], uin, uout, phibar, phi, spec, b->d_part, b->total_pairs, st));
-  BHIP_TRY(launch_batch_colsolve<T>(L, b->grid[2], spec, b->d_part, b->total_pairs, st));
+  BHIP_TRY(launch_batch_dual_fft<T>(L, grid[0], spec, phi, phibar, st));
+  BHIP_TRY(launch_batch_primal_res<T>(L, grid[1], uin, uout, phibar, phi, spec, b->d_part, b->total_pairs, st));
+  BHIP_TRY(launch_batch_colsolve<T>(L, grid[2], spec, b->d_part, b->total_pairs, st));
   return PDHG_OK;
 }
 
 template <typename T>
-int build_batch_graph(pdhg_batch* b, int chunk, T* u, T* phi, void* ws) {
+int build_batch_graph(pdhg_batch* b, int chunk, T* u, T* phi, void* ws, const int* grid) {
   if (b->gexec && b->gk_u == u && b->gk_phi == phi && b->gk_ws == ws && b->gk_chunk == chunk &&
-      std::equal(b->grid, b->grid + 3, b->gk_grid))
+      std::equal(grid, grid + 3, b->gk_grid))
     return PDHG_OK;
   if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
   if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
   BHIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = PDHG_OK;
-  for (int k = 0; k < chunk && rc == PDHG_OK; ++k) rc = enqueue_batch_body<T>(b, (k % 2) == 0, u, phi, ws, b->cap_stream);
+  for (int k = 0; k < chunk && rc == PDHG_OK; ++k)
+    rc = enqueue_batch_body<T>(b, (k % 2) == 0, u, phi, ws, grid, b->cap_stream);
   if (rc == PDHG_OK) {
     hipError_t e = launch_batch_compact(launch_of(b), b->cap_stream);
     if (e != hipSuccess) rc = bset_hip_error(b, e, "launch_batch_compact");
@@ -414,8 +415,22 @@ int build_batch_graph(pdhg_batch* b, int chunk, T* u, T* phi, void* ws) {
   b->gk_phi = phi;
   b->gk_ws = ws;
   b->gk_chunk = chunk;
-  std::copy(b->grid, b->grid + 3, b->gk_grid);
+  std::copy(grid, grid + 3, b->gk_grid);
   return PDHG_OK;
+}
+
+// Persistent grids for the tiles still running: the tuned grid of a pass divided by 4 while a quarter of it
+// still gives every tile a block (row tiles for A and B, column tiles for C) and every CU one; any grid
+// covers all tiles, so only the time changes.
+static void running_grids(const pdhg_batch* b, int row_tiles, int col_tiles, int* grid) {
+  auto shrink = [&](int g, int n) {
+    const int floor = std::max(n, b->ncu);
+    while (g / 4 >= floor) g /= 4;
+    return g;
+  };
+  grid[0] = shrink(b->grid[0], row_tiles);
+  grid[1] = shrink(b->grid[1], row_tiles);
+  grid[2] = shrink(b->grid[2], col_tiles);
 }
 
 // Copy problem i's slices of a checkpoint into u and phi and recompute its residual norms and
@@ -477,16 +492,31 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
   T* ck_u = (T*)bws(ws, W.ck_u);
   T* ck_phi = (T*)bws(ws, W.ck_phi);
   auto t0 = std::chrono::steady_clock::now();
+  // graphs of grids shrunk as problems drop out: kept until the stream has drained (a launch may be in flight)
+  std::vector<hipGraphExec_t> retired_exec;
+  std::vector<hipGraph_t> retired_graph;
+  auto retire_all = [&]() {
+    for (hipGraphExec_t g : retired_exec) hipGraphExecDestroy(g);
+    for (hipGraph_t g : retired_graph) hipGraphDestroy(g);
+    retired_exec.clear();
+    retired_graph.clear();
+  };
   if (prm->max_iter > 0) {
     BHIP_TRY(launch_batch_checkpoint<T>(L, u_alt, phi, ck_u, ck_phi, st));   // iterate 0
-    rc = build_batch_graph<T>(b, chunk, u, phi, ws);
+    int run[3] = {b->grid[0], b->grid[1], b->grid[2]};
+    rc = build_batch_graph<T>(b, chunk, u, phi, ws, run);
     if (rc) return rc;
     const long long bodies = prm->max_iter + 1;
     long long launched = 0;
     int idx = 0;
     bool stop = false;
     while (!stop && launched < bodies) {
-      BHIP_TRY(hipGraphLaunch(b->gexec, st));
+      hipError_t le = hipGraphLaunch(b->gexec, st);
+      if (le != hipSuccess) {
+        hipStreamSynchronize(st);
+        retire_all();
+        return bset_hip_error(b, le, "hipGraphLaunch");
+      }
       launched += chunk;
       BHIP_TRY(launch_batch_checkpoint<T>(L, u_alt, phi, ck_u, ck_phi, st));
       int* slot = b->h_counts + 4 * (idx & 1);
@@ -494,7 +524,26 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
       BHIP_TRY(hipEventRecord(b->ev[idx & 1], st));
       if (idx >= 1) {
         BHIP_TRY(hipEventSynchronize(b->ev[(idx - 1) & 1]));
-        if (b->h_counts[4 * ((idx - 1) & 1) + 2] == 0) stop = true;
+        const int* c = b->h_counts + 4 * ((idx - 1) & 1);
+        if (c[2] == 0) {
+          stop = true;
+        } else if (launched < bodies) {
+          int want[3];
+          running_grids(b, c[0], c[1], want);
+          if (!std::equal(want, want + 3, run)) {
+            retired_exec.push_back(b->gexec);
+            retired_graph.push_back(b->graph);
+            b->gexec = nullptr;
+            b->graph = nullptr;
+            std::copy(want, want + 3, run);
+            rc = build_batch_graph<T>(b, chunk, u, phi, ws, run);
+            if (rc) {
+              hipStreamSynchronize(st);
+              retire_all();
+              return rc;
+            }
+          }
+        }
       }
       ++idx;
     }
@@ -503,6 +552,7 @@ int batch_solve_impl(pdhg_batch* b, const T* u0, T* u, T* phi, void* ws, const p
   BHIP_TRY(hipMemcpyAsync(b->h_ctrls, b->d_ctrls, sizeof(Ctrl) * P, hipMemcpyDeviceToHost, st));
   BHIP_TRY(hipMemcpyAsync(b->h_scal, b->d_scal, sizeof(double) * P, hipMemcpyDeviceToHost, st));
   BHIP_TRY(hipStreamSynchronize(st));
+  retire_all();
   auto t1 = std::chrono::steady_clock::now();
   const double secs = std::chrono::duration<double>(t1 - t0).count();
   int worst = PDHG_OK;
