@@ -200,6 +200,76 @@ def chunked_solve(invd, e1, e2, b, dt):
     return np.concatenate([solve(c, *t[c], *h[c])[0] for c in range(nc)])
 
 
+def constant_chunk_solve(invd, e1, e2, b, x, w, lpl=8, lanes=32):
+    """One chunk of lanes * lpl levels of L L^T y = b, every level on the same factor row
+    (invd, e1, e2: scalars), entered with forward state x = (z_{-2}, z_{-1}) and backward state
+    w = (y_{n+1}, y_n), as the GPU's constant-tile kernels compute it (FP64): each lane's
+    particular part P from zero; M, the homogeneous map of lpl levels, and M^2, M^4, M^8; the
+    entering state folded into the first lane (P += M x); an inclusive scan within each row of 16
+    lanes (P_q += M^d P_{q-d} at d = 1, 2, 4, 8, lanes without a lane d before them unchanged);
+    the second row adds the scan of a vector started from M S in its first lane (S: the first
+    row's total); the state entering a lane is the inclusive P of the lane before it; every lane
+    solved again from it.  Backward mirrors it from the last lane.  b: (lanes * lpl, m)."""
+    n, m = b.shape
+    assert n == lanes * lpl and lanes == 32
+
+    def seg(z, s2, s1, fwd):   # lpl levels of one lane from state (s2, s1); returns values and state
+        out = np.zeros_like(z)
+        order = range(lpl) if fwd else range(lpl - 1, -1, -1)
+        for i in order:
+            v = invd * (z[i] - e1 * s1 - e2 * s2)
+            out[i] = v
+            s2, s1 = s1, v
+        return out, s2, s1
+
+    # M: states (a2, a1) and (b2, b1) after lpl homogeneous levels from (1, 0) and (0, 1)
+    _, a2, a1 = seg(np.zeros((lpl, 1)), np.ones(1), np.zeros(1), True)
+    _, b2, b1 = seg(np.zeros((lpl, 1)), np.zeros(1), np.ones(1), True)
+    m1 = np.array([[a2[0], b2[0]], [a1[0], b1[0]]])
+    pw = [m1]
+    for _ in range(3):
+        pw.append(pw[-1] @ pw[-1])
+
+    def row_scan(v, fwd):   # v: (lanes, 2, m), in place per row of 16 lanes
+        for s_, mp in enumerate(pw):
+            d = 1 << s_
+            new = v.copy()
+            for q in range(lanes):
+                r = q % 16
+                src = q - d if fwd else q + d
+                if (fwd and r >= d) or (not fwd and r + d <= 15):
+                    new[q] = v[q] + np.einsum("ij,jm->im", mp, v[src])
+            v[:] = new
+
+    def scan(blocks, x2, x1, fwd):
+        P = np.zeros((lanes, 2, m))
+        for q in range(lanes):
+            _, p2, p1 = seg(blocks[q], np.zeros(m), np.zeros(m), fwd)
+            P[q] = (p2, p1)
+        first = 0 if fwd else lanes - 1
+        P[first] += np.einsum("ij,jm->im", m1, np.stack([x2, x1]))
+        row_scan(P, fwd)
+        S = P[15] if fwd else P[16]
+        D = np.zeros_like(P)
+        D[16 if fwd else 15] = np.einsum("ij,jm->im", m1, S)
+        row_scan(D, fwd)
+        P += D
+        ent = np.zeros_like(P)
+        for q in range(lanes):
+            if q == first:
+                ent[q] = (x2, x1)
+            else:
+                ent[q] = P[q - 1] if fwd else P[q + 1]
+        return ent
+
+    blocks = b.reshape(lanes, lpl, m).astype(np.float64)
+    ent = scan(blocks, x[0], x[1], True)
+    z = np.stack([seg(blocks[q], ent[q][0], ent[q][1], True)[0] for q in range(lanes)])
+    ent = scan(z, w[0], w[1], False)
+    y = np.stack([seg(z[q], ent[q][0], ent[q][1], False)[0] for q in range(lanes)])
+    return y.reshape(n, m)
+
+
 def kd_solve_fp32_fd(prob, bands, r32):
     """K_d^{-1} r as the FP32 finite-difference path computes it (float FFTs, float spectrum; float
     segmented recurrences, or the chunked solve on long time axes)."""

@@ -168,6 +168,36 @@ def test_chunked_solve_without_rounding_is_the_oracle_solve(nt, time, ghat):
         assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref)), k
 
 
+@pytest.mark.parametrize("nt,time,k", [(600, "bdf2", 20), (512, "be", 31), (700, "bdf2", 1)])
+def test_constant_row_chunk_scan_is_sequential_substitution(nt, time, k):
+    """The constant-tile chunk solve (a chunk past the mode's last distinct factor row: particular
+    parts scanned per row with powers of the 8-level segment map, the second row completed by a
+    scan started from M S, the entering state folded into the first lane) equals forward then
+    backward substitution level by level on the same row, from the same entering states, for the
+    last row of a mode of the oracle's factor."""
+    from fp32_emulation import constant_chunk_solve
+    prob = Problem(nx=64, nt=nt, t_final=nt / 256, time=time, precond_c=0.8, precond_gamma_hat=0.0)
+    L = np.linalg.cholesky(opre.time_gram(prob) + opre.mode_shifts(prob)[k] * np.eye(nt))
+    invd, e1 = 1.0 / L[-1, -1], L[-1, -2]
+    e2 = L[-1, -3] if time == "bdf2" else 0.0
+    rng = np.random.default_rng(nt + k)
+    b = rng.standard_normal((256, 3))
+    x = rng.standard_normal((2, 3))
+    w = rng.standard_normal((2, 3))
+    z = np.zeros_like(b)
+    s2, s1 = x
+    for l in range(256):
+        s2, s1 = s1, invd * (b[l] - e1 * s1 - e2 * s2)
+        z[l] = s1
+    y = np.zeros_like(b)
+    s2, s1 = w
+    for l in range(255, -1, -1):
+        s2, s1 = s1, invd * (z[l] - e1 * s1 - e2 * s2)
+        y[l] = s1
+    got = constant_chunk_solve(invd, e1, e2, b, x, w)
+    assert np.max(np.abs(got - y)) <= 1e-11 * np.max(np.abs(y))
+
+
 def test_segmented_float_recurrence_is_the_excess():
     """N_t = 900, BDF2: the segmented float recurrence loses several times more than the
     sequential one; with FP64 recurrences and FP64 mode 0 the iterates are inside 1e-5."""
