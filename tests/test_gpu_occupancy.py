@@ -39,6 +39,12 @@ CASES = [
     # (float FFTs and spectrum, FP64 recurrences and mode 0) leaves 1.7e-6 here; at h_t = h_x / 8 the
     # same emulation leaves 1.7e-5 after 4 iterations (the rounding of s is differenced in time)
     (256, 1030, 2 * 1030 / 256, "bdf2", "fd_lf", 0.0, torch.float64, "gram_f32", 4),
+    # four or more row pairs per CU (N_t >= 2047), where several blocks queue for each CU, with
+    # ragged grids (1025, 1026 and 1538 pairs), E = 4 (FP64) and 8 (FP32) points per thread
+    (2048, 2050, 0.5, "bdf2", "fd_lf", 0.0, torch.float64, "gram", 3),
+    (1024, 2051, 0.5, "be", "fd_lf", 1e-3, torch.float32, "gram", 3),
+    (4096, 2049, 0.5, "bdf2", "fd_lf", 0.0, torch.float32, "gram", 3),
+    (512, 3075, 0.5, "be", "fd_lf", 1e-3, torch.float32, "gram", 4),
 ]
 
 
