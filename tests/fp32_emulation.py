@@ -33,6 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from oracle import fd as ofd
 from oracle import pdhg as opdhg
 from oracle import precond as opre
 
@@ -350,6 +351,47 @@ def run_fp32(prob, u0, tau, n_iter):
         phibar = phin + ts
         phi = phin
     return u.astype(np.float64), phi.astype(np.float64)
+
+
+def run_float_spectrum(prob, u0, tau, n_iter, ft=F32):
+    """Algorithm 1 (u^0 fixed) with the single-precision spectral pass of an FP64 problem emulated:
+    the residual rows rounded to float and transformed in float, a float spectrum, the banded
+    recurrences in FP64 on it, mode 0 of s kept in FP64 through the inverse transform; FP64
+    elsewhere.  ft is the type of the float pass (np.float64 removes the rounding).  Returns
+    (u, phi) after n_iter iterations."""
+    cx = np.complex64 if ft == F32 else np.complex128
+    invd, e1, e2 = cholesky_bands(prob)
+    nx, nt = prob.nx, prob.nt
+    cols = (np.repeat(invd, 2, axis=1), np.repeat(e1, 2, axis=1), np.repeat(e2, 2, axis=1))
+
+    def kd(r):
+        rh = np.fft.rfft(r.astype(ft), axis=1).astype(cx)
+        b = np.empty((nt, 2 * rh.shape[1]))
+        b[:, 0::2], b[:, 1::2] = rh.real, rh.imag
+        y = segmented_solve(*cols, b, 1, np.float64)
+        sh = y[:, 0::2] + 1j * y[:, 1::2]
+        s0 = sh[:, 0].real.copy()
+        sh[:, 0] = 0.0
+        s = np.fft.irfft(sh.astype(cx), n=nx, axis=1).astype(np.float64)
+        return s + s0[:, None] / nx
+
+    u = np.broadcast_to(np.asarray(u0, dtype=np.float64), (nt + 1, nx)).copy()
+    phi = np.zeros((nt, nx))
+    phibar = phi.copy()
+    for _ in range(n_iter):
+        jt = ofd.jacobian(prob, u).T.tocsr()
+        u[1:] -= tau * (jt @ phibar.ravel()).reshape(phibar.shape)
+        sv = kd(ofd.residual(prob, u))
+        phibar = phi + 2.0 * tau * sv
+        phi = phi + tau * sv
+    return u, phi
+
+
+def float_spectrum_bar(prob, u0, tau, n_iter, ref_u, ref_phi, flat=1e-5):
+    """(bar for u, bar for phi) of the single-precision spectral pass: the flat bar, or twice the
+    emulated error where that is larger."""
+    eu, ep = run_float_spectrum(prob, u0, tau, n_iter)
+    return max(flat, 2.0 * rel_err(eu, ref_u)), max(flat, 2.0 * rel_err(ep, ref_phi))
 
 
 def rel_err(a, ref):

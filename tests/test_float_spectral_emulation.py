@@ -213,6 +213,18 @@ def test_segmented_float_recurrence_is_the_excess():
     assert e_new < e_scan / 10
 
 
+def test_banded_float_spectrum_emulation_without_rounding_is_the_oracle():
+    """The banded emulation of the single-precision pass (used for the GPU bar on wide rows), run
+    with an FP64 'float' type, is Algorithm 1 of the oracle; with float it differs by rounding only."""
+    from fp32_emulation import rel_err, run_float_spectrum
+    prob, u0 = _case(300, "bdf2")
+    ref = opdhg.run(prob, u0, 0.6, 0.6, eps=0.0, max_iter=10)
+    u, phi = run_float_spectrum(prob, u0, 0.6, 10, ft=np.float64)
+    assert rel_err(u, ref.u) < 1e-12 and rel_err(phi, ref.phi) < 1e-12
+    u32, _ = run_float_spectrum(prob, u0, 0.6, 10)
+    assert 1e-8 < rel_err(u32, ref.u) < 1e-4
+
+
 def test_float_rounding_grows_with_the_time_axis():
     """The segmented float recurrence: the error grows with N_t (same h_t, longer horizon)."""
     errs = []

@@ -8,7 +8,9 @@ fixed point (A(u) = 0, the implicit scheme's solution) and the stopping test
 are those of the FP64 method; only the trajectory carries FP32-sized
 perturbations.  Checked against the FP64 oracle:
   * trajectories after 1, 10 and 100 iterations within the FP32 bar (1e-5
-    relative to max(1, max |oracle|));
+    relative to max(1, max |oracle|)); on rows of 1024 and 2048 points, where
+    the float transforms' rounding reaches that size, within twice the error of
+    a CPU emulation of the pass where that is larger;
   * the converged solution at 1e-8 against the oracle's Newton march at the
     bar of the FP64 solve, the oracle's residual norms of the returned (u, phi)
     within the tolerance, and the iteration count of the FP64 solve;
@@ -71,6 +73,27 @@ def test_mixed_trajectory_within_fp32_bar(gpu_lib, case):
         assert res.stats["variant"] == 2
         assert _err(res.u, ref.u, "u") < 1e-5
         assert _err(res.phi, ref.phi, "phi") < 1e-5
+
+
+@pytest.mark.parametrize("nx,nt,t_final", [(1024, 1030, 1030 / 128), (1024, 1030, 2 * 1030 / 1024),
+                                           (2048, 512, 0.5)])
+def test_mixed_trajectory_wide_rows(gpu_lib, nx, nt, t_final):
+    """Rows of 1024 and 2048 points (the last is the 2048 x 512 BDF2 workload): after 4 iterations the
+    rounding of the float transforms reaches about 1e-5 of u, so the bar is the flat one or twice the
+    error of the CPU emulation of the pass (float residual rows, transforms and spectrum, FP64
+    recurrences and mode 0 of s), whichever is larger."""
+    from fp32_emulation import float_spectrum_bar
+    cfg = dict(nx=nx, nt=nt, t_final=t_final, alpha=0.5, beta=0.0, gamma=0.0, time="bdf2", space="fd_lf")
+    u0 = syn.fourier_u0(13, nx)
+    oprob, gprob = _pair(gpu_lib, u0, **cfg)
+    tau, n = 0.6, 4
+    ref = opdhg.run(oprob, u0, tau, tau, eps=0.0, max_iter=n)
+    bar_u, bar_phi = float_spectrum_bar(oprob, u0, tau, n, ref.u, ref.phi)
+    _say(f"mixed wide rows {nx}x{nt} T={t_final:.4f}: bars u {bar_u:.2e}, phi {bar_phi:.2e}")
+    res = gpu_lib.Solver(gprob).solve(_dev(u0), tau_u=tau, tau_phi=tau, eps=0.0, max_iter=n, check_every=2)
+    assert res.stats["iters"] == n
+    assert _err(res.u, ref.u, "u") < bar_u
+    assert _err(res.phi, ref.phi, "phi") < bar_phi
 
 
 @pytest.mark.parametrize("time", ["be", "bdf2"])
