@@ -78,7 +78,7 @@ def test_mixed_trajectory_within_fp32_bar(gpu_lib, case):
 @pytest.mark.parametrize("nx,nt,t_final", [(1024, 1030, 1030 / 128), (1024, 1030, 2 * 1030 / 1024),
                                            (2048, 512, 0.5)])
 def test_mixed_trajectory_wide_rows(gpu_lib, nx, nt, t_final):
-    """Rows of 1024 and 2048 points (the last is the 2048 x 512 BDF2 workload): after 4 iterations the
+    """Rows of 1024 and 2048 points (the last on the grid of the 2048 x 512 BDF2 workload): after 4 iterations the
     rounding of the float transforms reaches about 1e-5 of u, so the bar is the flat one or twice the
     error of the CPU emulation of the pass (float residual rows, transforms and spectrum, FP64
     recurrences and mode 0 of s), whichever is larger."""
